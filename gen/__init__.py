@@ -1,0 +1,3 @@
+"""Seeded synthetic workloads (systems and query points); no solver arithmetic."""
+from .workloads import (SystemSpec, double_integrator, random_system,  # noqa: F401
+                        uniform_box_points, gaussian_points)

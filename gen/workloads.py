@@ -1,0 +1,79 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and the
+benchmark.
+
+This module only draws random systems and query points.  It contains none of
+the solver's arithmetic (no matrix exponential, quadrature, Hopf objective or
+primal-dual step), so the oracle and the HIP path can both read its output
+without sharing any of the method.
+
+Workload shapes follow the paper's examples and the configurations the
+library is benchmarked on:
+  * the double integrator of Sec. VI-A (n=2, m=1, |u| <= 1, ball target);
+  * random stable-ish linear systems: A = S diag(eig) S^{-1} with
+    eig ~ U[-1, 0.2] and S_ij ~ N(0, 1/n), B_ij ~ N(0,1)/sqrt(n), an
+    axis-aligned ellipsoid target W = diag(q), q ~ U[0.05, 0.2], and either
+    the unit l2 ball or the unit box as control set;
+  * query points either literal (uniform box / isotropic Gaussian) or a
+    "calibrated" isotropic Gaussian whose scale puts most points inside the
+    reachable band.
+All randomness comes from numpy.random.default_rng(seed).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class SystemSpec:
+    """Plain description of one system (all float64, row-major)."""
+    A: np.ndarray
+    B: np.ndarray
+    W: np.ndarray
+    c: np.ndarray
+    uset: str            # "l2" or "box"
+    N: int
+    t_max: float
+    quad: str            # "trap" or "left"
+    name: str = ""
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    @property
+    def m(self):
+        return self.B.shape[1]
+
+
+def double_integrator(r=0.1, N=100, t_max=10.0, quad="trap"):
+    """Sec. VI-A: position/velocity, scalar control in [-1, 1], ball target of
+    radius r at the origin (W = r^2 I)."""
+    A = np.array([[0.0, 1.0], [0.0, 0.0]])
+    B = np.array([[0.0], [1.0]])
+    W = (r * r) * np.eye(2)
+    return SystemSpec(A, B, W, np.zeros(2), "box", N, t_max, quad, f"double_integrator_r{r}")
+
+
+def random_system(n, m, N, uset, seed, t_max=10.0, quad="trap",
+                  eig_lo=-1.0, eig_hi=0.2, q_lo=0.05, q_hi=0.2):
+    """Random linear system by a seeded similarity transform (see module doc)."""
+    rng = np.random.default_rng(seed)
+    eig = rng.uniform(eig_lo, eig_hi, size=n)
+    S = rng.normal(0.0, 1.0 / np.sqrt(n), size=(n, n))
+    A = S @ np.diag(eig) @ np.linalg.inv(S)
+    B = rng.normal(0.0, 1.0, size=(n, m)) / np.sqrt(n)
+    q = rng.uniform(q_lo, q_hi, size=n)
+    return SystemSpec(A, B, np.diag(q), np.zeros(n), uset, N, t_max, quad,
+                      f"random_n{n}_m{m}_N{N}_{uset}_s{seed}")
+
+
+def uniform_box_points(npts, n, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(npts, n))
+
+
+def gaussian_points(npts, n, std, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, std, size=(npts, n))

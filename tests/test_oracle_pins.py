@@ -1,0 +1,366 @@
+"""Pins for the FP64 oracle: closed forms, brute force, strong duality,
+invariants and special cases.  Each test would fail under a plausible mistake
+in the oracle (dropped term, wrong sign or index, transposed operand)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle import hopf_oracle as O
+from gen import double_integrator, random_system
+from tests import pin_helpers as PH
+
+
+def sysobj(spec, **kw):
+    d = dict(uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+    d.update(kw)
+    return O.System(spec.A, spec.B, spec.W, spec.c, **d)
+
+
+def ball_system(n, r, uset, N=40, t_max=5.0, quad=O.TRAP):
+    """dx/dt = u (A = 0, B = I): the time-independent Hamiltonian case of
+    Sec. II-A, where the quadrature is exact."""
+    return O.System(np.zeros((n, n)), np.eye(n), (r * r) * np.eye(n), None, None,
+                    uset, N, t_max, quad)
+
+
+# ------------------------------------------------------------------ table / expm
+
+def test_K_rows_double_integrator_closed_form():
+    """e^{tau A} for the nilpotent A = [[0,1],[0,0]] is [[1,tau],[0,1]], so
+    K_k = -B^T e^{tau_k A^T} = -[tau_k, 1]."""
+    S = sysobj(double_integrator(0.1, 100))
+    tau = np.array([0.0, 0.3, 1.7, 9.9])
+    Ks = O.K_blocks(S, tau)
+    for k, t in enumerate(tau):
+        np.testing.assert_allclose(Ks[k], -np.array([[t, 1.0]]), rtol=0, atol=1e-14)
+
+
+def test_K_rows_rotation_and_diagonal_closed_form():
+    A = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    B = np.array([[0.0], [1.0]])
+    S = O.System(A, B, np.eye(2), uset=O.BOX, N=10, t_max=1.0)
+    t = 0.7
+    E = np.array([[math.cos(t), math.sin(t)], [-math.sin(t), math.cos(t)]])
+    np.testing.assert_allclose(O.K_blocks(S, [t])[0], -(E @ B).T, atol=1e-14)
+    d = np.array([-1.0, -0.25, 0.2])
+    S2 = O.System(np.diag(d), np.eye(3)[:, :2], np.eye(3), uset=O.L2, N=10, t_max=1.0)
+    np.testing.assert_allclose(O.K_blocks(S2, [t])[0], -(np.diag(np.exp(t * d))[:, :2]).T, atol=1e-14)
+
+
+# ------------------------------------------------------------------ quadrature
+
+@pytest.mark.parametrize("quad", [O.TRAP, O.LEFT])
+def test_weights_sum_to_horizon_and_are_nonnegative(quad):
+    S = ball_system(2, 0.3, O.L2, N=11, t_max=5.0, quad=quad)
+    for T in [0.0, 0.1, 0.5, 0.51, 1.234, 3.0, 4.99, 5.0]:
+        tau, w, partial = O.nodes_and_weights(S, T)
+        assert np.all(w >= 0.0)
+        assert abs(np.sum(w) - T) <= 1e-13
+        assert np.all(tau <= T + 1e-13)
+
+
+def test_trapezoid_weights_on_grid_and_exactness():
+    """On a grid horizon the weights are the composite trapezoid rule, which
+    integrates linear functions of tau exactly at every horizon."""
+    S = ball_system(2, 0.3, O.L2, N=11, t_max=5.0)
+    h = 0.5
+    tau, w, partial = O.nodes_and_weights(S, 2.0)
+    assert not partial
+    np.testing.assert_allclose(w, [h / 2, h, h, h, h / 2], atol=1e-15)
+    for T in [0.3, 1.7, 2.0, 4.6]:
+        tau, w, _ = O.nodes_and_weights(S, T)
+        assert abs(np.dot(w, 3.0 + 2.0 * tau) - (3.0 * T + T * T)) <= 1e-12
+
+
+def test_left_rule_matches_paper_layout_at_tmax():
+    """At T = t_max the left rule is the paper's t_i = i T/N, i = 0..N-1,
+    each with weight T/N (eq. (17))."""
+    S = ball_system(2, 0.3, O.L2, N=8, t_max=4.0, quad=O.LEFT)
+    tau, w, _ = O.nodes_and_weights(S, 4.0)
+    np.testing.assert_allclose(tau, np.arange(8) * 0.5, atol=1e-15)
+    np.testing.assert_allclose(w, np.full(8, 0.5), atol=1e-15)
+
+
+@pytest.mark.parametrize("quad", [O.TRAP, O.LEFT])
+def test_weights_continuous_across_grid_points(quad):
+    """phi_N must be continuous in T for bisection: the weight of every time
+    value is continuous as T crosses a grid point."""
+    S = ball_system(2, 0.3, O.L2, N=11, t_max=5.0, quad=quad)
+    h = O.grid_step(S)
+
+    def weight_map(T):
+        tau, w, _ = O.nodes_and_weights(S, T)
+        out = {}
+        for t, x in zip(tau, w):
+            out[round(t, 6)] = out.get(round(t, 6), 0.0) + x
+        return out
+    for k in [1, 3, 7]:
+        a, b = weight_map(k * h - 1e-9), weight_map(k * h + 1e-9)
+        keys = set(a) | set(b)
+        for key in keys:
+            assert abs(a.get(key, 0.0) - b.get(key, 0.0)) < 1e-8
+
+
+# ------------------------------------------------------------------ closed forms (A = 0)
+
+@pytest.mark.parametrize("x,t", [([0.9, -0.4, 0.2], 0.3), ([0.2, 0.1, 0.0], 0.5),
+                                 ([1.5, 1.0, -1.0], 1.2), ([0.5, 0.5, 0.5], 0.0)])
+def test_value_l2_ball_closed_form(x, t):
+    """dx/dt = u, ||u||_2 <= 1, ball target of radius r:
+    phi(x,t) = 1/2 (max(0, ||x|| - t)^2 / r^2 - 1)  (Hopf formula, eq. (6))."""
+    r = 0.3
+    S = ball_system(3, r, O.L2)
+    pr = O.solve_value(S, np.array(x), t, O.Options(c_tau=1.0, gap_tol=1e-9))
+    exact = 0.5 * (max(0.0, np.linalg.norm(x) - t) ** 2 / r ** 2 - 1.0)
+    assert pr.phi_lo - 1e-9 <= exact <= pr.phi_hi + 1e-9
+    assert pr.phi_hi - pr.phi_lo <= 1e-8 * max(1.0, abs(exact))
+
+
+@pytest.mark.parametrize("x,t", [([0.9, -0.4], 0.3), ([0.2, 0.7], 0.25), ([1.5, -1.0], 1.1)])
+def test_value_box_closed_form(x, t):
+    """dx/dt = u, ||u||_inf <= 1: each coordinate moves by at most t, so
+    phi = 1/2 (sum_i max(0, |x_i| - t)^2 / r^2 - 1)."""
+    r = 0.3
+    S = ball_system(2, r, O.BOX)
+    pr = O.solve_value(S, np.array(x), t, O.Options(c_tau=1.0, gap_tol=1e-9))
+    exact = 0.5 * (np.sum(np.maximum(0.0, np.abs(x) - t) ** 2) / r ** 2 - 1.0)
+    assert pr.phi_lo - 1e-9 <= exact <= pr.phi_hi + 1e-9
+
+
+@pytest.mark.parametrize("x", [[0.9, -0.4, 0.2], [2.0, 1.0, 0.5], [0.25, 0.0, 0.1]])
+def test_min_time_l2_ball_closed_form(x):
+    """T* = max(0, ||x|| - r) for dx/dt = u with the l2-ball control."""
+    r = 0.3
+    S = ball_system(3, r, O.L2, N=40, t_max=5.0)
+    res = O.min_time(S, np.array(x), O.Options(c_tau=1.0))
+    exact = max(0.0, np.linalg.norm(x) - r)
+    if exact == 0.0:
+        assert res.status == O.PT_INSIDE and res.T == 0.0
+        return
+    assert res.status == O.PT_OK
+    assert res.lo <= exact + 1e-9 and exact <= res.hi + 1e-9
+    assert abs(res.T - exact) <= 1e-4 * exact
+    assert res.gap_n <= 1e-6
+
+
+def test_min_time_off_centre_target():
+    """dx/dt = u with the target centred at c: T* = max(0, ||x - c|| - r)."""
+    r = 0.3
+    c = np.array([0.5, -1.0, 0.25])
+    S = O.System(np.zeros((3, 3)), np.eye(3), (r * r) * np.eye(3), c, None, O.L2, 40, 5.0)
+    x = np.array([1.5, 0.0, -0.5])
+    res = O.min_time(S, x, O.Options(c_tau=1.0))
+    exact = np.linalg.norm(x - c) - r
+    assert res.status == O.PT_OK and abs(res.T - exact) <= 1e-4 * exact
+
+
+def test_min_time_box_closed_form():
+    """Box control: T* solves sum_i max(0, |x_i| - T)^2 = r^2."""
+    r = 0.3
+    x = np.array([1.0, 0.6])
+    S = ball_system(2, r, O.BOX, N=40, t_max=5.0)
+    res = O.min_time(S, x, O.Options(c_tau=1.0))
+    f = lambda T: np.sum(np.maximum(0.0, np.abs(x) - T) ** 2) - r * r   # noqa: E731
+    lo, hi = 0.0, 2.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+    assert abs(res.T - hi) <= 1e-4 * hi
+
+
+def test_phi_monotone_in_t_for_integrator():
+    """For dx/dt = u the value is nonincreasing in t."""
+    S = ball_system(3, 0.3, O.L2)
+    x = np.array([1.0, -0.5, 0.3])
+    prev = math.inf
+    for t in [0.0, 0.2, 0.4, 0.8, 1.2, 1.6]:
+        pr = O.solve_value(S, x, t, O.Options(gap_tol=1e-9))
+        assert pr.phi_lo <= prev + 1e-9
+        prev = pr.phi_hi
+
+
+# ------------------------------------------------------------------ special values
+
+def test_phi_at_zero_horizon_is_terminal_cost():
+    """phi(x, 0) = J(x), the initial condition of eq. (4)."""
+    spec = random_system(6, 2, 20, "l2", seed=3)
+    S = sysobj(spec)
+    x = np.linspace(-1, 1, 6)
+    pr = O.solve_value(S, x, 0.0)
+    d = x - spec.c
+    exact = 0.5 * (d @ np.linalg.solve(spec.W, d) - 1.0)
+    assert abs(pr.phi_lo - exact) <= 1e-12 and abs(pr.phi_hi - exact) <= 1e-12
+
+
+# ------------------------------------------------------------------ strong duality vs an independent solver
+
+@pytest.mark.parametrize("uset,quad,T,shift", [("l2", O.TRAP, 1.37, 0.0), ("box", O.TRAP, 0.9, 0.2),
+                                               ("l2", O.LEFT, 2.2, -0.15), ("box", O.TRAP, 2.0, 0.0)])
+def test_strong_duality_against_independent_primal_solve(uset, quad, T, shift):
+    """phi_N equals the optimum of the primal control problem over discrete
+    controls (Fenchel-Rockafellar); the primal is solved here by projected
+    gradient with expm from scipy, independently of the primal-dual method.
+    Some cases move the target centre off the origin."""
+    spec = random_system(4, 2, 16, uset, seed=11, t_max=3.0, quad=quad)
+    c = shift * np.array([1.0, -2.0, 0.5, 1.0])
+    S = O.System(spec.A, spec.B, spec.W, c, None, uset, spec.N, spec.t_max, quad)
+    rng = np.random.default_rng(0)
+    x = rng.normal(0, 0.6, 4)
+    pr = O.solve_value(S, x, T, O.Options(c_tau=1.0, gap_tol=1e-10, max_iter=400000))
+    assert pr.gap_n() <= 1e-10
+    fval, _ = PH.primal_fista(spec.A, spec.B, spec.W, c, np.eye(2), uset, x, T,
+                              pr.tau, pr.w, iters=40000)
+    assert pr.phi_lo - 1e-9 <= fval + 1e-9
+    assert abs(fval - pr.phi_hi) <= 1e-7 * max(1.0, abs(fval))
+
+
+def test_terminal_state_matches_costate():
+    """At the optimum x_T = grad J*(lam*) = W lam* + c (Sec. V, eq. (29)), and
+    the read-out trajectory ends at x_T; p* = e^{T A^T} lam*."""
+    spec = random_system(4, 2, 16, "l2", seed=2, t_max=3.0)
+    S = sysobj(spec)
+    x = np.array([0.5, -0.3, 0.2, 0.4])
+    T = 1.3
+    pr = O.solve_value(S, x, T, O.Options(gap_tol=1e-11, max_iter=400000))
+    xT = O.terminal_state(S, pr.xf, pr.Ks, pr.y)
+    np.testing.assert_allclose(xT, spec.W @ pr.lam + spec.c, atol=1e-5)
+    s, u, xs, p = O.readout(S, x, pr)
+    np.testing.assert_allclose(xs[-1], xT, atol=1e-10)
+    np.testing.assert_allclose(p, expm(T * spec.A.T) @ pr.lam, atol=1e-12)
+    assert np.all(np.linalg.norm(u, axis=1) <= 1.0 + 1e-12)
+    assert abs(s[-1] - T) < 1e-12 and s[0] >= -1e-12
+
+
+def test_dphi_dT_equals_minus_hamiltonian():
+    """d phi/dT = -H_x(p*, x0) with H_x(p, x) = -x^T A^T p + ||Qu^T B^T p||_*
+    (Sec. IV); the discrete phi_N agrees up to the quadrature error."""
+    spec = random_system(4, 2, 400, "l2", seed=4, t_max=4.0)
+    S = sysobj(spec)
+    x = np.array([0.6, -0.5, 0.4, 0.3])
+    T, dT = 1.5, 1e-3
+    opt = O.Options(gap_tol=1e-12, max_iter=2000000, check_every=50)
+    a = O.solve_value(S, x, T - dT, opt)
+    b = O.solve_value(S, x, T + dT, opt)
+    mid = O.solve_value(S, x, T, opt)
+    fd = (b.phi_hi - a.phi_hi) / (2 * dT)
+    p = expm(T * spec.A.T) @ mid.lam
+    H = O.hamiltonian_x(S, p, x)
+    assert abs(fd + H) <= 2e-2 * max(1.0, abs(H))
+
+
+# ------------------------------------------------------------------ invariants
+
+def test_similarity_invariance():
+    """x' = S x, A' = S A S^-1, B' = S B, W' = S W S^T, c' = S c leave phi
+    and T* unchanged."""
+    spec = random_system(3, 1, 30, "l2", seed=8, t_max=4.0)
+    rng = np.random.default_rng(1)
+    Sm = rng.normal(size=(3, 3)) + 2 * np.eye(3)
+    S1 = sysobj(spec)
+    S2 = O.System(Sm @ spec.A @ np.linalg.inv(Sm), Sm @ spec.B, Sm @ spec.W @ Sm.T, Sm @ spec.c,
+                  uset="l2", N=30, t_max=4.0)
+    x = np.array([0.4, -0.35, 0.3])
+    opt = O.Options(gap_tol=1e-9, max_iter=400000)
+    a = O.solve_value(S1, x, 1.1, opt)
+    b = O.solve_value(S2, Sm @ x, 1.1, opt)
+    assert max(a.phi_lo, b.phi_lo) <= min(a.phi_hi, b.phi_hi) + 1e-9
+
+
+def test_control_scaling_equivalence():
+    """U = Qu C with Qu = 2 I equals B' = 2 B with Qu = I."""
+    spec = random_system(3, 2, 20, "box", seed=9, t_max=3.0)
+    S1 = O.System(spec.A, spec.B, spec.W, spec.c, 2 * np.eye(2), "box", 20, 3.0)
+    S2 = O.System(spec.A, 2 * spec.B, spec.W, spec.c, None, "box", 20, 3.0)
+    x = np.array([0.8, -0.6, 0.5])
+    opt = O.Options(gap_tol=1e-9, max_iter=400000)
+    a = O.solve_value(S1, x, 0.8, opt)
+    b = O.solve_value(S2, x, 0.8, opt)
+    assert max(a.phi_lo, b.phi_lo) <= min(a.phi_hi, b.phi_hi) + 1e-9
+
+
+def test_planted_point_value_bound():
+    """Plant x0 = e^{-T0 A}(x_T - sum_k w_k e^{tau_k A} B u_k) with x_T inside
+    the target and feasible u_k: then phi_N(x0, T0) <= J(x_T) < 0."""
+    spec = random_system(5, 2, 40, "l2", seed=6, t_max=3.0)
+    S = sysobj(spec)
+    rng = np.random.default_rng(5)
+    T0 = 1.7
+    tau, w, _ = O.nodes_and_weights(S, T0)
+    u = rng.normal(size=(len(tau), 2))
+    u /= np.maximum(1.0, np.linalg.norm(u, axis=1, keepdims=True))
+    xT = 0.5 * np.sqrt(np.diag(spec.W)) * rng.uniform(-1, 1, 5)
+    drive = sum(wk * expm(t * spec.A) @ spec.B @ uk for t, wk, uk in zip(tau, w, u))
+    x0 = expm(-T0 * spec.A) @ (xT - drive)
+    pr = O.solve_value(S, x0, T0, O.Options(gap_tol=1e-9, max_iter=400000))
+    JxT = 0.5 * (xT @ np.linalg.solve(spec.W, xT) - 1.0)
+    assert pr.phi_lo <= JxT + 1e-9
+
+
+# ------------------------------------------------------------------ double integrator (Sec. VI-A)
+
+def test_double_integrator_textbook_anchors():
+    """Closed-form anchors of the double integrator (the paper chose it
+    because closed-form optimal solutions exist, Sec. VI-A)."""
+    with open("tests/golden/double_integrator_origin.txt") as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for p, v, T in rows:
+        assert abs(PH.di_time_to_origin(float(p), float(v)) - float(T)) < 1e-12
+
+
+@pytest.mark.slow
+def test_double_integrator_min_time_vs_bang_bang():
+    """Discrete T_N* (trapezoid, N=100, r=0.1) against the continuous minimum
+    time from one-switch bang-bang brute force; the quadrature error is
+    O(h^2) with h = 10/99."""
+    spec = double_integrator(0.1, 100)
+    S = sysobj(spec)
+    opt = O.Options(c_tau=30.0)
+    for x in [(1.0, 0.0), (-0.5, 1.0), (1.2, -0.8)]:
+        Tc = PH.di_min_time_ball(x[0], x[1], 0.1)
+        res = O.min_time(S, np.array(x), opt)
+        assert res.status == O.PT_OK
+        assert abs(res.T - Tc) <= 3e-4 * Tc + 0.02 * O.grid_step(S) ** 2, (x, res.T, Tc)
+
+
+@pytest.mark.slow
+def test_double_integrator_converges_in_N():
+    """Convergence to the continuous minimum time as N grows: the left
+    rule's error is first order (doubling N roughly halves it once N >= 100)
+    and the trapezoid's error is smaller at every N."""
+    Tc = PH.di_min_time_ball(1.0, 0.0, 0.1)
+    errs = {O.LEFT: [], O.TRAP: []}
+    for quad in (O.LEFT, O.TRAP):
+        for N in [100, 200, 400]:
+            S = sysobj(double_integrator(0.1, N, quad=quad))
+            res = O.min_time(S, np.array([1.0, 0.0]), O.Options(c_tau=30.0, t_rel_tol=2e-7))
+            errs[quad].append(abs(res.T - Tc))
+    e = errs[O.LEFT]
+    assert e[0] > e[1] > e[2]
+    assert 1.3 < e[0] / e[1] < 2.6 and 1.3 < e[1] / e[2] < 2.6
+    t = errs[O.TRAP]
+    assert t[0] > t[1] > t[2]
+    assert all(a < b for a, b in zip(t, e))
+
+
+@pytest.mark.slow
+def test_double_integrator_vs_grid_hamilton_jacobi():
+    """Brute-force grid HJ (semi-Lagrangian dynamic programming) on 2-D
+    inputs: agreement within the grid's own error (a few cells of time)."""
+    g, Tg = PH.di_grid_min_time()
+    S = sysobj(double_integrator(0.1, 100))
+    for x in [(1.0, 0.0), (-1.0, 0.5), (0.5, -1.0), (1.5, 1.0)]:
+        res = O.min_time(S, np.array(x), O.Options(c_tau=30.0))
+        Tgrid = PH.grid_lookup(g, Tg, *x)
+        assert abs(res.T - Tgrid) <= 0.08 + 0.03 * res.T, (x, res.T, Tgrid)
+
+
+def test_unreachable_and_inside_statuses():
+    S = ball_system(2, 0.3, O.L2, N=20, t_max=1.0)
+    r = O.min_time(S, np.array([3.0, 0.0]))
+    assert r.status == O.PT_UNREACH and math.isinf(r.T)
+    r = O.min_time(S, np.array([0.1, 0.1]))
+    assert r.status == O.PT_INSIDE and r.T == 0.0
+    r = O.min_time(S, np.array([np.nan, 0.0]))
+    assert r.status == O.PT_NONFINITE
