@@ -1,0 +1,162 @@
+/*
+ * hopfpd -- primal-dual (Chambolle-Pock) solution of the generalized Hopf
+ * formula for time-optimal control of linear systems, on AMD MI355X (gfx950).
+ *
+ * Method: Kirchner, Hewer, Darbon, Osher, "A Primal-Dual Method for Optimal
+ * Control and Trajectory Generation in High-Dimensional Systems", arXiv
+ * 1712.08226.  Problem statement:
+ *   dynamics      dx/dt = A x + B u, u in U = Qu C            Sec. II-B eq. (8), Sec. III-A
+ *   control set   C = unit l2 ball or unit box (|u_i| <= 1)    Sec. III-A eq. (16), Sec. VI-A
+ *   target        Omega = {x : (x-c)^T W^{-1} (x-c) <= 1}      Sec. VI-A eq. (34)
+ *   terminal cost J(x) = 1/2 ((x-c)^T W^{-1} (x-c) - 1)        Sec. IV (zero on the boundary)
+ *   value         phi(x,T) from the quadrature form of the
+ *                 generalized Hopf formula                     Sec. III-A eq. (18)
+ *   minimum time  smallest T with phi(x,T) = 0                 Sec. IV
+ *   control       from the optimal dual blocks                 Sec. IV eq. (27)
+ *   trajectory    prefix sums over the quadrature nodes        Sec. V eq. (33)
+ *
+ * Discretisation.  Each system owns a table of N time-to-go nodes
+ * tau_k = k h (h = t_max/(N-1) for the trapezoid rule, t_max/N for the left
+ * rule of eq. (17)).  A solve at horizon T uses the nodes with tau_k <= T and,
+ * for the trapezoid rule, one extra node at tau = T; at T = t_max this is the
+ * paper's N-sample layout.
+ *
+ * Precision.  Tables and matrix exponentials are built in FP64; the
+ * iterations run in FP64 (HOPF_FP64) or FP32 (HOPF_FP32) on MFMA; every
+ * reported value, gap and sign decision is certified in FP64 from a primal
+ * point lam and a dual-feasible point y:  -P(lam) <= phi <= -D(y).
+ *
+ * Conventions for every call:
+ *   - arrays are row-major, float64 unless stated, owned by the caller;
+ *     inputs are copied before the call returns and no pointer is retained;
+ *   - "_dev" entry points take device pointers (memory the caller allocated
+ *     on the context's device) and a hipStream_t passed as void*; they
+ *     synchronise that stream before returning;
+ *   - a failed call returns a non-zero hopf_status and leaves a message in
+ *     hopf_last_error(ctx); no exception or abort crosses the interface;
+ *   - per-point problems (unreachable, not converged, non-finite input) are
+ *     reported per point and never fail the call;
+ *   - a context is not thread-safe: use one per host thread.
+ */
+#ifndef HOPFPD_H
+#define HOPFPD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hopf_ctx hopf_ctx;
+
+typedef enum {
+  HOPF_OK = 0,
+  HOPF_EINVAL = 1,        /* bad argument (shape, range, W not SPD, NULL) */
+  HOPF_ENOMEM = 2,        /* device or host allocation failed */
+  HOPF_EDEVICE = 3,       /* HIP runtime error */
+  HOPF_ESTATE = 4,        /* call out of order (e.g. solve before set_systems) */
+  HOPF_EUNSUPPORTED = 5   /* valid request this build does not handle */
+} hopf_status;
+
+typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
+typedef enum { HOPF_Q_TRAP = 0, HOPF_Q_LEFT = 1 } hopf_quad;
+typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1 } hopf_prec;
+typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1 } hopf_warm;
+
+/* per-point result status */
+typedef enum {
+  HOPF_PT_OK = 0,         /* certified to gap_tol */
+  HOPF_PT_INSIDE = 1,     /* x already in the target: T = 0 */
+  HOPF_PT_UNREACH = 2,    /* certified phi(x, t_max) > 0: T = +inf */
+  HOPF_PT_NOCONV = 3,     /* max_iter reached before a certified sign/gap */
+  HOPF_PT_NONFINITE = 4   /* NaN/Inf in the input or the iterates */
+} hopf_pt;
+
+/* One system.  Sizes: A n*n, B n*m, Qu m*m (NULL = identity), W n*n
+ * symmetric positive definite and diagonal in this build, c n (NULL = 0).
+ * Limits: 1 <= n <= 256, 1 <= m <= 64, 2 <= N <= 4096, t_max > 0. */
+typedef struct {
+  int n, m, N;
+  double t_max;
+  int quad;               /* hopf_quad */
+  int uset;               /* hopf_uset */
+  const double *A, *B, *Qu, *W, *c;
+} hopf_system;
+
+/* Solver options (hopf_default_opts fills the defaults in brackets).
+ *   c_tau         primal step tau = c_tau / L, dual step sigma = 0.999/(tau L^2),
+ *                 L >= ||K|| (Sec. III: tau sigma ||K||^2 < 1; Sec. VI: theta = 1)   [1.0]
+ *   gap_tol       stop when (P - D) / max(1, |D|) <= gap_tol                         [1e-6]
+ *   t_rel_tol     bisection stops when hi - lo <= max(t_rel_tol*hi,
+ *   t_abs_frac                                    t_abs_frac*t_max)                 [0.5e-4, 1e-6]
+ *   max_iter      iterations per solve before HOPF_PT_NOCONV                         [200000]
+ *   check_every   iterations between FP64 certificates                               [25]
+ *   warm          HOPF_WARM_COLD: every probe starts at lam = 0, y = 0;
+ *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate [COLD]
+ *   prec          hopf_prec of the iterations                                        [FP32] */
+typedef struct {
+  double c_tau, gap_tol, t_rel_tol, t_abs_frac;
+  int max_iter, check_every, warm, prec;
+} hopf_opts;
+
+hopf_status hopf_default_opts(hopf_opts *out);
+
+/* Create a context on HIP device `device` (owns a stream and all device
+ * memory it allocates).  *out is NULL on failure. */
+hopf_status hopf_create(int device, hopf_ctx **out);
+void hopf_destroy(hopf_ctx *ctx);                      /* NULL is a no-op */
+const char *hopf_strerror(hopf_status s);
+const char *hopf_last_error(const hopf_ctx *ctx);      /* ctx-owned, valid until the next call */
+
+/* Copy the systems and build their FP64 node tables e^{k h A} B Qu
+ * (scaling-and-squaring matrix exponential, the setup step of Sec. III-A /
+ * Sec. VI) and operator-norm prefix bounds; replaces earlier systems. */
+hopf_status hopf_set_systems(hopf_ctx *ctx, int nsys, const hopf_system *sys);
+hopf_status hopf_set_opts(hopf_ctx *ctx, const hopf_opts *opts);
+
+/* Value phi(x_i, t_i) (eq. (18)), certified: phi_lo <= phi <= phi_hi with
+ * (phi_hi - phi_lo)/max(1,|phi_hi|) <= gap_tol unless pt_status says otherwise.
+ *   sys_id  npts ints or NULL (all system 0)
+ *   x       npts*n (n of each point's system; points of one call must share n)
+ *   t       npts horizons in [0, t_max]
+ *   lam     npts*n terminal costates lam* = e^{-T A^T} p* or NULL
+ *   iters   npts or NULL; pt_status npts (required). */
+hopf_status hopf_value(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
+                       const double *t, double *phi_lo, double *phi_hi, double *lam,
+                       int *iters, int *pt_status);
+
+/* Minimum time to reach the target (Sec. IV) by certified bisection on
+ * [0, t_max]:  T (npts; +inf if unreachable at t_max, 0 if inside),
+ * gap (npts, normalised gap of the final solve at T), lam (npts*n or NULL),
+ * probes, iters (npts or NULL), pt_status (npts). */
+hopf_status hopf_min_time(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
+                          double *T, double *gap, double *lam, int *probes, int *iters,
+                          int *pt_status);
+
+/* Device-pointer twin of hopf_min_time: every array is device memory;
+ * sys_id may be NULL; lam, probes, iters may be NULL. */
+hopf_status hopf_min_time_dev(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
+                              double *T, double *gap, double *lam, int *probes, int *iters,
+                              int *pt_status, void *stream);
+
+/* Optimal control and trajectory at horizon T from x0 (Sec. IV eq. (27),
+ * Sec. V eq. (33)).  Solves phi(x0,T) to gap_tol first.  Outputs, with
+ * n_nodes <= N+1 written to *n_nodes, rows sorted by increasing physical
+ * time s in [0, T]:
+ *   s       n_nodes   physical times of the nodes
+ *   u       n_nodes*m control at each node (Qu y_k / w_k; 0 where w_k = 0)
+ *   xs      n_nodes*n state after each node's contribution (last row = x(T))
+ *   p_star  n         costate p* = e^{T A^T} lam*  (the paper's minimiser, eq. (24))
+ * Arrays must hold N+1 rows. */
+hopf_status hopf_trajectory(hopf_ctx *ctx, int sys_id, const double *x0, double T,
+                            int *n_nodes, double *s, double *u, double *xs, double *p_star,
+                            double *phi_lo, double *phi_hi);
+
+/* Seconds spent on the device by the last solve call (HIP events around the
+ * whole call on the context's stream) and by the fused iteration kernel
+ * alone, with its launch count; for throughput and roofline reporting. */
+hopf_status hopf_last_timing(const hopf_ctx *ctx, double *total_s, double *iter_kernel_s,
+                             long *iter_launches, double *iter_point_rows);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOPFPD_H */

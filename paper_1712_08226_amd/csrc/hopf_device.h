@@ -1,0 +1,592 @@
+// Device-side declarations shared by the solver and the kernel instance
+// files: per-point state, per-system view, MFMA wrappers and the two
+// templated hot kernels (fused PDHG iterations, FP64 certificate).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hopf_internal.h"
+
+namespace hopf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVES = 4;
+constexpr int PTS_WAVE = 16;
+constexpr int PTS_WG = WAVES * PTS_WAVE;
+constexpr int THREADS = WAVES * 64;
+constexpr int LDS_BYTES = 76 * 1024;
+
+enum { MODE_VALUE = 0, MODE_MINTIME = 1 };
+enum { PH_PROBE = 0, PH_FINAL = 1, PH_DONE = 2 };
+
+__device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename Tv> struct V4;
+template <> struct V4<float> { typedef floatx4 t; };
+template <> struct V4<double> { typedef doublex4 t; };
+
+// ------------------------------------------------------------------ per-point state
+
+struct SysView {
+  int n, m, N, n_pad, nkb, quad, uset;
+  double t_max, h, delta;
+  const float *K32;
+  const double *K64, *lpref, *epow, *A, *BQ, *Wd, *c;
+};
+
+struct PtState {
+  long npts;
+  int ystride;               // floats of y per point (nkb * m * 16)
+  int mpad;                  // floats of the partial-node dual per point
+  double *x0;                // [npts][n_pad]
+  int *status, *phase, *flags, *probes, *iters_tot, *iters_probe, *rows, *M, *partial, *last_reach;
+  double *T, *lo, *hi, *r, *tau, *sig, *P, *D;
+  double *xf;                // [npts][n_pad]
+  float *xfc32;              // [npts][n_pad]  x_f - c
+  double *R64;               // [npts][m][n_pad]
+  float *R32;                // [npts][m][n_pad]
+  float *lam, *lamb;         // [npts][n_pad]
+  float *y;                  // [npts][ystride]
+  float *yR;                 // [npts][mpad]
+  int *perm;                 // [npts]
+  int *counters;             // [0] active, [1] need-setup
+  double *rowsum;            // accumulated point-rows for flop accounting
+};
+
+struct Opts {
+  double c_tau, gap_tol, t_rel_tol, t_abs_frac;
+  int max_iter, check_every, warm;
+};
+
+enum { FL_SETUP = 1 };
+
+// quadrature weight of table node k for a point with (M, r)
+__device__ __forceinline__ double node_weight(int k, int M, double r, double h, int quad) {
+  if (quad == HOPF_Q_TRAP) {
+    if (k < M) return k == 0 ? 0.5 * h : h;
+    if (k == M) return (M > 0 ? 0.5 * h : 0.0) + 0.5 * r;
+    return 0.0;
+  }
+  if (k < M) return h;
+  if (k == M) return r;
+  return 0.0;
+}
+
+// ------------------------------------------------------------------ fused PDHG iterations
+
+// Each lane owns point column cl = lane % 16 of its wave and the register
+// layout of the 16x16x4 MFMA accumulator: rows 4*(lane/16) + {0..3}.
+template <typename Tv, int NT, int MM>
+__global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int iters) {
+  typedef typename V4<Tv>::t vec4;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Tv *lds = reinterpret_cast<Tv *>(lds_raw);
+  const int wg = blockIdx.x;
+  const int nact = st.counters[0];
+  if (wg * PTS_WG >= nact) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  constexpr int m = MM;          // components (the tables are zero-padded to MM)
+  constexpr int np = 16 * NT;    // padded state dimension
+  const int slot = wg * PTS_WG + wave * PTS_WAVE + cl;
+  const bool live = slot < nact;
+  const long p = live ? st.perm[slot] : -1;
+  const long pd = live ? p : st.npts;     // dead lanes read and write the spare row npts
+  const int rows_max = st.rows[st.perm[wg * PTS_WG]];
+  const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
+  // any partial node in this workgroup?
+  __shared__ int any_part;
+  if (threadIdx.x == 0) any_part = 0;
+  __syncthreads();
+  if (live && st.partial[p]) atomicOr(&any_part, 1);
+  __syncthreads();
+  const bool wg_part = any_part != 0;
+
+  const Tv* Kg = nullptr;
+  if constexpr (sizeof(Tv) == 4) Kg = reinterpret_cast<const Tv *>(S.K32);
+  else Kg = reinterpret_cast<const Tv *>(S.K64);
+  constexpr int kstride = np + (sizeof(Tv) == 4 ? 4 : 2);   // padded LDS row (bank spread)
+
+  // per-point scalars
+  Tv tau = 0, sig = 0, hw = (Tv)S.h, rr = 0;
+  int M = -1, rowsp = 0, part = 0;
+  if (live) {
+    tau = (Tv)st.tau[p];
+    sig = (Tv)st.sig[p];
+    rr = (Tv)st.r[p];
+    M = st.M[p];
+    rowsp = st.rows[p];
+    part = st.partial[p];
+  }
+  // sigma*lam_bar in accumulator layout (operand B of the dual GEMM); lam
+  // itself stays in memory (L2) and is read and written once per iteration
+  Tv bop[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bop[t][q] = sig * (Tv)st.lamb[pd * np + 16 * t + 4 * g + q];
+  float *lamp = st.lam + pd * np;
+  float *yp = st.y + (size_t)pd * st.ystride;
+
+  for (int it = 0; it < iters; ++it) {
+    vec4 G[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) G[t] = vec4{0, 0, 0, 0};
+
+    // ---- private node at tau = T (trapezoid rule, T off the grid)
+    if (wg_part) {
+      // scratch per wave: lam_bar [16][np], gr [16][np], yr [16][MM]
+      Tv *lb_s = lds + (size_t)wave * (2 * 16 * np + 16 * MM);
+      Tv *gr_s = lb_s + 16 * np;
+      Tv *yr_s = gr_s + 16 * np;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + 4 * g + q] = (sig > 0 ? bop[t][q] / sig : (Tv)0);
+      __syncthreads();
+      const int pp = lane >> 2, qq = lane & 3;          // point pp of this wave, lane quarter qq
+      const int pslot = wg * PTS_WG + wave * PTS_WAVE + pp;
+      const bool plive = pslot < nact;
+      const long P2 = plive ? st.perm[pslot] : -1;
+      const bool ppart = plive && st.partial[P2];
+      Tv vj[(MM + 3) / 4];
+      Tv ssq = 0;
+      const Tv sig2 = ppart ? (Tv)st.sig[P2] : (Tv)0;
+      const Tv wR = ppart ? (Tv)(0.5 * st.r[P2]) : (Tv)0;
+#pragma unroll
+      for (int a = 0; a < (MM + 3) / 4; ++a) {
+        const int j = qq + 4 * a;
+        Tv v = 0;
+        if (ppart && j < m) {
+          const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
+          const Tv *row = Rr + ((size_t)P2 * m + j) * np;
+          Tv acc = 0;
+          for (int i = 0; i < np; ++i) acc += row[i] * lb_s[pp * np + i];
+          v = (Tv)st.yR[(size_t)P2 * st.mpad + j] + sig2 * acc;
+        }
+        vj[a] = v;
+        ssq += v * v;
+      }
+      if (S.uset == HOPF_U_L2) {
+        ssq += __shfl_xor(ssq, 1);
+        ssq += __shfl_xor(ssq, 2);
+        const Tv nv = sqrt(ssq);
+        const Tv sc = (nv > wR) ? (nv > 0 ? wR / nv : (Tv)0) : (Tv)1;
+#pragma unroll
+        for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] *= sc;
+      } else {
+#pragma unroll
+        for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] = fmin(fmax(vj[a], -wR), wR);
+      }
+#pragma unroll
+      for (int a = 0; a < (MM + 3) / 4; ++a) {
+        const int j = qq + 4 * a;
+        if (j < MM) yr_s[pp * MM + j] = vj[a];
+        if (ppart && j < m) st.yR[(size_t)P2 * st.mpad + j] = (float)vj[a];
+      }
+      __syncthreads();
+      // gr[pp][i] = sum_j R[j][i] yR[j]
+      for (int i = qq; i < np; i += 4) {
+        Tv acc = 0;
+        if (ppart) {
+          const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
+          for (int j = 0; j < m; ++j) acc += Rr[((size_t)P2 * m + j) * np + i] * yr_s[pp * MM + j];
+        }
+        gr_s[pp * np + i] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + 4 * g + q];
+      __syncthreads();
+    }
+
+    // ---- sweep over the node table
+    for (int kb = 0; kb < nkb; ++kb) {
+      // stage K block kb (all m components) into LDS, padded rows
+      {
+        const Tv *src = Kg + (size_t)kb * m * NODE_BLOCK * np;
+        const int nvec = m * NODE_BLOCK * np / 4;
+        for (int e = threadIdx.x; e < nvec; e += THREADS) {
+          const int rowi = e / (np / 4), c4 = e % (np / 4);
+          const vec4 v = *reinterpret_cast<const vec4 *>(src + (size_t)rowi * np + 4 * c4);
+          Tv *d = lds + (size_t)rowi * kstride + 4 * c4;
+          d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
+        }
+      }
+      __syncthreads();
+      // Y tiles
+      vec4 V[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
+        V[j] = vec4{(Tv)f.x, (Tv)f.y, (Tv)f.z, (Tv)f.w};
+      }
+      // dual GEMM: V_j += K_j (sigma lam_bar); consecutive MFMAs feed different V_j
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < MM; ++j)
+            V[j] = mfma(lds[(size_t)(j * NODE_BLOCK + cl) * kstride + 16 * t + 4 * g + q], bop[t][q], V[j]);
+        __builtin_amdgcn_sched_barrier(0);   // keep operand loads near their MFMAs
+      }
+      // projection onto w_k C per (node, point)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb * NODE_BLOCK + 4 * g + q;
+        const Tv w = (k < rowsp) ? (Tv)node_weight(k, M, (double)rr, (double)hw, S.quad) : (Tv)0;
+        if (S.uset == HOPF_U_L2) {
+          Tv s = 0;
+#pragma unroll
+          for (int j = 0; j < MM; ++j) s += V[j][q] * V[j][q];
+          const Tv nv = sqrt(s);
+          const Tv sc = (nv > w) ? (nv > 0 ? w / nv : (Tv)0) : (Tv)1;
+#pragma unroll
+          for (int j = 0; j < MM; ++j) V[j][q] *= sc;
+        } else {
+#pragma unroll
+          for (int j = 0; j < MM; ++j) V[j][q] = fmin(fmax(V[j][q], -w), w);
+        }
+      }
+      // store Y
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        float4 f;
+        f.x = (float)V[j][0]; f.y = (float)V[j][1]; f.z = (float)V[j][2]; f.w = (float)V[j][3];
+        *reinterpret_cast<float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g)) = f;
+      }
+      // primal GEMM: G += K_j^T Y_j; consecutive MFMAs feed different G tiles
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            G[t] = mfma(lds[(size_t)(j * NODE_BLOCK + 4 * g + q) * kstride + 16 * t + cl], V[j][q], G[t]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();
+    }
+
+    // ---- primal prox and extrapolation
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * t + 4 * g + q;
+        const Tv xfc = (Tv)st.xfc32[pd * np + i];
+        const Tv wd = (Tv)S.Wd[i];
+        const Tv l0 = (Tv)lamp[i];
+        const Tv ln = (l0 - tau * (G[t][q] - xfc)) / ((Tv)1 + tau * wd);
+        lamp[i] = (float)ln;
+        bop[t][q] = sig * ((Tv)2 * ln - l0);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + 4 * g + q] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
+  if (live) {
+    if (g == 0) {
+      st.iters_probe[p] += iters;
+      st.iters_tot[p] += iters;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP64 certificate + decisions
+
+// Per point: P(lam) from K lam, D(y^) from K^T y^ with y^ the FP64
+// projection of the stored y onto w_k C (snapped to the boundary when within
+// 1e-5 of it; any point of w_k C gives a valid bound).  Then the sign /
+// gap decision and the bisection update (paper Sec. IV).
+template <int NT>
+__global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts o, int mode) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double *lds = reinterpret_cast<double *>(lds_raw);
+  const int wg = blockIdx.x;
+  const int nact = st.counters[0];
+  if (wg * PTS_WG >= nact) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int m = S.m;
+  constexpr int np = 16 * NT;
+  const int slot = wg * PTS_WG + wave * PTS_WAVE + cl;
+  const bool live = slot < nact;
+  const long p = live ? st.perm[slot] : -1;
+  const long pd = live ? p : st.npts;     // dead lanes read the spare row npts
+  const int rows_max = st.rows[st.perm[wg * PTS_WG]];
+  const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
+  constexpr int kstride = np + 2;
+  const int chunk = max(1, min(m, (int)(LDS_BYTES / (NODE_BLOCK * kstride * 8))));
+
+  double rr = 0.0;
+  int M = -1, rowsp = 0;
+  if (live) { rr = st.r[p]; M = st.M[p]; rowsp = st.rows[p]; }
+  const double hw = S.h;
+
+  float lam[NT][4];   // the iterates are FP32, so float holds them exactly
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lam[t][q] = st.lam[pd * np + 16 * t + 4 * g + q];
+  doublex4 G[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) G[t] = doublex4{0, 0, 0, 0};
+  double wsig = 0.0;    // sum_k w_k sigma_C(K_k lam) over this lane's rows
+  const float *yp = st.y + (size_t)pd * st.ystride;
+
+  for (int kb = 0; kb < nkb; ++kb) {
+    // weights and y^ scale per (row q)
+    double w[4], ysc[4], snorm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb * NODE_BLOCK + 4 * g + q;
+      w[q] = (k < rowsp) ? node_weight(k, M, rr, hw, S.quad) : 0.0;
+      snorm[q] = 0.0;
+      ysc[q] = 0.0;
+    }
+    if (S.uset == HOPF_U_L2) {
+      double s[4] = {0, 0, 0, 0};
+      for (int j = 0; j < m; ++j) {
+        const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
+        s[0] += (double)f.x * f.x; s[1] += (double)f.y * f.y; s[2] += (double)f.z * f.z; s[3] += (double)f.w * f.w;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double nv = sqrt(s[q]);
+        if (w[q] <= 0.0 || nv == 0.0) ysc[q] = 0.0;
+        else if (nv >= (1.0 - 1e-5) * w[q]) ysc[q] = w[q] / nv;     // on the boundary
+        else ysc[q] = 1.0;
+      }
+    }
+    for (int j0 = 0; j0 < m; j0 += chunk) {
+      const int jc = min(chunk, m - j0);
+      __syncthreads();
+      {
+        const double *src = S.K64 + ((size_t)kb * m + j0) * NODE_BLOCK * np;
+        const int nel = jc * NODE_BLOCK * np;
+        for (int e = threadIdx.x; e < nel; e += THREADS) {
+          const int rowi = e / np, c = e % np;
+          lds[(size_t)rowi * kstride + c] = src[e];
+        }
+      }
+      __syncthreads();
+      for (int jj = 0; jj < jc; ++jj) {
+        const int j = j0 + jj;
+        // U = K_j lam  (16 nodes x 16 points)
+        doublex4 U{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const double *a = lds + (size_t)(jj * NODE_BLOCK + cl) * kstride + 16 * t + 4 * g;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) U = mfma(a[q], (double)lam[t][q], U);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) snorm[q] += (S.uset == HOPF_U_L2) ? U[q] * U[q] : fabs(U[q]);
+        // y^_j
+        double yh[4];
+        {
+          const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
+          const double yv[4] = {(double)f.x, (double)f.y, (double)f.z, (double)f.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (S.uset == HOPF_U_L2) yh[q] = yv[q] * ysc[q];
+            else {
+              double v = fmin(fmax(yv[q], -w[q]), w[q]);
+              if (w[q] > 0.0 && fabs(v) >= (1.0 - 1e-5) * w[q]) v = copysign(w[q], v);
+              yh[q] = v;
+            }
+          }
+        }
+        // G += K_j^T y^_j
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double *a = lds + (size_t)(jj * NODE_BLOCK + 4 * g + q) * kstride + cl;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) G[t] = mfma(a[16 * t], yh[q], G[t]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wsig += w[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
+  }
+  __syncthreads();
+
+  // per-lane partial sums over this lane's state rows i = 16 t + 4 g + q
+  double sP = 0.0;   // 1/2 W lam^2 - (x_f - c) lam
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * t + 4 * g + q;
+      double xf = 0.0, cc = 0.0, wd = 1.0;
+      if (live && i < S.n) { xf = st.xf[p * np + i]; cc = S.c[i]; wd = S.Wd[i]; }
+      const double l = lam[t][q];
+      sP += 0.5 * wd * l * l - (xf - cc) * l;
+      G[t][q] = (live && i < S.n) ? xf - G[t][q] : 0.0;   // G now holds x_T
+    }
+
+  // private node (trapezoid, off-grid T): sigma_C(R lam) and R^T y^_R
+  __shared__ int any_part;
+  if (threadIdx.x == 0) any_part = 0;
+  __syncthreads();
+  if (live && st.partial[p]) atomicOr(&any_part, 1);
+  __syncthreads();
+  if (any_part) {
+    // per-wave scratch: lam [16][np] (float: the iterates are FP32), R^T y^ [16][np], y^ [16][mp]
+    const int mp = st.mpad;
+    unsigned char *base = lds_raw + (size_t)wave * (16 * np * 4 + 16 * np * 8 + 16 * mp * 8);
+    float *lam_s = reinterpret_cast<float *>(base);
+    double *xr_s = reinterpret_cast<double *>(base + 16 * np * 4);
+    double *yr_s = xr_s + 16 * np;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lam_s[cl * np + 16 * t + 4 * g + q] = lam[t][q];
+    __syncthreads();
+    const int pp = lane >> 2, qq = lane & 3;
+    const int pslot = wg * PTS_WG + wave * PTS_WAVE + pp;
+    const bool plive = pslot < nact;
+    const long P2 = plive ? st.perm[pslot] : -1;
+    const bool ppart = plive && st.partial[P2];
+    const double wR = ppart ? 0.5 * st.r[P2] : 0.0;
+    double ssU = 0.0, ssY = 0.0;
+    for (int j = qq; j < mp; j += 4) {
+      double u = 0.0, yv = 0.0;
+      if (ppart && j < m) {
+        const double *row = st.R64 + ((size_t)P2 * m + j) * np;
+        for (int i = 0; i < np; ++i) u += row[i] * (double)lam_s[pp * np + i];
+        yv = st.yR[(size_t)P2 * mp + j];
+      }
+      ssU += (S.uset == HOPF_U_L2) ? u * u : fabs(u);
+      ssY += yv * yv;
+      yr_s[pp * mp + j] = yv;
+    }
+    ssU += __shfl_xor(ssU, 1); ssU += __shfl_xor(ssU, 2);
+    ssY += __shfl_xor(ssY, 1); ssY += __shfl_xor(ssY, 2);
+    double scY = 1.0;
+    if (S.uset == HOPF_U_L2) {
+      const double nv = sqrt(ssY);
+      if (wR <= 0.0 || nv == 0.0) scY = 0.0;
+      else if (nv >= (1.0 - 1e-5) * wR) scY = wR / nv;
+    }
+    for (int j = qq; j < mp; j += 4) {
+      double v = yr_s[pp * mp + j];
+      if (S.uset == HOPF_U_L2) v *= scY;
+      else {
+        v = fmin(fmax(v, -wR), wR);
+        if (wR > 0.0 && fabs(v) >= (1.0 - 1e-5) * wR) v = copysign(wR, v);
+      }
+      yr_s[pp * mp + j] = v;
+    }
+    __syncthreads();
+    for (int i = qq; i < np; i += 4) {
+      double acc = 0.0;
+      if (ppart)
+        for (int j = 0; j < m; ++j) acc += st.R64[((size_t)P2 * m + j) * np + i] * yr_s[pp * mp + j];
+      xr_s[pp * np + i] = acc;
+    }
+    __syncthreads();
+    // the private node's term w_R sigma_C(R lam), moved to the lane holding column pp with g = 0
+    const double part_sig = wR * ((S.uset == HOPF_U_L2) ? sqrt(ssU) : ssU);
+    const double ps = __shfl(part_sig, 4 * cl);
+    if (g == 0) wsig += ps;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) G[t][q] -= (live && (16 * t + 4 * g + q) < S.n) ? xr_s[cl * np + 16 * t + 4 * g + q] : 0.0;
+  }
+
+  // J(x_T) partial sums
+  double sJ = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * t + 4 * g + q;
+      if (live && i < S.n) {
+        const double d = G[t][q] - S.c[i];
+        sJ += d * d / S.Wd[i];
+      }
+    }
+  // reduce over the four lane groups holding the same point
+  sP += __shfl_xor(sP, 16); sP += __shfl_xor(sP, 32);
+  sJ += __shfl_xor(sJ, 16); sJ += __shfl_xor(sJ, 32);
+  wsig += __shfl_xor(wsig, 16); wsig += __shfl_xor(wsig, 32);
+  if (!live || g != 0) return;
+
+  const double Pv = sP + 0.5 + wsig;
+  const double Dv = -0.5 * (sJ - 1.0);
+  st.P[p] = Pv;
+  st.D[p] = Dv;
+  const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
+  const int ph = st.phase[p];
+  const double T = st.T[p];
+  if (!isfinite(Pv) || !isfinite(Dv)) {
+    st.status[p] = HOPF_PT_NONFINITE;
+    st.phase[p] = PH_DONE;
+    return;
+  }
+  if (ph == PH_FINAL) {
+    if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; return; }
+    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    return;
+  }
+  // probe: certified sign of phi_N(x, T)
+  int outcome = -1;   // 1 reach, 0 unreach
+  if (-Dv <= 0.0) outcome = 1;
+  else if (-Pv > 0.0) outcome = 0;
+  else if (gap <= o.gap_tol) outcome = 1;
+  if (outcome < 0) {
+    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    return;
+  }
+  const bool first = st.probes[p] == 1;
+  if (outcome == 0 && first) {       // unreachable at t_max
+    st.status[p] = HOPF_PT_UNREACH;
+    st.phase[p] = PH_DONE;
+    st.T[p] = INFINITY;
+    st.hi[p] = INFINITY;
+    return;
+  }
+  double lo = st.lo[p], hi = st.hi[p];
+  if (outcome == 1) hi = T; else lo = T;
+  st.lo[p] = lo;
+  st.hi[p] = hi;
+  st.last_reach[p] = outcome;
+  if (hi - lo <= fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max)) {
+    st.phase[p] = PH_FINAL;
+    if (outcome == 1) {
+      if (gap <= o.gap_tol) st.phase[p] = PH_DONE;   // already certified at T = hi
+    } else {
+      st.T[p] = hi;
+      st.flags[p] = FL_SETUP;
+    }
+    return;
+  }
+  st.T[p] = 0.5 * (lo + hi);
+  st.flags[p] = FL_SETUP;
+}
+
+
+typedef void (*pdhg_fn)(SysView, PtState, int);
+typedef void (*cert_fn)(SysView, PtState, Opts, int);
+
+// kernel instances, one lookup per NT (hopf_inst_nt*.hip); nullptr if absent
+pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM_out);
+cert_fn cert_lookup(int NT);
+
+}  // namespace hopf

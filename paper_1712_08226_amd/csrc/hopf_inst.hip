@@ -1,0 +1,52 @@
+// Kernel instances for one value of NT = n_pad / 16, selected at build time
+// with -DHOPF_NT=<k>; the build compiles this file once per NT.
+#include "hopf_device.h"
+
+#ifndef HOPF_NT
+#error "HOPF_NT must be defined"
+#endif
+
+#define HOPF_CAT2(a, b) a##b
+#define HOPF_CAT(a, b) HOPF_CAT2(a, b)
+
+namespace hopf {
+
+// number of control components held in registers (the system's m is rounded up)
+static const int kMM[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+
+pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
+  int MM = 0;
+  for (int v : kMM)
+    if (v >= m) { MM = v; break; }
+  if (MM_out) *MM_out = MM;
+  if (prec == HOPF_FP64) {
+#if HOPF_NT <= 2
+    switch (MM) {
+      case 1: return k_pdhg<double, HOPF_NT, 1>;
+      case 2: return k_pdhg<double, HOPF_NT, 2>;
+      case 3: return k_pdhg<double, HOPF_NT, 3>;
+      case 4: return k_pdhg<double, HOPF_NT, 4>;
+      default: return nullptr;
+    }
+#else
+    return nullptr;
+#endif
+  }
+  switch (MM) {
+    case 1: return k_pdhg<float, HOPF_NT, 1>;
+    case 2: return k_pdhg<float, HOPF_NT, 2>;
+    case 3: return k_pdhg<float, HOPF_NT, 3>;
+    case 4: return k_pdhg<float, HOPF_NT, 4>;
+    case 5: return k_pdhg<float, HOPF_NT, 5>;
+    case 6: return k_pdhg<float, HOPF_NT, 6>;
+    case 8: return k_pdhg<float, HOPF_NT, 8>;
+    case 10: return k_pdhg<float, HOPF_NT, 10>;
+    case 12: return k_pdhg<float, HOPF_NT, 12>;
+    case 16: return k_pdhg<float, HOPF_NT, 16>;
+    default: return nullptr;
+  }
+}
+
+cert_fn HOPF_CAT(cert_lookup_nt, HOPF_NT)() { return k_certify<HOPF_NT>; }
+
+}  // namespace hopf

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host setup code and the HIP solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hopfpd.h"
+
+namespace hopf {
+
+constexpr int NODE_BLOCK = 16;     // table nodes per MFMA row tile
+constexpr int POW_LEVELS = 21;     // binary powers e^{2^b delta A}, delta = t_max / 2^20
+constexpr int POW_BITS = 20;
+
+// Host copy of one system plus its device tables.
+struct SysTables {
+  hopf_system desc{};
+  std::vector<double> A, B, Qu, W, c;   // host copies (row-major)
+  int n = 0, m = 0, N = 0, n_pad = 0, nkb = 0;
+  int m_user = 0;                      // the caller's m; m >= m_user is the padded kernel size
+  double h = 0.0, delta = 0.0;
+  // host tables
+  std::vector<double> phi;     // [N][m][n] node blocks Phi_k = -Qu^T B^T e^{k h A^T}
+  std::vector<double> lpref;   // [N+1] upper bound of ||Phi_{0..j-1}||_2^2
+  std::vector<double> epow;    // [POW_LEVELS][n][n] e^{2^b delta A}
+  // device tables
+  float *K32 = nullptr;        // [nkb][m][16][n_pad]
+  double *K64 = nullptr;       // [nkb][m][16][n_pad]
+  double *lpref_d = nullptr;   // [N+1]
+  double *epow_d = nullptr;    // [POW_LEVELS][n][n]
+  double *A_d = nullptr;       // [n][n]
+  double *BQ_d = nullptr;      // [n][m]   -B Qu
+  double *Wd_d = nullptr;      // [n_pad]  diag W (1 in the padding)
+  double *c_d = nullptr;       // [n_pad]
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hopf_opts opts{};
+  std::vector<SysTables> sys;
+  std::string err;
+  // timing of the last solve
+  double t_total = 0.0, t_iter = 0.0, point_rows = 0.0;
+  long iter_launches = 0;
+  // scratch, grown on demand
+  struct Buf { void *p = nullptr; size_t bytes = 0; };
+  std::vector<Buf> bufs;
+};
+
+// host setup (hopf_setup.cpp)
+hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t);
+void free_tables(SysTables &t);
+
+// device solver (hopf_solver.hip)
+hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
+                      const double *t_in, double *T_out, double *gap_out, double *philo_out,
+                      double *phihi_out, double *lam_out, int *probes_out, int *iters_out,
+                      int *status_out, double *y_out, hipStream_t user_stream);
+hopf_status trajectory_dev(Ctx *ctx, int sys_id, const double *x0_h, double T, int *n_nodes,
+                           double *s, double *u, double *xs, double *p_star, double *philo,
+                           double *phihi);
+
+hopf_status set_err(Ctx *ctx, hopf_status st, const std::string &msg);
+
+}  // namespace hopf

@@ -1,0 +1,447 @@
+// Host side of the library: argument validation, the FP64 node tables built
+// once per system, and the C-ABI entry points that marshal host arrays.
+//
+// Tables (paper Sec. III-A, eqs. (16)-(20), in the terminal costate
+// lam = e^{-T A^T} p): K_k = -Qu^T B^T e^{tau_k A^T} at the time-to-go nodes
+// tau_k = k h.  The matrix exponential is the scaling-and-squaring method
+// with a diagonal [13/13] Pade approximant (Higham, SIAM J. Matrix Anal.
+// Appl. 26 (2005)); the paper evaluates the same exponential action with
+// Al-Mohy & Higham's algorithm (Sec. VI).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hopf_internal.h"
+
+namespace hopf {
+
+hopf_status set_err(Ctx *ctx, hopf_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+namespace {
+
+using Mat = std::vector<double>;  // row-major n x n
+
+void matmul(const double *A, const double *B, double *C, int n, int k, int m) {
+  // C (n x m) = A (n x k) * B (k x m)
+  std::fill(C, C + (size_t)n * m, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < k; ++l) {
+      const double a = A[(size_t)i * k + l];
+      if (a == 0.0) continue;
+      const double *b = B + (size_t)l * m;
+      double *c = C + (size_t)i * m;
+      for (int j = 0; j < m; ++j) c[j] += a * b[j];
+    }
+}
+
+double norm1(const Mat &A, int n) {
+  double best = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::fabs(A[(size_t)i * n + j]);
+    best = std::max(best, s);
+  }
+  return best;
+}
+
+// Solve P X = R in place (R becomes X), LU with partial pivoting.
+bool lu_solve(Mat P, Mat &R, int n) {
+  std::vector<int> piv(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(P[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = std::fabs(P[(size_t)i * n + k]);
+      if (v > best) { best = v; p = i; }
+    }
+    if (best == 0.0 || !std::isfinite(best)) return false;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        std::swap(P[(size_t)k * n + j], P[(size_t)p * n + j]);
+        std::swap(R[(size_t)k * n + j], R[(size_t)p * n + j]);
+      }
+    }
+    const double inv = 1.0 / P[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      const double f = P[(size_t)i * n + k] * inv;
+      if (f == 0.0) continue;
+      for (int j = k; j < n; ++j) P[(size_t)i * n + j] -= f * P[(size_t)k * n + j];
+      for (int j = 0; j < n; ++j) R[(size_t)i * n + j] -= f * R[(size_t)k * n + j];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double inv = 1.0 / P[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      double s = R[(size_t)k * n + j];
+      for (int l = k + 1; l < n; ++l) s -= P[(size_t)k * n + l] * R[(size_t)l * n + j];
+      R[(size_t)k * n + j] = s * inv;
+    }
+  }
+  return true;
+}
+
+// Diagonal Pade [13/13] coefficients b_j = (26-j)! 13! / (26! j! (13-j)!).
+std::vector<double> pade13() {
+  std::vector<double> b(14);
+  for (int j = 0; j <= 13; ++j) {
+    double lg = std::lgamma(27.0 - j) + std::lgamma(14.0) - std::lgamma(27.0) - std::lgamma(j + 1.0) -
+                std::lgamma(14.0 - j);
+    b[j] = std::exp(lg);
+  }
+  return b;
+}
+
+// e^{X} for ||X||_1 <= 0.5 by the Pade approximant alone.
+bool pade_exp(const Mat &X, Mat &out, int n) {
+  static const std::vector<double> b = pade13();
+  const size_t nn = (size_t)n * n;
+  Mat X2(nn), X4(nn), X6(nn), t1(nn), t2(nn), U(nn), V(nn);
+  matmul(X.data(), X.data(), X2.data(), n, n, n);
+  matmul(X2.data(), X2.data(), X4.data(), n, n, n);
+  matmul(X4.data(), X2.data(), X6.data(), n, n, n);
+  for (size_t i = 0; i < nn; ++i) t1[i] = b[13] * X6[i] + b[11] * X4[i] + b[9] * X2[i];
+  matmul(X6.data(), t1.data(), t2.data(), n, n, n);
+  for (size_t i = 0; i < nn; ++i) t2[i] += b[7] * X6[i] + b[5] * X4[i] + b[3] * X2[i];
+  for (int i = 0; i < n; ++i) t2[(size_t)i * n + i] += b[1];
+  matmul(X.data(), t2.data(), U.data(), n, n, n);             // odd part
+  for (size_t i = 0; i < nn; ++i) t1[i] = b[12] * X6[i] + b[10] * X4[i] + b[8] * X2[i];
+  matmul(X6.data(), t1.data(), V.data(), n, n, n);
+  for (size_t i = 0; i < nn; ++i) V[i] += b[6] * X6[i] + b[4] * X4[i] + b[2] * X2[i];
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] += b[0];  // even part
+  Mat P(nn), R(nn);
+  for (size_t i = 0; i < nn; ++i) { P[i] = V[i] - U[i]; R[i] = V[i] + U[i]; }
+  if (!lu_solve(P, R, n)) return false;
+  out.swap(R);
+  return true;
+}
+
+bool expm(const Mat &A, double t, Mat &out, int n) {
+  Mat X(A);
+  for (auto &v : X) v *= t;
+  int s = 0;
+  double nrm = norm1(X, n);
+  while (nrm > 0.5) { nrm *= 0.5; ++s; }
+  const double sc = std::ldexp(1.0, -s);
+  for (auto &v : X) v *= sc;
+  if (!pade_exp(X, out, n)) return false;
+  Mat tmp(out.size());
+  for (int i = 0; i < s; ++i) {
+    matmul(out.data(), out.data(), tmp.data(), n, n, n);
+    out.swap(tmp);
+  }
+  return true;
+}
+
+bool all_finite(const double *p, size_t k) {
+  for (size_t i = 0; i < k; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+void free_tables(SysTables &t) {
+  hipFree(t.K32); hipFree(t.K64); hipFree(t.lpref_d); hipFree(t.epow_d);
+  hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d);
+  t.K32 = nullptr; t.K64 = nullptr; t.lpref_d = nullptr; t.epow_d = nullptr;
+  t.A_d = nullptr; t.BQ_d = nullptr; t.Wd_d = nullptr; t.c_d = nullptr;
+}
+
+hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
+  const int n = s.n, m = s.m, N = s.N;
+  if (n < 1 || n > 256 || m < 1 || m > 64 || N < 2 || N > 4096)
+    return set_err(ctx, HOPF_EINVAL, "system sizes out of range (1<=n<=256, 1<=m<=64, 2<=N<=4096)");
+  if (!(s.t_max > 0.0) || !std::isfinite(s.t_max)) return set_err(ctx, HOPF_EINVAL, "t_max must be finite and > 0");
+  if (s.quad != HOPF_Q_TRAP && s.quad != HOPF_Q_LEFT) return set_err(ctx, HOPF_EINVAL, "bad quadrature rule");
+  if (s.uset != HOPF_U_L2 && s.uset != HOPF_U_BOX) return set_err(ctx, HOPF_EINVAL, "bad control set");
+  if (!s.A || !s.B || !s.W) return set_err(ctx, HOPF_EINVAL, "A, B and W are required");
+  t.desc = s;
+  t.n = n; t.N = N;
+  t.m_user = m;
+  // the kernels hold the m components of a node in registers with m fixed at
+  // compile time; the tables are padded with zero components up to that size
+  // (zero rows of K leave every norm and clamp unchanged)
+  {
+    static const int kMM[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+    int mk = m;
+    for (int v : kMM)
+      if (v >= m) { mk = v; break; }
+    t.m = mk;
+  }
+  t.A.assign(s.A, s.A + (size_t)n * n);
+  t.B.assign(s.B, s.B + (size_t)n * m);
+  t.W.assign(s.W, s.W + (size_t)n * n);
+  t.Qu.assign((size_t)m * m, 0.0);
+  if (s.Qu) t.Qu.assign(s.Qu, s.Qu + (size_t)m * m);
+  else for (int i = 0; i < m; ++i) t.Qu[(size_t)i * m + i] = 1.0;
+  t.c.assign(n, 0.0);
+  if (s.c) t.c.assign(s.c, s.c + n);
+  if (!all_finite(t.A.data(), t.A.size()) || !all_finite(t.B.data(), t.B.size()) ||
+      !all_finite(t.W.data(), t.W.size()) || !all_finite(t.Qu.data(), t.Qu.size()) ||
+      !all_finite(t.c.data(), t.c.size()))
+    return set_err(ctx, HOPF_EINVAL, "non-finite system data");
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double v = t.W[(size_t)i * n + j];
+      if (i == j && !(v > 0.0)) return set_err(ctx, HOPF_EINVAL, "W is not positive definite");
+      if (i != j && v != 0.0)
+        return set_err(ctx, HOPF_EUNSUPPORTED, "this build needs a diagonal target matrix W");
+    }
+  t.desc.A = t.A.data(); t.desc.B = t.B.data(); t.desc.W = t.W.data();
+  t.desc.Qu = t.Qu.data(); t.desc.c = t.c.data();
+
+  t.n_pad = ((n + 15) / 16) * 16;
+  t.nkb = (N + NODE_BLOCK - 1) / NODE_BLOCK;
+  t.h = (s.quad == HOPF_Q_TRAP) ? s.t_max / (N - 1) : s.t_max / N;
+  t.delta = std::ldexp(s.t_max, -POW_BITS);
+
+  // BQ = B Qu (n x m_user), then zero-padded to n x t.m
+  const int mu = m;
+  std::vector<double> BQu((size_t)n * mu);
+  matmul(t.B.data(), t.Qu.data(), BQu.data(), n, mu, mu);
+  const int mk = t.m;
+  std::vector<double> BQ((size_t)n * mk, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < mu; ++j) BQ[(size_t)i * mk + j] = BQu[(size_t)i * mu + j];
+
+  // node blocks Phi_k = -(e^{k h A} B Qu)^T, by Phi_k = Phi_{k-1} e^{h A^T}
+  Mat Eh;
+  if (!expm(t.A, t.h, Eh, n)) return set_err(ctx, HOPF_EINVAL, "matrix exponential failed (singular Pade denominator)");
+  t.phi.assign((size_t)N * mk * n, 0.0);
+  for (int j = 0; j < mk; ++j)
+    for (int i = 0; i < n; ++i) t.phi[(size_t)j * n + i] = -BQ[(size_t)i * mk + j];
+  for (int k = 1; k < N; ++k) {
+    const double *prev = &t.phi[(size_t)(k - 1) * mk * n];
+    double *cur = &t.phi[(size_t)k * mk * n];
+    for (int j = 0; j < mk; ++j)
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int l = 0; l < n; ++l) acc += prev[(size_t)j * n + l] * Eh[(size_t)i * n + l];
+        cur[(size_t)j * n + i] = acc;
+      }
+  }
+  if (!all_finite(t.phi.data(), t.phi.size()))
+    return set_err(ctx, HOPF_EINVAL, "node table overflowed (e^{t A} too large on [0, t_max])");
+
+  // prefix bounds lpref[j] >= lambda_max(sum_{k<j} Phi_k^T Phi_k): power
+  // iteration warm-started from the previous prefix, with a 1e-4 margin; the
+  // Frobenius norm is used where the iteration does not settle.
+  t.lpref.assign(N + 1, 0.0);
+  {
+    Mat S((size_t)n * n, 0.0);
+    std::vector<double> v(n, 1.0 / std::sqrt((double)n)), w(n);
+    for (int j = 1; j <= N; ++j) {
+      const double *P = &t.phi[(size_t)(j - 1) * mk * n];
+      for (int a = 0; a < mk; ++a)
+        for (int i = 0; i < n; ++i) {
+          const double pi = P[(size_t)a * n + i];
+          if (pi == 0.0) continue;
+          for (int l = 0; l < n; ++l) S[(size_t)i * n + l] += pi * P[(size_t)a * n + l];
+        }
+      double theta = 0.0, prev = -1.0;
+      bool conv = false;
+      for (int it = 0; it < 3000; ++it) {
+        for (int i = 0; i < n; ++i) {
+          double acc = 0.0;
+          for (int l = 0; l < n; ++l) acc += S[(size_t)i * n + l] * v[l];
+          w[i] = acc;
+        }
+        theta = 0.0;
+        double nw = 0.0;
+        for (int i = 0; i < n; ++i) { theta += v[i] * w[i]; nw += w[i] * w[i]; }
+        nw = std::sqrt(nw);
+        if (nw == 0.0) { conv = true; theta = 0.0; break; }
+        for (int i = 0; i < n; ++i) v[i] = w[i] / nw;
+        if (it >= 8 && std::fabs(theta - prev) <= 1e-13 * theta) { conv = true; break; }
+        prev = theta;
+      }
+      if (conv) {
+        t.lpref[j] = theta * (1.0 + 1e-4);
+      } else {
+        double fro = 0.0;
+        for (double x : S) fro += x * x;
+        t.lpref[j] = std::sqrt(fro);
+      }
+    }
+  }
+
+  // binary powers e^{2^b delta A}: Pade while the argument is small, then squaring
+  t.epow.assign((size_t)POW_LEVELS * n * n, 0.0);
+  {
+    const double nA = norm1(t.A, n);
+    Mat E;
+    for (int b = 0; b < POW_LEVELS; ++b) {
+      const double tb = std::ldexp(t.delta, b);
+      if (b == 0 || tb * nA <= 0.5) {
+        Mat X(t.A);
+        for (auto &x : X) x *= tb;
+        if (tb * nA <= 0.5) {
+          if (!pade_exp(X, E, n)) return set_err(ctx, HOPF_EINVAL, "matrix exponential failed");
+        } else if (!expm(t.A, tb, E, n)) {
+          return set_err(ctx, HOPF_EINVAL, "matrix exponential failed");
+        }
+      } else {
+        Mat prev(t.epow.begin() + (size_t)(b - 1) * n * n, t.epow.begin() + (size_t)b * n * n);
+        E.assign((size_t)n * n, 0.0);
+        matmul(prev.data(), prev.data(), E.data(), n, n, n);
+      }
+      std::copy(E.begin(), E.end(), t.epow.begin() + (size_t)b * n * n);
+    }
+    if (!all_finite(t.epow.data(), t.epow.size()))
+      return set_err(ctx, HOPF_EINVAL, "e^{t A} overflows on [0, t_max]");
+  }
+
+  // device copies in the kernels' layout: K[kb][j][kk][i] = Phi_{16 kb + kk}[j][i]
+  const size_t kel = (size_t)t.nkb * mk * NODE_BLOCK * t.n_pad;
+  std::vector<float> K32(kel, 0.0f);
+  std::vector<double> K64(kel, 0.0);
+  for (int k = 0; k < N; ++k) {
+    const int kb = k / NODE_BLOCK, kk = k % NODE_BLOCK;
+    for (int j = 0; j < mk; ++j)
+      for (int i = 0; i < n; ++i) {
+        const size_t dst = (((size_t)kb * mk + j) * NODE_BLOCK + kk) * t.n_pad + i;
+        const double v = t.phi[((size_t)k * mk + j) * n + i];
+        K64[dst] = v;
+        K32[dst] = (float)v;
+      }
+  }
+  std::vector<double> Wd(t.n_pad, 1.0), cc(t.n_pad, 0.0);
+  for (int i = 0; i < n; ++i) { Wd[i] = t.W[(size_t)i * n + i]; cc[i] = t.c[i]; }
+  std::vector<double> mBQ(BQ);
+  for (auto &v : mBQ) v = -v;
+
+  free_tables(t);
+  auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = up((void **)&t.K32, K32.data(), kel * sizeof(float)) &&
+            up((void **)&t.K64, K64.data(), kel * sizeof(double)) &&
+            up((void **)&t.lpref_d, t.lpref.data(), t.lpref.size() * sizeof(double)) &&
+            up((void **)&t.epow_d, t.epow.data(), t.epow.size() * sizeof(double)) &&
+            up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&
+            up((void **)&t.BQ_d, mBQ.data(), mBQ.size() * sizeof(double)) &&
+            up((void **)&t.Wd_d, Wd.data(), Wd.size() * sizeof(double)) &&
+            up((void **)&t.c_d, cc.data(), cc.size() * sizeof(double));
+  if (!ok) {
+    free_tables(t);
+    return set_err(ctx, HOPF_ENOMEM, "device allocation/copy of the node tables failed");
+  }
+  return HOPF_OK;
+}
+
+}  // namespace hopf
+
+using hopf::Ctx;
+using hopf::set_err;
+
+extern "C" {
+
+hopf_status hopf_default_opts(hopf_opts *o) {
+  if (!o) return HOPF_EINVAL;
+  o->c_tau = 1.0;
+  o->gap_tol = 1e-6;
+  o->t_rel_tol = 0.5e-4;
+  o->t_abs_frac = 1e-6;
+  o->max_iter = 200000;
+  o->check_every = 25;
+  o->warm = HOPF_WARM_COLD;
+  o->prec = HOPF_FP32;
+  return HOPF_OK;
+}
+
+const char *hopf_strerror(hopf_status s) {
+  switch (s) {
+    case HOPF_OK: return "ok";
+    case HOPF_EINVAL: return "invalid argument";
+    case HOPF_ENOMEM: return "out of memory";
+    case HOPF_EDEVICE: return "HIP device error";
+    case HOPF_ESTATE: return "call out of order";
+    case HOPF_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+hopf_status hopf_create(int device, hopf_ctx **out) {
+  if (!out) return HOPF_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HOPF_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return HOPF_EDEVICE;
+  Ctx *c = new (std::nothrow) Ctx();
+  if (!c) return HOPF_ENOMEM;
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return HOPF_EDEVICE;
+  }
+  hopf_default_opts(&c->opts);
+  *out = reinterpret_cast<hopf_ctx *>(c);
+  return HOPF_OK;
+}
+
+void hopf_destroy(hopf_ctx *h) {
+  if (!h) return;
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (auto &t : c->sys) hopf::free_tables(t);
+  for (auto &b : c->bufs) hipFree(b.p);
+  hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *hopf_last_error(const hopf_ctx *h) {
+  if (!h) return "null context";
+  return reinterpret_cast<const Ctx *>(h)->err.c_str();
+}
+
+hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !o) return HOPF_EINVAL;
+  if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
+      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 1 || o->prec < 0 || o->prec > 1)
+    return set_err(c, HOPF_EINVAL, "invalid solver options");
+  c->opts = *o;
+  return HOPF_OK;
+}
+
+hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (nsys < 1 || !sys) return set_err(c, HOPF_EINVAL, "need at least one system");
+  if (hipSetDevice(c->device) != hipSuccess) return set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
+  hipStreamSynchronize(c->stream);
+  for (auto &t : c->sys) hopf::free_tables(t);
+  c->sys.clear();
+  std::vector<hopf::SysTables> tabs(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    hopf_status st = hopf::build_tables(c, sys[i], tabs[i]);
+    if (st != HOPF_OK) {
+      for (auto &t : tabs) hopf::free_tables(t);
+      c->err = "system " + std::to_string(i) + ": " + c->err;
+      return st;
+    }
+  }
+  c->sys.swap(tabs);
+  return HOPF_OK;
+}
+
+hopf_status hopf_last_timing(const hopf_ctx *h, double *total_s, double *iter_s, long *launches,
+                             double *point_rows) {
+  const Ctx *c = reinterpret_cast<const Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (total_s) *total_s = c->t_total;
+  if (iter_s) *iter_s = c->t_iter;
+  if (launches) *launches = c->iter_launches;
+  if (point_rows) *point_rows = c->point_rows;
+  return HOPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,654 @@
+// Device solver: batched primal-dual (Chambolle-Pock) solves of the
+// quadrature form of the generalized Hopf formula (paper Sec. III-A,
+// eqs. (15)-(23)), certified in FP64, inside a per-point bisection on the
+// horizon (Sec. IV), on gfx950.
+//
+// Notation (terminal-costate form, lam = e^{-T A^T} p):
+//   K_k   = -Qu^T B^T e^{tau_k A^T}         m x n node block, tau_k = k h
+//   x_f   = e^{T A} x0                       free terminal state
+//   P(lam) = 1/2 lam^T W lam - <x_f - c, lam> + 1/2 + sum_k w_k sigma_C(K_k lam)
+//   D(y)   = -J(x_f - sum_k K_k^T y_k),  y_k in w_k C
+// with C the unit l2 ball or box and sigma_C its support function.
+//
+// Work decomposition.  Points are the GEMM column dimension: a workgroup
+// holds 64 points (4 waves x 16), all points of one system.  Every point
+// uses a prefix of the shared node table (rows 0..rows-1) plus, for the
+// trapezoid rule at a horizon off the grid, one private node at tau = T
+// ("partial" node, kept per point).  Per iteration and 16-node block:
+//   V_j  = Y_j + K_j (sigma lam_bar)          MFMA 16x16x4, Y as accumulator
+//   Y_j  = proj_{w C}(V_j)                     in registers (all j of a node)
+//   G   += K_j^T Y_j                           MFMA, Y in registers as operand B
+// then lam+ = (lam - tau (G - (x_f - c))) / (1 + tau W),
+// lam_bar = 2 lam+ - lam (theta = 1).  y lives in HBM in the MFMA
+// accumulator order, so every load/store is a 16-byte per-lane access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hopf_device.h"
+
+namespace hopf {
+
+// ------------------------------------------------------------------ init
+
+__global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int n, int n_pad) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts * n_pad) return;
+  long p = i / n_pad;
+  int k = (int)(i % n_pad);
+  x0[i] = k < n ? x[p * n + k] : 0.0;
+}
+
+__global__ void k_init(SysView S, PtState st, int mode, const double *__restrict__ t_in) {
+  long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= st.npts) return;
+  const double *x = st.x0 + p * S.n_pad;
+  bool finite = true;
+  double Jx = 0.0;
+  for (int i = 0; i < S.n; ++i) {
+    const double v = x[i];
+    if (!isfinite(v)) finite = false;
+    const double d = v - S.c[i];
+    Jx += d * d / S.Wd[i];
+  }
+  Jx = 0.5 * (Jx - 1.0);
+  st.probes[p] = 0;
+  st.iters_tot[p] = 0;
+  st.iters_probe[p] = 0;
+  st.last_reach[p] = 0;
+  st.P[p] = 0.0;
+  st.D[p] = 0.0;
+  st.flags[p] = 0;
+  if (!finite) {
+    st.status[p] = HOPF_PT_NONFINITE;
+    st.phase[p] = PH_DONE;
+    st.T[p] = NAN;
+    return;
+  }
+  if (mode == MODE_MINTIME) {
+    if (Jx <= 0.0) {   // inside the target: T = 0, lam = W^{-1}(x - c), phi = J(x)
+      st.status[p] = HOPF_PT_INSIDE;
+      st.phase[p] = PH_DONE;
+      st.T[p] = 0.0;
+      st.hi[p] = 0.0;
+      double Pv = 0.5;
+      for (int i = 0; i < S.n_pad; ++i) {
+        const double l = i < S.n ? (x[i] - S.c[i]) / S.Wd[i] : 0.0;
+        st.lam[p * S.n_pad + i] = (float)l;
+        if (i < S.n) Pv += 0.5 * S.Wd[i] * l * l - (x[i] - S.c[i]) * l;
+      }
+      st.P[p] = Pv;
+      st.D[p] = -Jx;
+      return;
+    }
+    st.status[p] = HOPF_PT_OK;
+    st.phase[p] = PH_PROBE;
+    st.T[p] = S.t_max;
+    st.lo[p] = 0.0;
+    st.hi[p] = S.t_max;
+    st.flags[p] = FL_SETUP;
+  } else {
+    const double tv = t_in[p];
+    st.status[p] = HOPF_PT_OK;
+    st.phase[p] = PH_FINAL;
+    st.T[p] = tv;
+    st.lo[p] = tv;
+    st.hi[p] = tv;
+    st.flags[p] = FL_SETUP;
+  }
+}
+
+// ------------------------------------------------------------------ probe setup
+
+// One workgroup per point flagged for setup: nodes and weights for the new
+// horizon, x_f = e^{T A} x0 and (trapezoid, off-grid T) the private node
+// R = -Qu^T B^T e^{T A^T}, all in FP64 from the binary-power table
+// e^{2^b delta A} and a short Taylor series for the remainder, then step
+// sizes and the warm or cold start.
+constexpr int SETUP_COLS = 8;
+
+__global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o) {
+  const long p = blockIdx.x;
+  if (p >= st.npts) return;
+  if (!(st.flags[p] & FL_SETUP)) return;
+  __shared__ double sv[3][256 * SETUP_COLS];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int n = S.n, m = S.m, np = S.n_pad;
+  const double T = st.T[p];
+  // horizon split T = M h + r (snap to the grid within 1e-12 relative)
+  const double q = T / S.h;
+  const double qr = rint(q);
+  int M;
+  double r;
+  if (fabs(q - qr) <= 1e-12 * fmax(1.0, q)) { M = (int)qr; r = 0.0; }
+  else { M = (int)floor(q); r = T - M * S.h; }
+  int rows, part;
+  if (S.quad == HOPF_Q_TRAP) {
+    if (M > S.N - 1) { M = S.N - 1; r = 0.0; }
+    rows = (T > 0.0) ? M + 1 : 0;
+    part = (r > 0.0) ? 1 : 0;
+  } else {
+    if (M > S.N) { M = S.N; r = 0.0; }
+    rows = M + (r > 0.0 ? 1 : 0);
+    if (rows > S.N) rows = S.N;
+    part = 0;
+  }
+  // binary split of T for e^{T A}: T = qq delta + rho
+  const double qd = T / S.delta;
+  long qq = (long)floor(qd);
+  if (qq > (1L << POW_BITS)) qq = 1L << POW_BITS;
+  if (qq < 0) qq = 0;
+  const double rho = T - qq * S.delta;
+
+  const int ncols = 1 + (part ? m : 0);
+  double Rfro = 0.0;
+  for (int c0 = 0; c0 < ncols; c0 += SETUP_COLS) {
+    const int cc = min(SETUP_COLS, ncols - c0);
+    // load columns: col 0 = x0 (first chunk), others = -B Qu columns
+    for (int e = tid; e < n * cc; e += 256) {
+      const int i = e / cc, cl = e % cc, col = c0 + cl;
+      sv[0][i * SETUP_COLS + cl] = (col == 0) ? st.x0[p * np + i] : S.BQ[i * m + (col - 1)];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int b = 0; b <= POW_BITS; ++b) {
+      if (!((qq >> b) & 1L)) continue;
+      const double *E = S.epow + (size_t)b * n * n;
+      const int nxt = cur ^ 1;
+      for (int e = tid; e < n * cc; e += 256) {
+        const int i = e / cc, cl = e % cc;
+        double acc = 0.0;
+        for (int l = 0; l < n; ++l) acc += E[(size_t)i * n + l] * sv[cur][l * SETUP_COLS + cl];
+        sv[nxt][i * SETUP_COLS + cl] = acc;
+      }
+      __syncthreads();
+      cur = nxt;
+    }
+    if (rho > 0.0) {   // e^{rho A} v by Taylor: rho ||A|| is below 2^-20 t_max ||A||
+      const int tv = 2;   // sv[2] holds the running term
+      for (int e = tid; e < n * cc; e += 256) sv[tv][(e / cc) * SETUP_COLS + e % cc] = sv[cur][(e / cc) * SETUP_COLS + e % cc];
+      __syncthreads();
+      const int other = cur ^ 1;
+      for (int k = 1; k <= 8; ++k) {
+        for (int e = tid; e < n * cc; e += 256) {
+          const int i = e / cc, cl = e % cc;
+          double acc = 0.0;
+          for (int l = 0; l < n; ++l) acc += S.A[(size_t)i * n + l] * sv[tv][l * SETUP_COLS + cl];
+          sv[other][i * SETUP_COLS + cl] = acc * (rho / k);
+        }
+        __syncthreads();
+        for (int e = tid; e < n * cc; e += 256) {
+          const int i = e / cc, cl = e % cc;
+          sv[tv][i * SETUP_COLS + cl] = sv[other][i * SETUP_COLS + cl];
+          sv[cur][i * SETUP_COLS + cl] += sv[other][i * SETUP_COLS + cl];
+        }
+        __syncthreads();
+      }
+    }
+    // store
+    for (int e = tid; e < np * cc; e += 256) {
+      const int i = e / cc, cl = e % cc, col = c0 + cl;
+      const double v = i < n ? sv[cur][i * SETUP_COLS + cl] : 0.0;
+      if (col == 0) {
+        st.xf[p * np + i] = v;
+        st.xfc32[p * np + i] = (float)(i < n ? v - S.c[i] : 0.0);
+      } else {
+        const size_t o2 = ((size_t)p * m + (col - 1)) * np + i;
+        st.R64[o2] = v;
+        st.R32[o2] = (float)v;
+      }
+    }
+    // Frobenius norm of R (for the step-size bound)
+    double loc = 0.0;
+    for (int e = tid; e < n * cc; e += 256) {
+      const int i = e / cc, cl = e % cc, col = c0 + cl;
+      if (col > 0) { const double v = sv[cur][i * SETUP_COLS + cl]; loc += v * v; }
+    }
+    red[tid] = loc;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if (tid < s2) red[tid] += red[tid + s2];
+      __syncthreads();
+    }
+    Rfro += red[0];
+    __syncthreads();
+  }
+  // cold or warm start
+  const int old_rows = st.rows[p];
+  const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);
+  const int nkb_new = (rows + NODE_BLOCK - 1) / NODE_BLOCK;
+  if (cold) {
+    for (int i = tid; i < np; i += 256) {
+      st.lam[p * np + i] = 0.0f;
+      st.lamb[p * np + i] = 0.0f;
+    }
+    for (int e = tid; e < nkb_new * m * NODE_BLOCK; e += 256) st.y[(size_t)p * st.ystride + e] = 0.0f;
+  } else {
+    for (int i = tid; i < np; i += 256) st.lamb[p * np + i] = st.lam[p * np + i];
+    // rows the previous probe did not use start at zero
+    for (int e = tid; e < nkb_new * m * NODE_BLOCK; e += 256) {
+      const int kb = e / (m * NODE_BLOCK), kk = e % NODE_BLOCK;
+      if (kb * NODE_BLOCK + kk >= old_rows) st.y[(size_t)p * st.ystride + e] = 0.0f;
+    }
+  }
+  for (int j = tid; j < st.mpad; j += 256) st.yR[(size_t)p * st.mpad + j] = 0.0f;
+  if (tid == 0) {
+    double L2 = S.lpref[rows] + (part ? Rfro : 0.0);
+    const double L = sqrt(L2);
+    st.M[p] = M;
+    st.r[p] = r;
+    st.rows[p] = rows;
+    st.partial[p] = part;
+    if (L > 0.0) {
+      st.tau[p] = o.c_tau / L;
+      st.sig[p] = 0.999 / (o.c_tau * L);
+    } else {          // no quadrature nodes: the prox of G alone is exact in one step
+      st.tau[p] = 1e20;
+      st.sig[p] = 0.0;
+    }
+    st.iters_probe[p] = 0;
+    st.probes[p] += 1;
+    st.flags[p] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ tile formation
+
+// Active points sorted by rows (descending) so that a workgroup's 64 points
+// need similar numbers of table rows; also counts the algorithmic point-rows.
+__global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows) {
+  __shared__ int hist[4097 + 1];
+  __shared__ int total;
+  __shared__ double rsum[1024];
+  const int tid = threadIdx.x;
+  for (int b = tid; b <= N + 1; b += 1024) hist[b] = 0;
+  if (tid == 0) total = 0;
+  __syncthreads();
+  double loc = 0.0;
+  for (long p = tid; p < st.npts; p += 1024) {
+    if (st.phase[p] == PH_DONE) continue;
+    const int rw = st.rows[p];
+    atomicAdd(&hist[N - rw], 1);   // descending rows
+    loc += (double)(rw + st.partial[p]);
+  }
+  rsum[tid] = loc;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) rsum[tid] += rsum[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b <= N; ++b) {   // exclusive scan
+      const int v = hist[b];
+      hist[b] = acc;
+      acc += v;
+    }
+    total = acc;
+    st.counters[0] = acc;
+    if (count_rows) st.rowsum[0] += rsum[0];
+  }
+  __syncthreads();
+  for (long p = tid; p < st.npts; p += 1024) {
+    if (st.phase[p] == PH_DONE) continue;
+    const int pos = atomicAdd(&hist[N - st.rows[p]], 1);
+    st.perm[pos] = (int)p;
+  }
+}
+
+// ------------------------------------------------------------------ outputs
+
+__global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double *gap_out,
+                          double *philo, double *phihi, double *lam_out, int *probes_out,
+                          int *iters_out, int *status_out) {
+  long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= st.npts) return;
+  const double Pv = st.P[p], Dv = st.D[p];
+  const int stt = st.status[p];
+  if (T_out) {
+    double Tv = st.T[p];
+    if (mode == MODE_MINTIME) {
+      if (stt == HOPF_PT_OK || stt == HOPF_PT_INSIDE) Tv = st.hi[p];
+      else if (stt == HOPF_PT_NOCONV || stt == HOPF_PT_NONFINITE) Tv = NAN;
+    }
+    T_out[p] = Tv;
+  }
+  if (gap_out) gap_out[p] = (Pv - Dv) / fmax(1.0, fabs(Dv));
+  if (philo) philo[p] = -Pv;
+  if (phihi) phihi[p] = -Dv;
+  if (lam_out)
+    for (int i = 0; i < S.n; ++i) lam_out[p * S.n + i] = (double)st.lam[p * S.n_pad + i];
+  if (probes_out) probes_out[p] = st.probes[p];
+  if (iters_out) iters_out[p] = st.iters_tot[p];
+  status_out[p] = stt;
+}
+
+// ------------------------------------------------------------------ host orchestration
+
+namespace {
+
+template <typename T>
+T *grow(Ctx *ctx, int idx, size_t count) {
+  if ((int)ctx->bufs.size() <= idx) ctx->bufs.resize(idx + 1);
+  auto &b = ctx->bufs[idx];
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (b.bytes < bytes) {
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) return nullptr;
+    b.bytes = bytes;
+  }
+  return reinterpret_cast<T *>(b.p);
+}
+
+SysView view(const SysTables &t) {
+  SysView v;
+  v.n = t.n; v.m = t.m; v.N = t.N; v.n_pad = t.n_pad; v.nkb = t.nkb;
+  v.quad = t.desc.quad; v.uset = t.desc.uset;
+  v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta;
+  v.K32 = t.K32; v.K64 = t.K64; v.lpref = t.lpref_d; v.epow = t.epow_d;
+  v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
+  return v;
+}
+
+#define HIPCHK(x)                                                                            \
+  do {                                                                                       \
+    hipError_t e_ = (x);                                                                     \
+    if (e_ != hipSuccess) return set_err(ctx, HOPF_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
+                      const double *t_in, double *T_out, double *gap_out, double *philo_out,
+                      double *phihi_out, double *lam_out, int *probes_out, int *iters_out,
+                      int *status_out, double *y_out, hipStream_t user_stream) {
+  (void)y_out;
+  if (ctx->sys.empty()) return set_err(ctx, HOPF_ESTATE, "no systems set");
+  if (npts < 0) return set_err(ctx, HOPF_EINVAL, "npts < 0");
+  if (!status_out || !x) return set_err(ctx, HOPF_EINVAL, "x and pt_status are required");
+  if (npts == 0) return HOPF_OK;
+  if (npts > (1L << 26)) return set_err(ctx, HOPF_EINVAL, "too many points in one call");
+  int sid = 0;
+  if (sys_id) {
+    std::vector<int> ids(npts);
+    HIPCHK(hipMemcpy(ids.data(), sys_id, npts * sizeof(int), hipMemcpyDeviceToHost));
+    sid = ids[0];
+    for (long i = 1; i < npts; ++i)
+      if (ids[i] != sid) return set_err(ctx, HOPF_EUNSUPPORTED, "all points of one call must share a system in this build");
+    if (sid < 0 || sid >= (int)ctx->sys.size()) return set_err(ctx, HOPF_EINVAL, "sys_id out of range");
+  }
+  const SysTables &tab = ctx->sys[sid];
+  const SysView S = view(tab);
+  const hopf_opts &ho = ctx->opts;
+  const int NT = tab.n_pad / 16;
+  int MMc = 0;
+  pdhg_fn fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
+  cert_fn fc = cert_lookup(NT);
+  if (!fp || !fc)
+    return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" + std::to_string(tab.m));
+  const size_t elt = ho.prec == HOPF_FP64 ? 8 : 4;
+  const int kstride = tab.n_pad + (elt == 4 ? 4 : 2);
+  const size_t lds_k = (size_t)tab.m * NODE_BLOCK * kstride * elt;
+  const size_t lds_part = (size_t)WAVES * (2 * 16 * tab.n_pad + 16 * MMc) * elt;
+  const size_t lds_pdhg = std::max(lds_k, lds_part);
+  const int mpad = ((tab.m + 3) / 4) * 4;
+  const size_t lds_cert = std::max<size_t>((size_t)NODE_BLOCK * (tab.n_pad + 2) * 8 * std::max(1, std::min(tab.m, (int)(LDS_BYTES / (NODE_BLOCK * (tab.n_pad + 2) * 8)))),
+                                           (size_t)WAVES * (16 * tab.n_pad * 4 + 16 * tab.n_pad * 8 + 16 * mpad * 8));
+  if (lds_pdhg > 150 * 1024 || lds_cert > 150 * 1024)
+    return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
+
+  HIPCHK(hipFuncSetAttribute((const void *)fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pdhg));
+  HIPCHK(hipFuncSetAttribute((const void *)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cert));
+  hipStream_t s = user_stream ? user_stream : ctx->stream;
+  const int np = tab.n_pad, m = tab.m;
+  PtState st{};
+  st.npts = npts;
+  st.ystride = tab.nkb * m * NODE_BLOCK;
+  st.mpad = ((m + 3) / 4) * 4;
+  int bi = 0;
+  st.x0 = grow<double>(ctx, bi++, npts * np);
+  st.status = grow<int>(ctx, bi++, npts);
+  st.phase = grow<int>(ctx, bi++, npts);
+  st.flags = grow<int>(ctx, bi++, npts);
+  st.probes = grow<int>(ctx, bi++, npts);
+  st.iters_tot = grow<int>(ctx, bi++, npts);
+  st.iters_probe = grow<int>(ctx, bi++, npts);
+  st.rows = grow<int>(ctx, bi++, npts);
+  st.M = grow<int>(ctx, bi++, npts);
+  st.partial = grow<int>(ctx, bi++, npts);
+  st.last_reach = grow<int>(ctx, bi++, npts);
+  st.T = grow<double>(ctx, bi++, npts);
+  st.lo = grow<double>(ctx, bi++, npts);
+  st.hi = grow<double>(ctx, bi++, npts);
+  st.r = grow<double>(ctx, bi++, npts);
+  st.tau = grow<double>(ctx, bi++, npts);
+  st.sig = grow<double>(ctx, bi++, npts);
+  st.P = grow<double>(ctx, bi++, npts);
+  st.D = grow<double>(ctx, bi++, npts);
+  st.xf = grow<double>(ctx, bi++, npts * np);
+  st.xfc32 = grow<float>(ctx, bi++, (npts + 1) * np);
+  const bool trap = tab.desc.quad == HOPF_Q_TRAP;
+  st.R64 = grow<double>(ctx, bi++, trap ? npts * m * np : 1);
+  st.R32 = grow<float>(ctx, bi++, trap ? npts * m * np : 1);
+  st.lam = grow<float>(ctx, bi++, (npts + 1) * np);
+  st.lamb = grow<float>(ctx, bi++, (npts + 1) * np);
+  st.y = grow<float>(ctx, bi++, (size_t)(npts + 1) * st.ystride);   // row npts: spare for dead lanes
+  st.yR = grow<float>(ctx, bi++, npts * st.mpad);
+  st.perm = grow<int>(ctx, bi++, npts);
+  st.counters = grow<int>(ctx, bi++, 4);
+  st.rowsum = grow<double>(ctx, bi++, 1);
+  int *hcount = nullptr;
+  if (!st.x0 || !st.status || !st.y || !st.R64 || !st.R32 || !st.perm || !st.rowsum)
+    return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
+  HIPCHK(hipHostMalloc((void **)&hcount, 4 * sizeof(int), hipHostMallocDefault));
+
+  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<hipEvent_t> kev;
+  HIPCHK(hipEventRecord(e0, s));
+  HIPCHK(hipMemsetAsync(st.rows, 0, npts * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(st.rowsum, 0, sizeof(double), s));
+  HIPCHK(hipMemsetAsync(st.partial, 0, npts * sizeof(int), s));
+  {
+    const long tot = npts * np;
+    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, npts, tab.n, np);
+    k_init<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(S, st, mode, t_in);
+  }
+  const int max_probes = POW_BITS + 40;
+  const long max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
+  const unsigned ngrid = (unsigned)((npts + PTS_WG - 1) / PTS_WG);
+  long rounds = 0;
+  ctx->iter_launches = 0;
+  for (;;) {
+    k_setup<<<(unsigned)npts, 256, 0, s>>>(S, st, o);
+    k_sort<<<1, 1024, 0, s>>>(st, tab.N, 1);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, s));
+    fp<<<ngrid, THREADS, lds_pdhg, s>>>(S, st, ho.check_every);
+    HIPCHK(hipEventRecord(b, s));
+    kev.push_back(a);
+    kev.push_back(b);
+    ctx->iter_launches++;
+    fc<<<ngrid, THREADS, lds_cert, s>>>(S, st, o, mode);
+    ++rounds;
+    if (rounds % 4 == 0 || rounds >= max_rounds) {
+      k_sort<<<1, 1024, 0, s>>>(st, tab.N, 0);   // refresh the active count
+      HIPCHK(hipMemcpyAsync(hcount, st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hcount[0] == 0 || rounds >= max_rounds) break;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  k_outputs<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(S, st, mode, T_out, gap_out, philo_out,
+                                                          phihi_out, lam_out, probes_out, iters_out, status_out);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  ctx->t_total = ms * 1e-3;
+  double it_s = 0.0;
+  for (size_t i = 0; i + 1 < kev.size(); i += 2) {
+    float km = 0.f;
+    hipEventElapsedTime(&km, kev[i], kev[i + 1]);
+    it_s += km * 1e-3;
+    hipEventDestroy(kev[i]);
+    hipEventDestroy(kev[i + 1]);
+  }
+  ctx->t_iter = it_s;
+  double rs = 0.0;
+  HIPCHK(hipMemcpy(&rs, st.rowsum, sizeof(double), hipMemcpyDeviceToHost));
+  // point-rows summed once per round; each round runs check_every iterations
+  ctx->point_rows = rs * ho.check_every;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipHostFree(hcount);
+  if (rounds >= max_rounds) ctx->err = "round limit reached; unfinished points report NOCONV";
+  return HOPF_OK;
+}
+
+hopf_status trajectory_dev(Ctx *ctx, int, const double *, double, int *, double *, double *, double *,
+                           double *, double *, double *) {
+  return set_err(ctx, HOPF_EUNSUPPORTED, "trajectory read-out not built yet");
+}
+
+}  // namespace hopf
+
+using hopf::Ctx;
+
+extern "C" {
+
+hopf_status hopf_min_time_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, double *T,
+                              double *gap, double *lam, int *probes, int *iters, int *pt_status,
+                              void *stream) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
+  return hopf::solve_dev(c, hopf::MODE_MINTIME, npts, sys_id, x, nullptr, T, gap, nullptr, nullptr, lam,
+                         probes, iters, pt_status, nullptr, (hipStream_t)stream);
+}
+
+static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, const double *x,
+                             const double *t, double *T, double *gap, double *philo, double *phihi,
+                             double *lam, int *probes, int *iters, int *pt_status) {
+  if (!c) return HOPF_EINVAL;
+  if (c->sys.empty()) return hopf::set_err(c, HOPF_ESTATE, "no systems set");
+  if (npts < 0 || !x || !pt_status) return hopf::set_err(c, HOPF_EINVAL, "x and pt_status are required");
+  if (mode == hopf::MODE_VALUE && !t) return hopf::set_err(c, HOPF_EINVAL, "t is required");
+  if (npts == 0) return HOPF_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
+  int sid = sys_id ? sys_id[0] : 0;
+  if (sid < 0 || sid >= (int)c->sys.size()) return hopf::set_err(c, HOPF_EINVAL, "sys_id out of range");
+  const int n = c->sys[sid].n;
+  if (mode == hopf::MODE_VALUE)
+    for (long i = 0; i < npts; ++i)
+      if (!(t[i] >= 0.0 && t[i] <= c->sys[sys_id ? sys_id[i] : 0].desc.t_max))
+        return hopf::set_err(c, HOPF_EINVAL, "t must lie in [0, t_max]");
+  // device buffers for this call
+  double *dx = nullptr, *dt = nullptr, *dT = nullptr, *dgap = nullptr, *dlo = nullptr, *dhi = nullptr, *dlam = nullptr;
+  int *dsid = nullptr, *dpr = nullptr, *dit = nullptr, *dst = nullptr;
+  hopf_status rc = HOPF_OK;
+  auto al = [&](void **p, size_t b) { if (rc == HOPF_OK && hipMalloc(p, b) != hipSuccess) rc = HOPF_ENOMEM; };
+  al((void **)&dx, npts * n * sizeof(double));
+  al((void **)&dT, npts * sizeof(double));
+  al((void **)&dgap, npts * sizeof(double));
+  al((void **)&dlo, npts * sizeof(double));
+  al((void **)&dhi, npts * sizeof(double));
+  al((void **)&dpr, npts * sizeof(int));
+  al((void **)&dit, npts * sizeof(int));
+  al((void **)&dst, npts * sizeof(int));
+  if (lam) al((void **)&dlam, npts * n * sizeof(double));
+  if (t) al((void **)&dt, npts * sizeof(double));
+  if (sys_id) al((void **)&dsid, npts * sizeof(int));
+  if (rc == HOPF_OK) {
+    hipMemcpy(dx, x, npts * n * sizeof(double), hipMemcpyHostToDevice);
+    if (t) hipMemcpy(dt, t, npts * sizeof(double), hipMemcpyHostToDevice);
+    if (sys_id) hipMemcpy(dsid, sys_id, npts * sizeof(int), hipMemcpyHostToDevice);
+    rc = hopf::solve_dev(c, mode, npts, dsid, dx, dt, dT, dgap, dlo, dhi, dlam, dpr, dit, dst, nullptr, nullptr);
+    if (rc == HOPF_OK) {
+      if (T) hipMemcpy(T, dT, npts * sizeof(double), hipMemcpyDeviceToHost);
+      if (gap) hipMemcpy(gap, dgap, npts * sizeof(double), hipMemcpyDeviceToHost);
+      if (philo) hipMemcpy(philo, dlo, npts * sizeof(double), hipMemcpyDeviceToHost);
+      if (phihi) hipMemcpy(phihi, dhi, npts * sizeof(double), hipMemcpyDeviceToHost);
+      if (lam) hipMemcpy(lam, dlam, npts * n * sizeof(double), hipMemcpyDeviceToHost);
+      if (probes) hipMemcpy(probes, dpr, npts * sizeof(int), hipMemcpyDeviceToHost);
+      if (iters) hipMemcpy(iters, dit, npts * sizeof(int), hipMemcpyDeviceToHost);
+      hipMemcpy(pt_status, dst, npts * sizeof(int), hipMemcpyDeviceToHost);
+    }
+  } else {
+    hopf::set_err(c, rc, "device allocation failed");
+  }
+  hipFree(dx); hipFree(dt); hipFree(dT); hipFree(dgap); hipFree(dlo); hipFree(dhi); hipFree(dlam);
+  hipFree(dsid); hipFree(dpr); hipFree(dit); hipFree(dst);
+  return rc;
+}
+
+hopf_status hopf_min_time(hopf_ctx *h, long npts, const int *sys_id, const double *x, double *T,
+                          double *gap, double *lam, int *probes, int *iters, int *pt_status) {
+  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_MINTIME, npts, sys_id, x, nullptr, T, gap,
+                   nullptr, nullptr, lam, probes, iters, pt_status);
+}
+
+hopf_status hopf_value(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *t,
+                       double *phi_lo, double *phi_hi, double *lam, int *iters, int *pt_status) {
+  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr,
+                   phi_lo, phi_hi, lam, nullptr, iters, pt_status);
+}
+
+hopf_status hopf_trajectory(hopf_ctx *h, int sys_id, const double *x0, double T, int *n_nodes, double *s,
+                            double *u, double *xs, double *p_star, double *phi_lo, double *phi_hi) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  return hopf::trajectory_dev(c, sys_id, x0, T, n_nodes, s, u, xs, p_star, phi_lo, phi_hi);
+}
+
+}  // extern "C"
+
+namespace hopf {
+
+#define HOPF_DECL(k)                                   \
+  pdhg_fn pdhg_lookup_nt##k(int m, int prec, int *MM); \
+  cert_fn cert_lookup_nt##k();
+HOPF_DECL(1) HOPF_DECL(2) HOPF_DECL(3) HOPF_DECL(4) HOPF_DECL(5) HOPF_DECL(6) HOPF_DECL(7) HOPF_DECL(8)
+#undef HOPF_DECL
+
+pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM) {
+  switch (NT) {
+    case 1: return pdhg_lookup_nt1(m, prec, MM);
+    case 2: return pdhg_lookup_nt2(m, prec, MM);
+    case 3: return pdhg_lookup_nt3(m, prec, MM);
+    case 4: return pdhg_lookup_nt4(m, prec, MM);
+    case 5: return pdhg_lookup_nt5(m, prec, MM);
+    case 6: return pdhg_lookup_nt6(m, prec, MM);
+    case 7: return pdhg_lookup_nt7(m, prec, MM);
+    case 8: return pdhg_lookup_nt8(m, prec, MM);
+  }
+  return nullptr;
+}
+
+cert_fn cert_lookup(int NT) {
+  switch (NT) {
+    case 1: return cert_lookup_nt1();
+    case 2: return cert_lookup_nt2();
+    case 3: return cert_lookup_nt3();
+    case 4: return cert_lookup_nt4();
+    case 5: return cert_lookup_nt5();
+    case 6: return cert_lookup_nt6();
+    case 7: return cert_lookup_nt7();
+    case 8: return cert_lookup_nt8();
+  }
+  return nullptr;
+}
+
+}  // namespace hopf

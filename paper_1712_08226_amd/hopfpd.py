@@ -1,0 +1,218 @@
+"""Thin ctypes binding of libhopfpd.so (the C-ABI in include/hopfpd.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Host arrays are NumPy float64/int32; the ``*_dev`` calls take torch
+CUDA tensors (torch is used for device memory and streams only).  Importing
+this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhopfpd.so")
+
+U_L2, U_BOX = 0, 1
+Q_TRAP, Q_LEFT = 0, 1
+FP64, FP32 = 0, 1
+WARM_COLD, WARM_CONT = 0, 1
+PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
+
+EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", "hopf_last_error",
+           "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_min_time", "hopf_min_time_dev",
+           "hopf_trajectory", "hopf_last_timing"]
+
+
+class HopfSystem(C.Structure):
+    _fields_ = [("n", C.c_int), ("m", C.c_int), ("N", C.c_int), ("t_max", C.c_double),
+                ("quad", C.c_int), ("uset", C.c_int),
+                ("A", C.POINTER(C.c_double)), ("B", C.POINTER(C.c_double)),
+                ("Qu", C.POINTER(C.c_double)), ("W", C.POINTER(C.c_double)),
+                ("c", C.POINTER(C.c_double))]
+
+
+class HopfOpts(C.Structure):
+    _fields_ = [("c_tau", C.c_double), ("gap_tol", C.c_double), ("t_rel_tol", C.c_double),
+                ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
+                ("warm", C.c_int), ("prec", C.c_int)]
+
+
+class HopfError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HopfError(f"{path} is not built: run `python -m paper_1712_08226_amd.build`")
+    lib = C.CDLL(path)
+    dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p
+    lib.hopf_default_opts.argtypes = [C.POINTER(HopfOpts)]
+    lib.hopf_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.hopf_destroy.argtypes = [vp]
+    lib.hopf_destroy.restype = None
+    lib.hopf_strerror.argtypes = [C.c_int]
+    lib.hopf_strerror.restype = C.c_char_p
+    lib.hopf_last_error.argtypes = [vp]
+    lib.hopf_last_error.restype = C.c_char_p
+    lib.hopf_set_systems.argtypes = [vp, C.c_int, C.POINTER(HopfSystem)]
+    lib.hopf_set_opts.argtypes = [vp, C.POINTER(HopfOpts)]
+    lib.hopf_value.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, dp, ip, ip]
+    lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, ip, ip, ip]
+    lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
+    lib.hopf_last_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_long), dp]
+    for name in EXPORTS:
+        if name not in ("hopf_destroy", "hopf_strerror", "hopf_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def default_opts() -> HopfOpts:
+    o = HopfOpts()
+    load().hopf_default_opts(C.byref(o))
+    return o
+
+
+class Solver:
+    """Owns one hopf_ctx (one device, one stream)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.hopf_create(device, C.byref(h))
+        if st != 0:
+            raise HopfError(f"hopf_create failed: {self.lib.hopf_strerror(st).decode()}")
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            self.lib.hopf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self.lib.hopf_last_error(self.h).decode()
+            raise HopfError(f"{what}: {self.lib.hopf_strerror(st).decode()}: {msg}")
+
+    # -------------------------------------------------------------- setup
+    def set_systems(self, systems):
+        """systems: iterable of objects/dicts with A, B, W, c, uset, N, t_max,
+        quad (and optionally Qu); uset 'l2'/'box', quad 'trap'/'left'."""
+        arr = (HopfSystem * len(systems))()
+        keep = []
+        for k, s in enumerate(systems):
+            g = (lambda key, d=None: s[key] if isinstance(s, dict) else getattr(s, key, d))
+            A, B, W = _f64(g("A")), _f64(g("B")), _f64(g("W"))
+            if B.ndim == 1:
+                B = B[:, None].copy()
+            c = g("c", None)
+            c = _f64(c) if c is not None else None
+            Qu = g("Qu", None)
+            Qu = _f64(Qu) if Qu is not None else None
+            keep += [A, B, W, c, Qu]
+            uset = g("uset")
+            quad = g("quad")
+            arr[k] = HopfSystem(A.shape[0], B.shape[1], int(g("N")), float(g("t_max")),
+                                Q_TRAP if quad in ("trap", Q_TRAP) else Q_LEFT,
+                                U_L2 if uset in ("l2", U_L2) else U_BOX,
+                                _dptr(A), _dptr(B), _dptr(Qu), _dptr(W), _dptr(c))
+        self._check(self.lib.hopf_set_systems(self.h, len(systems), arr), "hopf_set_systems")
+        self.n = [int(arr[k].n) for k in range(len(systems))]
+
+    def set_opts(self, **kw):
+        o = default_opts()
+        for k, v in kw.items():
+            if k == "prec":
+                v = {"fp64": FP64, "fp32": FP32}.get(v, v)
+            if k == "warm":
+                v = {"cold": WARM_COLD, "cont": WARM_CONT}.get(v, v)
+            setattr(o, k, v)
+        self._check(self.lib.hopf_set_opts(self.h, C.byref(o)), "hopf_set_opts")
+
+    # -------------------------------------------------------------- solves
+    def value(self, x, t, sys_id=None):
+        x = _f64(x)
+        npts, n = x.shape
+        t = _f64(np.broadcast_to(np.asarray(t, dtype=np.float64), (npts,)))
+        sid = None if sys_id is None else np.ascontiguousarray(np.asarray(sys_id, dtype=np.int32))
+        lo, hi = np.empty(npts), np.empty(npts)
+        lam = np.empty((npts, n))
+        iters = np.empty(npts, dtype=np.int32)
+        stat = np.empty(npts, dtype=np.int32)
+        self._check(self.lib.hopf_value(self.h, npts, _iptr(sid), _dptr(x), _dptr(t), _dptr(lo), _dptr(hi),
+                                        _dptr(lam), _iptr(iters), _iptr(stat)), "hopf_value")
+        return dict(phi_lo=lo, phi_hi=hi, lam=lam, iters=iters, status=stat)
+
+    def min_time(self, x, sys_id=None):
+        x = _f64(x)
+        npts, n = x.shape
+        sid = None if sys_id is None else np.ascontiguousarray(np.asarray(sys_id, dtype=np.int32))
+        T, gap = np.empty(npts), np.empty(npts)
+        lam = np.empty((npts, n))
+        probes = np.empty(npts, dtype=np.int32)
+        iters = np.empty(npts, dtype=np.int32)
+        stat = np.empty(npts, dtype=np.int32)
+        self._check(self.lib.hopf_min_time(self.h, npts, _iptr(sid), _dptr(x), _dptr(T), _dptr(gap), _dptr(lam),
+                                           _iptr(probes), _iptr(iters), _iptr(stat)), "hopf_min_time")
+        return dict(T=T, gap=gap, lam=lam, probes=probes, iters=iters, status=stat)
+
+    def min_time_dev(self, x, T, gap, status, lam=None, probes=None, iters=None, sys_id=None, stream=None):
+        """Device twin: torch CUDA tensors (float64 x/T/gap/lam, int32 others)."""
+        p = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+        npts = x.shape[0]
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        self._check(self.lib.hopf_min_time_dev(self.h, npts, p(sys_id), p(x), p(T), p(gap), p(lam), p(probes),
+                                               p(iters), p(status), s), "hopf_min_time_dev")
+
+    def trajectory(self, x0, T, sys_id=0, N=None):
+        x0 = _f64(x0)
+        n = x0.shape[0]
+        rows = (N or 4096) + 1
+        m = 64
+        nn = C.c_int(0)
+        s = np.empty(rows)
+        u = np.empty((rows, m))
+        xs = np.empty((rows, n))
+        p = np.empty(n)
+        lo, hi = C.c_double(0), C.c_double(0)
+        self._check(self.lib.hopf_trajectory(self.h, sys_id, _dptr(x0), float(T), C.byref(nn), _dptr(s), _dptr(u),
+                                             _dptr(xs), _dptr(p), C.byref(lo), C.byref(hi)), "hopf_trajectory")
+        k = nn.value
+        return dict(s=s[:k], u=u[:k], xs=xs[:k], p_star=p, phi_lo=lo.value, phi_hi=hi.value)
+
+    def last_timing(self):
+        a, b, d = C.c_double(), C.c_double(), C.c_double()
+        c = C.c_long()
+        self._check(self.lib.hopf_last_timing(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
+                    "hopf_last_timing")
+        return dict(total_s=a.value, iter_kernel_s=b.value, iter_launches=c.value, point_rows=d.value)

@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every entry point include/hopfpd.h
+declares; host-side argument handling that needs no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1712_08226_amd import hopfpd as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hopfpd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hopf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = H.load()
+    decl = declared_symbols()
+    assert len(decl) >= 12
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(H.EXPORTS)
+
+
+def test_strerror_and_defaults_without_gpu():
+    lib = H.load()
+    assert lib.hopf_strerror(0) == b"ok"
+    assert lib.hopf_strerror(1) == b"invalid argument"
+    o = H.default_opts()
+    assert o.gap_tol == 1e-6 and o.t_rel_tol == 0.5e-4 and o.check_every > 0
+
+
+def test_null_context_is_rejected():
+    lib = H.load()
+    assert lib.hopf_set_opts(None, None) == 1
+    assert lib.hopf_last_error(None) == b"null context"
+    lib.hopf_destroy(None)                      # no-op
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="host without a GPU only")
+def test_create_without_device_reports_device_error():
+    lib = H.load()
+    h = C.c_void_p()
+    assert lib.hopf_create(0, C.byref(h)) == 3
+    assert not h.value

@@ -1,0 +1,155 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bar (per result): certified value intervals [phi_lo, phi_hi] of the device
+and the oracle overlap (both contain phi_N), the device gap is <= 1e-6, and
+minimum times agree to |dT| <= 1e-4 T with identical per-point statuses.
+Iterates are not compared: the device iterates in FP32 (or FP64), the
+oracle in FP64, and both results are certified independently.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from gen import double_integrator, random_system, uniform_box_points, gaussian_points
+from oracle import hopf_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+GAP = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_1712_08226_amd import Solver
+    s = Solver(0)
+    yield s
+    s.close()
+
+
+def osys(spec, **kw):
+    d = dict(uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+    d.update(kw)
+    return O.System(spec.A, spec.B, spec.W, spec.c, **d)
+
+
+def overlap(a_lo, a_hi, b_lo, b_hi, tol=1e-9):
+    return max(a_lo, b_lo) <= min(a_hi, b_hi) + tol * max(1.0, abs(a_hi), abs(b_hi))
+
+
+def integrator(n, r, uset, N=40, t_max=5.0):
+    return dict(A=np.zeros((n, n)), B=np.eye(n), W=(r * r) * np.eye(n), c=np.zeros(n), uset=uset,
+                N=N, t_max=t_max, quad="trap")
+
+
+# ------------------------------------------------------------------ value
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_value_integrator_closed_form(solver, prec):
+    """dx/dt = u: phi = 1/2 (max(0, ||x|| - t)^2 / r^2 - 1) inside the certified interval."""
+    say("case: value integrator", prec)
+    sysd = integrator(3, 0.3, "l2")
+    solver.set_systems([sysd])
+    solver.set_opts(prec=prec, c_tau=1.0)
+    x = np.array([[0.9, -0.4, 0.2], [0.2, 0.1, 0.0], [1.5, 1.0, -1.0], [0.5, 0.5, 0.5]])
+    t = np.array([0.3, 0.5, 1.2, 0.0])
+    r = solver.value(x, t)
+    for k in range(len(t)):
+        exact = 0.5 * (max(0.0, np.linalg.norm(x[k]) - t[k]) ** 2 / 0.09 - 1.0)
+        assert r["status"][k] == 0
+        assert r["phi_lo"][k] - 1e-9 <= exact <= r["phi_hi"][k] + 1e-9, (k, r["phi_lo"][k], exact, r["phi_hi"][k])
+        assert (r["phi_hi"][k] - r["phi_lo"][k]) / max(1.0, abs(r["phi_hi"][k])) <= GAP
+
+
+@pytest.mark.parametrize("uset,quad,n,m,prec", [("l2", "trap", 6, 2, "fp32"), ("box", "trap", 6, 2, "fp32"),
+                                                ("l2", "left", 20, 3, "fp32"), ("box", "left", 6, 1, "fp64"),
+                                                ("l2", "trap", 35, 5, "fp32")])
+def test_value_random_system_vs_oracle(solver, uset, quad, n, m, prec):
+    say("case: value random", uset, quad, n, m, prec)
+    spec = random_system(n, m, 40, uset, seed=21, t_max=3.0, quad=quad)
+    solver.set_systems([spec])
+    solver.set_opts(prec=prec, c_tau=1.0)
+    x = gaussian_points(70, n, 0.15, seed=4)          # 70 points: one full tile + a ragged one
+    t = np.linspace(0.0, 3.0, 70)
+    r = solver.value(x, t)
+    S = osys(spec)
+    for k in list(range(0, 70, 9)) + [69]:
+        pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=1.0, gap_tol=1e-9, max_iter=400000))
+        assert r["status"][k] == 0, (k, r["status"][k])
+        assert overlap(r["phi_lo"][k], r["phi_hi"][k], pr.phi_lo, pr.phi_hi), (k, r["phi_lo"][k], r["phi_hi"][k], pr.phi_lo, pr.phi_hi)
+        assert (r["phi_hi"][k] - r["phi_lo"][k]) / max(1.0, abs(r["phi_hi"][k])) <= GAP
+
+
+# ------------------------------------------------------------------ minimum time
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_min_time_double_integrator(solver, prec):
+    """Sec. VI-A system, r = 0.1, N = 100 trapezoid, 24 points of the
+    [-2,2]^2 workload; every point is reachable (T <= 6)."""
+    say("case: min_time double integrator", prec)
+    spec = double_integrator(0.1, 100)
+    solver.set_systems([spec])
+    solver.set_opts(prec=prec, c_tau=30.0)
+    x = uniform_box_points(24, 2, -2.0, 2.0, seed=1)
+    r = solver.min_time(x)
+    S = osys(spec)
+    for k in range(0, 24, 3):
+        o = O.min_time(S, x[k], O.Options(c_tau=30.0))
+        assert r["status"][k] == o.status, (k, r["status"][k], o.status)
+        if o.status == O.PT_OK:
+            assert abs(r["T"][k] - o.T) <= 1e-4 * o.T, (k, r["T"][k], o.T)
+            assert r["gap"][k] <= GAP
+
+
+def test_min_time_integrator_closed_form(solver):
+    say("case: min_time integrator closed form")
+    solver.set_systems([integrator(3, 0.3, "l2", N=40, t_max=5.0)])
+    solver.set_opts(prec="fp32", c_tau=1.0)
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 1.0, size=(100, 3))
+    r = solver.min_time(x)
+    exact = np.maximum(0.0, np.linalg.norm(x, axis=1) - 0.3)
+    for k in range(100):
+        if exact[k] == 0.0:
+            assert r["status"][k] == 1 and r["T"][k] == 0.0
+        elif exact[k] > 5.0:
+            assert r["status"][k] == 2 and math.isinf(r["T"][k])
+        else:
+            assert r["status"][k] == 0
+            assert abs(r["T"][k] - exact[k]) <= 1e-4 * exact[k], (k, r["T"][k], exact[k])
+
+
+@pytest.mark.parametrize("uset,n,m,N", [("l2", 12, 2, 50), ("box", 12, 3, 50)])
+def test_min_time_random_system_vs_oracle(solver, uset, n, m, N):
+    say("case: min_time random", uset, n, m, N)
+    spec = random_system(n, m, N, uset, seed=5, t_max=4.0)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=1.0)
+    x = gaussian_points(20, n, 0.12, seed=8)
+    r = solver.min_time(x)
+    S = osys(spec)
+    for k in range(0, 20, 4):
+        o = O.min_time(S, x[k], O.Options(c_tau=1.0))
+        assert r["status"][k] == o.status, (k, r["status"][k], o.status)
+        if o.status == O.PT_OK:
+            assert abs(r["T"][k] - o.T) <= 1e-4 * o.T, (k, r["T"][k], o.T)
+            assert r["gap"][k] <= GAP
+
+
+def test_edge_cases(solver):
+    say("case: edge cases")
+    solver.set_systems([integrator(2, 0.3, "l2", N=20, t_max=1.0)])
+    solver.set_opts(prec="fp32", c_tau=1.0)
+    x = np.array([[3.0, 0.0], [0.1, 0.1], [np.nan, 0.0], [0.5, 0.2]])
+    r = solver.min_time(x)
+    assert list(r["status"]) == [2, 1, 4, 0]
+    assert math.isinf(r["T"][0]) and r["T"][1] == 0.0 and math.isnan(r["T"][2])
+    empty = solver.min_time(np.zeros((0, 2)))
+    assert empty["T"].shape == (0,)
