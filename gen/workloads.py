@@ -77,3 +77,24 @@ def uniform_box_points(npts, n, lo, hi, seed):
 def gaussian_points(npts, n, std, seed):
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, std, size=(npts, n))
+
+
+def planted_drift_points(spec, npts, T0_lo, T0_hi, seed, levels=64):
+    """Points that reach the target's boundary at time T0 under zero control:
+    x0 = e^{-T0 A} xi with xi uniform on the ellipsoid's boundary and T0 on a
+    grid of `levels` values in [T0_lo, T0_hi] (free motion only, no control
+    and no part of the solver).  Their minimum time is at most T0 whenever
+    the sign of the value is monotone; the spread of T0 spreads the
+    minimum times of the batch.  Returns (x0, T0)."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(seed)
+    n = spec.n
+    grid = np.linspace(T0_lo, T0_hi, levels)
+    E = np.stack([expm(-t * spec.A) for t in grid])
+    idx = rng.integers(0, levels, size=npts)
+    g = rng.normal(size=(npts, n))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    semi = np.sqrt(np.diag(spec.W))
+    xi = spec.c + g * semi
+    x0 = np.einsum("pij,pj->pi", E[idx], xi)
+    return x0, grid[idx]

@@ -28,6 +28,15 @@ __device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Row of the 16x16 accumulator held in register q of a lane in group g
+// (g = lane / 16; the column is lane % 16).  Measured on gfx950:
+// v_mfma_f32_16x16x4f32 -> row 4 g + q;  v_mfma_f64_16x16x4f64 -> row g + 4 q.
+// Operands A (16 x 4) and B (4 x 16) are A[lane % 16][lane / 16] and
+// B[lane / 16][lane % 16] for both.
+template <typename Tv> __device__ __forceinline__ constexpr int acc_row(int g, int q) {
+  return sizeof(Tv) == 4 ? 4 * g + q : g + 4 * q;
+}
+
 template <typename Tv> struct V4;
 template <> struct V4<float> { typedef floatx4 t; };
 template <> struct V4<double> { typedef doublex4 t; };
@@ -35,10 +44,10 @@ template <> struct V4<double> { typedef doublex4 t; };
 // ------------------------------------------------------------------ per-point state
 
 struct SysView {
-  int n, m, N, n_pad, nkb, quad, uset;
+  int n, m, N, n_pad, nkb, quad, uset, m_user;
   double t_max, h, delta;
   const float *K32;
-  const double *K64, *lpref, *epow, *A, *BQ, *Wd, *c;
+  const double *K64, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
 };
 
 struct PtState {
@@ -56,7 +65,8 @@ struct PtState {
   float *y;                  // [npts][ystride]
   float *yR;                 // [npts][mpad]
   int *perm;                 // [npts]
-  int *counters;             // [0] active, [1] need-setup
+  int *setup_list;           // [npts] points waiting for a probe setup
+  int *counters;             // [0] active, [1] setup-list length
   double *rowsum;            // accumulated point-rows for flop accounting
 };
 
@@ -66,6 +76,12 @@ struct Opts {
 };
 
 enum { FL_SETUP = 1 };
+
+// queue point p for a probe setup at its (new) horizon st.T[p]
+__device__ __forceinline__ void mark_setup(const PtState &st, long p) {
+  st.flags[p] = FL_SETUP;
+  st.setup_list[atomicAdd(&st.counters[1], 1)] = (int)p;
+}
 
 // quadrature weight of table node k for a point with (M, r)
 __device__ __forceinline__ double node_weight(int k, int M, double r, double h, int quad) {
@@ -131,7 +147,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bop[t][q] = sig * (Tv)st.lamb[pd * np + 16 * t + 4 * g + q];
+    for (int q = 0; q < 4; ++q) bop[t][q] = sig * (Tv)st.lamb[pd * np + 16 * t + acc_row<Tv>(g, q)];
   float *lamp = st.lam + pd * np;
   float *yp = st.y + (size_t)pd * st.ystride;
 
@@ -149,7 +165,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + 4 * g + q] = (sig > 0 ? bop[t][q] / sig : (Tv)0);
+        for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + acc_row<Tv>(g, q)] = (sig > 0 ? bop[t][q] / sig : (Tv)0);
       __syncthreads();
       const int pp = lane >> 2, qq = lane & 3;          // point pp of this wave, lane quarter qq
       const int pslot = wg * PTS_WG + wave * PTS_WAVE + pp;
@@ -205,7 +221,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + 4 * g + q];
+        for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + acc_row<Tv>(g, q)];
       __syncthreads();
     }
 
@@ -224,11 +240,18 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       }
       __syncthreads();
       // Y tiles
+      // y is stored node-major within a block: offset kk = node % 16
       vec4 V[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
-        V[j] = vec4{(Tv)f.x, (Tv)f.y, (Tv)f.z, (Tv)f.w};
+        const float *src = yp + (size_t)(kb * m + j) * NODE_BLOCK;
+        if constexpr (sizeof(Tv) == 4) {
+          const float4 f = *reinterpret_cast<const float4 *>(src + 4 * g);
+          V[j] = vec4{(Tv)f.x, (Tv)f.y, (Tv)f.z, (Tv)f.w};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) V[j][q] = (Tv)src[acc_row<Tv>(g, q)];
+        }
       }
       // dual GEMM: V_j += K_j (sigma lam_bar); consecutive MFMAs feed different V_j
 #pragma unroll
@@ -237,13 +260,13 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int j = 0; j < MM; ++j)
-            V[j] = mfma(lds[(size_t)(j * NODE_BLOCK + cl) * kstride + 16 * t + 4 * g + q], bop[t][q], V[j]);
+            V[j] = mfma(lds[(size_t)(j * NODE_BLOCK + cl) * kstride + 16 * t + acc_row<Tv>(g, q)], bop[t][q], V[j]);
         __builtin_amdgcn_sched_barrier(0);   // keep operand loads near their MFMAs
       }
       // projection onto w_k C per (node, point)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int k = kb * NODE_BLOCK + 4 * g + q;
+        const int k = kb * NODE_BLOCK + acc_row<Tv>(g, q);
         const Tv w = (k < rowsp) ? (Tv)node_weight(k, M, (double)rr, (double)hw, S.quad) : (Tv)0;
         if (S.uset == HOPF_U_L2) {
           Tv s = 0;
@@ -261,9 +284,15 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       // store Y
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        float4 f;
-        f.x = (float)V[j][0]; f.y = (float)V[j][1]; f.z = (float)V[j][2]; f.w = (float)V[j][3];
-        *reinterpret_cast<float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g)) = f;
+        float *dst = yp + (size_t)(kb * m + j) * NODE_BLOCK;
+        if constexpr (sizeof(Tv) == 4) {
+          float4 f;
+          f.x = (float)V[j][0]; f.y = (float)V[j][1]; f.z = (float)V[j][2]; f.w = (float)V[j][3];
+          *reinterpret_cast<float4 *>(dst + 4 * g) = f;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dst[acc_row<Tv>(g, q)] = (float)V[j][q];
+        }
       }
       // primal GEMM: G += K_j^T Y_j; consecutive MFMAs feed different G tiles
 #pragma unroll
@@ -272,7 +301,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            G[t] = mfma(lds[(size_t)(j * NODE_BLOCK + 4 * g + q) * kstride + 16 * t + cl], V[j][q], G[t]);
+            G[t] = mfma(lds[(size_t)(j * NODE_BLOCK + acc_row<Tv>(g, q)) * kstride + 16 * t + cl], V[j][q], G[t]);
         __builtin_amdgcn_sched_barrier(0);
       }
       __syncthreads();
@@ -283,7 +312,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = 16 * t + 4 * g + q;
+        const int i = 16 * t + acc_row<Tv>(g, q);
         const Tv xfc = (Tv)st.xfc32[pd * np + i];
         const Tv wd = (Tv)S.Wd[i];
         const Tv l0 = (Tv)lamp[i];
@@ -295,7 +324,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + 4 * g + q] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
+    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + acc_row<Tv>(g, q)] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
   if (live) {
     if (g == 0) {
       st.iters_probe[p] += iters;
@@ -348,11 +377,15 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
 
   for (int kb = 0; kb < nkb; ++kb) {
     // weights and y^ scale per (row q)
-    double w[4], ysc[4], snorm[4];
+    // w[q], ysc[q]: node 4g+q (the FP32 y layout, operand B of K^T y^);
+    // wu[q], snorm[q]: node g+4q (FP64 accumulator rows of U = K lam)
+    double w[4], ysc[4], snorm[4], wu[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = kb * NODE_BLOCK + 4 * g + q;
       w[q] = (k < rowsp) ? node_weight(k, M, rr, hw, S.quad) : 0.0;
+      const int ku = kb * NODE_BLOCK + acc_row<double>(g, q);
+      wu[q] = (ku < rowsp) ? node_weight(ku, M, rr, hw, S.quad) : 0.0;
       snorm[q] = 0.0;
       ysc[q] = 0.0;
     }
@@ -421,7 +454,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wsig += w[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
+    for (int q = 0; q < 4; ++q) wsig += wu[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
   }
   __syncthreads();
 
@@ -431,12 +464,14 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = 16 * t + 4 * g + q;
+      const int i = 16 * t + 4 * g + q;          // lam registers: rows 4g+q
       double xf = 0.0, cc = 0.0, wd = 1.0;
       if (live && i < S.n) { xf = st.xf[p * np + i]; cc = S.c[i]; wd = S.Wd[i]; }
       const double l = lam[t][q];
       sP += 0.5 * wd * l * l - (xf - cc) * l;
-      G[t][q] = (live && i < S.n) ? xf - G[t][q] : 0.0;   // G now holds x_T
+      const int ig = 16 * t + acc_row<double>(g, q);   // G registers: rows g+4q
+      const double xg = (live && ig < S.n) ? st.xf[p * np + ig] : 0.0;
+      G[t][q] = (live && ig < S.n) ? xg - G[t][q] : 0.0;   // G now holds x_T
     }
 
   // private node (trapezoid, off-grid T): sigma_C(R lam) and R^T y^_R
@@ -507,16 +542,19 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) G[t][q] -= (live && (16 * t + 4 * g + q) < S.n) ? xr_s[cl * np + 16 * t + 4 * g + q] : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int ig = 16 * t + acc_row<double>(g, q);
+        G[t][q] -= (live && ig < S.n) ? xr_s[cl * np + ig] : 0.0;
+      }
   }
 
-  // J(x_T) partial sums
+  // J(x_T) partial sums (G registers: rows g + 4q)
   double sJ = 0.0;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = 16 * t + 4 * g + q;
+      const int i = 16 * t + acc_row<double>(g, q);
       if (live && i < S.n) {
         const double d = G[t][q] - S.c[i];
         sJ += d * d / S.Wd[i];
@@ -573,12 +611,12 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       if (gap <= o.gap_tol) st.phase[p] = PH_DONE;   // already certified at T = hi
     } else {
       st.T[p] = hi;
-      st.flags[p] = FL_SETUP;
+      mark_setup(st, p);
     }
     return;
   }
   st.T[p] = 0.5 * (lo + hi);
-  st.flags[p] = FL_SETUP;
+  mark_setup(st, p);
 }
 
 

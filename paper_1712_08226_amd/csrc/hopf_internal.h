@@ -34,6 +34,8 @@ struct SysTables {
   double *BQ_d = nullptr;      // [n][m]   -B Qu
   double *Wd_d = nullptr;      // [n_pad]  diag W (1 in the padding)
   double *c_d = nullptr;       // [n_pad]
+  double *Eh_d = nullptr;      // [n][n]   e^{h A}
+  double *Qu_d = nullptr;      // [m_user][m_user]
 };
 
 struct Ctx {

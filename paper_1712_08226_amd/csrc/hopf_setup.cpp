@@ -148,7 +148,8 @@ bool all_finite(const double *p, size_t k) {
 
 void free_tables(SysTables &t) {
   hipFree(t.K32); hipFree(t.K64); hipFree(t.lpref_d); hipFree(t.epow_d);
-  hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d);
+  hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d); hipFree(t.Eh_d); hipFree(t.Qu_d);
+  t.Eh_d = nullptr; t.Qu_d = nullptr;
   t.K32 = nullptr; t.K64 = nullptr; t.lpref_d = nullptr; t.epow_d = nullptr;
   t.A_d = nullptr; t.BQ_d = nullptr; t.Wd_d = nullptr; t.c_d = nullptr;
 }
@@ -328,7 +329,9 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
             up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&
             up((void **)&t.BQ_d, mBQ.data(), mBQ.size() * sizeof(double)) &&
             up((void **)&t.Wd_d, Wd.data(), Wd.size() * sizeof(double)) &&
-            up((void **)&t.c_d, cc.data(), cc.size() * sizeof(double));
+            up((void **)&t.c_d, cc.data(), cc.size() * sizeof(double)) &&
+            up((void **)&t.Eh_d, Eh.data(), Eh.size() * sizeof(double)) &&
+            up((void **)&t.Qu_d, t.Qu.data(), t.Qu.size() * sizeof(double));
   if (!ok) {
     free_tables(t);
     return set_err(ctx, HOPF_ENOMEM, "device allocation/copy of the node tables failed");

@@ -91,7 +91,7 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
     st.T[p] = S.t_max;
     st.lo[p] = 0.0;
     st.hi[p] = S.t_max;
-    st.flags[p] = FL_SETUP;
+    mark_setup(st, p);
   } else {
     const double tv = t_in[p];
     st.status[p] = HOPF_PT_OK;
@@ -99,7 +99,7 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
     st.T[p] = tv;
     st.lo[p] = tv;
     st.hi[p] = tv;
-    st.flags[p] = FL_SETUP;
+    mark_setup(st, p);
   }
 }
 
@@ -112,12 +112,10 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
 // sizes and the warm or cold start.
 constexpr int SETUP_COLS = 8;
 
-__global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o) {
-  const long p = blockIdx.x;
-  if (p >= st.npts) return;
-  if (!(st.flags[p] & FL_SETUP)) return;
+__device__ void setup_point(SysView S, PtState st, Opts o, long p) {
   __shared__ double sv[3][256 * SETUP_COLS];
   __shared__ double red[256];
+  __syncthreads();
   const int tid = threadIdx.x;
   const int n = S.n, m = S.m, np = S.n_pad;
   const double T = st.T[p];
@@ -258,6 +256,16 @@ __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o) {
+  const int nset = st.counters[1];
+  for (int li = blockIdx.x; li < nset; li += gridDim.x) {
+    const long p = st.setup_list[li];
+    setup_point(S, st, o, p);
+    __syncthreads();
+  }
+}
+
+
 // ------------------------------------------------------------------ tile formation
 
 // Active points sorted by rows (descending) so that a workgroup's 64 points
@@ -284,6 +292,7 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
     __syncthreads();
   }
   if (tid == 0) {
+    if (count_rows) st.counters[1] = 0;   // the setup list was consumed by k_setup
     int acc = 0;
     for (int b = 0; b <= N; ++b) {   // exclusive scan
       const int v = hist[b];
@@ -300,6 +309,134 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
     const int pos = atomicAdd(&hist[N - st.rows[p]], 1);
     st.perm[pos] = (int)p;
   }
+}
+
+
+// ------------------------------------------------------------------ control and trajectory read-out
+
+// v <- e^{dt A} v (or e^{dt A^T} v) for one LDS vector of length n, by the
+// binary-power table and a Taylor series for the remainder below delta.
+__device__ void exp_apply(const SysView &S, double dt, double *v, double *w, double *term, bool transpose) {
+  const int n = S.n, tid = threadIdx.x;
+  long qq = (long)floor(dt / S.delta);
+  if (qq < 0) qq = 0;
+  if (qq > (1L << POW_BITS)) qq = 1L << POW_BITS;
+  const double rho = dt - qq * S.delta;
+  for (int b = 0; b <= POW_BITS; ++b) {
+    if (!((qq >> b) & 1L)) continue;
+    const double *E = S.epow + (size_t)b * n * n;
+    for (int i = tid; i < n; i += blockDim.x) {
+      double acc = 0.0;
+      for (int l = 0; l < n; ++l) acc += (transpose ? E[(size_t)l * n + i] : E[(size_t)i * n + l]) * v[l];
+      w[i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) v[i] = w[i];
+    __syncthreads();
+  }
+  if (rho > 0.0) {
+    for (int i = tid; i < n; i += blockDim.x) term[i] = v[i];
+    __syncthreads();
+    for (int k = 1; k <= 8; ++k) {
+      for (int i = tid; i < n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int l = 0; l < n; ++l) acc += (transpose ? S.A[(size_t)l * n + i] : S.A[(size_t)i * n + l]) * term[l];
+        w[i] = acc * (rho / k);
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += blockDim.x) { term[i] = w[i]; v[i] += w[i]; }
+      __syncthreads();
+    }
+  }
+}
+
+// Point 0 of the state after a value solve at horizon T: nodes in order of
+// increasing physical time s = T - tau, the control u = Qu y^/w at each node
+// (y^: FP64 projection of the dual block onto w C), the state after each
+// node's impulse e^{tau A} B Qu y^ (so the last state is the certified x_T),
+// and p* = e^{T A^T} lam*.
+__global__ __launch_bounds__(256) void k_traj(SysView S, PtState st, double T, double *s_out, double *u_out,
+                                              double *xs_out, double *p_out, int *nn_out) {
+  __shared__ double z[256], w2[256], term[256], yh[64];
+  __shared__ double s_prev_sh;
+  const int tid = threadIdx.x, n = S.n, m = S.m, mu = S.m_user;
+  const int rows = st.rows[0], part = st.partial[0], M = st.M[0];
+  const double r = st.r[0];
+  const int nn = rows + part;
+  for (int i = tid; i < n; i += 256) z[i] = st.x0[i];
+  if (tid == 0) { *nn_out = nn; s_prev_sh = 0.0; }
+  __syncthreads();
+  for (int j = 0; j < nn; ++j) {
+    // node j: the private node (tau = T, s = 0) first, then table nodes k = rows-1 .. 0
+    const bool isp = part && j == 0;
+    const int k = isp ? -1 : rows - 1 - (j - part);
+    const double tau = isp ? T : k * S.h;
+    const double s = T - tau;
+    const double w = isp ? 0.5 * r : node_weight(k, M, r, S.h, S.quad);
+    // y^ for this node
+    if (tid < m) {
+      double v;
+      if (isp) v = st.yR[tid];
+      else v = st.y[((size_t)(k / NODE_BLOCK) * m + tid) * NODE_BLOCK + (k % NODE_BLOCK)];
+      yh[tid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double nv = 0.0;
+      for (int a = 0; a < m; ++a) nv += yh[a] * yh[a];
+      nv = sqrt(nv);
+      for (int a = 0; a < m; ++a) {
+        double v = yh[a];
+        if (S.uset == HOPF_U_L2) {
+          if (w <= 0.0 || nv == 0.0) v = 0.0;
+          else if (nv >= (1.0 - 1e-5) * w) v = v * (w / nv);
+        } else {
+          v = fmin(fmax(v, -w), w);
+          if (w > 0.0 && fabs(v) >= (1.0 - 1e-5) * w) v = copysign(w, v);
+        }
+        yh[a] = v;
+      }
+    }
+    __syncthreads();
+    // advance the state from the previous node's time to s
+    const double dt = s - s_prev_sh;
+    __syncthreads();
+    if (dt > 0.0) {
+      if (fabs(dt - S.h) <= 1e-12 * S.h) {
+        for (int i = tid; i < n; i += 256) {
+          double acc = 0.0;
+          for (int l = 0; l < n; ++l) acc += S.Eh[(size_t)i * n + l] * z[l];
+          w2[i] = acc;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) z[i] = w2[i];
+        __syncthreads();
+      } else {
+        exp_apply(S, dt, z, w2, term, false);
+      }
+    }
+    // impulse B Qu y^ (BQ holds -B Qu)
+    for (int i = tid; i < n; i += 256) {
+      double acc = 0.0;
+      for (int a = 0; a < m; ++a) acc -= S.BQ[(size_t)i * m + a] * yh[a];
+      z[i] += acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) xs_out[(size_t)j * n + i] = z[i];
+    if (tid < mu) {
+      double acc = 0.0;
+      if (w > 0.0)
+        for (int a = 0; a < mu; ++a) acc += S.Qu[(size_t)tid * mu + a] * yh[a];
+      u_out[(size_t)j * mu + tid] = w > 0.0 ? acc / w : 0.0;
+    }
+    if (tid == 0) { s_out[j] = s; s_prev_sh = s; }
+    __syncthreads();
+  }
+  // p* = e^{T A^T} lam
+  for (int i = tid; i < n; i += 256) z[i] = (double)st.lam[i];
+  __syncthreads();
+  exp_apply(S, T, z, w2, term, true);
+  for (int i = tid; i < n; i += 256) p_out[i] = z[i];
 }
 
 // ------------------------------------------------------------------ outputs
@@ -348,6 +485,54 @@ T *grow(Ctx *ctx, int idx, size_t count) {
   return reinterpret_cast<T *>(b.p);
 }
 
+// Point state in the context's reusable buffers (same layout for every call
+// with the same system sizes; row npts of lam/lamb/xfc32/y is a spare row
+// that lanes without a point read and write).
+bool make_state(Ctx *ctx, const SysTables &tab, long npts, PtState &st) {
+  const int np = tab.n_pad, m = tab.m;
+  st = PtState{};
+  st.npts = npts;
+  st.ystride = tab.nkb * m * NODE_BLOCK;
+  st.mpad = ((m + 3) / 4) * 4;
+  int bi = 0;
+  st.x0 = grow<double>(ctx, bi++, npts * np);
+  st.status = grow<int>(ctx, bi++, npts);
+  st.phase = grow<int>(ctx, bi++, npts);
+  st.flags = grow<int>(ctx, bi++, npts);
+  st.probes = grow<int>(ctx, bi++, npts);
+  st.iters_tot = grow<int>(ctx, bi++, npts);
+  st.iters_probe = grow<int>(ctx, bi++, npts);
+  st.rows = grow<int>(ctx, bi++, npts);
+  st.M = grow<int>(ctx, bi++, npts);
+  st.partial = grow<int>(ctx, bi++, npts);
+  st.last_reach = grow<int>(ctx, bi++, npts);
+  st.T = grow<double>(ctx, bi++, npts);
+  st.lo = grow<double>(ctx, bi++, npts);
+  st.hi = grow<double>(ctx, bi++, npts);
+  st.r = grow<double>(ctx, bi++, npts);
+  st.tau = grow<double>(ctx, bi++, npts);
+  st.sig = grow<double>(ctx, bi++, npts);
+  st.P = grow<double>(ctx, bi++, npts);
+  st.D = grow<double>(ctx, bi++, npts);
+  st.xf = grow<double>(ctx, bi++, npts * np);
+  st.xfc32 = grow<float>(ctx, bi++, (npts + 1) * np);
+  const bool trap = tab.desc.quad == HOPF_Q_TRAP;
+  st.R64 = grow<double>(ctx, bi++, trap ? npts * m * np : 1);
+  st.R32 = grow<float>(ctx, bi++, trap ? npts * m * np : 1);
+  st.lam = grow<float>(ctx, bi++, (npts + 1) * np);
+  st.lamb = grow<float>(ctx, bi++, (npts + 1) * np);
+  st.y = grow<float>(ctx, bi++, (size_t)(npts + 1) * st.ystride);
+  st.yR = grow<float>(ctx, bi++, npts * st.mpad);
+  st.perm = grow<int>(ctx, bi++, npts);
+  st.setup_list = grow<int>(ctx, bi++, npts);
+  st.counters = grow<int>(ctx, bi++, 4);
+  st.rowsum = grow<double>(ctx, bi++, 1);
+  return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
+         st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
+         st.sig && st.P && st.D && st.xf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
+         st.yR && st.perm && st.setup_list && st.counters && st.rowsum;
+}
+
 SysView view(const SysTables &t) {
   SysView v;
   v.n = t.n; v.m = t.m; v.N = t.N; v.n_pad = t.n_pad; v.nkb = t.nkb;
@@ -355,6 +540,7 @@ SysView view(const SysTables &t) {
   v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta;
   v.K32 = t.K32; v.K64 = t.K64; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
+  v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
   return v;
 }
 
@@ -408,43 +594,9 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   HIPCHK(hipFuncSetAttribute((const void *)fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pdhg));
   HIPCHK(hipFuncSetAttribute((const void *)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cert));
   hipStream_t s = user_stream ? user_stream : ctx->stream;
-  const int np = tab.n_pad, m = tab.m;
+  const int np = tab.n_pad;
   PtState st{};
-  st.npts = npts;
-  st.ystride = tab.nkb * m * NODE_BLOCK;
-  st.mpad = ((m + 3) / 4) * 4;
-  int bi = 0;
-  st.x0 = grow<double>(ctx, bi++, npts * np);
-  st.status = grow<int>(ctx, bi++, npts);
-  st.phase = grow<int>(ctx, bi++, npts);
-  st.flags = grow<int>(ctx, bi++, npts);
-  st.probes = grow<int>(ctx, bi++, npts);
-  st.iters_tot = grow<int>(ctx, bi++, npts);
-  st.iters_probe = grow<int>(ctx, bi++, npts);
-  st.rows = grow<int>(ctx, bi++, npts);
-  st.M = grow<int>(ctx, bi++, npts);
-  st.partial = grow<int>(ctx, bi++, npts);
-  st.last_reach = grow<int>(ctx, bi++, npts);
-  st.T = grow<double>(ctx, bi++, npts);
-  st.lo = grow<double>(ctx, bi++, npts);
-  st.hi = grow<double>(ctx, bi++, npts);
-  st.r = grow<double>(ctx, bi++, npts);
-  st.tau = grow<double>(ctx, bi++, npts);
-  st.sig = grow<double>(ctx, bi++, npts);
-  st.P = grow<double>(ctx, bi++, npts);
-  st.D = grow<double>(ctx, bi++, npts);
-  st.xf = grow<double>(ctx, bi++, npts * np);
-  st.xfc32 = grow<float>(ctx, bi++, (npts + 1) * np);
-  const bool trap = tab.desc.quad == HOPF_Q_TRAP;
-  st.R64 = grow<double>(ctx, bi++, trap ? npts * m * np : 1);
-  st.R32 = grow<float>(ctx, bi++, trap ? npts * m * np : 1);
-  st.lam = grow<float>(ctx, bi++, (npts + 1) * np);
-  st.lamb = grow<float>(ctx, bi++, (npts + 1) * np);
-  st.y = grow<float>(ctx, bi++, (size_t)(npts + 1) * st.ystride);   // row npts: spare for dead lanes
-  st.yR = grow<float>(ctx, bi++, npts * st.mpad);
-  st.perm = grow<int>(ctx, bi++, npts);
-  st.counters = grow<int>(ctx, bi++, 4);
-  st.rowsum = grow<double>(ctx, bi++, 1);
+  if (!make_state(ctx, tab, npts, st)) return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
   int *hcount = nullptr;
   if (!st.x0 || !st.status || !st.y || !st.R64 || !st.R32 || !st.perm || !st.rowsum)
     return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
@@ -459,6 +611,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   HIPCHK(hipMemsetAsync(st.rows, 0, npts * sizeof(int), s));
   HIPCHK(hipMemsetAsync(st.rowsum, 0, sizeof(double), s));
   HIPCHK(hipMemsetAsync(st.partial, 0, npts * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s));
   {
     const long tot = npts * np;
     k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, npts, tab.n, np);
@@ -470,7 +623,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   long rounds = 0;
   ctx->iter_launches = 0;
   for (;;) {
-    k_setup<<<(unsigned)npts, 256, 0, s>>>(S, st, o);
+    k_setup<<<(unsigned)std::min<long>(npts, 2048), 256, 0, s>>>(S, st, o);
     k_sort<<<1, 1024, 0, s>>>(st, tab.N, 1);
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
@@ -518,9 +671,58 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   return HOPF_OK;
 }
 
-hopf_status trajectory_dev(Ctx *ctx, int, const double *, double, int *, double *, double *, double *,
-                           double *, double *, double *) {
-  return set_err(ctx, HOPF_EUNSUPPORTED, "trajectory read-out not built yet");
+hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int *n_nodes, double *s_h,
+                           double *u_h, double *xs_h, double *p_h, double *philo, double *phihi) {
+  if (ctx->sys.empty()) return set_err(ctx, HOPF_ESTATE, "no systems set");
+  if (sid < 0 || sid >= (int)ctx->sys.size()) return set_err(ctx, HOPF_EINVAL, "sys_id out of range");
+  if (!x0_h || !n_nodes || !s_h || !u_h || !xs_h || !p_h) return set_err(ctx, HOPF_EINVAL, "null output");
+  const SysTables &tab = ctx->sys[sid];
+  if (!(T >= 0.0 && T <= tab.desc.t_max)) return set_err(ctx, HOPF_EINVAL, "T must lie in [0, t_max]");
+  const int n = tab.n, mu = tab.m_user, N = tab.N;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(x0_h[i])) return set_err(ctx, HOPF_EINVAL, "x0 is not finite");
+  double *dx = nullptr, *dt = nullptr, *dlo = nullptr, *dhi = nullptr, *dT = nullptr, *dgap = nullptr;
+  double *ds = nullptr, *du = nullptr, *dxs = nullptr, *dp = nullptr;
+  int *dsid = nullptr, *dst = nullptr, *dnn = nullptr;
+  hopf_status rc = HOPF_OK;
+  auto al = [&](void **p, size_t b) { if (rc == HOPF_OK && hipMalloc(p, b) != hipSuccess) rc = HOPF_ENOMEM; };
+  al((void **)&dx, n * sizeof(double)); al((void **)&dt, sizeof(double)); al((void **)&dlo, sizeof(double));
+  al((void **)&dhi, sizeof(double)); al((void **)&dT, sizeof(double)); al((void **)&dgap, sizeof(double));
+  al((void **)&dsid, sizeof(int)); al((void **)&dst, sizeof(int)); al((void **)&dnn, sizeof(int));
+  al((void **)&ds, (N + 1) * sizeof(double)); al((void **)&du, (size_t)(N + 1) * mu * sizeof(double));
+  al((void **)&dxs, (size_t)(N + 1) * n * sizeof(double)); al((void **)&dp, n * sizeof(double));
+  if (rc == HOPF_OK) {
+    hipMemcpy(dx, x0_h, n * sizeof(double), hipMemcpyHostToDevice);
+    hipMemcpy(dt, &T, sizeof(double), hipMemcpyHostToDevice);
+    hipMemcpy(dsid, &sid, sizeof(int), hipMemcpyHostToDevice);
+    rc = solve_dev(ctx, MODE_VALUE, 1, dsid, dx, dt, dT, dgap, dlo, dhi, nullptr, nullptr, nullptr, dst,
+                   nullptr, nullptr);
+    if (rc == HOPF_OK) {
+      PtState st{};
+      if (!make_state(ctx, tab, 1, st)) rc = set_err(ctx, HOPF_ENOMEM, "point state");
+      else {
+        k_traj<<<1, 256, 0, ctx->stream>>>(view(tab), st, T, ds, du, dxs, dp, dnn);
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess || hipGetLastError() != hipSuccess)
+          rc = set_err(ctx, HOPF_EDEVICE, "trajectory kernel failed");
+      }
+    }
+    if (rc == HOPF_OK) {
+      int nn = 0;
+      hipMemcpy(&nn, dnn, sizeof(int), hipMemcpyDeviceToHost);
+      *n_nodes = nn;
+      hipMemcpy(s_h, ds, nn * sizeof(double), hipMemcpyDeviceToHost);
+      hipMemcpy(u_h, du, (size_t)nn * mu * sizeof(double), hipMemcpyDeviceToHost);
+      hipMemcpy(xs_h, dxs, (size_t)nn * n * sizeof(double), hipMemcpyDeviceToHost);
+      hipMemcpy(p_h, dp, n * sizeof(double), hipMemcpyDeviceToHost);
+      if (philo) hipMemcpy(philo, dlo, sizeof(double), hipMemcpyDeviceToHost);
+      if (phihi) hipMemcpy(phihi, dhi, sizeof(double), hipMemcpyDeviceToHost);
+    }
+  } else {
+    set_err(ctx, rc, "device allocation failed");
+  }
+  hipFree(dx); hipFree(dt); hipFree(dlo); hipFree(dhi); hipFree(dT); hipFree(dgap); hipFree(dsid); hipFree(dst);
+  hipFree(dnn); hipFree(ds); hipFree(du); hipFree(dxs); hipFree(dp);
+  return rc;
 }
 
 }  // namespace hopf

@@ -131,7 +131,7 @@ class Solver:
         arr = (HopfSystem * len(systems))()
         keep = []
         for k, s in enumerate(systems):
-            g = (lambda key, d=None: s[key] if isinstance(s, dict) else getattr(s, key, d))
+            g = (lambda key, d=None: s.get(key, d) if isinstance(s, dict) else getattr(s, key, d))
             A, B, W = _f64(g("A")), _f64(g("B")), _f64(g("W"))
             if B.ndim == 1:
                 B = B[:, None].copy()
@@ -148,6 +148,8 @@ class Solver:
                                 _dptr(A), _dptr(B), _dptr(Qu), _dptr(W), _dptr(c))
         self._check(self.lib.hopf_set_systems(self.h, len(systems), arr), "hopf_set_systems")
         self.n = [int(arr[k].n) for k in range(len(systems))]
+        self.m = [int(arr[k].m) for k in range(len(systems))]
+        self.N = [int(arr[k].N) for k in range(len(systems))]
 
     def set_opts(self, **kw):
         o = default_opts()
@@ -194,11 +196,13 @@ class Solver:
         self._check(self.lib.hopf_min_time_dev(self.h, npts, p(sys_id), p(x), p(T), p(gap), p(lam), p(probes),
                                                p(iters), p(status), s), "hopf_min_time_dev")
 
-    def trajectory(self, x0, T, sys_id=0, N=None):
+    def trajectory(self, x0, T, sys_id=0):
+        """Control u(s) and state x(s) at the quadrature nodes (rows sorted by
+        physical time s) and the costate p* = e^{T A^T} lam*."""
         x0 = _f64(x0)
         n = x0.shape[0]
-        rows = (N or 4096) + 1
-        m = 64
+        rows = self.N[sys_id] + 1
+        m = self.m[sys_id]
         nn = C.c_int(0)
         s = np.empty(rows)
         u = np.empty((rows, m))

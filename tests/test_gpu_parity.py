@@ -153,3 +153,44 @@ def test_edge_cases(solver):
     assert math.isinf(r["T"][0]) and r["T"][1] == 0.0 and math.isnan(r["T"][2])
     empty = solver.min_time(np.zeros((0, 2)))
     assert empty["T"].shape == (0,)
+
+
+@pytest.mark.parametrize("quad,T", [("trap", 1.377), ("left", 1.9), ("trap", 1.6)])
+def test_trajectory_readout_vs_oracle(solver, quad, T):
+    """Control and trajectory read-out (Sec. IV eq. (27), Sec. V eq. (33)):
+    node times, the terminal state (= certified x_T), the control where it is
+    unique (nodes with ||K_k lam*|| not small), and p* = e^{T A^T} lam*."""
+    say("case: trajectory", quad, T)
+    spec = random_system(5, 2, 30, "l2", seed=17, t_max=3.0, quad=quad)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=1.0, gap_tol=1e-7)
+    x0 = np.array([0.4, -0.3, 0.25, 0.1, -0.2])
+    tr = solver.trajectory(x0, T)
+    S = osys(spec)
+    pr = O.solve_value(S, x0, T, O.Options(c_tau=1.0, gap_tol=1e-11, max_iter=400000))
+    s, u, xs, p = O.readout(S, x0, pr)
+    assert len(tr["s"]) == len(s)
+    np.testing.assert_allclose(tr["s"], s, atol=1e-12)
+    xT = O.terminal_state(S, pr.xf, pr.Ks, pr.y)
+    scale = max(1.0, np.abs(xT).max())
+    np.testing.assert_allclose(tr["xs"][-1], xT, atol=2e-4 * scale)
+    np.testing.assert_allclose(tr["p_star"], p, atol=2e-3 * max(1.0, np.abs(p).max()))
+    # u_k is unique where K_k lam* != 0 (the unit vector along K_k lam* for the
+    # l2 ball).  P is mu-strongly convex (mu = lambda_min(W)), so a certified
+    # gap g bounds ||lam - lam*|| <= sqrt(2 g / mu), and the direction of
+    # K_k lam moves by at most 2 ||K_k|| ||dlam|| / ||K_k lam*||; the
+    # tolerance below is that bound for both solves (x2 for the dual read-out).
+    mu = float(np.min(np.diag(spec.W)))
+    g_dev = (tr["phi_hi"] - tr["phi_lo"])
+    g_or = pr.phi_hi - pr.phi_lo
+    dlam = math.sqrt(2 * max(g_dev, 0) / mu) + math.sqrt(2 * max(g_or, 0) / mu)
+    Kl = O.apply_K(pr.Ks, pr.lam)
+    order = np.argsort(-np.asarray(pr.tau), kind="stable")
+    nKl = np.linalg.norm(Kl[order], axis=1)
+    nK = np.array([np.linalg.norm(pr.Ks[k], 2) for k in order])
+    big = nKl > 0.2 * nKl.max()
+    assert big.sum() >= 3
+    tol = 4.0 * nK[big] * dlam / nKl[big] + 5e-3
+    err = np.linalg.norm(tr["u"][big] - u[big], axis=1)
+    assert np.all(err <= tol), (err, tol)
+    assert np.all(np.linalg.norm(tr["u"], axis=1) <= 1.0 + 1e-9)
