@@ -15,6 +15,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int WAVES = 4;
 constexpr int PTS_WAVE = 16;
 constexpr int PTS_WG = WAVES * PTS_WAVE;
+constexpr int PTS_TILE = 16;       // points per workgroup in the iteration and certificate kernels
 constexpr int THREADS = WAVES * 64;
 constexpr int LDS_BYTES = 76 * 1024;
 
@@ -46,8 +47,8 @@ template <> struct V4<double> { typedef doublex4 t; };
 struct SysView {
   int n, m, N, n_pad, nkb, quad, uset, m_user;
   double t_max, h, delta;
-  const float *K32;
-  const double *K64, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
+  const float *K32, *K32T;
+  const double *K64, *K64T, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
 };
 
 struct PtState {
@@ -97,58 +98,64 @@ __device__ __forceinline__ double node_weight(int k, int M, double r, double h, 
 
 // ------------------------------------------------------------------ fused PDHG iterations
 
-// Each lane owns point column cl = lane % 16 of its wave and the register
-// layout of the 16x16x4 MFMA accumulator: rows 4*(lane/16) + {0..3}.
+// Tile = 16 points (the MFMA column dimension); the 4 waves of a workgroup
+// split the tile's node blocks (wave w takes blocks w, w+4, ...), so one
+// tile's iteration runs on all four SIMDs of a CU.  Operand A of both GEMMs
+// is read straight from L2 in two pre-swizzled copies of the node table:
+//   dual   Kd[kb][j][16 nodes][n_pad]  -> lane reads 4 consecutive state columns
+//   primal Kp[kb][j][n_pad][16 nodes]  -> lane reads 4 consecutive nodes
+// Each lane owns column cl = lane % 16 and accumulator rows acc_row(g, q).
+// The per-wave partial G is summed over the waves through LDS once per
+// iteration; every wave then applies the (cheap) prox redundantly so that
+// all of them hold sigma * lam_bar for the next dual GEMM.
 template <typename Tv, int NT, int MM>
 __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int iters) {
   typedef typename V4<Tv>::t vec4;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Tv *lds = reinterpret_cast<Tv *>(lds_raw);
-  const int wg = blockIdx.x;
+  Tv *gred = reinterpret_cast<Tv *>(lds_raw);                       // [2][WAVES][NT][4][64]
+  Tv *pscr = gred + 2 * WAVES * NT * 4 * 64;                        // partial-node scratch
+  const int tile = blockIdx.x;
   const int nact = st.counters[0];
-  if (wg * PTS_WG >= nact) return;
+  if (tile * PTS_TILE >= nact) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, g = lane >> 4;
   constexpr int m = MM;          // components (the tables are zero-padded to MM)
   constexpr int np = 16 * NT;    // padded state dimension
-  const int slot = wg * PTS_WG + wave * PTS_WAVE + cl;
+  const int slot = tile * PTS_TILE + cl;
   const bool live = slot < nact;
   const long p = live ? st.perm[slot] : -1;
-  const long pd = live ? p : st.npts;     // dead lanes read and write the spare row npts
-  const int rows_max = st.rows[st.perm[wg * PTS_WG]];
+  const long pd = live ? p : st.npts;     // lanes without a point use the spare row npts
+  const int rows_max = st.rows[st.perm[tile * PTS_TILE]];
   const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
-  // any partial node in this workgroup?
   __shared__ int any_part;
   if (threadIdx.x == 0) any_part = 0;
   __syncthreads();
-  if (live && st.partial[p]) atomicOr(&any_part, 1);
+  if (wave == 0 && g == 0 && live && st.partial[p]) atomicOr(&any_part, 1);
   __syncthreads();
   const bool wg_part = any_part != 0;
 
-  const Tv* Kg = nullptr;
-  if constexpr (sizeof(Tv) == 4) Kg = reinterpret_cast<const Tv *>(S.K32);
-  else Kg = reinterpret_cast<const Tv *>(S.K64);
-  constexpr int kstride = np + (sizeof(Tv) == 4 ? 4 : 2);   // padded LDS row (bank spread)
+  const Tv *Kd = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(S.K32) : reinterpret_cast<const Tv *>(S.K64);
+  const Tv *Kp = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(S.K32T) : reinterpret_cast<const Tv *>(S.K64T);
 
-  // per-point scalars
-  Tv tau = 0, sig = 0, hw = (Tv)S.h, rr = 0;
-  int M = -1, rowsp = 0, part = 0;
+  Tv tau = 0, sig = 0, rr = 0;
+  const Tv hw = (Tv)S.h;
+  int M = -1, rowsp = 0;
   if (live) {
     tau = (Tv)st.tau[p];
     sig = (Tv)st.sig[p];
     rr = (Tv)st.r[p];
     M = st.M[p];
     rowsp = st.rows[p];
-    part = st.partial[p];
   }
-  // sigma*lam_bar in accumulator layout (operand B of the dual GEMM); lam
-  // itself stays in memory (L2) and is read and written once per iteration
-  Tv bop[NT][4];
+  Tv lam[NT][4], bop[NT][4];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bop[t][q] = sig * (Tv)st.lamb[pd * np + 16 * t + acc_row<Tv>(g, q)];
-  float *lamp = st.lam + pd * np;
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * t + acc_row<Tv>(g, q);
+      lam[t][q] = (Tv)st.lam[pd * np + i];
+      bop[t][q] = sig * (Tv)st.lamb[pd * np + i];
+    }
   float *yp = st.y + (size_t)pd * st.ystride;
 
   for (int it = 0; it < iters; ++it) {
@@ -156,90 +163,86 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
     for (int t = 0; t < NT; ++t) G[t] = vec4{0, 0, 0, 0};
 
-    // ---- private node at tau = T (trapezoid rule, T off the grid)
+    // ---- private node at tau = T (trapezoid rule, T off the grid): wave 0
     if (wg_part) {
-      // scratch per wave: lam_bar [16][np], gr [16][np], yr [16][MM]
-      Tv *lb_s = lds + (size_t)wave * (2 * 16 * np + 16 * MM);
-      Tv *gr_s = lb_s + 16 * np;
-      Tv *yr_s = gr_s + 16 * np;
+      Tv *lb_s = pscr;                 // [16][np]
+      Tv *gr_s = lb_s + 16 * np;       // [16][np]
+      Tv *yr_s = gr_s + 16 * np;       // [16][MM]
+      if (wave == 0) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + acc_row<Tv>(g, q)] = (sig > 0 ? bop[t][q] / sig : (Tv)0);
+          for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + acc_row<Tv>(g, q)] = (sig > 0 ? bop[t][q] / sig : (Tv)0);
+      }
       __syncthreads();
-      const int pp = lane >> 2, qq = lane & 3;          // point pp of this wave, lane quarter qq
-      const int pslot = wg * PTS_WG + wave * PTS_WAVE + pp;
-      const bool plive = pslot < nact;
-      const long P2 = plive ? st.perm[pslot] : -1;
-      const bool ppart = plive && st.partial[P2];
-      Tv vj[(MM + 3) / 4];
-      Tv ssq = 0;
-      const Tv sig2 = ppart ? (Tv)st.sig[P2] : (Tv)0;
-      const Tv wR = ppart ? (Tv)(0.5 * st.r[P2]) : (Tv)0;
+      if (wave == 0) {
+        const int pp = lane >> 2, qq = lane & 3;     // point pp of the tile, lane quarter qq
+        const int pslot = tile * PTS_TILE + pp;
+        const bool plive = pslot < nact;
+        const long P2 = plive ? st.perm[pslot] : -1;
+        const bool ppart = plive && st.partial[P2];
+        const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
+        Tv vj[(MM + 3) / 4];
+        Tv ssq = 0;
+        const Tv sig2 = ppart ? (Tv)st.sig[P2] : (Tv)0;
+        const Tv wR = ppart ? (Tv)(0.5 * st.r[P2]) : (Tv)0;
 #pragma unroll
-      for (int a = 0; a < (MM + 3) / 4; ++a) {
-        const int j = qq + 4 * a;
-        Tv v = 0;
-        if (ppart && j < m) {
-          const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
-          const Tv *row = Rr + ((size_t)P2 * m + j) * np;
+        for (int a = 0; a < (MM + 3) / 4; ++a) {
+          const int j = qq + 4 * a;
+          Tv v = 0;
+          if (ppart && j < m) {
+            const Tv *row = Rr + ((size_t)P2 * m + j) * np;
+            Tv acc = 0;
+            for (int i = 0; i < np; ++i) acc += row[i] * lb_s[pp * np + i];
+            v = (Tv)st.yR[(size_t)P2 * st.mpad + j] + sig2 * acc;
+          }
+          vj[a] = v;
+          ssq += v * v;
+        }
+        if (S.uset == HOPF_U_L2) {
+          ssq += __shfl_xor(ssq, 1);
+          ssq += __shfl_xor(ssq, 2);
+          const Tv nv = sqrt(ssq);
+          const Tv sc = (nv > wR) ? (nv > 0 ? wR / nv : (Tv)0) : (Tv)1;
+#pragma unroll
+          for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] *= sc;
+        } else {
+#pragma unroll
+          for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] = fmin(fmax(vj[a], -wR), wR);
+        }
+#pragma unroll
+        for (int a = 0; a < (MM + 3) / 4; ++a) {
+          const int j = qq + 4 * a;
+          if (j < MM) yr_s[pp * MM + j] = vj[a];
+          if (ppart && j < m) st.yR[(size_t)P2 * st.mpad + j] = (float)vj[a];
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const int pp = lane >> 2, qq = lane & 3;
+        const int pslot = tile * PTS_TILE + pp;
+        const bool plive = pslot < nact;
+        const long P2 = plive ? st.perm[pslot] : -1;
+        const bool ppart = plive && st.partial[P2];
+        const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
+        for (int i = qq; i < np; i += 4) {
           Tv acc = 0;
-          for (int i = 0; i < np; ++i) acc += row[i] * lb_s[pp * np + i];
-          v = (Tv)st.yR[(size_t)P2 * st.mpad + j] + sig2 * acc;
+          if (ppart)
+            for (int j = 0; j < m; ++j) acc += Rr[((size_t)P2 * m + j) * np + i] * yr_s[pp * MM + j];
+          gr_s[pp * np + i] = acc;
         }
-        vj[a] = v;
-        ssq += v * v;
-      }
-      if (S.uset == HOPF_U_L2) {
-        ssq += __shfl_xor(ssq, 1);
-        ssq += __shfl_xor(ssq, 2);
-        const Tv nv = sqrt(ssq);
-        const Tv sc = (nv > wR) ? (nv > 0 ? wR / nv : (Tv)0) : (Tv)1;
-#pragma unroll
-        for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] *= sc;
-      } else {
-#pragma unroll
-        for (int a = 0; a < (MM + 3) / 4; ++a) vj[a] = fmin(fmax(vj[a], -wR), wR);
-      }
-#pragma unroll
-      for (int a = 0; a < (MM + 3) / 4; ++a) {
-        const int j = qq + 4 * a;
-        if (j < MM) yr_s[pp * MM + j] = vj[a];
-        if (ppart && j < m) st.yR[(size_t)P2 * st.mpad + j] = (float)vj[a];
       }
       __syncthreads();
-      // gr[pp][i] = sum_j R[j][i] yR[j]
-      for (int i = qq; i < np; i += 4) {
-        Tv acc = 0;
-        if (ppart) {
-          const Tv *Rr = (sizeof(Tv) == 4) ? reinterpret_cast<const Tv *>(st.R32) : reinterpret_cast<const Tv *>(st.R64);
-          for (int j = 0; j < m; ++j) acc += Rr[((size_t)P2 * m + j) * np + i] * yr_s[pp * MM + j];
-        }
-        gr_s[pp * np + i] = acc;
+      if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + acc_row<Tv>(g, q)];
       }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + acc_row<Tv>(g, q)];
-      __syncthreads();
     }
 
-    // ---- sweep over the node table
-    for (int kb = 0; kb < nkb; ++kb) {
-      // stage K block kb (all m components) into LDS, padded rows
-      {
-        const Tv *src = Kg + (size_t)kb * m * NODE_BLOCK * np;
-        const int nvec = m * NODE_BLOCK * np / 4;
-        for (int e = threadIdx.x; e < nvec; e += THREADS) {
-          const int rowi = e / (np / 4), c4 = e % (np / 4);
-          const vec4 v = *reinterpret_cast<const vec4 *>(src + (size_t)rowi * np + 4 * c4);
-          Tv *d = lds + (size_t)rowi * kstride + 4 * c4;
-          d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
-        }
-      }
-      __syncthreads();
-      // Y tiles
+    // ---- this wave's share of the node table
+    for (int kb = wave; kb < nkb; kb += WAVES) {
       // y is stored node-major within a block: offset kk = node % 16
       vec4 V[MM];
 #pragma unroll
@@ -253,15 +256,27 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
           for (int q = 0; q < 4; ++q) V[j][q] = (Tv)src[acc_row<Tv>(g, q)];
         }
       }
-      // dual GEMM: V_j += K_j (sigma lam_bar); consecutive MFMAs feed different V_j
+      // dual GEMM: V_j += K_j (sigma lam_bar), A = Kd[kb][j][node cl][16 t + acc_row(g, q)]
+      const Tv *kd = Kd + ((size_t)kb * m * NODE_BLOCK + cl) * np;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
+        Tv af[MM][4];
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          const Tv *a = kd + (size_t)j * NODE_BLOCK * np + 16 * t;
+          if constexpr (sizeof(Tv) == 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(a + 4 * g);
+            af[j][0] = f.x; af[j][1] = f.y; af[j][2] = f.z; af[j][3] = f.w;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) af[j][q] = a[acc_row<Tv>(g, q)];
+          }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int j = 0; j < MM; ++j)
-            V[j] = mfma(lds[(size_t)(j * NODE_BLOCK + cl) * kstride + 16 * t + acc_row<Tv>(g, q)], bop[t][q], V[j]);
-        __builtin_amdgcn_sched_barrier(0);   // keep operand loads near their MFMAs
+          for (int j = 0; j < MM; ++j) V[j] = mfma(af[j][q], bop[t][q], V[j]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       // projection onto w_k C per (node, point)
 #pragma unroll
@@ -294,39 +309,62 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
           for (int q = 0; q < 4; ++q) dst[acc_row<Tv>(g, q)] = (float)V[j][q];
         }
       }
-      // primal GEMM: G += K_j^T Y_j; consecutive MFMAs feed different G tiles
+      // primal GEMM: G += K_j^T Y_j, A = Kp[kb][j][16 t + cl][node acc_row(g, q)]
+      const Tv *kp = Kp + (size_t)kb * m * np * NODE_BLOCK;
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
+        Tv ap[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const Tv *a = kp + ((size_t)j * np + 16 * t + cl) * NODE_BLOCK;
+          if constexpr (sizeof(Tv) == 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(a + 4 * g);
+            ap[t][0] = f.x; ap[t][1] = f.y; ap[t][2] = f.z; ap[t][3] = f.w;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ap[t][q] = a[acc_row<Tv>(g, q)];
+          }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            G[t] = mfma(lds[(size_t)(j * NODE_BLOCK + acc_row<Tv>(g, q)) * kstride + 16 * t + cl], V[j][q], G[t]);
+          for (int t = 0; t < NT; ++t) G[t] = mfma(ap[t][q], V[j][q], G[t]);
         __builtin_amdgcn_sched_barrier(0);
       }
-      __syncthreads();
     }
 
-    // ---- primal prox and extrapolation
+    // ---- sum G over the waves (double-buffered LDS), then prox and extrapolation
+    Tv *gb = gred + (size_t)(it & 1) * WAVES * NT * 4 * 64;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) gb[((wave * NT + t) * 4 + q) * 64 + lane] = G[t][q];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Tv gs = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < WAVES; ++w2) gs += gb[((w2 * NT + t) * 4 + q) * 64 + lane];
+        const int i = 16 * t + acc_row<Tv>(g, q);
+        const Tv xfc = (Tv)st.xfc32[pd * np + i];
+        const Tv wd = (Tv)S.Wd[i];
+        const Tv ln = (lam[t][q] - tau * (gs - xfc)) / ((Tv)1 + tau * wd);
+        bop[t][q] = sig * ((Tv)2 * ln - lam[t][q]);
+        lam[t][q] = ln;
+      }
+  }
+  if (wave == 0) {
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 16 * t + acc_row<Tv>(g, q);
-        const Tv xfc = (Tv)st.xfc32[pd * np + i];
-        const Tv wd = (Tv)S.Wd[i];
-        const Tv l0 = (Tv)lamp[i];
-        const Tv ln = (l0 - tau * (G[t][q] - xfc)) / ((Tv)1 + tau * wd);
-        lamp[i] = (float)ln;
-        bop[t][q] = sig * ((Tv)2 * ln - l0);
+        st.lam[pd * np + i] = (float)lam[t][q];
+        st.lamb[pd * np + i] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
       }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + acc_row<Tv>(g, q)] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
-  if (live) {
-    if (g == 0) {
+    if (live && g == 0) {
       st.iters_probe[p] += iters;
       st.iters_tot[p] += iters;
     }
@@ -336,35 +374,36 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 // ------------------------------------------------------------------ FP64 certificate + decisions
 
 // Per point: P(lam) from K lam, D(y^) from K^T y^ with y^ the FP64
-// projection of the stored y onto w_k C (snapped to the boundary when within
-// 1e-5 of it; any point of w_k C gives a valid bound).  Then the sign /
-// gap decision and the bisection update (paper Sec. IV).
+// projection of the stored y onto w_k C (moved onto the boundary when within
+// 1e-5 of it; any point of w_k C gives a valid bound).  Then the sign / gap
+// decision and the bisection update (paper Sec. IV).  Same tiling as the
+// iteration kernel: 16 points per workgroup, node blocks split over waves,
+// operands from the FP64 copies of the two table layouts.
 template <int NT>
 __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts o, int mode) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double *lds = reinterpret_cast<double *>(lds_raw);
-  const int wg = blockIdx.x;
+  const int tile = blockIdx.x;
   const int nact = st.counters[0];
-  if (wg * PTS_WG >= nact) return;
+  if (tile * PTS_TILE >= nact) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, g = lane >> 4;
   const int m = S.m;
   constexpr int np = 16 * NT;
-  const int slot = wg * PTS_WG + wave * PTS_WAVE + cl;
+  const int slot = tile * PTS_TILE + cl;
   const bool live = slot < nact;
   const long p = live ? st.perm[slot] : -1;
-  const long pd = live ? p : st.npts;     // dead lanes read the spare row npts
-  const int rows_max = st.rows[st.perm[wg * PTS_WG]];
+  const long pd = live ? p : st.npts;
+  const int rows_max = st.rows[st.perm[tile * PTS_TILE]];
   const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
-  constexpr int kstride = np + 2;
-  const int chunk = max(1, min(m, (int)(LDS_BYTES / (NODE_BLOCK * kstride * 8))));
+  double *gred = reinterpret_cast<double *>(lds_raw);            // [WAVES][NT][4][64] + [WAVES][64]
+  double *sred = gred + WAVES * NT * 4 * 64;
 
   double rr = 0.0;
   int M = -1, rowsp = 0;
   if (live) { rr = st.r[p]; M = st.M[p]; rowsp = st.rows[p]; }
   const double hw = S.h;
 
-  float lam[NT][4];   // the iterates are FP32, so float holds them exactly
+  float lam[NT][4];   // the iterates are FP32, so float holds them exactly (rows 4g+q)
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -375,9 +414,8 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   double wsig = 0.0;    // sum_k w_k sigma_C(K_k lam) over this lane's rows
   const float *yp = st.y + (size_t)pd * st.ystride;
 
-  for (int kb = 0; kb < nkb; ++kb) {
-    // weights and y^ scale per (row q)
-    // w[q], ysc[q]: node 4g+q (the FP32 y layout, operand B of K^T y^);
+  for (int kb = wave; kb < nkb; kb += WAVES) {
+    // w[q], ysc[q]: node 4g+q (FP32 y layout, operand B of K^T y^);
     // wu[q], snorm[q]: node g+4q (FP64 accumulator rows of U = K lam)
     double w[4], ysc[4], snorm[4], wu[4];
 #pragma unroll
@@ -387,7 +425,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       const int ku = kb * NODE_BLOCK + acc_row<double>(g, q);
       wu[q] = (ku < rowsp) ? node_weight(ku, M, rr, hw, S.quad) : 0.0;
       snorm[q] = 0.0;
-      ysc[q] = 0.0;
+      ysc[q] = 1.0;
     }
     if (S.uset == HOPF_U_L2) {
       double s[4] = {0, 0, 0, 0};
@@ -403,62 +441,73 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
         else ysc[q] = 1.0;
       }
     }
-    for (int j0 = 0; j0 < m; j0 += chunk) {
-      const int jc = min(chunk, m - j0);
-      __syncthreads();
-      {
-        const double *src = S.K64 + ((size_t)kb * m + j0) * NODE_BLOCK * np;
-        const int nel = jc * NODE_BLOCK * np;
-        for (int e = threadIdx.x; e < nel; e += THREADS) {
-          const int rowi = e / np, c = e % np;
-          lds[(size_t)rowi * kstride + c] = src[e];
-        }
+    const double *kd = S.K64 + ((size_t)kb * m * NODE_BLOCK + cl) * np;
+    const double *kp = S.K64T + (size_t)kb * m * np * NODE_BLOCK;
+    for (int j = 0; j < m; ++j) {
+      // U = K_j lam  (16 nodes x 16 points), contraction over rows 16t + 4g + q
+      doublex4 U{0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double *a = kd + (size_t)j * NODE_BLOCK * np + 16 * t + 4 * g;
+        const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+        U = mfma(a0, (double)lam[t][0], U);
+        U = mfma(a1, (double)lam[t][1], U);
+        U = mfma(a2, (double)lam[t][2], U);
+        U = mfma(a3, (double)lam[t][3], U);
       }
-      __syncthreads();
-      for (int jj = 0; jj < jc; ++jj) {
-        const int j = j0 + jj;
-        // U = K_j lam  (16 nodes x 16 points)
-        doublex4 U{0, 0, 0, 0};
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const double *a = lds + (size_t)(jj * NODE_BLOCK + cl) * kstride + 16 * t + 4 * g;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) U = mfma(a[q], (double)lam[t][q], U);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) snorm[q] += (S.uset == HOPF_U_L2) ? U[q] * U[q] : fabs(U[q]);
-        // y^_j
-        double yh[4];
-        {
-          const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
-          const double yv[4] = {(double)f.x, (double)f.y, (double)f.z, (double)f.w};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (S.uset == HOPF_U_L2) yh[q] = yv[q] * ysc[q];
-            else {
-              double v = fmin(fmax(yv[q], -w[q]), w[q]);
-              if (w[q] > 0.0 && fabs(v) >= (1.0 - 1e-5) * w[q]) v = copysign(w[q], v);
-              yh[q] = v;
-            }
-          }
-        }
-        // G += K_j^T y^_j
+      for (int q = 0; q < 4; ++q) snorm[q] += (S.uset == HOPF_U_L2) ? U[q] * U[q] : fabs(U[q]);
+      // y^_j on nodes 4g+q
+      double yh[4];
+      {
+        const float4 f = *reinterpret_cast<const float4 *>(yp + ((size_t)(kb * m + j) * NODE_BLOCK + 4 * g));
+        const double yv[4] = {(double)f.x, (double)f.y, (double)f.z, (double)f.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double *a = lds + (size_t)(jj * NODE_BLOCK + 4 * g + q) * kstride + cl;
-#pragma unroll
-          for (int t = 0; t < NT; ++t) G[t] = mfma(a[16 * t], yh[q], G[t]);
-          __builtin_amdgcn_sched_barrier(0);
+          if (S.uset == HOPF_U_L2) yh[q] = yv[q] * ysc[q];
+          else {
+            double v = fmin(fmax(yv[q], -w[q]), w[q]);
+            if (w[q] > 0.0 && fabs(v) >= (1.0 - 1e-5) * w[q]) v = copysign(w[q], v);
+            yh[q] = v;
+          }
         }
+      }
+      // G += K_j^T y^_j, A = Kp[kb][j][16 t + cl][node 4g + q]
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double *a = kp + ((size_t)j * np + 16 * t + cl) * NODE_BLOCK + 4 * g;
+        const double a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+        G[t] = mfma(a0, yh[0], G[t]);
+        G[t] = mfma(a1, yh[1], G[t]);
+        G[t] = mfma(a2, yh[2], G[t]);
+        G[t] = mfma(a3, yh[3], G[t]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) wsig += wu[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
   }
+  // sum over the waves
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gred[((wave * NT + t) * 4 + q) * 64 + lane] = G[t][q];
+  sred[wave * 64 + lane] = wsig;
   __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double gs = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < WAVES; ++w2) gs += gred[((w2 * NT + t) * 4 + q) * 64 + lane];
+      G[t][q] = gs;
+    }
+  wsig = 0.0;
+#pragma unroll
+  for (int w2 = 0; w2 < WAVES; ++w2) wsig += sred[w2 * 64 + lane];
 
-  // per-lane partial sums over this lane's state rows i = 16 t + 4 g + q
   double sP = 0.0;   // 1/2 W lam^2 - (x_f - c) lam
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -474,16 +523,16 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       G[t][q] = (live && ig < S.n) ? xg - G[t][q] : 0.0;   // G now holds x_T
     }
 
-  // private node (trapezoid, off-grid T): sigma_C(R lam) and R^T y^_R
-  __shared__ int any_part;
-  if (threadIdx.x == 0) any_part = 0;
-  __syncthreads();
-  if (live && st.partial[p]) atomicOr(&any_part, 1);
-  __syncthreads();
+  // private node (trapezoid, off-grid T): sigma_C(R lam) and R^T y^_R, in wave 0
+  bool any_part = false;
+  {
+    const bool mine = live && st.partial[p];
+    any_part = __any(mine);
+  }
   if (any_part) {
-    // per-wave scratch: lam [16][np] (float: the iterates are FP32), R^T y^ [16][np], y^ [16][mp]
+    // scratch: lam [16][np] (float), R^T y^ [16][np], y^ [16][mp]; reuses the reduction area
     const int mp = st.mpad;
-    unsigned char *base = lds_raw + (size_t)wave * (16 * np * 4 + 16 * np * 8 + 16 * mp * 8);
+    unsigned char *base = reinterpret_cast<unsigned char *>(sred + WAVES * 64);
     float *lam_s = reinterpret_cast<float *>(base);
     double *xr_s = reinterpret_cast<double *>(base + 16 * np * 4);
     double *yr_s = xr_s + 16 * np;
@@ -491,9 +540,10 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) lam_s[cl * np + 16 * t + 4 * g + q] = lam[t][q];
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     const int pp = lane >> 2, qq = lane & 3;
-    const int pslot = wg * PTS_WG + wave * PTS_WAVE + pp;
+    const int pslot = tile * PTS_TILE + pp;
     const bool plive = pslot < nact;
     const long P2 = plive ? st.perm[pslot] : -1;
     const bool ppart = plive && st.partial[P2];
@@ -527,14 +577,16 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       }
       yr_s[pp * mp + j] = v;
     }
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     for (int i = qq; i < np; i += 4) {
       double acc = 0.0;
       if (ppart)
         for (int j = 0; j < m; ++j) acc += st.R64[((size_t)P2 * m + j) * np + i] * yr_s[pp * mp + j];
       xr_s[pp * np + i] = acc;
     }
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     // the private node's term w_R sigma_C(R lam), moved to the lane holding column pp with g = 0
     const double part_sig = wR * ((S.uset == HOPF_U_L2) ? sqrt(ssU) : ssU);
     const double ps = __shfl(part_sig, 4 * cl);

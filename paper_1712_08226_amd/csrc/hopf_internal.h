@@ -26,8 +26,10 @@ struct SysTables {
   std::vector<double> lpref;   // [N+1] upper bound of ||Phi_{0..j-1}||_2^2
   std::vector<double> epow;    // [POW_LEVELS][n][n] e^{2^b delta A}
   // device tables
-  float *K32 = nullptr;        // [nkb][m][16][n_pad]
+  float *K32 = nullptr;        // [nkb][m][16][n_pad]   dual-operand layout
   double *K64 = nullptr;       // [nkb][m][16][n_pad]
+  float *K32T = nullptr;       // [nkb][m][n_pad][16]   primal-operand layout
+  double *K64T = nullptr;      // [nkb][m][n_pad][16]
   double *lpref_d = nullptr;   // [N+1]
   double *epow_d = nullptr;    // [POW_LEVELS][n][n]
   double *A_d = nullptr;       // [n][n]

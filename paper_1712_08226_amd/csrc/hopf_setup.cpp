@@ -147,7 +147,8 @@ bool all_finite(const double *p, size_t k) {
 }  // namespace
 
 void free_tables(SysTables &t) {
-  hipFree(t.K32); hipFree(t.K64); hipFree(t.lpref_d); hipFree(t.epow_d);
+  hipFree(t.K32); hipFree(t.K64); hipFree(t.K32T); hipFree(t.K64T); hipFree(t.lpref_d); hipFree(t.epow_d);
+  t.K32T = nullptr; t.K64T = nullptr;
   hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d); hipFree(t.Eh_d); hipFree(t.Qu_d);
   t.Eh_d = nullptr; t.Qu_d = nullptr;
   t.K32 = nullptr; t.K64 = nullptr; t.lpref_d = nullptr; t.epow_d = nullptr;
@@ -300,16 +301,19 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
 
   // device copies in the kernels' layout: K[kb][j][kk][i] = Phi_{16 kb + kk}[j][i]
   const size_t kel = (size_t)t.nkb * mk * NODE_BLOCK * t.n_pad;
-  std::vector<float> K32(kel, 0.0f);
-  std::vector<double> K64(kel, 0.0);
+  std::vector<float> K32(kel, 0.0f), K32T(kel, 0.0f);
+  std::vector<double> K64(kel, 0.0), K64T(kel, 0.0);
   for (int k = 0; k < N; ++k) {
     const int kb = k / NODE_BLOCK, kk = k % NODE_BLOCK;
     for (int j = 0; j < mk; ++j)
       for (int i = 0; i < n; ++i) {
         const size_t dst = (((size_t)kb * mk + j) * NODE_BLOCK + kk) * t.n_pad + i;
+        const size_t dstT = (((size_t)kb * mk + j) * t.n_pad + i) * NODE_BLOCK + kk;
         const double v = t.phi[((size_t)k * mk + j) * n + i];
         K64[dst] = v;
         K32[dst] = (float)v;
+        K64T[dstT] = v;
+        K32T[dstT] = (float)v;
       }
   }
   std::vector<double> Wd(t.n_pad, 1.0), cc(t.n_pad, 0.0);
@@ -324,6 +328,8 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
   };
   bool ok = up((void **)&t.K32, K32.data(), kel * sizeof(float)) &&
             up((void **)&t.K64, K64.data(), kel * sizeof(double)) &&
+            up((void **)&t.K32T, K32T.data(), kel * sizeof(float)) &&
+            up((void **)&t.K64T, K64T.data(), kel * sizeof(double)) &&
             up((void **)&t.lpref_d, t.lpref.data(), t.lpref.size() * sizeof(double)) &&
             up((void **)&t.epow_d, t.epow.data(), t.epow.size() * sizeof(double)) &&
             up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&

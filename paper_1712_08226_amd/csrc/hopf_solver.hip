@@ -538,7 +538,7 @@ SysView view(const SysTables &t) {
   v.n = t.n; v.m = t.m; v.N = t.N; v.n_pad = t.n_pad; v.nkb = t.nkb;
   v.quad = t.desc.quad; v.uset = t.desc.uset;
   v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta;
-  v.K32 = t.K32; v.K64 = t.K64; v.lpref = t.lpref_d; v.epow = t.epow_d;
+  v.K32 = t.K32; v.K64 = t.K64; v.K32T = t.K32T; v.K64T = t.K64T; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
   v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
   return v;
@@ -581,16 +581,14 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   if (!fp || !fc)
     return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" + std::to_string(tab.m));
   const size_t elt = ho.prec == HOPF_FP64 ? 8 : 4;
-  const int kstride = tab.n_pad + (elt == 4 ? 4 : 2);
-  const size_t lds_k = (size_t)tab.m * NODE_BLOCK * kstride * elt;
-  const size_t lds_part = (size_t)WAVES * (2 * 16 * tab.n_pad + 16 * MMc) * elt;
-  const size_t lds_pdhg = std::max(lds_k, lds_part);
   const int mpad = ((tab.m + 3) / 4) * 4;
-  const size_t lds_cert = std::max<size_t>((size_t)NODE_BLOCK * (tab.n_pad + 2) * 8 * std::max(1, std::min(tab.m, (int)(LDS_BYTES / (NODE_BLOCK * (tab.n_pad + 2) * 8)))),
-                                           (size_t)WAVES * (16 * tab.n_pad * 4 + 16 * tab.n_pad * 8 + 16 * mpad * 8));
+  // iteration kernel: double-buffered cross-wave G sums + the private-node scratch
+  const size_t lds_pdhg = (size_t)2 * WAVES * NT * 4 * 64 * elt + (size_t)(2 * 16 * tab.n_pad + 16 * MMc) * elt;
+  // certificate: G sums, sigma sums, private-node scratch
+  const size_t lds_cert = (size_t)WAVES * NT * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 +
+                          (size_t)16 * tab.n_pad * 4 + (size_t)16 * tab.n_pad * 8 + (size_t)16 * mpad * 8;
   if (lds_pdhg > 150 * 1024 || lds_cert > 150 * 1024)
     return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
-
   HIPCHK(hipFuncSetAttribute((const void *)fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pdhg));
   HIPCHK(hipFuncSetAttribute((const void *)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cert));
   hipStream_t s = user_stream ? user_stream : ctx->stream;
@@ -619,7 +617,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   }
   const int max_probes = POW_BITS + 40;
   const long max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
-  const unsigned ngrid = (unsigned)((npts + PTS_WG - 1) / PTS_WG);
+  const unsigned ngrid = (unsigned)((npts + PTS_TILE - 1) / PTS_TILE);
   long rounds = 0;
   ctx->iter_launches = 0;
   for (;;) {
