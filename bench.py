@@ -57,8 +57,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--npts", type=int, default=65536)
     ap.add_argument("--warm", default="cold", choices=["cold", "cont"])
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle queries (0 = one per worker)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle queries, first ones of the batch (0 = one per worker, 8 workers)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the queries are independent, "
@@ -87,6 +90,13 @@ def main():
 
     def step():
         solver.min_time_dev(x, T, gap, status, probes=probes, iters=iters, stream=stream)
+
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for i in range(args.warmup):
         step()
@@ -134,7 +144,7 @@ def main():
                        "mean_probes": float(probes.cpu().numpy().mean())},
            "roofline": roofline}
     if not args.no_cpu:
-        workers = min(16, os.cpu_count() or 1)
+        workers = min(8, os.cpu_count() or 1)
         ns = args.cpu_sample or workers
         cq, cdt, res = cpu_baseline(w, ns, workers)
         out["cpu_baseline"] = {"value": round(cq, 4), "unit": "queries/s", "cores": workers, "kind": "oracle",
