@@ -59,7 +59,7 @@ typedef enum {
 typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
 typedef enum { HOPF_Q_TRAP = 0, HOPF_Q_LEFT = 1 } hopf_quad;
 typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1 } hopf_prec;
-typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1 } hopf_warm;
+typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1, HOPF_WARM_MLP = 2, HOPF_WARM_MLP_LAM = 3 } hopf_warm;
 
 /* per-point result status */
 typedef enum {
@@ -90,7 +90,14 @@ typedef struct {
  *   max_iter      iterations per solve before HOPF_PT_NOCONV                         [200000]
  *   check_every   iterations between FP64 certificates                               [25]
  *   warm          HOPF_WARM_COLD: every probe starts at lam = 0, y = 0;
- *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate [COLD]
+ *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate;
+ *                 HOPF_WARM_MLP: as CONT, and the system's trained network proposes
+ *                 the two probes after t_max (its bracket [T e^-d, T e^d]);
+ *                 HOPF_WARM_MLP_LAM: as MLP, and every probe starts from the
+ *                 network's lam_0 (y from the previous probe).  Both fall back to
+ *                 CONT where no trained network exists.  When phi(x,.) changes sign
+ *                 more than once on [0, t_max] a different probe sequence can end
+ *                 at a different certified crossing                              [COLD]
  *   prec          hopf_prec of the iterations                                        [FP32] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
@@ -149,6 +156,30 @@ hopf_status hopf_min_time_dev(hopf_ctx *ctx, long npts, const int *sys_id, const
 hopf_status hopf_trajectory(hopf_ctx *ctx, int sys_id, const double *x0, double T,
                             int *n_nodes, double *s, double *u, double *xs, double *p_star,
                             double *phi_lo, double *phi_hi);
+
+/* Learned warm start (not in the paper): per system, an MLP (x, t) -> (lam_0,
+ * log T_hat, bracket half-width) with three hidden layers of width 256 and
+ * GELU, trained on the final costates of the solver's own probes.
+ *   hopf_warm_init      (re)initialise the network of sys_id (He init, seed)
+ *   hopf_warm_params    get (set=0) or set (set=1) the flat FP32 parameter
+ *                       vector (count must equal the network's size) and
+ *                       optionally the normalisation norm = [x_mean (n),
+ *                       x_std (n), t_scale, lam_scale]; setting with norm
+ *                       marks the network as trained
+ *   hopf_warm_loss_grad loss and FP32 gradient of the current parameters on
+ *                       rows Z (nrows x (n+1)), Y (nrows x (n+2)): targets
+ *                       lam/lam_scale (n), log T*, reach flag (0/1)
+ *   hopf_warm_train     solve min-time for the npts training points x (host,
+ *                       npts x n), log every probe's (x, T, lam), then train
+ *                       `epochs` epochs of Adam (batch rows, learning rate lr);
+ *                       epoch_loss (epochs, may be NULL) gets the mean loss per
+ *                       epoch and *pairs the number of training rows */
+hopf_status hopf_warm_init(hopf_ctx *ctx, int sys_id, unsigned seed);
+hopf_status hopf_warm_params(hopf_ctx *ctx, int sys_id, int set, float *theta, long count, float *norm);
+hopf_status hopf_warm_loss_grad(hopf_ctx *ctx, int sys_id, int nrows, const float *Z, const float *Y,
+                                double *loss, float *grad);
+hopf_status hopf_warm_train(hopf_ctx *ctx, int sys_id, long npts, const double *x, int epochs, int batch,
+                            float lr, unsigned seed, double *epoch_loss, long *pairs);
 
 /* Seconds spent on the device by the last solve call (HIP events around the
  * whole call on the context's stream) and by the fused iteration kernel

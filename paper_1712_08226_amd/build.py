@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhopfpd.so")
-SOURCES = ["hopf_setup.cpp", "hopf_solver.hip"]
+SOURCES = ["hopf_setup.cpp", "hopf_solver.hip", "hopf_mlp.hip"]
 NT_INSTANCES = list(range(1, 9))     # hopf_inst.hip is compiled once per n_pad/16
 
 

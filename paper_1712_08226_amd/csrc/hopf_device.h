@@ -38,6 +38,11 @@ template <typename Tv> __device__ __forceinline__ constexpr int acc_row(int g, i
   return sizeof(Tv) == 4 ? 4 * g + q : g + 4 * q;
 }
 
+__device__ __forceinline__ float gelu_f(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float v) {
+  return 0.5f * (1.0f + erff(v * 0.70710678118654752f)) + v * expf(-0.5f * v * v) * 0.3989422804014327f;
+}
+
 template <typename Tv> struct V4;
 template <> struct V4<float> { typedef floatx4 t; };
 template <> struct V4<double> { typedef doublex4 t; };
@@ -67,7 +72,12 @@ struct PtState {
   float *yR;                 // [npts][mpad]
   int *perm;                 // [npts]
   int *setup_list;           // [npts] points waiting for a probe setup
-  int *counters;             // [0] active, [1] setup-list length
+  int *counters;             // [0] active, [1] setup-list length, [2] probe-log length
+  int *stage;                // [npts] warm-start bracket stage
+  float *bT, *bD;            // [npts] predicted minimum time and log-bracket half-width
+  int *log_pt;               // optional probe log: point, horizon, final lam of each probe
+  float *log_T, *log_lam;
+  int log_cap;
   double *rowsum;            // accumulated point-rows for flop accounting
 };
 
@@ -76,7 +86,24 @@ struct Opts {
   int max_iter, check_every, warm;
 };
 
+// Read-only view of a trained warm-start network (see hopf_mlp.hip).
+struct MlpView {
+  const float *theta, *xm, *xs;
+  float t_scale, lam_scale;
+  int n, H, valid;
+};
+
 enum { FL_SETUP = 1 };
+
+// append (point, horizon, final lam) of a finished probe to the optional log
+__device__ __forceinline__ void log_probe(const PtState &st, long p, int np) {
+  if (!st.log_pt) return;
+  const int e = atomicAdd(&st.counters[2], 1);
+  if (e >= st.log_cap) return;
+  st.log_pt[e] = (int)p;
+  st.log_T[e] = (float)st.T[p];
+  for (int i = 0; i < np; ++i) st.log_lam[(long)e * np + i] = st.lam[p * np + i];
+}
 
 // queue point p for a probe setup at its (new) horizon st.T[p]
 __device__ __forceinline__ void mark_setup(const PtState &st, long p) {
@@ -631,7 +658,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     return;
   }
   if (ph == PH_FINAL) {
-    if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; return; }
+    if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); return; }
     if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
     return;
   }
@@ -644,6 +671,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
     return;
   }
+  log_probe(st, p, np);
   const bool first = st.probes[p] == 1;
   if (outcome == 0 && first) {       // unreachable at t_max
     st.status[p] = HOPF_PT_UNREACH;
@@ -660,14 +688,29 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   if (hi - lo <= fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max)) {
     st.phase[p] = PH_FINAL;
     if (outcome == 1) {
-      if (gap <= o.gap_tol) st.phase[p] = PH_DONE;   // already certified at T = hi
+      if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); }   // already certified at T = hi
     } else {
       st.T[p] = hi;
       mark_setup(st, p);
     }
     return;
   }
-  st.T[p] = 0.5 * (lo + hi);
+  // next probe: the midpoint, or (learned warm start) the network's
+  // proposed bracket ends right after the certified probe at t_max
+  double Tn = 0.5 * (lo + hi);
+  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.bT[p] > 0.0f) {
+    const int stg = st.stage[p];
+    if (first && outcome == 1) {
+      const double hi0 = (double)st.bT[p] * exp((double)st.bD[p]);
+      if (hi0 > lo && hi0 < hi) Tn = hi0;
+      st.stage[p] = 1;
+    } else if (stg == 1) {
+      const double lo0 = (double)st.bT[p] * exp(-(double)st.bD[p]);
+      if (lo0 > lo && lo0 < hi) Tn = lo0;
+      st.stage[p] = 0;
+    }
+  }
+  st.T[p] = Tn;
   mark_setup(st, p);
 }
 

@@ -40,12 +40,31 @@ struct SysTables {
   double *Qu_d = nullptr;      // [m_user][m_user]
 };
 
+constexpr int MLP_WIDTH = 256;
+
+// Warm-start network of one system (device memory).
+struct MlpState {
+  int n = 0, H = 0;
+  size_t nparam = 0;
+  float *theta = nullptr, *m = nullptr, *v = nullptr;   // parameters and Adam moments
+  float *xm = nullptr, *xs = nullptr;                   // input normalisation
+  float t_scale = 1.0f, lam_scale = 1.0f;
+  int step = 0, valid = 0;
+};
+void mlp_free(MlpState &w);
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   hopf_opts opts{};
   std::vector<SysTables> sys;
+  std::vector<MlpState> mlp;       // one per system (optional)
   std::string err;
+  // optional probe log of the next solve (filled by the warm-start trainer)
+  int *log_pt = nullptr;
+  float *log_T = nullptr, *log_lam = nullptr;
+  long log_cap = 0;
+  long log_count = 0;
   // timing of the last solve
   double t_total = 0.0, t_iter = 0.0, point_rows = 0.0;
   long iter_launches = 0;

@@ -1,0 +1,492 @@
+// Learned warm start: a small MLP (x, t) -> (lam_0, log T_hat, bracket
+// width) trained on pairs the solver itself generates (the final costate of
+// every probe), with hand-written HIP kernels for the forward pass, the
+// backward pass and Adam.  Cold-start PDHG stays the fallback: the network only
+// proposes starting points and probe horizons; every result is still certified
+// by the FP64 duality gap.
+//
+// Network (per system, n states): z = ((x - mean)/std, t/t_max) in R^{n+1};
+// three hidden layers of width H = 256 with the exact GELU; linear output
+// [lam_hat/lam_scale (n), log T_hat, r], bracket half-width
+// delta = softplus(r) + 1e-3 in log-time.  Loss per sample:
+//   (1/n)|lam_hat - lam|^2 + reach * ((e)^2 + max(0,|e| - delta) + 0.05 delta),
+//   e = log T_hat - log T*.
+// Parameters are one flat FP32 vector [W1 (n+1,H), b1, W2, b2, W3, b3, W4 (H,n+2), b4].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "hopf_device.h"
+
+namespace hopf {
+
+constexpr float MLP_DELTA_MIN = 1e-3f;
+constexpr float MLP_ETA = 0.05f;
+
+
+// ------------------------------------------------------------------ GEMM
+
+// C (M x N) = op(A) (M x K) * op(B) (K x N) [+ bias_j], with A(i,k) at
+// A[i*ars + k*acs] and B(k,j) at B[k*brs + j*bcs] (strides express the
+// transposes of the backward pass).  64x64 tile per workgroup, K in chunks
+// of 16 through LDS, 4x4 outputs per thread, FP32 FMA.
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *__restrict__ A, long ars, long acs,
+                                              const float *__restrict__ B, long brs, long bcs, float *__restrict__ C,
+                                              long ldc, const float *__restrict__ bias) {
+  __shared__ float As[16][64 + 1];
+  __shared__ float Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int kk = e / 64, r = e % 64;
+      const int ia = i0 + r, ka = k0 + kk;
+      As[kk][r] = (ia < M && ka < K) ? A[(long)ia * ars + (long)ka * acs] : 0.0f;
+      const int jb = j0 + r;
+      Bs[kk][r] = (jb < N && ka < K) ? B[(long)ka * brs + (long)jb * bcs] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty * 4 + u]; b[u] = Bs[kk][tx * 4 + u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+      if (i < M && j < N) C[(long)i * ldc + j] = acc[u][v] + (bias ? bias[j] : 0.0f);
+    }
+}
+
+__global__ void k_gelu_fwd(const float *__restrict__ a, float *__restrict__ h, long count) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) h[i] = gelu_f(a[i]);
+}
+
+__global__ void k_gelu_bwd(float *__restrict__ g, const float *__restrict__ a, long count) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) g[i] *= gelu_grad_f(a[i]);
+}
+
+// loss and gradient with respect to the output rows
+__global__ void k_loss_grad(const float *__restrict__ out, const float *__restrict__ Y, int Bn, int n,
+                            float *__restrict__ gout, double *__restrict__ loss) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= Bn) return;
+  const int d = n + 2;
+  const float *o = out + (long)s * d;
+  const float *y = Y + (long)s * d;
+  float *go = gout + (long)s * d;
+  double ls = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const float df = o[i] - y[i];
+    ls += (double)df * df / n;
+    go[i] = 2.0f * df / ((float)n * Bn);
+  }
+  const float mk = y[n + 1];
+  const float r = o[n + 1];
+  const float delta = log1pf(expf(-fabsf(r))) + fmaxf(r, 0.0f) + MLP_DELTA_MIN;
+  const float e = o[n] - y[n];
+  const bool miss = fabsf(e) > delta;
+  ls += mk * ((double)e * e + fmax(0.0, (double)fabsf(e) - delta) + MLP_ETA * delta);
+  go[n] = mk * (2.0f * e + (miss ? (e > 0 ? 1.0f : (e < 0 ? -1.0f : 0.0f)) : 0.0f)) / Bn;
+  const float sg = 1.0f / (1.0f + expf(-r));
+  go[n + 1] = mk * ((miss ? -1.0f : 0.0f) + MLP_ETA) * sg / Bn;
+  atomicAdd(loss, ls / Bn);
+}
+
+// column sums (bias gradients): out[j] = sum_i g[i*N + j]
+__global__ void k_colsum(const float *__restrict__ g, int M, int N, float *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.0f;
+  for (int i = 0; i < M; ++i) s += g[(long)i * N + j];
+  out[j] = s;
+}
+
+__global__ void k_adam(float *__restrict__ th, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, long count, float lr, float c1, float c2) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// training rows from the probe log: Z = ((x - mean)/std, T/t_max),
+// Y = (lam/lam_scale, log T*, reach)
+__global__ void k_make_rows(const int *__restrict__ idx, int Bn, const int *__restrict__ log_pt,
+                            const float *__restrict__ log_T, const float *__restrict__ log_lam, int lstride,
+                            const double *__restrict__ xq, const double *__restrict__ Tq,
+                            const int *__restrict__ stq, int n, const float *__restrict__ xm,
+                            const float *__restrict__ xs, float t_scale, float lam_scale,
+                            float *__restrict__ Z, float *__restrict__ Y) {
+  const int s = blockIdx.x;
+  if (s >= Bn) return;
+  const int e = idx[s];
+  const int p = log_pt[e];
+  for (int i = threadIdx.x; i < n + 2; i += blockDim.x) {
+    if (i < n) {
+      Z[(long)s * (n + 1) + i] = (float)((xq[(long)p * n + i] - xm[i]) / xs[i]);
+      Y[(long)s * (n + 2) + i] = log_lam[(long)e * lstride + i] / lam_scale;
+    } else if (i == n) {
+      Z[(long)s * (n + 1) + n] = log_T[e] / t_scale;
+      const bool reach = stq[p] == HOPF_PT_OK;
+      Y[(long)s * (n + 2) + n] = reach ? (float)log(Tq[p]) : 0.0f;
+    } else {
+      Y[(long)s * (n + 2) + n + 1] = (stq[p] == HOPF_PT_OK) ? 1.0f : 0.0f;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+struct MlpBufs {
+  float *Z = nullptr, *Y = nullptr, *a1 = nullptr, *h1 = nullptr, *a2 = nullptr, *h2 = nullptr, *a3 = nullptr,
+        *h3 = nullptr, *out = nullptr, *g = nullptr, *g2 = nullptr, *grad = nullptr;
+  double *loss = nullptr;
+  int cap = 0;
+  void free_all() {
+    hipFree(Z); hipFree(Y); hipFree(a1); hipFree(h1); hipFree(a2); hipFree(h2); hipFree(a3); hipFree(h3);
+    hipFree(out); hipFree(g); hipFree(g2); hipFree(grad); hipFree(loss);
+    *this = MlpBufs();
+  }
+};
+
+size_t nparams(int n, int H) {
+  const size_t di = n + 1, dout = n + 2;
+  return di * H + H + (size_t)H * H + H + (size_t)H * H + H + (size_t)H * dout + dout;
+}
+
+void gemm(hipStream_t s, int M, int N, int K, const float *A, long ars, long acs, const float *B, long brs,
+          long bcs, float *C, long ldc, const float *bias) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, ars, acs, B, brs, bcs, C, ldc, bias);
+}
+
+bool alloc_bufs(MlpBufs &b, int Bn, int n, int H, size_t np_) {
+  if (b.cap >= Bn && b.grad) return true;
+  b.free_all();
+  auto al = [&](float **p, size_t c) { return hipMalloc(p, c * sizeof(float)) == hipSuccess; };
+  bool ok = al(&b.Z, (size_t)Bn * (n + 1)) && al(&b.Y, (size_t)Bn * (n + 2)) && al(&b.a1, (size_t)Bn * H) &&
+            al(&b.h1, (size_t)Bn * H) && al(&b.a2, (size_t)Bn * H) && al(&b.h2, (size_t)Bn * H) &&
+            al(&b.a3, (size_t)Bn * H) && al(&b.h3, (size_t)Bn * H) && al(&b.out, (size_t)Bn * (n + 2)) &&
+            al(&b.g, (size_t)Bn * std::max(H, n + 2)) && al(&b.g2, (size_t)Bn * std::max(H, n + 2)) &&
+            al(&b.grad, np_) && hipMalloc(&b.loss, sizeof(double)) == hipSuccess;
+  if (!ok) { b.free_all(); return false; }
+  b.cap = Bn;
+  return true;
+}
+
+// forward + loss + backward on rows Z, Y (device); gradient into b.grad, loss into b.loss
+void loss_grad(hipStream_t s, const float *th, MlpBufs &b, int Bn, int n, int H) {
+  const int di = n + 1, dout = n + 2;
+  const float *W1 = th, *b1 = W1 + (size_t)di * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *W3 = b2 + H,
+              *b3 = W3 + (size_t)H * H, *W4 = b3 + H, *b4 = W4 + (size_t)H * dout;
+  float *gW1 = b.grad, *gb1 = gW1 + (size_t)di * H, *gW2 = gb1 + H, *gb2 = gW2 + (size_t)H * H, *gW3 = gb2 + H,
+        *gb3 = gW3 + (size_t)H * H, *gW4 = gb3 + H, *gb4 = gW4 + (size_t)H * dout;
+  const long BH = (long)Bn * H;
+  const unsigned eb = (unsigned)((BH + 255) / 256);
+  gemm(s, Bn, H, di, b.Z, di, 1, W1, H, 1, b.a1, H, b1);
+  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a1, b.h1, BH);
+  gemm(s, Bn, H, H, b.h1, H, 1, W2, H, 1, b.a2, H, b2);
+  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a2, b.h2, BH);
+  gemm(s, Bn, H, H, b.h2, H, 1, W3, H, 1, b.a3, H, b3);
+  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a3, b.h3, BH);
+  gemm(s, Bn, dout, H, b.h3, H, 1, W4, dout, 1, b.out, dout, b4);
+  hipMemsetAsync(b.loss, 0, sizeof(double), s);
+  k_loss_grad<<<(Bn + 127) / 128, 128, 0, s>>>(b.out, b.Y, Bn, n, b.g, b.loss);   // g = dL/dout (Bn x dout)
+  // layer 4
+  gemm(s, H, dout, Bn, b.h3, 1, H, b.g, dout, 1, gW4, dout, nullptr);             // h3^T g
+  k_colsum<<<(dout + 127) / 128, 128, 0, s>>>(b.g, Bn, dout, gb4);
+  gemm(s, Bn, H, dout, b.g, dout, 1, W4, 1, dout, b.g2, H, nullptr);              // g W4^T
+  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g2, b.a3, BH);
+  // layer 3
+  gemm(s, H, H, Bn, b.h2, 1, H, b.g2, H, 1, gW3, H, nullptr);
+  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g2, Bn, H, gb3);
+  gemm(s, Bn, H, H, b.g2, H, 1, W3, 1, H, b.g, H, nullptr);
+  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g, b.a2, BH);
+  // layer 2
+  gemm(s, H, H, Bn, b.h1, 1, H, b.g, H, 1, gW2, H, nullptr);
+  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g, Bn, H, gb2);
+  gemm(s, Bn, H, H, b.g, H, 1, W2, 1, H, b.g2, H, nullptr);
+  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g2, b.a1, BH);
+  // layer 1
+  gemm(s, di, H, Bn, b.Z, 1, di, b.g2, H, 1, gW1, H, nullptr);
+  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g2, Bn, H, gb1);
+}
+
+}  // namespace
+
+void mlp_free(MlpState &w) {
+  hipFree(w.theta); hipFree(w.m); hipFree(w.v); hipFree(w.xm); hipFree(w.xs);
+  w.theta = w.m = w.v = w.xm = w.xs = nullptr;
+  w.valid = 0;
+}
+
+static hopf_status mlp_ensure(Ctx *ctx, int sid, MlpState &w) {
+  const SysTables &t = ctx->sys[sid];
+  const int n = t.n, H = MLP_WIDTH;
+  const size_t np_ = nparams(n, H);
+  if (w.theta && w.n == n && w.nparam == np_) return HOPF_OK;
+  mlp_free(w);
+  w.n = n;
+  w.H = H;
+  w.nparam = np_;
+  if (hipMalloc(&w.theta, np_ * 4) != hipSuccess || hipMalloc(&w.m, np_ * 4) != hipSuccess ||
+      hipMalloc(&w.v, np_ * 4) != hipSuccess || hipMalloc(&w.xm, n * 4) != hipSuccess ||
+      hipMalloc(&w.xs, n * 4) != hipSuccess) {
+    mlp_free(w);
+    return set_err(ctx, HOPF_ENOMEM, "warm-start network allocation failed");
+  }
+  w.t_scale = (float)t.desc.t_max;
+  w.lam_scale = 1.0f;
+  std::vector<float> one(n, 1.0f), zero(n, 0.0f);
+  hipMemcpy(w.xm, zero.data(), n * 4, hipMemcpyHostToDevice);
+  hipMemcpy(w.xs, one.data(), n * 4, hipMemcpyHostToDevice);
+  return HOPF_OK;
+}
+
+static void he_init(std::vector<float> &th, int n, int H, unsigned seed) {
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<float> nd(0.0f, 1.0f);
+  const int di = n + 1, dout = n + 2;
+  size_t o = 0;
+  auto fill = [&](int fan_in, size_t count, bool weight) {
+    const float sc = weight ? std::sqrt(2.0f / fan_in) : 0.0f;
+    for (size_t i = 0; i < count; ++i) th[o++] = weight ? sc * nd(rng) : 0.0f;
+  };
+  fill(di, (size_t)di * H, true); fill(di, H, false);
+  fill(H, (size_t)H * H, true); fill(H, H, false);
+  fill(H, (size_t)H * H, true); fill(H, H, false);
+  fill(H, (size_t)H * dout, true); fill(H, dout, false);
+  // the output layer starts small so that early predictions are near the bias
+  o = (size_t)di * H + H + 2 * ((size_t)H * H + H);
+  for (size_t i = 0; i < (size_t)H * dout; ++i) th[o + i] *= 0.1f;
+}
+
+__global__ void k_sumsq_rows(const float *__restrict__ a, long rows, int n, int stride, double *__restrict__ out) {
+  long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double v = a[r * stride + i];
+    s += v * v;
+  }
+  atomicAdd(out, s);
+}
+
+}  // namespace hopf
+
+using hopf::Ctx;
+using hopf::set_err;
+
+extern "C" {
+
+hopf_status hopf_warm_init(hopf_ctx *h, int sys_id, unsigned seed) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->sys.size()) return set_err(c, HOPF_EINVAL, "sys_id out of range");
+  hipSetDevice(c->device);
+  if ((int)c->mlp.size() < (int)c->sys.size()) c->mlp.resize(c->sys.size());
+  hopf::MlpState &w = c->mlp[sys_id];
+  hopf_status st = hopf::mlp_ensure(c, sys_id, w);
+  if (st != HOPF_OK) return st;
+  std::vector<float> th(w.nparam);
+  hopf::he_init(th, w.n, w.H, seed);
+  hipMemcpy(w.theta, th.data(), w.nparam * 4, hipMemcpyHostToDevice);
+  hipMemset(w.m, 0, w.nparam * 4);
+  hipMemset(w.v, 0, w.nparam * 4);
+  w.step = 0;
+  w.valid = 0;
+  return HOPF_OK;
+}
+
+hopf_status hopf_warm_params(hopf_ctx *h, int sys_id, int set, float *theta, long count, float *norm) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !theta) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->mlp.size() || !c->mlp[sys_id].theta)
+    return set_err(c, HOPF_ESTATE, "no warm-start network for this system (call hopf_warm_init)");
+  hopf::MlpState &w = c->mlp[sys_id];
+  if (count != (long)w.nparam) return set_err(c, HOPF_EINVAL, "parameter count mismatch");
+  hipSetDevice(c->device);
+  const int n = w.n;
+  if (set) {
+    hipMemcpy(w.theta, theta, w.nparam * 4, hipMemcpyHostToDevice);
+    if (norm) {   // norm = [x_mean (n), x_std (n), t_scale, lam_scale]
+      hipMemcpy(w.xm, norm, n * 4, hipMemcpyHostToDevice);
+      hipMemcpy(w.xs, norm + n, n * 4, hipMemcpyHostToDevice);
+      w.t_scale = norm[2 * n];
+      w.lam_scale = norm[2 * n + 1];
+      w.valid = 1;
+    }
+  } else {
+    hipMemcpy(theta, w.theta, w.nparam * 4, hipMemcpyDeviceToHost);
+    if (norm) {
+      hipMemcpy(norm, w.xm, n * 4, hipMemcpyDeviceToHost);
+      hipMemcpy(norm + n, w.xs, n * 4, hipMemcpyDeviceToHost);
+      norm[2 * n] = w.t_scale;
+      norm[2 * n + 1] = w.lam_scale;
+    }
+  }
+  return HOPF_OK;
+}
+
+hopf_status hopf_warm_loss_grad(hopf_ctx *h, int sys_id, int nrows, const float *Z, const float *Y, double *loss,
+                                float *grad) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !Z || !Y || !loss || !grad || nrows < 1) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->mlp.size() || !c->mlp[sys_id].theta)
+    return set_err(c, HOPF_ESTATE, "no warm-start network for this system (call hopf_warm_init)");
+  hopf::MlpState &w = c->mlp[sys_id];
+  hipSetDevice(c->device);
+  hopf::MlpBufs b;
+  if (!hopf::alloc_bufs(b, nrows, w.n, w.H, w.nparam)) return set_err(c, HOPF_ENOMEM, "MLP buffers");
+  hipMemcpy(b.Z, Z, (size_t)nrows * (w.n + 1) * 4, hipMemcpyHostToDevice);
+  hipMemcpy(b.Y, Y, (size_t)nrows * (w.n + 2) * 4, hipMemcpyHostToDevice);
+  hopf::loss_grad(c->stream, w.theta, b, nrows, w.n, w.H);
+  hipStreamSynchronize(c->stream);
+  hipMemcpy(loss, b.loss, sizeof(double), hipMemcpyDeviceToHost);
+  hipMemcpy(grad, b.grad, w.nparam * 4, hipMemcpyDeviceToHost);
+  hipError_t e = hipGetLastError();
+  b.free_all();
+  if (e != hipSuccess) return set_err(c, HOPF_EDEVICE, hipGetErrorString(e));
+  return HOPF_OK;
+}
+
+hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x, int epochs, int batch, float lr,
+                            unsigned seed, double *epoch_loss, long *pairs) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !x || npts < 1 || epochs < 0 || batch < 1 || !(lr > 0.0f)) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->sys.size()) return set_err(c, HOPF_EINVAL, "sys_id out of range");
+  hipSetDevice(c->device);
+  if ((int)c->mlp.size() < (int)c->sys.size()) c->mlp.resize(c->sys.size());
+  hopf::MlpState &w = c->mlp[sys_id];
+  if (!w.theta) {
+    hopf_status st = hopf_warm_init(h, sys_id, seed);
+    if (st != HOPF_OK) return st;
+  }
+  const hopf::SysTables &tab = c->sys[sys_id];
+  const int n = tab.n, np = tab.n_pad;
+  // input normalisation from the training points
+  std::vector<float> xm(n, 0.0f), xs(n, 1.0f);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0, s2 = 0.0;
+    for (long p = 0; p < npts; ++p) { const double v = x[p * n + i]; s += v; s2 += v * v; }
+    const double mu = s / npts, var = std::max(s2 / npts - mu * mu, 1e-24);
+    xm[i] = (float)mu;
+    xs[i] = (float)std::sqrt(var);
+  }
+  hipMemcpy(w.xm, xm.data(), n * 4, hipMemcpyHostToDevice);
+  hipMemcpy(w.xs, xs.data(), n * 4, hipMemcpyHostToDevice);
+  w.t_scale = (float)tab.desc.t_max;
+  // 1. solve the training points with the probe log on
+  const long cap = npts * 48;
+  double *dx = nullptr, *dT = nullptr, *dgap = nullptr;
+  int *dst = nullptr, *dsid = nullptr;
+  hopf_status rc = HOPF_OK;
+  auto al = [&](void **p, size_t b) { if (rc == HOPF_OK && hipMalloc(p, b) != hipSuccess) rc = HOPF_ENOMEM; };
+  al((void **)&dx, (size_t)npts * n * 8);
+  al((void **)&dT, npts * 8);
+  al((void **)&dgap, npts * 8);
+  al((void **)&dst, npts * 4);
+  al((void **)&c->log_pt, cap * 4);
+  al((void **)&c->log_T, cap * 4);
+  al((void **)&c->log_lam, (size_t)cap * np * 4);
+  if (sys_id != 0) al((void **)&dsid, npts * 4);
+  hopf::MlpBufs b;
+  int *didx = nullptr;
+  double *dss = nullptr;
+  if (rc == HOPF_OK) {
+    c->log_cap = cap;
+    c->log_count = 0;
+    hipMemcpy(dx, x, (size_t)npts * n * 8, hipMemcpyHostToDevice);
+    if (dsid) {
+      std::vector<int> ids(npts, sys_id);
+      hipMemcpy(dsid, ids.data(), npts * 4, hipMemcpyHostToDevice);
+    }
+    rc = hopf::solve_dev(c, 1, npts, dsid, dx, nullptr, dT, dgap, nullptr, nullptr, nullptr, nullptr, nullptr, dst,
+                         nullptr, nullptr);
+  }
+  const long rows = c->log_count;
+  if (pairs) *pairs = rows;
+  if (rc == HOPF_OK && rows < 1) rc = set_err(c, HOPF_ESTATE, "the training solve logged no probes");
+  // 2. costate scale
+  if (rc == HOPF_OK) {
+    al((void **)&dss, 8);
+    if (rc == HOPF_OK) {
+      hipMemset(dss, 0, 8);
+      hopf::k_sumsq_rows<<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(c->log_lam, rows, n, np, dss);
+      double ss = 0.0;
+      hipStreamSynchronize(c->stream);
+      hipMemcpy(&ss, dss, 8, hipMemcpyDeviceToHost);
+      w.lam_scale = (float)std::max(std::sqrt(ss / ((double)rows * n)), 1e-12);
+    }
+  }
+  // 3. Adam epochs over shuffled rows
+  if (rc == HOPF_OK) {
+    const int Bn = (int)std::min<long>(batch, rows);
+    if (!hopf::alloc_bufs(b, Bn, n, w.H, w.nparam)) rc = set_err(c, HOPF_ENOMEM, "MLP buffers");
+    al((void **)&didx, rows * 4);
+  }
+  if (rc == HOPF_OK) {
+    std::vector<int> order(rows);
+    for (long i = 0; i < rows; ++i) order[i] = (int)i;
+    std::mt19937_64 rng(seed ^ 0x9e3779b97f4a7c15ULL);
+    const int Bn = b.cap;
+    for (int ep = 0; ep < epochs; ++ep) {
+      std::shuffle(order.begin(), order.end(), rng);
+      hipMemcpy(didx, order.data(), rows * 4, hipMemcpyHostToDevice);
+      double tot = 0.0;
+      long seen = 0;
+      for (long s0 = 0; s0 + Bn <= rows || (s0 == 0 && rows < Bn); s0 += Bn) {
+        const int nb = (int)std::min<long>(Bn, rows - s0);
+        hopf::k_make_rows<<<nb, 128, 0, c->stream>>>(didx + s0, nb, c->log_pt, c->log_T, c->log_lam, np, dx, dT, dst,
+                                                     n, w.xm, w.xs, w.t_scale, w.lam_scale, b.Z, b.Y);
+        hopf::loss_grad(c->stream, w.theta, b, nb, n, w.H);
+        w.step += 1;
+        const float c1 = 1.0f - std::pow(0.9f, (float)w.step), c2 = 1.0f - std::pow(0.999f, (float)w.step);
+        hopf::k_adam<<<(unsigned)((w.nparam + 255) / 256), 256, 0, c->stream>>>(w.theta, b.grad, w.m, w.v,
+                                                                                 (long)w.nparam, lr, c1, c2);
+        double l = 0.0;
+        hipMemcpyAsync(&l, b.loss, 8, hipMemcpyDeviceToHost, c->stream);
+        hipStreamSynchronize(c->stream);
+        tot += l * nb;
+        seen += nb;
+      }
+      if (epoch_loss) epoch_loss[ep] = seen ? tot / seen : 0.0;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = set_err(c, HOPF_EDEVICE, hipGetErrorString(e));
+    else w.valid = 1;
+  }
+  b.free_all();
+  hipFree(didx); hipFree(dss); hipFree(dx); hipFree(dT); hipFree(dgap); hipFree(dst); hipFree(dsid);
+  hipFree(c->log_pt); hipFree(c->log_T); hipFree(c->log_lam);
+  c->log_pt = nullptr; c->log_T = nullptr; c->log_lam = nullptr;
+  c->log_cap = 0;
+  if (rc != HOPF_OK && c->err.empty()) c->err = "warm-start training failed";
+  return rc;
+}
+
+}  // extern "C"

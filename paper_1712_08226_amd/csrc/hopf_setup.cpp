@@ -401,6 +401,7 @@ void hopf_destroy(hopf_ctx *h) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (auto &t : c->sys) hopf::free_tables(t);
+  for (auto &w : c->mlp) hopf::mlp_free(w);
   for (auto &b : c->bufs) hipFree(b.p);
   hipStreamDestroy(c->stream);
   delete c;
@@ -415,7 +416,7 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
-      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 1 || o->prec < 0 || o->prec > 1)
+      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 1)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;
@@ -428,6 +429,8 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
   if (hipSetDevice(c->device) != hipSuccess) return set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
   hipStreamSynchronize(c->stream);
   for (auto &t : c->sys) hopf::free_tables(t);
+  for (auto &w : c->mlp) hopf::mlp_free(w);
+  c->mlp.clear();
   c->sys.clear();
   std::vector<hopf::SysTables> tabs(nsys);
   for (int i = 0; i < nsys; ++i) {

@@ -112,7 +112,7 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
 // sizes and the warm or cold start.
 constexpr int SETUP_COLS = 8;
 
-__device__ void setup_point(SysView S, PtState st, Opts o, long p) {
+__device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
   __shared__ double sv[3][256 * SETUP_COLS];
   __shared__ double red[256];
   __syncthreads();
@@ -219,7 +219,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, long p) {
   }
   // cold or warm start
   const int old_rows = st.rows[p];
-  const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);
+  const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);   // CONT and MLP keep y
   const int nkb_new = (rows + NODE_BLOCK - 1) / NODE_BLOCK;
   if (cold) {
     for (int i = tid; i < np; i += 256) {
@@ -236,6 +236,54 @@ __device__ void setup_point(SysView S, PtState st, Opts o, long p) {
     }
   }
   for (int j = tid; j < st.mpad; j += 256) st.yR[(size_t)p * st.mpad + j] = 0.0f;
+  // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
+  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && mv.valid && mv.n == n && mv.H == 256) {
+    __shared__ float zin[260], ha[256], hb[256], outv[260];
+    const int di = n + 1, dout = n + 2, H = 256;
+    __syncthreads();
+    for (int i = tid; i < di; i += 256)
+      zin[i] = (i < n) ? (float)((st.x0[p * np + i] - mv.xm[i]) / mv.xs[i]) : (float)(T / mv.t_scale);
+    __syncthreads();
+    const float *W1 = mv.theta, *b1 = W1 + (size_t)di * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H,
+                *W3 = b2 + H, *b3 = W3 + (size_t)H * H, *W4 = b3 + H, *b4 = W4 + (size_t)H * dout;
+    {
+      float a = b1[tid];
+      for (int i = 0; i < di; ++i) a += zin[i] * W1[(size_t)i * H + tid];
+      ha[tid] = gelu_f(a);
+    }
+    __syncthreads();
+    {
+      float a = b2[tid];
+      for (int i = 0; i < H; ++i) a += ha[i] * W2[(size_t)i * H + tid];
+      hb[tid] = gelu_f(a);
+    }
+    __syncthreads();
+    {
+      float a = b3[tid];
+      for (int i = 0; i < H; ++i) a += hb[i] * W3[(size_t)i * H + tid];
+      ha[tid] = gelu_f(a);
+    }
+    __syncthreads();
+    for (int k = tid; k < dout; k += 256) {
+      float a = b4[k];
+      for (int i = 0; i < H; ++i) a += ha[i] * W4[(size_t)i * dout + k];
+      outv[k] = a;
+    }
+    __syncthreads();
+    if (o.warm == HOPF_WARM_MLP_LAM) {
+      for (int i = tid; i < np; i += 256) {
+        const float l = i < n ? outv[i] * mv.lam_scale : 0.0f;
+        st.lam[p * np + i] = l;
+        st.lamb[p * np + i] = l;
+      }
+    }
+    if (tid == 0 && st.probes[p] == 0) {
+      const float r2 = outv[n + 1];
+      st.bT[p] = expf(outv[n]);
+      st.bD[p] = log1pf(expf(-fabsf(r2))) + fmaxf(r2, 0.0f) + 1e-3f;
+    }
+    __syncthreads();
+  }
   if (tid == 0) {
     double L2 = S.lpref[rows] + (part ? Rfro : 0.0);
     const double L = sqrt(L2);
@@ -256,11 +304,11 @@ __device__ void setup_point(SysView S, PtState st, Opts o, long p) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o) {
+__global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, MlpView mv) {
   const int nset = st.counters[1];
   for (int li = blockIdx.x; li < nset; li += gridDim.x) {
     const long p = st.setup_list[li];
-    setup_point(S, st, o, p);
+    setup_point(S, st, o, mv, p);
     __syncthreads();
   }
 }
@@ -525,12 +573,19 @@ bool make_state(Ctx *ctx, const SysTables &tab, long npts, PtState &st) {
   st.yR = grow<float>(ctx, bi++, npts * st.mpad);
   st.perm = grow<int>(ctx, bi++, npts);
   st.setup_list = grow<int>(ctx, bi++, npts);
+  st.stage = grow<int>(ctx, bi++, npts);
+  st.bT = grow<float>(ctx, bi++, npts);
+  st.bD = grow<float>(ctx, bi++, npts);
+  st.log_pt = ctx->log_pt;
+  st.log_T = ctx->log_T;
+  st.log_lam = ctx->log_lam;
+  st.log_cap = (int)std::min<long>(ctx->log_cap, 2000000000L);
   st.counters = grow<int>(ctx, bi++, 4);
   st.rowsum = grow<double>(ctx, bi++, 1);
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
          st.sig && st.P && st.D && st.xf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
-         st.yR && st.perm && st.setup_list && st.counters && st.rowsum;
+         st.yR && st.perm && st.setup_list && st.stage && st.bT && st.bD && st.counters && st.rowsum;
 }
 
 SysView view(const SysTables &t) {
@@ -610,6 +665,15 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   HIPCHK(hipMemsetAsync(st.rowsum, 0, sizeof(double), s));
   HIPCHK(hipMemsetAsync(st.partial, 0, npts * sizeof(int), s));
   HIPCHK(hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(st.stage, 0, npts * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(st.bT, 0, npts * sizeof(float), s));
+  HIPCHK(hipMemsetAsync(st.bD, 0, npts * sizeof(float), s));
+  MlpView mv{};
+  if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM) && sid < (int)ctx->mlp.size() &&
+      ctx->mlp[sid].valid) {
+    const MlpState &w = ctx->mlp[sid];
+    mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
+  }
   {
     const long tot = npts * np;
     k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, npts, tab.n, np);
@@ -621,7 +685,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   long rounds = 0;
   ctx->iter_launches = 0;
   for (;;) {
-    k_setup<<<(unsigned)std::min<long>(npts, 2048), 256, 0, s>>>(S, st, o);
+    k_setup<<<(unsigned)std::min<long>(npts, 2048), 256, 0, s>>>(S, st, o, mv);
     k_sort<<<1, 1024, 0, s>>>(st, tab.N, 1);
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
@@ -662,6 +726,11 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   HIPCHK(hipMemcpy(&rs, st.rowsum, sizeof(double), hipMemcpyDeviceToHost));
   // point-rows summed once per round; each round runs check_every iterations
   ctx->point_rows = rs * ho.check_every;
+  if (ctx->log_pt) {
+    int lc = 0;
+    HIPCHK(hipMemcpy(&lc, st.counters + 2, sizeof(int), hipMemcpyDeviceToHost));
+    ctx->log_count = std::min<long>(lc, ctx->log_cap);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipHostFree(hcount);

@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(HERE, "libhopfpd.so")
 U_L2, U_BOX = 0, 1
 Q_TRAP, Q_LEFT = 0, 1
 FP64, FP32 = 0, 1
-WARM_COLD, WARM_CONT = 0, 1
+WARM_COLD, WARM_CONT, WARM_MLP, WARM_MLP_LAM = 0, 1, 2, 3
 PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
 EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", "hopf_last_error",
            "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_min_time", "hopf_min_time_dev",
-           "hopf_trajectory", "hopf_last_timing"]
+           "hopf_trajectory", "hopf_last_timing", "hopf_warm_init", "hopf_warm_params",
+           "hopf_warm_loss_grad", "hopf_warm_train"]
 
 
 class HopfSystem(C.Structure):
@@ -71,6 +72,12 @@ def load(path: str = LIB_PATH):
     lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
     lib.hopf_last_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_long), dp]
+    fp = C.POINTER(C.c_float)
+    lib.hopf_warm_init.argtypes = [vp, C.c_int, C.c_uint]
+    lib.hopf_warm_params.argtypes = [vp, C.c_int, C.c_int, fp, C.c_long, fp]
+    lib.hopf_warm_loss_grad.argtypes = [vp, C.c_int, C.c_int, fp, fp, dp, fp]
+    lib.hopf_warm_train.argtypes = [vp, C.c_int, C.c_long, dp, C.c_int, C.c_int, C.c_float, C.c_uint, dp,
+                                    C.POINTER(C.c_long)]
     for name in EXPORTS:
         if name not in ("hopf_destroy", "hopf_strerror", "hopf_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -157,7 +164,7 @@ class Solver:
             if k == "prec":
                 v = {"fp64": FP64, "fp32": FP32}.get(v, v)
             if k == "warm":
-                v = {"cold": WARM_COLD, "cont": WARM_CONT}.get(v, v)
+                v = {"cold": WARM_COLD, "cont": WARM_CONT, "mlp": WARM_MLP, "mlp_lam": WARM_MLP_LAM}.get(v, v)
             setattr(o, k, v)
         self._check(self.lib.hopf_set_opts(self.h, C.byref(o)), "hopf_set_opts")
 
@@ -213,6 +220,48 @@ class Solver:
                                              _dptr(xs), _dptr(p), C.byref(lo), C.byref(hi)), "hopf_trajectory")
         k = nn.value
         return dict(s=s[:k], u=u[:k], xs=xs[:k], p_star=p, phi_lo=lo.value, phi_hi=hi.value)
+
+    # -------------------------------------------------------------- learned warm start
+    def warm_nparams(self, sys_id=0, H=256):
+        n = self.n[sys_id]
+        return (n + 1) * H + H + 2 * (H * H + H) + H * (n + 2) + (n + 2)
+
+    def warm_init(self, sys_id=0, seed=0):
+        self._check(self.lib.hopf_warm_init(self.h, sys_id, seed), "hopf_warm_init")
+
+    def warm_get(self, sys_id=0):
+        """Returns (theta, norm) with norm = [x_mean, x_std, t_scale, lam_scale]."""
+        th = np.empty(self.warm_nparams(sys_id), dtype=np.float32)
+        norm = np.empty(2 * self.n[sys_id] + 2, dtype=np.float32)
+        self._check(self.lib.hopf_warm_params(self.h, sys_id, 0, th.ctypes.data_as(C.POINTER(C.c_float)), th.size,
+                                              norm.ctypes.data_as(C.POINTER(C.c_float))), "hopf_warm_params")
+        return th, norm
+
+    def warm_set(self, theta, norm=None, sys_id=0):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        self._check(self.lib.hopf_warm_params(self.h, sys_id, 1, th.ctypes.data_as(C.POINTER(C.c_float)), th.size,
+                                              None if nm is None else nm.ctypes.data_as(C.POINTER(C.c_float))),
+                    "hopf_warm_params")
+
+    def warm_loss_grad(self, Z, Y, sys_id=0):
+        Z = np.ascontiguousarray(Z, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        g = np.empty(self.warm_nparams(sys_id), dtype=np.float32)
+        loss = C.c_double()
+        fp = C.POINTER(C.c_float)
+        self._check(self.lib.hopf_warm_loss_grad(self.h, sys_id, Z.shape[0], Z.ctypes.data_as(fp),
+                                                 Y.ctypes.data_as(fp), C.byref(loss), g.ctypes.data_as(fp)),
+                    "hopf_warm_loss_grad")
+        return loss.value, g
+
+    def warm_train(self, x, epochs=20, batch=4096, lr=1e-3, seed=0, sys_id=0):
+        x = _f64(x)
+        el = np.zeros(max(epochs, 1))
+        pairs = C.c_long()
+        self._check(self.lib.hopf_warm_train(self.h, sys_id, x.shape[0], _dptr(x), epochs, batch, lr, seed,
+                                             _dptr(el), C.byref(pairs)), "hopf_warm_train")
+        return dict(epoch_loss=el[:epochs], pairs=pairs.value)
 
     def last_timing(self):
         a, b, d = C.c_double(), C.c_double(), C.c_double()

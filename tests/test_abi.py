@@ -20,7 +20,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     lib = H.load()
     decl = declared_symbols()
-    assert len(decl) >= 12
+    assert len(decl) >= 16
     for name in decl:
         assert hasattr(lib, name), name
     assert set(decl) == set(H.EXPORTS)
