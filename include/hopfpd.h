@@ -22,9 +22,12 @@
  * paper's N-sample layout.
  *
  * Precision.  Tables and matrix exponentials are built in FP64; the
- * iterations run in FP64 (HOPF_FP64) or FP32 (HOPF_FP32) on MFMA; every
+ * iterations run in FP64 (HOPF_FP64), FP32 (HOPF_FP32) or with K and the
+ * iterates split into bf16 hi + lo pairs, three bf16 MFMAs per product and
+ * FP32 accumulation (HOPF_BF16X3); every
  * reported value, gap and sign decision is certified in FP64 from a primal
- * point lam and a dual-feasible point y:  -P(lam) <= phi <= -D(y).
+ * point lam and a dual-feasible point y:  -min(P(lam), 1/2) <= phi <= -D(y)
+ * (P(0) = 1/2 because the terminal cost is at least -1/2).
  *
  * Conventions for every call:
  *   - arrays are row-major, float64 unless stated, owned by the caller;
@@ -58,7 +61,7 @@ typedef enum {
 
 typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
 typedef enum { HOPF_Q_TRAP = 0, HOPF_Q_LEFT = 1 } hopf_quad;
-typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1 } hopf_prec;
+typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1, HOPF_BF16X3 = 2 } hopf_prec;
 typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1, HOPF_WARM_MLP = 2, HOPF_WARM_MLP_LAM = 3 } hopf_warm;
 
 /* per-point result status */
@@ -98,7 +101,9 @@ typedef struct {
  *                 CONT where no trained network exists.  When phi(x,.) changes sign
  *                 more than once on [0, t_max] a different probe sequence can end
  *                 at a different certified crossing                              [COLD]
- *   prec          hopf_prec of the iterations                                        [FP32] */
+ *   prec          hopf_prec of the iterations; with HOPF_BF16X3 a probe that is not
+ *                 certified after 4000 iterations continues in FP32 (its iterates
+ *                 carry over unchanged)                                              [FP32] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;

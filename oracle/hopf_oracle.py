@@ -324,8 +324,11 @@ def pdhg_iteration(sys: System, pr: Probe):
 
 
 def certify(sys: System, pr: Probe):
-    """Primal value P(lam), dual value D(y) and the certified interval."""
-    pr.P = primal_obj(sys, pr.xf, pr.Ks, pr.w, pr.lam)
+    """Primal value P(lam), dual value D(y) and the certified interval.  The
+    primal bound takes the better of the iterate and lam = 0: P(0) = J*(0)
+    = 1/2 = -min J (the terminal cost of Sec. IV is at least -1/2), which
+    certifies phi >= -1/2 exactly when the target's centre is reachable."""
+    pr.P = min(primal_obj(sys, pr.xf, pr.Ks, pr.w, pr.lam), 0.5)
     pr.D = dual_obj(sys, pr.xf, pr.Ks, pr.y)
     pr.history.append((pr.iters, pr.P, pr.D))
 

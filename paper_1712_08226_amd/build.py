@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhopfpd.so")
 SOURCES = ["hopf_setup.cpp", "hopf_solver.hip", "hopf_mlp.hip"]
-NT_INSTANCES = list(range(1, 9))     # hopf_inst.hip is compiled once per n_pad/16
+NT_INSTANCES = list(range(1, 17))    # hopf_inst.hip is compiled once per n_pad/16
 
 
 def hipcc():

@@ -53,6 +53,7 @@ struct SysView {
   int n, m, N, n_pad, nkb, quad, uset, m_user;
   double t_max, h, delta;
   const float *K32, *K32T;
+  const __bf16 *Kd16h, *Kd16l, *Kp16h, *Kp16l;     // BF16 hi/lo copies (dual and primal layouts)
   const double *K64, *K64T, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
 };
 
@@ -74,6 +75,7 @@ struct PtState {
   int *setup_list;           // [npts] points waiting for a probe setup
   int *counters;             // [0] active, [1] setup-list length, [2] probe-log length
   int *stage;                // [npts] warm-start bracket stage
+  int *esc;                  // [npts] 1: iterate in FP32 (escalated from BF16 hi+lo)
   float *bT, *bD;            // [npts] predicted minimum time and log-bracket half-width
   int *log_pt;               // optional probe log: point, horizon, final lam of each probe
   float *log_T, *log_lam;
@@ -83,8 +85,15 @@ struct PtState {
 
 struct Opts {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
-  int max_iter, check_every, warm;
+  int max_iter, check_every, warm, prec, esc_iters;
 };
+
+// point range of one iteration launch: 0 = FP32-escalated points
+// [0, counters[3]), 1 = the others [counters[3], counters[0]), 2 = all
+__device__ __forceinline__ void launch_range(const PtState &st, int part, int &beg, int &end) {
+  beg = part == 1 ? st.counters[3] : 0;
+  end = part == 0 ? st.counters[3] : st.counters[0];
+}
 
 // Read-only view of a trained warm-start network (see hopf_mlp.hip).
 struct MlpView {
@@ -136,23 +145,24 @@ __device__ __forceinline__ double node_weight(int k, int M, double r, double h, 
 // iteration; every wave then applies the (cheap) prox redundantly so that
 // all of them hold sigma * lam_bar for the next dual GEMM.
 template <typename Tv, int NT, int MM>
-__global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int iters) {
+__global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int iters, int part) {
   typedef typename V4<Tv>::t vec4;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Tv *gred = reinterpret_cast<Tv *>(lds_raw);                       // [2][WAVES][NT][4][64]
   Tv *pscr = gred + 2 * WAVES * NT * 4 * 64;                        // partial-node scratch
   const int tile = blockIdx.x;
-  const int nact = st.counters[0];
-  if (tile * PTS_TILE >= nact) return;
+  int beg, nact;
+  launch_range(st, part, beg, nact);
+  if (beg + tile * PTS_TILE >= nact) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, g = lane >> 4;
   constexpr int m = MM;          // components (the tables are zero-padded to MM)
   constexpr int np = 16 * NT;    // padded state dimension
-  const int slot = tile * PTS_TILE + cl;
+  const int slot = beg + tile * PTS_TILE + cl;
   const bool live = slot < nact;
   const long p = live ? st.perm[slot] : -1;
   const long pd = live ? p : st.npts;     // lanes without a point use the spare row npts
-  const int rows_max = st.rows[st.perm[tile * PTS_TILE]];
+  const int rows_max = st.rows[st.perm[beg + tile * PTS_TILE]];
   const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
   __shared__ int any_part;
   if (threadIdx.x == 0) any_part = 0;
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       __syncthreads();
       if (wave == 0) {
         const int pp = lane >> 2, qq = lane & 3;     // point pp of the tile, lane quarter qq
-        const int pslot = tile * PTS_TILE + pp;
+        const int pslot = beg + tile * PTS_TILE + pp;
         const bool plive = pslot < nact;
         const long P2 = plive ? st.perm[pslot] : -1;
         const bool ppart = plive && st.partial[P2];
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       __syncthreads();
       if (wave == 0) {
         const int pp = lane >> 2, qq = lane & 3;
-        const int pslot = tile * PTS_TILE + pp;
+        const int pslot = beg + tile * PTS_TILE + pp;
         const bool plive = pslot < nact;
         const long P2 = plive ? st.perm[pslot] : -1;
         const bool ppart = plive && st.partial[P2];
@@ -408,22 +418,24 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 // operands from the FP64 copies of the two table layouts.
 template <int NT>
 __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts o, int mode) {
+  const int part = 2;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tile = blockIdx.x;
-  const int nact = st.counters[0];
-  if (tile * PTS_TILE >= nact) return;
+  int beg, nact;
+  launch_range(st, part, beg, nact);
+  if (beg + tile * PTS_TILE >= nact) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, g = lane >> 4;
   const int m = S.m;
   constexpr int np = 16 * NT;
-  const int slot = tile * PTS_TILE + cl;
+  const int slot = beg + tile * PTS_TILE + cl;
   const bool live = slot < nact;
   const long p = live ? st.perm[slot] : -1;
   const long pd = live ? p : st.npts;
-  const int rows_max = st.rows[st.perm[tile * PTS_TILE]];
+  const int rows_max = st.rows[st.perm[beg + tile * PTS_TILE]];
   const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
-  double *gred = reinterpret_cast<double *>(lds_raw);            // [WAVES][NT][4][64] + [WAVES][64]
-  double *sred = gred + WAVES * NT * 4 * 64;
+  double *gred = reinterpret_cast<double *>(lds_raw);            // [WAVES-1][2][4][64] + [WAVES][64]
+  double *sred = gred + (WAVES - 1) * 2 * 4 * 64;
 
   double rr = 0.0;
   int M = -1, rowsp = 0;
@@ -514,23 +526,31 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
 #pragma unroll
     for (int q = 0; q < 4; ++q) wsig += wu[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
   }
-  // sum over the waves
+  // sum over the waves into wave 0, CT tiles at a time (bounded LDS)
+  constexpr int CT = 2;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t0 = 0; t0 < NT; t0 += CT) {
+    if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) gred[((wave * NT + t) * 4 + q) * 64 + lane] = G[t][q];
+      for (int tt = 0; tt < CT; ++tt)
+        if (t0 + tt < NT)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) gred[(((wave - 1) * CT + tt) * 4 + q) * 64 + lane] = G[t0 + tt < NT ? t0 + tt : 0][q];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int tt = 0; tt < CT; ++tt)
+        if (t0 + tt < NT)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            for (int w2 = 0; w2 < WAVES - 1; ++w2) G[t0 + tt < NT ? t0 + tt : 0][q] += gred[((w2 * CT + tt) * 4 + q) * 64 + lane];
+    }
+    __syncthreads();
+  }
   sred[wave * 64 + lane] = wsig;
   __syncthreads();
   if (wave != 0) return;
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double gs = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < WAVES; ++w2) gs += gred[((w2 * NT + t) * 4 + q) * 64 + lane];
-      G[t][q] = gs;
-    }
   wsig = 0.0;
 #pragma unroll
   for (int w2 = 0; w2 < WAVES; ++w2) wsig += sred[w2 * 64 + lane];
@@ -570,7 +590,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     const int pp = lane >> 2, qq = lane & 3;
-    const int pslot = tile * PTS_TILE + pp;
+    const int pslot = beg + tile * PTS_TILE + pp;
     const bool plive = pslot < nact;
     const long P2 = plive ? st.perm[pslot] : -1;
     const bool ppart = plive && st.partial[P2];
@@ -645,7 +665,8 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   wsig += __shfl_xor(wsig, 16); wsig += __shfl_xor(wsig, 32);
   if (!live || g != 0) return;
 
-  const double Pv = sP + 0.5 + wsig;
+  // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J)
+  const double Pv = fmin(sP + 0.5 + wsig, 0.5);
   const double Dv = -0.5 * (sJ - 1.0);
   st.P[p] = Pv;
   st.D[p] = Dv;
@@ -660,6 +681,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   if (ph == PH_FINAL) {
     if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); return; }
     if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
     return;
   }
   // probe: certified sign of phi_N(x, T)
@@ -669,6 +691,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   else if (gap <= o.gap_tol) outcome = 1;
   if (outcome < 0) {
     if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
     return;
   }
   log_probe(st, p, np);
@@ -715,11 +738,351 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
 }
 
 
-typedef void (*pdhg_fn)(SysView, PtState, int);
+// ------------------------------------------------------------------ streaming variant (any m, large n, BF16 hi+lo)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// hi = bf16(v), lo = bf16(v - hi): v ~ hi + lo to about 2^-17 relative
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+// Components are processed a pair at a time, so registers do not grow with
+// m: for the box the pair is projected right after its dual GEMM; for the l2
+// ball a first pass stores the unprojected V and accumulates the node norms,
+// a second pass scales, stores and runs the primal GEMM.  Wave 0 owns lam
+// (in L2) and broadcasts sigma*lam_bar through LDS.  With BF: K is held as a
+// hi + lo pair of bf16 tables, operands are split the same way on the fly,
+// and each product takes three bf16 MFMAs (hi*hi + hi*lo + lo*hi) with FP32
+// accumulation; the contraction chunk of 32 is (tiles t, t+1) for the dual
+// GEMM and (components j, j+1) x 16 nodes for the primal GEMM.
+template <int NT, bool BF>
+__global__ __launch_bounds__(THREADS, 1) void k_pdhg_stream(SysView S, PtState st, int iters, int part) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  constexpr int TCH = 4;                                             // tiles per reduction chunk
+  float *gred = reinterpret_cast<float *>(lds_raw);                  // [WAVES-1][TCH][4][64]
+  float *bopb = gred + (WAVES - 1) * TCH * 4 * 64;                   // [NT][4][64]
+  float *pscr = bopb + NT * 4 * 64;                                  // private-node scratch
+  const int tile = blockIdx.x;
+  int beg, nact;
+  launch_range(st, part, beg, nact);
+  if (beg + tile * PTS_TILE >= nact) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int m = S.m;
+  constexpr int np = 16 * NT;
+  const int slot = beg + tile * PTS_TILE + cl;
+  const bool live = slot < nact;
+  const long p = live ? st.perm[slot] : -1;
+  const long pd = live ? p : st.npts;
+  const int rows_max = st.rows[st.perm[beg + tile * PTS_TILE]];
+  const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
+  __shared__ int any_part;
+  if (threadIdx.x == 0) any_part = 0;
+  __syncthreads();
+  if (wave == 0 && g == 0 && live && st.partial[p]) atomicOr(&any_part, 1);
+  __syncthreads();
+  const bool wg_part = any_part != 0;
+
+  float tau = 0.f, sig = 0.f, rr = 0.f;
+  int M = -1, rowsp = 0;
+  if (live) {
+    tau = (float)st.tau[p];
+    sig = (float)st.sig[p];
+    rr = (float)st.r[p];
+    M = st.M[p];
+    rowsp = st.rows[p];
+  }
+  const float hw = (float)S.h;
+  float bop[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bop[t][q] = sig * st.lamb[pd * np + 16 * t + 4 * g + q];
+  float *yp = st.y + (size_t)pd * st.ystride;
+  float *lamp = st.lam + pd * np;
+
+  for (int it = 0; it < iters; ++it) {
+    floatx4 G[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) G[t] = floatx4{0, 0, 0, 0};
+
+    // ---- private node (trapezoid, T off the grid): wave 0, FP32
+    if (wg_part) {
+      float *lb_s = pscr, *gr_s = pscr + 16 * np, *yr_s = pscr + 32 * np;   // yr_s [16][mpad]
+      const int mp = st.mpad;
+      if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lb_s[cl * np + 16 * t + 4 * g + q] = (sig > 0 ? bop[t][q] / sig : 0.f);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const int pp = lane >> 2, qq = lane & 3;
+        const int pslot = beg + tile * PTS_TILE + pp;
+        const long P2 = pslot < nact ? st.perm[pslot] : -1;
+        const bool ppart = P2 >= 0 && st.partial[P2];
+        const float sig2 = ppart ? (float)st.sig[P2] : 0.f;
+        const float wR = ppart ? (float)(0.5 * st.r[P2]) : 0.f;
+        float ssq = 0.f;
+        for (int j = qq; j < mp; j += 4) {
+          float v = 0.f;
+          if (ppart && j < m) {
+            const float *row = st.R32 + ((size_t)P2 * m + j) * np;
+            float acc = 0.f;
+            for (int i = 0; i < np; ++i) acc += row[i] * lb_s[pp * np + i];
+            v = st.yR[(size_t)P2 * mp + j] + sig2 * acc;
+          }
+          yr_s[pp * mp + j] = v;
+          ssq += v * v;
+        }
+        if (S.uset == HOPF_U_L2) {
+          ssq += __shfl_xor(ssq, 1);
+          ssq += __shfl_xor(ssq, 2);
+        }
+        const float nv = sqrtf(ssq);
+        const float sc = (nv > wR) ? (nv > 0 ? wR / nv : 0.f) : 1.f;
+        for (int j = qq; j < mp; j += 4) {
+          float v = yr_s[pp * mp + j];
+          v = (S.uset == HOPF_U_L2) ? v * sc : fminf(fmaxf(v, -wR), wR);
+          yr_s[pp * mp + j] = v;
+          if (ppart && j < m) st.yR[(size_t)P2 * mp + j] = v;
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const int pp = lane >> 2, qq = lane & 3;
+        const int pslot = beg + tile * PTS_TILE + pp;
+        const long P2 = pslot < nact ? st.perm[pslot] : -1;
+        const bool ppart = P2 >= 0 && st.partial[P2];
+        for (int i = qq; i < np; i += 4) {
+          float acc = 0.f;
+          if (ppart)
+            for (int j = 0; j < m; ++j) acc += st.R32[((size_t)P2 * m + j) * np + i] * yr_s[pp * mp + j];
+          gr_s[pp * np + i] = acc;
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) G[t][q] = gr_s[cl * np + 16 * t + 4 * g + q];
+      }
+    }
+
+    // B operand of the dual GEMM, split once per iteration
+    bf16x8 bdh[(NT + 1) / 2], bdl[(NT + 1) / 2];
+    if constexpr (BF) {
+#pragma unroll
+      for (int c = 0; c < (NT + 1) / 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int t = 2 * c + (e >> 2);
+          const float v = (t < NT) ? bop[t < NT ? t : 0][e & 3] : 0.f;
+          __bf16 hi, lo;
+          split_bf16(v, hi, lo);
+          bdh[c][e] = hi;
+          bdl[c][e] = lo;
+        }
+    }
+
+    for (int kb = wave; kb < nkb; kb += WAVES) {
+      float w4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb * NODE_BLOCK + 4 * g + q;
+        w4[q] = (k < rowsp) ? (float)node_weight(k, M, (double)rr, (double)hw, S.quad) : 0.f;
+      }
+      const bool l2 = S.uset == HOPF_U_L2;
+      float s4[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int pass = 0; pass < (l2 ? 2 : 1); ++pass) {
+        float sc4[4];
+        if (l2 && pass == 1) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float nv = sqrtf(s4[q]);
+            sc4[q] = (nv > w4[q]) ? (nv > 0 ? w4[q] / nv : 0.f) : 1.f;
+          }
+        }
+        for (int j = 0; j < m; j += 2) {
+          const bool has2 = j + 1 < m;
+          floatx4 V[2];
+          // y (node-major within the block)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            V[u] = floatx4{0, 0, 0, 0};
+            if (u == 0 || has2) {
+              const float4 f = *reinterpret_cast<const float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g);
+              V[u] = floatx4{f.x, f.y, f.z, f.w};
+            }
+          }
+          if (!l2 || pass == 0) {
+            // dual GEMM for components j, j+1
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if (u == 1 && !has2) break;
+              if constexpr (BF) {
+                const __bf16 *kh = S.Kd16h + (((size_t)kb * m + j + u) * NODE_BLOCK + cl) * np;
+                const __bf16 *kl = S.Kd16l + (((size_t)kb * m + j + u) * NODE_BLOCK + cl) * np;
+#pragma unroll
+                for (int c = 0; c < (NT + 1) / 2; ++c) {
+                  bf16x8 ah, al;
+#pragma unroll
+                  for (int e = 0; e < 8; ++e) {
+                    const int t = 2 * c + (e >> 2);
+                    const int col = 16 * (t < NT ? t : 0) + 4 * g + (e & 3);
+                    ah[e] = (t < NT) ? kh[col] : (__bf16)0.0f;
+                    al[e] = (t < NT) ? kl[col] : (__bf16)0.0f;
+                  }
+                  V[u] = mfma_bf16(ah, bdh[c], V[u]);
+                  V[u] = mfma_bf16(ah, bdl[c], V[u]);
+                  V[u] = mfma_bf16(al, bdh[c], V[u]);
+                }
+              } else {
+                const float *kd = S.K32 + (((size_t)kb * m + j + u) * NODE_BLOCK + cl) * np;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                  const float4 f = *reinterpret_cast<const float4 *>(kd + 16 * t + 4 * g);
+                  V[u] = mfma(f.x, bop[t][0], V[u]);
+                  V[u] = mfma(f.y, bop[t][1], V[u]);
+                  V[u] = mfma(f.z, bop[t][2], V[u]);
+                  V[u] = mfma(f.w, bop[t][3], V[u]);
+                }
+              }
+            }
+          }
+          if (l2 && pass == 0) {       // store unprojected, accumulate node norms
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if (u == 1 && !has2) break;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) s4[q] += V[u][q] * V[u][q];
+              float4 f;
+              f.x = V[u][0]; f.y = V[u][1]; f.z = V[u][2]; f.w = V[u][3];
+              *reinterpret_cast<float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g) = f;
+            }
+            continue;
+          }
+          // project, store, primal GEMM
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !has2) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) V[u][q] = l2 ? V[u][q] * sc4[q] : fminf(fmaxf(V[u][q], -w4[q]), w4[q]);
+            float4 f;
+            f.x = V[u][0]; f.y = V[u][1]; f.z = V[u][2]; f.w = V[u][3];
+            *reinterpret_cast<float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g) = f;
+          }
+          if constexpr (BF) {
+            bf16x8 byh, byl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              __bf16 hi, lo;
+              split_bf16((e < 4 || has2) ? V[e >> 2][e & 3] : 0.f, hi, lo);
+              byh[e] = hi;
+              byl[e] = lo;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              bf16x8 ah, al;
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const int u = e >> 2;
+                const bool okc = u == 0 || has2;
+                const size_t off = (((size_t)kb * m + j + (okc ? u : 0)) * np + 16 * t + cl) * NODE_BLOCK + 4 * g + (e & 3);
+                ah[e] = okc ? S.Kp16h[off] : (__bf16)0.0f;
+                al[e] = okc ? S.Kp16l[off] : (__bf16)0.0f;
+              }
+              G[t] = mfma_bf16(ah, byh, G[t]);
+              G[t] = mfma_bf16(ah, byl, G[t]);
+              G[t] = mfma_bf16(al, byh, G[t]);
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if (u == 1 && !has2) break;
+              const float *kp = S.K32T + ((size_t)kb * m + j + u) * np * NODE_BLOCK;
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                const float4 f = *reinterpret_cast<const float4 *>(kp + (size_t)(16 * t + cl) * NODE_BLOCK + 4 * g);
+                G[t] = mfma(f.x, V[u][0], G[t]);
+                G[t] = mfma(f.y, V[u][1], G[t]);
+                G[t] = mfma(f.z, V[u][2], G[t]);
+                G[t] = mfma(f.w, V[u][3], G[t]);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // ---- sum G over the waves into wave 0, in chunks of TCH tiles
+#pragma unroll
+    for (int t0 = 0; t0 < NT; t0 += TCH) {
+      if (wave > 0) {
+#pragma unroll
+        for (int tt = 0; tt < TCH; ++tt)
+          if (t0 + tt < NT)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gred[(((wave - 1) * TCH + tt) * 4 + q) * 64 + lane] = G[t0 + tt < NT ? t0 + tt : 0][q];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int tt = 0; tt < TCH; ++tt)
+          if (t0 + tt < NT)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              for (int w2 = 0; w2 < WAVES - 1; ++w2) G[t0 + tt < NT ? t0 + tt : 0][q] += gred[((w2 * TCH + tt) * 4 + q) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    // ---- prox and extrapolation in wave 0, broadcast of sigma * lam_bar
+    if (wave == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * t + 4 * g + q;
+          const float xfc = st.xfc32[pd * np + i];
+          const float wd = (float)S.Wd[i];
+          const float l0 = lamp[i];
+          const float ln = (l0 - tau * (G[t][q] - xfc)) / (1.0f + tau * wd);
+          lamp[i] = ln;
+          bopb[(t * 4 + q) * 64 + lane] = sig * (2.0f * ln - l0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bop[t][q] = bopb[(t * 4 + q) * 64 + lane];
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + 4 * g + q] = sig > 0 ? bop[t][q] / sig : 0.f;
+    if (live && g == 0) {
+      st.iters_probe[p] += iters;
+      st.iters_tot[p] += iters;
+    }
+  }
+}
+
+typedef void (*pdhg_fn)(SysView, PtState, int, int);
 typedef void (*cert_fn)(SysView, PtState, Opts, int);
 
 // kernel instances, one lookup per NT (hopf_inst_nt*.hip); nullptr if absent
 pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM_out);
 cert_fn cert_lookup(int NT);
+pdhg_fn stream_lookup(int NT, int bf16);
 
 }  // namespace hopf

@@ -15,6 +15,11 @@ namespace hopf {
 static const int kMM[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
 
 pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
+#if HOPF_NT > 8
+  (void)m; (void)prec;
+  if (MM_out) *MM_out = 0;
+  return nullptr;
+#else
   int MM = 0;
   for (int v : kMM)
     if (v >= m) { MM = v; break; }
@@ -45,6 +50,11 @@ pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
     case 16: return k_pdhg<float, HOPF_NT, 16>;
     default: return nullptr;
   }
+#endif
+}
+
+pdhg_fn HOPF_CAT(stream_lookup_nt, HOPF_NT)(int bf16) {
+  return bf16 ? k_pdhg_stream<HOPF_NT, true> : k_pdhg_stream<HOPF_NT, false>;
 }
 
 cert_fn HOPF_CAT(cert_lookup_nt, HOPF_NT)() { return k_certify<HOPF_NT>; }

@@ -30,6 +30,8 @@ struct SysTables {
   double *K64 = nullptr;       // [nkb][m][16][n_pad]
   float *K32T = nullptr;       // [nkb][m][n_pad][16]   primal-operand layout
   double *K64T = nullptr;      // [nkb][m][n_pad][16]
+  __bf16 *Kd16h = nullptr, *Kd16l = nullptr;   // BF16 hi/lo split, dual layout
+  __bf16 *Kp16h = nullptr, *Kp16l = nullptr;   // BF16 hi/lo split, primal layout
   double *lpref_d = nullptr;   // [N+1]
   double *epow_d = nullptr;    // [POW_LEVELS][n][n]
   double *A_d = nullptr;       // [n][n]

@@ -148,7 +148,9 @@ bool all_finite(const double *p, size_t k) {
 
 void free_tables(SysTables &t) {
   hipFree(t.K32); hipFree(t.K64); hipFree(t.K32T); hipFree(t.K64T); hipFree(t.lpref_d); hipFree(t.epow_d);
+  hipFree(t.Kd16h); hipFree(t.Kd16l); hipFree(t.Kp16h); hipFree(t.Kp16l);
   t.K32T = nullptr; t.K64T = nullptr;
+  t.Kd16h = t.Kd16l = t.Kp16h = t.Kp16l = nullptr;
   hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d); hipFree(t.Eh_d); hipFree(t.Qu_d);
   t.Eh_d = nullptr; t.Qu_d = nullptr;
   t.K32 = nullptr; t.K64 = nullptr; t.lpref_d = nullptr; t.epow_d = nullptr;
@@ -303,6 +305,7 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
   const size_t kel = (size_t)t.nkb * mk * NODE_BLOCK * t.n_pad;
   std::vector<float> K32(kel, 0.0f), K32T(kel, 0.0f);
   std::vector<double> K64(kel, 0.0), K64T(kel, 0.0);
+  std::vector<__bf16> Kdh(kel, (__bf16)0.0f), Kdl(kel, (__bf16)0.0f), Kph(kel, (__bf16)0.0f), Kpl(kel, (__bf16)0.0f);
   for (int k = 0; k < N; ++k) {
     const int kb = k / NODE_BLOCK, kk = k % NODE_BLOCK;
     for (int j = 0; j < mk; ++j)
@@ -314,6 +317,10 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
         K32[dst] = (float)v;
         K64T[dstT] = v;
         K32T[dstT] = (float)v;
+        // hi = bf16(v), lo = bf16(v - hi), both rounded to nearest even
+        const __bf16 hi = (__bf16)(float)v;
+        const __bf16 lo = (__bf16)(float)(v - (double)(float)hi);
+        Kdh[dst] = hi; Kdl[dst] = lo; Kph[dstT] = hi; Kpl[dstT] = lo;
       }
   }
   std::vector<double> Wd(t.n_pad, 1.0), cc(t.n_pad, 0.0);
@@ -330,6 +337,10 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
             up((void **)&t.K64, K64.data(), kel * sizeof(double)) &&
             up((void **)&t.K32T, K32T.data(), kel * sizeof(float)) &&
             up((void **)&t.K64T, K64T.data(), kel * sizeof(double)) &&
+            up((void **)&t.Kd16h, Kdh.data(), kel * sizeof(__bf16)) &&
+            up((void **)&t.Kd16l, Kdl.data(), kel * sizeof(__bf16)) &&
+            up((void **)&t.Kp16h, Kph.data(), kel * sizeof(__bf16)) &&
+            up((void **)&t.Kp16l, Kpl.data(), kel * sizeof(__bf16)) &&
             up((void **)&t.lpref_d, t.lpref.data(), t.lpref.size() * sizeof(double)) &&
             up((void **)&t.epow_d, t.epow.data(), t.epow.size() * sizeof(double)) &&
             up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&
@@ -416,7 +427,7 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
-      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 1)
+      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 2)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;

@@ -318,19 +318,22 @@ __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, Ml
 
 // Active points sorted by rows (descending) so that a workgroup's 64 points
 // need similar numbers of table rows; also counts the algorithmic point-rows.
+// Active points sorted by class (FP32-escalated first) and by rows
+// (descending) so that a tile's points need similar table prefixes; also
+// counts the algorithmic point-rows.
 __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows) {
-  __shared__ int hist[4097 + 1];
-  __shared__ int total;
+  __shared__ int hist[2 * 4097 + 2];
   __shared__ double rsum[1024];
   const int tid = threadIdx.x;
-  for (int b = tid; b <= N + 1; b += 1024) hist[b] = 0;
-  if (tid == 0) total = 0;
+  const int nb = 2 * (N + 1);
+  for (int b = tid; b < nb; b += 1024) hist[b] = 0;
   __syncthreads();
   double loc = 0.0;
   for (long p = tid; p < st.npts; p += 1024) {
     if (st.phase[p] == PH_DONE) continue;
     const int rw = st.rows[p];
-    atomicAdd(&hist[N - rw], 1);   // descending rows
+    const int bin = (st.esc[p] ? 0 : N + 1) + (N - rw);
+    atomicAdd(&hist[bin], 1);
     loc += (double)(rw + st.partial[p]);
   }
   rsum[tid] = loc;
@@ -341,24 +344,25 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
   }
   if (tid == 0) {
     if (count_rows) st.counters[1] = 0;   // the setup list was consumed by k_setup
-    int acc = 0;
-    for (int b = 0; b <= N; ++b) {   // exclusive scan
+    int acc = 0, nesc = 0;
+    for (int b = 0; b < nb; ++b) {   // exclusive scan
       const int v = hist[b];
       hist[b] = acc;
       acc += v;
+      if (b == N) nesc = acc;
     }
-    total = acc;
     st.counters[0] = acc;
+    st.counters[3] = nesc;
     if (count_rows) st.rowsum[0] += rsum[0];
   }
   __syncthreads();
   for (long p = tid; p < st.npts; p += 1024) {
     if (st.phase[p] == PH_DONE) continue;
-    const int pos = atomicAdd(&hist[N - st.rows[p]], 1);
+    const int bin = (st.esc[p] ? 0 : N + 1) + (N - st.rows[p]);
+    const int pos = atomicAdd(&hist[bin], 1);
     st.perm[pos] = (int)p;
   }
 }
-
 
 // ------------------------------------------------------------------ control and trajectory read-out
 
@@ -574,6 +578,7 @@ bool make_state(Ctx *ctx, const SysTables &tab, long npts, PtState &st) {
   st.perm = grow<int>(ctx, bi++, npts);
   st.setup_list = grow<int>(ctx, bi++, npts);
   st.stage = grow<int>(ctx, bi++, npts);
+  st.esc = grow<int>(ctx, bi++, npts);
   st.bT = grow<float>(ctx, bi++, npts);
   st.bD = grow<float>(ctx, bi++, npts);
   st.log_pt = ctx->log_pt;
@@ -585,7 +590,7 @@ bool make_state(Ctx *ctx, const SysTables &tab, long npts, PtState &st) {
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
          st.sig && st.P && st.D && st.xf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
-         st.yR && st.perm && st.setup_list && st.stage && st.bT && st.bD && st.counters && st.rowsum;
+         st.yR && st.perm && st.setup_list && st.stage && st.esc && st.bT && st.bD && st.counters && st.rowsum;
 }
 
 SysView view(const SysTables &t) {
@@ -593,7 +598,8 @@ SysView view(const SysTables &t) {
   v.n = t.n; v.m = t.m; v.N = t.N; v.n_pad = t.n_pad; v.nkb = t.nkb;
   v.quad = t.desc.quad; v.uset = t.desc.uset;
   v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta;
-  v.K32 = t.K32; v.K64 = t.K64; v.K32T = t.K32T; v.K64T = t.K64T; v.lpref = t.lpref_d; v.epow = t.epow_d;
+  v.K32 = t.K32; v.K64 = t.K64; v.K32T = t.K32T; v.K64T = t.K64T;
+  v.Kd16h = t.Kd16h; v.Kd16l = t.Kd16l; v.Kp16h = t.Kp16h; v.Kp16l = t.Kp16l; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
   v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
   return v;
@@ -631,19 +637,46 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   const hopf_opts &ho = ctx->opts;
   const int NT = tab.n_pad / 16;
   int MMc = 0;
-  pdhg_fn fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
+  // register-resident kernel where an instance exists (FP32/FP64, m <= 16,
+  // n <= 128), the streaming kernel otherwise and for BF16 hi+lo
+  pdhg_fn fp = nullptr;
+  bool streaming = false;
+  if (ho.prec != HOPF_BF16X3) fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
+  if (!fp && ho.prec != HOPF_FP64) {
+    fp = stream_lookup(NT, ho.prec == HOPF_BF16X3 ? 1 : 0);
+    streaming = true;
+  }
   cert_fn fc = cert_lookup(NT);
   if (!fp || !fc)
-    return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" + std::to_string(tab.m));
+    return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" +
+                                               std::to_string(tab.m) + " at this precision");
   const size_t elt = ho.prec == HOPF_FP64 ? 8 : 4;
   const int mpad = ((tab.m + 3) / 4) * 4;
-  // iteration kernel: double-buffered cross-wave G sums + the private-node scratch
-  const size_t lds_pdhg = (size_t)2 * WAVES * NT * 4 * 64 * elt + (size_t)(2 * 16 * tab.n_pad + 16 * MMc) * elt;
-  // certificate: G sums, sigma sums, private-node scratch
-  const size_t lds_cert = (size_t)WAVES * NT * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 +
+  size_t lds_pdhg;
+  if (streaming)   // cross-wave G chunks + broadcast of sigma*lam_bar + private-node scratch
+    lds_pdhg = ((size_t)(WAVES - 1) * 4 * 4 * 64 + (size_t)NT * 4 * 64 + 32 * (size_t)tab.n_pad + 16 * (size_t)mpad) * 4;
+  else             // double-buffered cross-wave G sums + the private-node scratch
+    lds_pdhg = (size_t)2 * WAVES * NT * 4 * 64 * elt + (size_t)(2 * 16 * tab.n_pad + 16 * MMc) * elt;
+  // certificate: G chunks, sigma sums, private-node scratch
+  const size_t lds_cert = (size_t)(WAVES - 1) * 2 * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 +
                           (size_t)16 * tab.n_pad * 4 + (size_t)16 * tab.n_pad * 8 + (size_t)16 * mpad * 8;
   if (lds_pdhg > 150 * 1024 || lds_cert > 150 * 1024)
     return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
+  if (ho.prec == HOPF_BF16X3 && !tab.Kd16h)
+    return set_err(ctx, HOPF_ESTATE, "BF16 tables missing");
+  // BF16 hi+lo: points that stall are escalated to an FP32 kernel
+  pdhg_fn fp32_esc = nullptr;
+  size_t lds_esc = 0;
+  if (ho.prec == HOPF_BF16X3) {
+    int mm2 = 0;
+    fp32_esc = pdhg_lookup(NT, tab.m, HOPF_FP32, &mm2);
+    if (fp32_esc) lds_esc = (size_t)2 * WAVES * NT * 4 * 64 * 4 + (size_t)(2 * 16 * tab.n_pad + 16 * mm2) * 4;
+    else {
+      fp32_esc = stream_lookup(NT, 0);
+      lds_esc = ((size_t)(WAVES - 1) * 4 * 4 * 64 + (size_t)NT * 4 * 64 + 32 * (size_t)tab.n_pad + 16 * (size_t)mpad) * 4;
+    }
+    HIPCHK(hipFuncSetAttribute((const void *)fp32_esc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_esc));
+  }
   HIPCHK(hipFuncSetAttribute((const void *)fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pdhg));
   HIPCHK(hipFuncSetAttribute((const void *)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cert));
   hipStream_t s = user_stream ? user_stream : ctx->stream;
@@ -655,7 +688,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
   HIPCHK(hipHostMalloc((void **)&hcount, 4 * sizeof(int), hipHostMallocDefault));
 
-  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm};
+  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -666,6 +699,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   HIPCHK(hipMemsetAsync(st.partial, 0, npts * sizeof(int), s));
   HIPCHK(hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s));
   HIPCHK(hipMemsetAsync(st.stage, 0, npts * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(st.esc, 0, npts * sizeof(int), s));
   HIPCHK(hipMemsetAsync(st.bT, 0, npts * sizeof(float), s));
   HIPCHK(hipMemsetAsync(st.bD, 0, npts * sizeof(float), s));
   MlpView mv{};
@@ -691,7 +725,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     HIPCHK(hipEventRecord(a, s));
-    fp<<<ngrid, THREADS, lds_pdhg, s>>>(S, st, ho.check_every);
+    if (fp32_esc) fp32_esc<<<ngrid, THREADS, lds_esc, s>>>(S, st, ho.check_every, 0);   // escalated points
+    fp<<<ngrid, THREADS, lds_pdhg, s>>>(S, st, ho.check_every, fp32_esc ? 1 : 2);
     HIPCHK(hipEventRecord(b, s));
     kev.push_back(a);
     kev.push_back(b);
@@ -888,36 +923,39 @@ namespace hopf {
 
 #define HOPF_DECL(k)                                   \
   pdhg_fn pdhg_lookup_nt##k(int m, int prec, int *MM); \
+  pdhg_fn stream_lookup_nt##k(int bf16);               \
   cert_fn cert_lookup_nt##k();
 HOPF_DECL(1) HOPF_DECL(2) HOPF_DECL(3) HOPF_DECL(4) HOPF_DECL(5) HOPF_DECL(6) HOPF_DECL(7) HOPF_DECL(8)
+HOPF_DECL(9) HOPF_DECL(10) HOPF_DECL(11) HOPF_DECL(12) HOPF_DECL(13) HOPF_DECL(14) HOPF_DECL(15) HOPF_DECL(16)
 #undef HOPF_DECL
 
-pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM) {
-  switch (NT) {
-    case 1: return pdhg_lookup_nt1(m, prec, MM);
-    case 2: return pdhg_lookup_nt2(m, prec, MM);
-    case 3: return pdhg_lookup_nt3(m, prec, MM);
-    case 4: return pdhg_lookup_nt4(m, prec, MM);
-    case 5: return pdhg_lookup_nt5(m, prec, MM);
-    case 6: return pdhg_lookup_nt6(m, prec, MM);
-    case 7: return pdhg_lookup_nt7(m, prec, MM);
-    case 8: return pdhg_lookup_nt8(m, prec, MM);
-  }
+#define HOPF_SW(expr_k)                                                               \
+  switch (NT) {                                                                       \
+    case 1: return expr_k(1); case 2: return expr_k(2); case 3: return expr_k(3);      \
+    case 4: return expr_k(4); case 5: return expr_k(5); case 6: return expr_k(6);      \
+    case 7: return expr_k(7); case 8: return expr_k(8); case 9: return expr_k(9);      \
+    case 10: return expr_k(10); case 11: return expr_k(11); case 12: return expr_k(12); \
+    case 13: return expr_k(13); case 14: return expr_k(14); case 15: return expr_k(15); \
+    case 16: return expr_k(16);                                                       \
+  }                                                                                   \
   return nullptr;
+
+pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM) {
+#define E(k) pdhg_lookup_nt##k(m, prec, MM)
+  HOPF_SW(E)
+#undef E
+}
+
+pdhg_fn stream_lookup(int NT, int bf16) {
+#define E(k) stream_lookup_nt##k(bf16)
+  HOPF_SW(E)
+#undef E
 }
 
 cert_fn cert_lookup(int NT) {
-  switch (NT) {
-    case 1: return cert_lookup_nt1();
-    case 2: return cert_lookup_nt2();
-    case 3: return cert_lookup_nt3();
-    case 4: return cert_lookup_nt4();
-    case 5: return cert_lookup_nt5();
-    case 6: return cert_lookup_nt6();
-    case 7: return cert_lookup_nt7();
-    case 8: return cert_lookup_nt8();
-  }
-  return nullptr;
+#define E(k) cert_lookup_nt##k()
+  HOPF_SW(E)
+#undef E
 }
 
 }  // namespace hopf

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libhopfpd.so")
 
 U_L2, U_BOX = 0, 1
 Q_TRAP, Q_LEFT = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 WARM_COLD, WARM_CONT, WARM_MLP, WARM_MLP_LAM = 0, 1, 2, 3
 PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
@@ -162,7 +162,7 @@ class Solver:
         o = default_opts()
         for k, v in kw.items():
             if k == "prec":
-                v = {"fp64": FP64, "fp32": FP32}.get(v, v)
+                v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(v, v)
             if k == "warm":
                 v = {"cold": WARM_COLD, "cont": WARM_CONT, "mlp": WARM_MLP, "mlp_lam": WARM_MLP_LAM}.get(v, v)
             setattr(o, k, v)

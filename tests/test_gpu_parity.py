@@ -194,3 +194,50 @@ def test_trajectory_readout_vs_oracle(solver, quad, T):
     err = np.linalg.norm(tr["u"][big] - u[big], axis=1)
     assert np.all(err <= tol), (err, tol)
     assert np.all(np.linalg.norm(tr["u"], axis=1) <= 1.0 + 1e-9)
+
+
+# ------------------------------------------------------------------ streaming kernel and BF16 hi+lo
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("uset,n,m", [("l2", 40, 20), ("box", 40, 20), ("l2", 30, 5)])
+def test_value_streaming_and_bf16_vs_oracle(solver, prec, uset, n, m):
+    """Large m (streaming kernel) and the BF16 hi+lo split: the certified
+    interval must still contain phi_N and reach the gap tolerance."""
+    say("case: value streaming", prec, uset, n, m)
+    spec = random_system(n, m, 40, uset, seed=31, t_max=3.0)
+    solver.set_systems([spec])
+    solver.set_opts(prec=prec, c_tau=1.0)
+    x = gaussian_points(40, n, 0.1, seed=6)
+    t = np.linspace(0.2, 3.0, 40)
+    r = solver.value(x, t)
+    S = osys(spec)
+    for k in [0, 13, 27, 39]:
+        pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=1.0, gap_tol=1e-9, max_iter=400000))
+        assert r["status"][k] == 0, (k, r["status"][k])
+        assert overlap(r["phi_lo"][k], r["phi_hi"][k], pr.phi_lo, pr.phi_hi), (k, r["phi_lo"][k], r["phi_hi"][k], pr.phi_lo, pr.phi_hi)
+        assert (r["phi_hi"][k] - r["phi_lo"][k]) / max(1.0, abs(r["phi_hi"][k])) <= GAP
+
+
+def test_value_bf16_c3_shape(solver):
+    """n=200, m=20, box control, x ~ N(0, 4I) (the precision workload's
+    shape and points, N reduced to 60 for test time): BF16 hi+lo, FP32 and the
+    FP64 oracle give overlapping certified intervals at gap <= 1e-6."""
+    say("case: value bf16 c3 shape")
+    spec = random_system(200, 20, 60, "box", seed=1003, t_max=10.0)
+    solver.set_systems([spec])
+    x = gaussian_points(64, 200, 2.0, seed=3)
+    t = np.linspace(0.5, 10.0, 64)
+    res = {}
+    for prec in ("fp32", "bf16x3"):
+        solver.set_opts(prec=prec, c_tau=5.0)
+        res[prec] = r = solver.value(x, t)
+        say(prec, "status", np.bincount(r["status"], minlength=5), "iters", r["iters"].mean())
+        assert np.all(r["status"] == 0)
+        assert np.all((r["phi_hi"] - r["phi_lo"]) / np.maximum(1.0, np.abs(r["phi_hi"])) <= GAP)
+    a, b = res["fp32"], res["bf16x3"]
+    for k in range(64):
+        assert overlap(a["phi_lo"][k], a["phi_hi"][k], b["phi_lo"][k], b["phi_hi"][k]), k
+    S = osys(spec)
+    for k in (0, 21, 63):
+        pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=5.0))
+        assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), (k, b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi)
