@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 METRIC = "min-time queries/sec at dual gap≤1e-6 (n=100,N=300): plain vs warm-start"
@@ -30,11 +31,12 @@ def _oracle_query(args):
     spec, x, opts = args
     from oracle import hopf_oracle as O
     S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
-    r = O.min_time(S, x, O.Options(c_tau=opts.get("c_tau", 1.0)))
+    r = O.min_time(S, x, O.Options(c_tau=opts.get("c_tau", 1.0), warm=opts.get("warm", "cont"),
+                                   root=opts.get("root", "bisect")))
     return r.status, r.T, r.iters
 
 
-def cpu_baseline(w, budget_s, workers):
+def cpu_baseline(w, budget_s, workers, warm, root):
     """The FP64 oracle, as it stands, on the batch's queries in order, one
     query per worker process (one thread each), for a wall-clock budget:
     the rate counts the queries finished within the budget.  Slow queries
@@ -43,7 +45,8 @@ def cpu_baseline(w, budget_s, workers):
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
     os.environ.setdefault("MKL_NUM_THREADS", "1")
-    jobs = [(w.systems[0], w.x[i], w.opts) for i in range(min(len(w.x), 64 * workers))]
+    opts = dict(w.opts, warm=warm, root=root)
+    jobs = [(w.systems[0], w.x[i], opts) for i in range(min(len(w.x), 64 * workers))]
     ctx = mp.get_context("spawn")
     pool = ctx.Pool(workers)
     done = 0
@@ -72,12 +75,20 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--npts", type=int, default=65536)
-    ap.add_argument("--warm", default="all", choices=["all", "cold", "cont", "mlp", "mlp_lam"],
-                    help="start of every probe; 'all' times cold, cont and the learned variants and "
+    ap.add_argument("--variants", default="all",
+                    help="comma list of warm[+newton] variants (warm: cold, cont, mlp, mlp_lam; +newton: the "
+                         "hybrid Newton-bisection of Sec. IV instead of bisection); 'all' times cont, "
+                         "cont+newton, mlp, mlp+newton, mlp_lam and cold and "
                          "reports the best warm start as value")
     ap.add_argument("--train-npts", type=int, default=80000, help="training queries for the learned warm start")
     ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle wall time")
+    ap.add_argument("--cpu-budget", type=float, default=40.0, help="seconds of oracle wall time")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4"],
+                    help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
+                         "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call")
+    ap.add_argument("--c4-scale", type=float, default=1.0, help="c4: fraction of each system's points")
+    ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
+                    help="iteration precision (default: the workload's, fp32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
@@ -92,7 +103,14 @@ def main():
     from gen.configs import config5
     from paper_1712_08226_amd import Solver
 
+    if args.workload == "c4":
+        return bench_c4(args)
+    if args.workload == "c3":
+        return bench_c3(args)
+
     w = config5(npts=args.npts)
+    if args.prec:
+        w.opts["prec"] = args.prec
     spec = w.systems[0]
     dev = torch.device("cuda:0")
     solver = Solver(0)
@@ -116,7 +134,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    modes = ["cont", "mlp", "mlp_lam", "cold"] if args.warm == "all" else [args.warm]
+    modes = (["cont", "cont+newton", "mlp", "mlp+newton", "mlp_lam", "cold"] if args.variants == "all"
+             else args.variants.split(","))
     train_info = None
     if any(m.startswith("mlp") for m in modes):
         # learned warm start: trained on separate drift-planted queries (not timed)
@@ -130,7 +149,8 @@ def main():
         print(f"warm-start network trained: {train_info}", file=sys.stderr, flush=True)
 
     def run_mode(mode, nsteps, nwarm):
-        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=mode)
+        warm, _, root = mode.partition("+")
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=warm, root=root or "bisect")
         for i in range(nwarm):
             step()
             print(f"[{mode}] warmup step {i + 1}/{nwarm} done", file=sys.stderr, flush=True)
@@ -164,7 +184,7 @@ def main():
     tk, launches, rows = R["tk"], R["launches"], R["rows"]
     ms = dt_ms
     status_np, T_np, gap_np, it_np, pr_np = R["status"], R["T"], R["gap"], R["iters"], R["probes"]
-    ref = results.get("cont", R)
+    ref = results.get("cont", R)        # T of other variants compared with bisection from continuation
     variants = {}
     for k, v in results.items():
         okk = v["status"] == 0
@@ -175,19 +195,25 @@ def main():
                        "mean_probes": round(float(v["probes"].mean()), 3),
                        "ok": int(okk.sum()), "unreachable": int((v["status"] == 2).sum()),
                        "noconv": int((v["status"] == 3).sum()),
+                       "max_iters": int(v["iters"].max()),
+                       "iter_kernel_s": round(v["tk"] / max(1, args.steps), 3),
+                       "iter_launches": int(v["launches"] // max(1, args.steps)),
                        "T_equal_to_cont_frac": round(float(same[okk].mean()) if okk.any() else 1.0, 5)}
     st, Tn, gn, itn = status_np, T_np, gap_np, it_np
     ok = st == 0
     flops = 4.0 * spec.m * spec.n * rows           # algorithmic: K lam and K^T y per point-row
     achieved = flops / tk / 1e12 if tk > 0 else 0.0
     per_launch_ms = 1e3 * tk / max(1, launches)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-                "kernel": "k_pdhg (fused FP32 PDHG iterations)", "avg_launch_ms": round(per_launch_ms, 4),
-                "launches": launches}
+    bf = w.opts["prec"] == "bf16x3"
+    peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": ("k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"
+                           if bf else "k_pdhg (fused FP32 PDHG iterations)"),
+                "avg_launch_ms": round(per_launch_ms, 4), "launches": launches}
     out = {"metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "vs_baseline": None, "dtype": w.opts["prec"], "data": "synthetic",
            "config": {"workload": f"min-time, n={spec.n} m={spec.m} N={spec.N} l2 control, ellipsoid target, "
                                   f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points",
                       "npts": npts, "n": spec.n, "m": spec.m, "N": spec.N, "warm": best,
@@ -203,12 +229,138 @@ def main():
            "roofline": roofline}
     if not args.no_cpu:
         workers = min(16, os.cpu_count() or 1)
-        cq, cdt, done = cpu_baseline(w, args.cpu_budget, workers)
+        bw, _, broot = best.partition("+")
+        cw = bw if bw in ("cold", "cont") else "cont"        # the oracle has no learned warm start
+        cq, cdt, done = cpu_baseline(w, args.cpu_budget, workers, cw, broot or "bisect")
         out["cpu_baseline"] = {"value": round(cq, 4), "unit": "queries/s", "cores": workers, "kind": "oracle",
+                               "options": {"warm": cw, "root": broot or "bisect"},
                                "sample": f"batch queries in order on {workers} single-thread processes for "
                                          f"{cdt:.1f} s wall; {done} finished (unfinished slow queries not "
                                          f"counted, which overstates the CPU rate)"}
     print(json.dumps(out), flush=True)
+
+
+def _oracle_value(args):
+    """One oracle value solve (worker process): certified [phi_lo, phi_hi]."""
+    spec, x, t, c_tau = args
+    from oracle import hopf_oracle as O
+    S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+    pr = O.solve_value(S, x, t, O.Options(c_tau=c_tau))
+    return pr.phi_lo, pr.phi_hi
+
+
+def bench_c3(args):
+    """Precision workload (n=200, m=20, N=400, box): value solves phi(x, t) of
+    16384 points in BF16 hi+lo (FP32 accumulate, FP32 escalation of stalled
+    probes) and in FP32, both certified in FP64; the error against the FP64
+    oracle on a sample, and the one-probe min-time queries."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    from gen.configs import config3
+    from paper_1712_08226_amd import Solver
+    w = config3(npts=args.npts if args.npts != 65536 else 16384)
+    spec = w.systems[0]
+    npts = len(w.x)
+    t = w.meta["t"]
+    solver = Solver(0)
+    t0 = time.perf_counter()
+    solver.set_systems([spec])
+    setup_s = time.perf_counter() - t0
+    out = {}
+    for prec in ("bf16x3", "fp32"):
+        solver.set_opts(prec=prec, c_tau=w.opts["c_tau"])
+        for i in range(args.warmup):
+            solver.value(w.x[:256], t[:256])
+        t0 = time.perf_counter()
+        r = solver.value(w.x, t)
+        dt = time.perf_counter() - t0
+        tm = solver.last_timing()
+        out[prec] = dict(r=r, dt=dt, tm=tm)
+        print(f"[c3 {prec}] {npts} value solves in {dt:.2f} s", file=sys.stderr, flush=True)
+    solver.set_opts(prec="bf16x3", c_tau=w.opts["c_tau"])
+    t0 = time.perf_counter()
+    rm = solver.min_time(w.x)
+    dtm = time.perf_counter() - t0
+    b, f = out["bf16x3"]["r"], out["fp32"]["r"]
+    mid_b = 0.5 * (b["phi_lo"] + b["phi_hi"])
+    mid_f = 0.5 * (f["phi_lo"] + f["phi_hi"])
+    nsamp = min(16, npts)
+    idx = np.linspace(0, npts - 1, nsamp).astype(int)
+    workers = min(16, os.cpu_count() or 1)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        orc = pool.map(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])
+    o_mid = np.array([0.5 * (a + c) for a, c in orc])
+    overl = [max(b["phi_lo"][i], lo) <= min(b["phi_hi"][i], hi) + 1e-9 for i, (lo, hi) in zip(idx, orc)]
+    tmb = out["bf16x3"]["tm"]
+    ach = tmb["alg_flops"] / tmb["iter_kernel_s"] / 1e12 if tmb["iter_kernel_s"] > 0 else 0.0
+    res = {"metric": "value solves/sec at dual gap<=1e-6, BF16 hi+lo (n=200, m=20, N=400, box)",
+           "value": round(npts / out["bf16x3"]["dt"], 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * out["bf16x3"]["dt"], 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+           "config": {"workload": f"value phi(x,t), n=200 m=20 N=400 box control, {npts} points x~N(0,4I), "
+                                  "t~U[0.5,10], K as bf16 hi+lo with fp32 accumulation, fp64 tables and certificate"},
+           "fp32_solves_per_s": round(npts / out["fp32"]["dt"], 2),
+           "statuses_bf16": np.bincount(b["status"], minlength=5).tolist(),
+           "statuses_fp32": np.bincount(f["status"], minlength=5).tolist(),
+           "mean_iters_bf16_fp32": [float(b["iters"].mean()), float(f["iters"].mean())],
+           "max_gap_bf16": float(np.max((b["phi_hi"] - b["phi_lo"]) / np.maximum(1, np.abs(b["phi_hi"])))),
+           "error": {"max_abs_phi_bf16_vs_fp32_all": float(np.max(np.abs(mid_b - mid_f))),
+                     "max_abs_phi_bf16_vs_fp64_oracle_sample": float(np.max(np.abs(mid_b[idx] - o_mid))),
+                     "intervals_overlap_oracle": int(sum(overl)), "sample": int(nsamp)},
+           "min_time": {"queries_per_s": round(npts / dtm, 2),
+                        "statuses": np.bincount(rm["status"], minlength=5).tolist()},
+           "setup_s": round(setup_s, 2),
+           "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(ach / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
+                        "kernel": "k_pdhg_stream<bf16 hi+lo>; achieved counts algorithmic flops (x3 executed)"}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_c4(args):
+    """64 uneven systems in one min-time call (every system's points mixed in
+    random order): jobs per system on a pool of streams."""
+    import numpy as np
+    from gen.configs import config4
+    from paper_1712_08226_amd import Solver
+    w = config4(scale=args.c4_scale)
+    npts = len(w.x)
+    solver = Solver(0)
+    t0 = time.perf_counter()
+    solver.set_systems(w.systems)
+    setup_s = time.perf_counter() - t0
+    print(f"[c4] {len(w.systems)} systems set up in {setup_s:.1f} s; {npts} queries", file=sys.stderr, flush=True)
+    solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont")
+    for i in range(args.warmup):
+        sel = np.concatenate([np.flatnonzero(w.sys_id == k)[:16] for k in range(len(w.systems))])
+        solver.min_time(w.x[sel], sys_id=w.sys_id[sel])
+        print(f"[c4] warmup {i + 1} done", file=sys.stderr, flush=True)
+    times = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        r = solver.min_time(w.x, sys_id=w.sys_id)
+        times.append(time.perf_counter() - t0)
+        print(f"[c4] step {i + 1}/{args.steps}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    tm = solver.last_timing()
+    dt = float(np.mean(times))
+    st = r["status"]
+    ach = tm["alg_flops"] / tm["total_s"] / 1e12 if tm["total_s"] > 0 else 0.0
+    res = {"metric": "min-time queries/sec at dual gap<=1e-6, 64 uneven systems in one call",
+           "value": round(npts / dt, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * dt, 1), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"min-time, 64 systems n log-uniform [4,256] (drawn {min(s.A.shape[0] for s in w.systems)}"
+                                  f"-{max(s.A.shape[0] for s in w.systems)}), m=max(1,n/4), N in 100..500, l2/box 32/32, "
+                                  f"{npts} drift-planted queries (256-4096 per system), continuation warm start"},
+           "results": {"ok": int((st == 0).sum()), "unreachable": int((st == 2).sum()), "noconv": int((st == 3).sum()),
+                       "inside": int((st == 1).sum()), "mean_iters": float(r["iters"].mean()),
+                       "max_iters": int(r["iters"].max()), "mean_probes": float(r["probes"].mean())},
+           "setup_s": round(setup_s, 2),
+           "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                        "basis": "algorithmic flops of all systems / device time of the whole call"}}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

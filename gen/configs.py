@@ -55,3 +55,52 @@ def config5(npts=65536, seed=5, literal=False):
         x, T0 = planted_drift_points(spec, npts, 0.2, 3.0, seed)
         meta = dict(points="drift-planted T0~U[0.2,3]")
     return Workload("c5_n100_m10_N300", [spec], x, None, dict(prec="fp32", c_tau=5.0), meta)
+
+
+def config3(npts=16384, seed=3, N=400):
+    """Precision workload: n=200, m=20, N=400, unit box control, same A/B/W
+    generators; x ~ N(0, 4I) (the literal distribution; almost all of these
+    points cannot reach the target by t_max, so a min-time query is one
+    certified unreachable probe at t_max) and horizons t ~ U[0.5, 10] for the
+    value solves that carry the error statement."""
+    spec = random_system(200, 20, N, "box", seed=1003)
+    x = gaussian_points(npts, 200, 2.0, seed)
+    t = np.random.default_rng(seed + 1).uniform(0.5, 10.0, npts)
+    return Workload("c3_n200_m20_N400_box", [spec], x, None, dict(prec="bf16x3", c_tau=5.0),
+                    dict(points="literal N(0,4I)", t=t))
+
+
+def config4_systems(nsys=64, seed=4):
+    """64 systems: n log-uniform in [4, 256], m = max(1, n // 4), N uniform in
+    {100..500}, l2 and box control sets 32/32 in random order."""
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(np.log(4.0), np.log(256.0), nsys))).astype(int)
+    Ns = rng.integers(100, 501, nsys)
+    usets = np.array(["l2"] * (nsys // 2) + ["box"] * (nsys - nsys // 2))
+    rng.shuffle(usets)
+    specs = [random_system(int(n), max(1, int(n) // 4), int(N), str(u), seed=4000 + k)
+             for k, (n, N, u) in enumerate(zip(ns, Ns, usets))]
+    return specs
+
+
+def config4(seed=4, nsys=64, pts_lo=256, pts_hi=4096, scale=1.0):
+    """Batched uneven systems: config4_systems, 256-4096 drift-planted points
+    per system (T0 ~ U[0.2, 3]), all systems' points mixed in one call in
+    random order; x rows padded to the largest n.  `scale` shrinks the point
+    counts (for tests)."""
+    specs = config4_systems(nsys, seed)
+    rng = np.random.default_rng(seed + 100)
+    counts = np.maximum(1, (rng.integers(pts_lo, pts_hi + 1, nsys) * scale).astype(int))
+    nmax = max(s.A.shape[0] for s in specs)
+    xs, ids = [], []
+    for k, (s, c) in enumerate(zip(specs, counts)):
+        xk, _ = planted_drift_points(s, int(c), 0.2, 3.0, seed=7000 + k)
+        pad = np.zeros((int(c), nmax))
+        pad[:, :xk.shape[1]] = xk
+        xs.append(pad)
+        ids.append(np.full(int(c), k, dtype=np.int32))
+    x = np.concatenate(xs)
+    sid = np.concatenate(ids)
+    perm = rng.permutation(len(sid))
+    return Workload("c4_batched_uneven", specs, x[perm], sid[perm], dict(prec="fp32", c_tau=1.0),
+                    dict(points="drift-planted T0~U[0.2,3] per system", counts=counts.tolist()))

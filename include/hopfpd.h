@@ -63,6 +63,7 @@ typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
 typedef enum { HOPF_Q_TRAP = 0, HOPF_Q_LEFT = 1 } hopf_quad;
 typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1, HOPF_BF16X3 = 2 } hopf_prec;
 typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1, HOPF_WARM_MLP = 2, HOPF_WARM_MLP_LAM = 3 } hopf_warm;
+typedef enum { HOPF_ROOT_BISECT = 0, HOPF_ROOT_NEWTON = 1 } hopf_root;
 
 /* per-point result status */
 typedef enum {
@@ -103,10 +104,24 @@ typedef struct {
  *                 at a different certified crossing                              [COLD]
  *   prec          hopf_prec of the iterations; with HOPF_BF16X3 a probe that is not
  *                 certified after 4000 iterations continues in FP32 (its iterates
- *                 carry over unchanged)                                              [FP32] */
+ *                 carry over unchanged)                                              [FP32]
+ *   root          minimum-time search on the certified bracket [lo, hi]:
+ *                 HOPF_ROOT_BISECT: midpoint;  HOPF_ROOT_NEWTON: the hybrid of Sec. IV,
+ *                 t - phi/(d phi/dt) with d phi/dt = -H_x(p*, x0) (eq. of the Newton
+ *                 update with the Hamiltonian), phi the midpoint of the certified
+ *                 interval, moved 0.4 of the stopping tolerance towards the side not yet
+ *                 bracketed, and the midpoint wherever the step leaves (lo, hi) or the
+ *                 slope is not negative                                             [BISECT]
+ *   newton_after  hybrid only: probes (counting the one at t_max) placed by bisection
+ *                 before Newton steps start                                          [3]
+ *   newton_rho    hybrid only: from probe newton_after on, a probe also runs until
+ *                 P - D <= newton_rho |P + D| / 2 so the Newton step sees an accurate
+ *                 value                                                              [0.5] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;
+  int root, newton_after;
+  double newton_rho;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);
@@ -126,19 +141,25 @@ hopf_status hopf_set_opts(hopf_ctx *ctx, const hopf_opts *opts);
 
 /* Value phi(x_i, t_i) (eq. (18)), certified: phi_lo <= phi <= phi_hi with
  * (phi_hi - phi_lo)/max(1,|phi_hi|) <= gap_tol unless pt_status says otherwise.
- *   sys_id  npts ints or NULL (all system 0)
- *   x       npts*n (n of each point's system; points of one call must share n)
+ *   sys_id  npts ints or NULL (all system 0).  Points of different systems may
+ *           be mixed in one call: each system's points run as their own job
+ *           (own kernels and tiles) and the jobs run concurrently
+ *   x       npts rows of stride n_max = the largest n among the systems the call
+ *           uses; a row holds its system's n entries first (the rest is ignored)
  *   t       npts horizons in [0, t_max]
- *   lam     npts*n terminal costates lam* = e^{-T A^T} p* or NULL
+ *   lam     npts rows of stride n_max: terminal costates lam* = e^{-T A^T} p*
+ *           (the system's n entries first; the rest is not written) or NULL
  *   iters   npts or NULL; pt_status npts (required). */
 hopf_status hopf_value(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
                        const double *t, double *phi_lo, double *phi_hi, double *lam,
                        int *iters, int *pt_status);
 
-/* Minimum time to reach the target (Sec. IV) by certified bisection on
- * [0, t_max]:  T (npts; +inf if unreachable at t_max, 0 if inside),
- * gap (npts, normalised gap of the final solve at T), lam (npts*n or NULL),
- * probes, iters (npts or NULL), pt_status (npts). */
+/* Minimum time to reach the target (Sec. IV) by a certified search on
+ * [0, t_max] (bisection or the hybrid Newton step, opts.root):  T (npts; +inf
+ * if unreachable at t_max, 0 if inside), gap (npts, normalised gap of the
+ * final solve at T), lam (npts rows of stride n_max as for hopf_value, or
+ * NULL), probes, iters (npts or NULL), pt_status (npts).  sys_id and x as
+ * for hopf_value (systems may be mixed). */
 hopf_status hopf_min_time(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
                           double *T, double *gap, double *lam, int *probes, int *iters,
                           int *pt_status);
@@ -187,10 +208,15 @@ hopf_status hopf_warm_train(hopf_ctx *ctx, int sys_id, long npts, const double *
                             float lr, unsigned seed, double *epoch_loss, long *pairs);
 
 /* Seconds spent on the device by the last solve call (HIP events around the
- * whole call on the context's stream) and by the fused iteration kernel
- * alone, with its launch count; for throughput and roofline reporting. */
+ * whole call on the caller's or the context's stream) and by the fused
+ * iteration kernels alone (summed over launches; the launches of a
+ * multi-system call run on several streams and can overlap), their launch
+ * count, the point-rows they processed (one row = one quadrature node of one
+ * point in one iteration) and the algorithmic flops, 4 m n per point-row
+ * (K lam and K^T y), summed over the systems of the call; for throughput
+ * and roofline reporting. */
 hopf_status hopf_last_timing(const hopf_ctx *ctx, double *total_s, double *iter_kernel_s,
-                             long *iter_launches, double *iter_point_rows);
+                             long *iter_launches, double *iter_point_rows, double *alg_flops);
 
 #ifdef __cplusplus
 }

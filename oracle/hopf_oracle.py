@@ -100,6 +100,9 @@ class Options:
     max_iter: int = 200000
     check_every: int = 25
     warm: str = "cold"          # "cold": lam0 = 0 at every probe; "cont": previous probe's iterate
+    root: str = "bisect"        # "bisect": midpoint; "newton": Sec. IV hybrid Newton-bisection step
+    newton_rho: float = 0.5     # hybrid: a probe also runs until gap <= rho |phi| (Newton accuracy)
+    newton_after: int = 1       # hybrid: probes (counting t_max) decided by bisection first
 
 
 # ---------------------------------------------------------------- terminal data
@@ -266,6 +269,7 @@ class Probe:
     iters: int = 0
     P: float = math.inf
     D: float = -math.inf
+    tight: bool = False          # run to the hybrid's relative accuracy as well as the sign
     history: list = field(default_factory=list)
 
     @property
@@ -359,7 +363,7 @@ def solve_value(sys: System, x0, T, opt: Options = Options(), lam0=None, y0=None
 REACH, UNREACH, NOCONV = "reach", "unreach", "noconv"
 
 
-def sign_probe(sys: System, pr: Probe, opt: Options):
+def sign_probe(sys: System, pr: Probe, opt: Options, tight: bool = False):
     """Run a probe until the sign of phi_N is certified (Sec. IV: phi < 0
     means the target is reachable at T):  -D <= 0 certifies reachable, -P > 0
     certifies unreachable, and a gap below tolerance with neither counts as
@@ -371,12 +375,14 @@ def sign_probe(sys: System, pr: Probe, opt: Options):
         pdhg_iteration(sys, pr)
         if pr.iters % opt.check_every == 0:
             certify(sys, pr)
+            if pr.gap_n() <= opt.gap_tol:
+                return UNREACH if -pr.P > 0.0 else REACH
+            if tight and pr.P - pr.D > opt.newton_rho * 0.5 * abs(pr.P + pr.D):
+                continue                # the Newton step needs a tighter value
             if -pr.D <= 0.0:
                 return REACH
             if -pr.P > 0.0:
                 return UNREACH
-            if pr.gap_n() <= opt.gap_tol:
-                return REACH
     return NOCONV
 
 
@@ -396,15 +402,57 @@ class MinTimeResult:
     final: Probe | None = None
 
 
+def value_slope(sys: System, pr: Probe):
+    """d phi_N / dT at the probe's horizon from its iterate (Sec. IV: the
+    time derivative of the value is -H_x(p*, x0); with p = e^{T A^T} lam the
+    two terms are <A x_f, lam> and the support function of the node at
+    time-to-go T).  The node used is the one with the largest time-to-go and
+    a positive weight (the last entry of the node list): for the left rule
+    this is the exact one-sided derivative of the discretised value, for the
+    trapezoid rule the derivative up to a term of order r = T - M h."""
+    if len(pr.tau) == 0:
+        return math.nan
+    lam = pr.lam
+    return float((sys.A @ pr.xf) @ lam - support(pr.Ks[-1] @ lam, sys.uset))
+
+
+def next_horizon(sys: System, opt: Options, pr: Probe, reached: bool, lo: float, hi: float):
+    """Next probe of the root search on the certified bracket [lo, hi].
+
+    Bisection: the midpoint.  Hybrid (Sec. IV): the Newton step
+    T - phi/(d phi/dT) from the probe just certified, with phi the midpoint of
+    its certified interval [-P, -D]; the step is moved 0.4 of the stopping
+    tolerance towards the side of the root not yet bracketed (so that an
+    accurate step closes the bracket in one probe), and is replaced by the
+    midpoint when it falls outside (lo, hi) or the slope is not negative.
+    Newton steps start once the probe count reaches newton_after (earlier
+    probes are placed by bisection: where phi_N changes sign more than once,
+    a Newton step from t_max heads for the last crossing), and those probes
+    run until P - D <= newton_rho |P + D| / 2 so that the step sees an
+    accurate value.  Returns (T_next, newton_used)."""
+    mid = 0.5 * (lo + hi)
+    if opt.root != "newton" or not pr.tight:
+        return mid, False
+    s = value_slope(sys, pr)
+    if not (s < 0.0) or not math.isfinite(s):
+        return mid, False
+    phi = -0.5 * (pr.P + pr.D)
+    tol = max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max)
+    t = pr.T - phi / s + (-0.4 * tol if reached else 0.4 * tol)
+    if lo < t < hi:
+        return t, True
+    return mid, False
+
+
 def min_time(sys: System, x0, opt: Options = Options()):
     """Minimum time to reach Omega (Sec. IV): the horizon where phi_N changes
-    sign, found by bisection on [0, t_max] with certified signs; the paper's
-    hybrid Newton step is a separate option of the product.
+    sign, found on [0, t_max] with certified signs, by bisection or by the
+    hybrid Newton-bisection of Sec. IV (next_horizon).
 
     Steps: inside the target -> T = 0.  Probe t_max: certified unreachable ->
-    T = inf.  Otherwise bisect (midpoint) until hi - lo <= max(t_rel_tol hi,
-    t_abs_tol_frac t_max); return T = hi and the solve at hi continued to the
-    gap tolerance."""
+    T = inf.  Otherwise probe inside the bracket until hi - lo <=
+    max(t_rel_tol hi, t_abs_tol_frac t_max); return T = hi and the solve at hi
+    continued to the gap tolerance."""
     x0 = np.asarray(x0, dtype=np.float64)
     if not np.all(np.isfinite(x0)):
         return MinTimeResult(math.nan, PT_NONFINITE, 0, 0, np.full(sys.n, math.nan), None,
@@ -415,7 +463,8 @@ def min_time(sys: System, x0, opt: Options = Options()):
                              -J(sys, x0), 0.0, 0.0, 0.0)
     probes, iters = 0, 0
     pr = make_probe(sys, x0, sys.t_max, opt)
-    out = sign_probe(sys, pr, opt)
+    pr.tight = opt.root == "newton" and opt.newton_after <= 1
+    out = sign_probe(sys, pr, opt, pr.tight)
     probes += 1
     iters += pr.iters
     if out == NOCONV:
@@ -427,21 +476,22 @@ def min_time(sys: System, x0, opt: Options = Options()):
     lo, hi = 0.0, sys.t_max
     last, last_is_hi = pr, True
     while hi - lo > max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max):
-        mid = 0.5 * (lo + hi)
+        nxt, _ = next_horizon(sys, opt, last, last_is_hi, lo, hi)
         if opt.warm == "cont":
-            pr = make_probe(sys, x0, mid, opt, last.lam, last.y)
+            pr = make_probe(sys, x0, nxt, opt, last.lam, last.y)
         else:
-            pr = make_probe(sys, x0, mid, opt)
-        out = sign_probe(sys, pr, opt)
+            pr = make_probe(sys, x0, nxt, opt)
+        pr.tight = opt.root == "newton" and probes + 1 >= opt.newton_after
+        out = sign_probe(sys, pr, opt, pr.tight)
         probes += 1
         iters += pr.iters
         if out == NOCONV:
             return MinTimeResult(math.nan, PT_NOCONV, probes, iters, pr.lam, pr.y, pr.P, pr.D,
                                  pr.gap_n(), lo, hi, pr)
         if out == REACH:
-            hi, last_is_hi = mid, True
+            hi, last_is_hi = nxt, True
         else:
-            lo, last_is_hi = mid, False
+            lo, last_is_hi = nxt, False
         last = pr
     if last_is_hi:
         fin = last
@@ -459,8 +509,6 @@ def min_time(sys: System, x0, opt: Options = Options()):
     return MinTimeResult(hi, st, probes, iters, fin.lam, fin.y, fin.P, fin.D, fin.gap_n(),
                          lo, hi, fin)
 
-
-# ---------------------------------------------------------------- read-out
 
 def readout(sys: System, x0, pr: Probe):
     """Control, trajectory and costate from a solved probe.

@@ -65,6 +65,7 @@ struct PtState {
   int *status, *phase, *flags, *probes, *iters_tot, *iters_probe, *rows, *M, *partial, *last_reach;
   double *T, *lo, *hi, *r, *tau, *sig, *P, *D;
   double *xf;                // [npts][n_pad]
+  double *axf;               // [npts][n_pad]  A x_f (time derivative of x_f, for the Newton slope)
   float *xfc32;              // [npts][n_pad]  x_f - c
   double *R64;               // [npts][m][n_pad]
   float *R32;                // [npts][m][n_pad]
@@ -86,6 +87,8 @@ struct PtState {
 struct Opts {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec, esc_iters;
+  int root, newton_after;
+  double newton_rho;
 };
 
 // point range of one iteration launch: 0 = FP32-escalated points
@@ -451,6 +454,8 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
 #pragma unroll
   for (int t = 0; t < NT; ++t) G[t] = doublex4{0, 0, 0, 0};
   double wsig = 0.0;    // sum_k w_k sigma_C(K_k lam) over this lane's rows
+  double slast = 0.0;   // sigma_C(K_k lam) of the last table node (Newton slope)
+  const int klast = (live && !st.partial[p]) ? rowsp - 1 : -1;
   const float *yp = st.y + (size_t)pd * st.ystride;
 
   for (int kb = wave; kb < nkb; kb += WAVES) {
@@ -524,7 +529,11 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wsig += wu[q] * ((S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q]);
+    for (int q = 0; q < 4; ++q) {
+      const double sg = (S.uset == HOPF_U_L2) ? sqrt(snorm[q]) : snorm[q];
+      wsig += wu[q] * sg;
+      if (kb * NODE_BLOCK + acc_row<double>(g, q) == klast) slast = sg;
+    }
   }
   // sum over the waves into wave 0, CT tiles at a time (bounded LDS)
   constexpr int CT = 2;
@@ -549,11 +558,13 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     __syncthreads();
   }
   sred[wave * 64 + lane] = wsig;
+  gred[wave * 64 + lane] = slast;    // the G reduction area is free again
   __syncthreads();
   if (wave != 0) return;
   wsig = 0.0;
+  slast = 0.0;
 #pragma unroll
-  for (int w2 = 0; w2 < WAVES; ++w2) wsig += sred[w2 * 64 + lane];
+  for (int w2 = 0; w2 < WAVES; ++w2) { wsig += sred[w2 * 64 + lane]; slast += gred[w2 * 64 + lane]; }
 
   double sP = 0.0;   // 1/2 W lam^2 - (x_f - c) lam
 #pragma unroll
@@ -638,6 +649,8 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     const double part_sig = wR * ((S.uset == HOPF_U_L2) ? sqrt(ssU) : ssU);
     const double ps = __shfl(part_sig, 4 * cl);
     if (g == 0) wsig += ps;
+    const double sR = __shfl((S.uset == HOPF_U_L2) ? sqrt(ssU) : ssU, 4 * cl);
+    if (g == 0 && live && st.partial[p]) slast = sR;     // the node at tau = T is the last one
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -659,7 +672,18 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
         sJ += d * d / S.Wd[i];
       }
     }
+  // <A x_f, lam> (lam registers: rows 4g+q)
+  double sAx = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * t + 4 * g + q;
+      if (live && i < S.n) sAx += st.axf[p * np + i] * (double)lam[t][q];
+    }
   // reduce over the four lane groups holding the same point
+  sAx += __shfl_xor(sAx, 16); sAx += __shfl_xor(sAx, 32);
+  slast += __shfl_xor(slast, 16); slast += __shfl_xor(slast, 32);
   sP += __shfl_xor(sP, 16); sP += __shfl_xor(sP, 32);
   sJ += __shfl_xor(sJ, 16); sJ += __shfl_xor(sJ, 32);
   wsig += __shfl_xor(wsig, 16); wsig += __shfl_xor(wsig, 32);
@@ -684,11 +708,14 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
     return;
   }
-  // probe: certified sign of phi_N(x, T)
+  // probe: certified sign of phi_N(x, T); with the Newton hybrid, probes
+  // from newton_after on also need a value accurate to newton_rho relative
+  const bool tight = o.root == HOPF_ROOT_NEWTON && st.probes[p] >= o.newton_after;
   int outcome = -1;   // 1 reach, 0 unreach
-  if (-Dv <= 0.0) outcome = 1;
+  if (gap <= o.gap_tol) outcome = (-Pv > 0.0) ? 0 : 1;
+  else if (tight && Pv - Dv > o.newton_rho * 0.5 * fabs(Pv + Dv)) outcome = -1;
+  else if (-Dv <= 0.0) outcome = 1;
   else if (-Pv > 0.0) outcome = 0;
-  else if (gap <= o.gap_tol) outcome = 1;
   if (outcome < 0) {
     if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
     else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
@@ -718,9 +745,19 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
     }
     return;
   }
-  // next probe: the midpoint, or (learned warm start) the network's
-  // proposed bracket ends right after the certified probe at t_max
+  // next probe: the midpoint; the Newton step of Sec. IV (hybrid); or
+  // (learned warm start) the network's proposed bracket ends right after the
+  // certified probe at t_max
   double Tn = 0.5 * (lo + hi);
+  if (tight) {
+    const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
+    if (slope < 0.0 && isfinite(slope)) {
+      const double phi = -0.5 * (Pv + Dv);
+      const double tl = fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max);
+      const double tn = T - phi / slope + (outcome == 1 ? -0.4 * tl : 0.4 * tl);
+      if (tn > lo && tn < hi) Tn = tn;
+    }
+  }
   if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.bT[p] > 0.0f) {
     const int stg = st.stage[p];
     if (first && outcome == 1) {

@@ -68,11 +68,13 @@ struct Ctx {
   long log_cap = 0;
   long log_count = 0;
   // timing of the last solve
-  double t_total = 0.0, t_iter = 0.0, point_rows = 0.0;
+  double t_total = 0.0, t_iter = 0.0, point_rows = 0.0, alg_flops = 0.0;
   long iter_launches = 0;
-  // scratch, grown on demand
+  // point-state buffers of each job (one job per system in a call), grown on demand
   struct Buf { void *p = nullptr; size_t bytes = 0; };
-  std::vector<Buf> bufs;
+  std::vector<std::vector<Buf>> jbufs;
+  // extra streams (default priority) on which the jobs of a multi-system call run
+  std::vector<hipStream_t> pool;
 };
 
 // host setup (hopf_setup.cpp)

@@ -373,6 +373,9 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->check_every = 25;
   o->warm = HOPF_WARM_COLD;
   o->prec = HOPF_FP32;
+  o->root = HOPF_ROOT_BISECT;
+  o->newton_after = 3;
+  o->newton_rho = 0.5;
   return HOPF_OK;
 }
 
@@ -413,7 +416,12 @@ void hopf_destroy(hopf_ctx *h) {
   hipStreamSynchronize(c->stream);
   for (auto &t : c->sys) hopf::free_tables(t);
   for (auto &w : c->mlp) hopf::mlp_free(w);
-  for (auto &b : c->bufs) hipFree(b.p);
+  for (auto &v : c->jbufs)
+    for (auto &b : v) hipFree(b.p);
+  for (auto &ps : c->pool) {
+    hipStreamSynchronize(ps);
+    hipStreamDestroy(ps);
+  }
   hipStreamDestroy(c->stream);
   delete c;
 }
@@ -427,7 +435,8 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
-      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 2)
+      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 2 ||
+      o->root < 0 || o->root > 1 || o->newton_after < 1 || !(o->newton_rho > 0.0))
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;
@@ -457,13 +466,14 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
 }
 
 hopf_status hopf_last_timing(const hopf_ctx *h, double *total_s, double *iter_s, long *launches,
-                             double *point_rows) {
+                             double *point_rows, double *alg_flops) {
   const Ctx *c = reinterpret_cast<const Ctx *>(h);
   if (!c) return HOPF_EINVAL;
   if (total_s) *total_s = c->t_total;
   if (iter_s) *iter_s = c->t_iter;
   if (launches) *launches = c->iter_launches;
   if (point_rows) *point_rows = c->point_rows;
+  if (alg_flops) *alg_flops = c->alg_flops;
   return HOPF_OK;
 }
 

@@ -36,15 +36,19 @@ namespace hopf {
 
 // ------------------------------------------------------------------ init
 
-__global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int n, int n_pad) {
+// x0[p] = row idx[p] (or p) of the caller's x, whose rows are xs doubles apart
+__global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int n, int n_pad,
+                       int xs, const int *__restrict__ idx) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npts * n_pad) return;
   long p = i / n_pad;
   int k = (int)(i % n_pad);
-  x0[i] = k < n ? x[p * n + k] : 0.0;
+  const long q = idx ? idx[p] : p;
+  x0[i] = k < n ? x[q * xs + k] : 0.0;
 }
 
-__global__ void k_init(SysView S, PtState st, int mode, const double *__restrict__ t_in) {
+__global__ void k_init(SysView S, PtState st, int mode, const double *__restrict__ t_in,
+                       const int *__restrict__ idx) {
   long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= st.npts) return;
   const double *x = st.x0 + p * S.n_pad;
@@ -93,7 +97,7 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
     st.hi[p] = S.t_max;
     mark_setup(st, p);
   } else {
-    const double tv = t_in[p];
+    const double tv = t_in[idx ? idx[p] : p];
     st.status[p] = HOPF_PT_OK;
     st.phase[p] = PH_FINAL;
     st.T[p] = tv;
@@ -196,6 +200,10 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
       if (col == 0) {
         st.xf[p * np + i] = v;
         st.xfc32[p * np + i] = (float)(i < n ? v - S.c[i] : 0.0);
+        double ax = 0.0;   // (A x_f)_i
+        if (i < n)
+          for (int l = 0; l < n; ++l) ax += S.A[(size_t)i * n + l] * sv[cur][l * SETUP_COLS + cl];
+        st.axf[p * np + i] = ax;
       } else {
         const size_t o2 = ((size_t)p * m + (col - 1)) * np + i;
         st.R64[o2] = v;
@@ -220,20 +228,22 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
   // cold or warm start
   const int old_rows = st.rows[p];
   const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);   // CONT and MLP keep y
-  const int nkb_new = (rows + NODE_BLOCK - 1) / NODE_BLOCK;
   if (cold) {
     for (int i = tid; i < np; i += 256) {
       st.lam[p * np + i] = 0.0f;
       st.lamb[p * np + i] = 0.0f;
     }
-    for (int e = tid; e < nkb_new * m * NODE_BLOCK; e += 256) st.y[(size_t)p * st.ystride + e] = 0.0f;
   } else {
     for (int i = tid; i < np; i += 256) st.lamb[p * np + i] = st.lam[p * np + i];
-    // rows the previous probe did not use start at zero
-    for (int e = tid; e < nkb_new * m * NODE_BLOCK; e += 256) {
-      const int kb = e / (m * NODE_BLOCK), kk = e % NODE_BLOCK;
-      if (kb * NODE_BLOCK + kk >= old_rows) st.y[(size_t)p * st.ystride + e] = 0.0f;
-    }
+  }
+  // The kernels read the node blocks of the tile's longest point, so every
+  // row of the point's dual iterate must hold a finite value: rows this probe
+  // does not carry over from the previous one (all rows for a cold start,
+  // rows beyond either probe's node count otherwise) start at zero.
+  const int keep = cold ? 0 : min(old_rows, rows);
+  for (int e = tid; e < st.ystride; e += 256) {
+    const int kb = e / (m * NODE_BLOCK), kk = e % NODE_BLOCK;
+    if (kb * NODE_BLOCK + kk >= keep) st.y[(size_t)p * st.ystride + e] = 0.0f;
   }
   for (int j = tid; j < st.mpad; j += 256) st.yR[(size_t)p * st.mpad + j] = 0.0f;
   // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
@@ -316,8 +326,6 @@ __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, Ml
 
 // ------------------------------------------------------------------ tile formation
 
-// Active points sorted by rows (descending) so that a workgroup's 64 points
-// need similar numbers of table rows; also counts the algorithmic point-rows.
 // Active points sorted by class (FP32-escalated first) and by rows
 // (descending) so that a tile's points need similar table prefixes; also
 // counts the algorithmic point-rows.
@@ -493,11 +501,14 @@ __global__ __launch_bounds__(256) void k_traj(SysView S, PtState st, double T, d
 
 // ------------------------------------------------------------------ outputs
 
+// results of job point p go to the caller's index idx[p] (or p); lam rows are ls apart
 __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double *gap_out,
                           double *philo, double *phihi, double *lam_out, int *probes_out,
-                          int *iters_out, int *status_out) {
-  long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= st.npts) return;
+                          int *iters_out, int *status_out, const int *__restrict__ idx, int ls) {
+  const long p0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p0 >= st.npts) return;
+  const long p = p0;
+  const long q = idx ? idx[p0] : p0;
   const double Pv = st.P[p], Dv = st.D[p];
   const int stt = st.status[p];
   if (T_out) {
@@ -506,16 +517,16 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
       if (stt == HOPF_PT_OK || stt == HOPF_PT_INSIDE) Tv = st.hi[p];
       else if (stt == HOPF_PT_NOCONV || stt == HOPF_PT_NONFINITE) Tv = NAN;
     }
-    T_out[p] = Tv;
+    T_out[q] = Tv;
   }
-  if (gap_out) gap_out[p] = (Pv - Dv) / fmax(1.0, fabs(Dv));
-  if (philo) philo[p] = -Pv;
-  if (phihi) phihi[p] = -Dv;
+  if (gap_out) gap_out[q] = (Pv - Dv) / fmax(1.0, fabs(Dv));
+  if (philo) philo[q] = -Pv;
+  if (phihi) phihi[q] = -Dv;
   if (lam_out)
-    for (int i = 0; i < S.n; ++i) lam_out[p * S.n + i] = (double)st.lam[p * S.n_pad + i];
-  if (probes_out) probes_out[p] = st.probes[p];
-  if (iters_out) iters_out[p] = st.iters_tot[p];
-  status_out[p] = stt;
+    for (int i = 0; i < S.n; ++i) lam_out[q * ls + i] = (double)st.lam[p * S.n_pad + i];
+  if (probes_out) probes_out[q] = st.probes[p];
+  if (iters_out) iters_out[q] = st.iters_tot[p];
+  status_out[q] = stt;
 }
 
 // ------------------------------------------------------------------ host orchestration
@@ -523,9 +534,9 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
 namespace {
 
 template <typename T>
-T *grow(Ctx *ctx, int idx, size_t count) {
-  if ((int)ctx->bufs.size() <= idx) ctx->bufs.resize(idx + 1);
-  auto &b = ctx->bufs[idx];
+T *grow(std::vector<Ctx::Buf> &bufs, int idx, size_t count) {
+  if ((int)bufs.size() <= idx) bufs.resize(idx + 1);
+  auto &b = bufs[idx];
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
   if (b.bytes < bytes) {
     hipFree(b.p);
@@ -540,56 +551,59 @@ T *grow(Ctx *ctx, int idx, size_t count) {
 // Point state in the context's reusable buffers (same layout for every call
 // with the same system sizes; row npts of lam/lamb/xfc32/y is a spare row
 // that lanes without a point read and write).
-bool make_state(Ctx *ctx, const SysTables &tab, long npts, PtState &st) {
+bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st) {
+  if ((int)ctx->jbufs.size() <= job) ctx->jbufs.resize(job + 1);
+  auto &bufs = ctx->jbufs[job];
   const int np = tab.n_pad, m = tab.m;
   st = PtState{};
   st.npts = npts;
   st.ystride = tab.nkb * m * NODE_BLOCK;
   st.mpad = ((m + 3) / 4) * 4;
   int bi = 0;
-  st.x0 = grow<double>(ctx, bi++, npts * np);
-  st.status = grow<int>(ctx, bi++, npts);
-  st.phase = grow<int>(ctx, bi++, npts);
-  st.flags = grow<int>(ctx, bi++, npts);
-  st.probes = grow<int>(ctx, bi++, npts);
-  st.iters_tot = grow<int>(ctx, bi++, npts);
-  st.iters_probe = grow<int>(ctx, bi++, npts);
-  st.rows = grow<int>(ctx, bi++, npts);
-  st.M = grow<int>(ctx, bi++, npts);
-  st.partial = grow<int>(ctx, bi++, npts);
-  st.last_reach = grow<int>(ctx, bi++, npts);
-  st.T = grow<double>(ctx, bi++, npts);
-  st.lo = grow<double>(ctx, bi++, npts);
-  st.hi = grow<double>(ctx, bi++, npts);
-  st.r = grow<double>(ctx, bi++, npts);
-  st.tau = grow<double>(ctx, bi++, npts);
-  st.sig = grow<double>(ctx, bi++, npts);
-  st.P = grow<double>(ctx, bi++, npts);
-  st.D = grow<double>(ctx, bi++, npts);
-  st.xf = grow<double>(ctx, bi++, npts * np);
-  st.xfc32 = grow<float>(ctx, bi++, (npts + 1) * np);
+  st.x0 = grow<double>(bufs, bi++, npts * np);
+  st.status = grow<int>(bufs, bi++, npts);
+  st.phase = grow<int>(bufs, bi++, npts);
+  st.flags = grow<int>(bufs, bi++, npts);
+  st.probes = grow<int>(bufs, bi++, npts);
+  st.iters_tot = grow<int>(bufs, bi++, npts);
+  st.iters_probe = grow<int>(bufs, bi++, npts);
+  st.rows = grow<int>(bufs, bi++, npts);
+  st.M = grow<int>(bufs, bi++, npts);
+  st.partial = grow<int>(bufs, bi++, npts);
+  st.last_reach = grow<int>(bufs, bi++, npts);
+  st.T = grow<double>(bufs, bi++, npts);
+  st.lo = grow<double>(bufs, bi++, npts);
+  st.hi = grow<double>(bufs, bi++, npts);
+  st.r = grow<double>(bufs, bi++, npts);
+  st.tau = grow<double>(bufs, bi++, npts);
+  st.sig = grow<double>(bufs, bi++, npts);
+  st.P = grow<double>(bufs, bi++, npts);
+  st.D = grow<double>(bufs, bi++, npts);
+  st.xf = grow<double>(bufs, bi++, npts * np);
+  st.axf = grow<double>(bufs, bi++, npts * np);
+  st.xfc32 = grow<float>(bufs, bi++, (npts + 1) * np);
   const bool trap = tab.desc.quad == HOPF_Q_TRAP;
-  st.R64 = grow<double>(ctx, bi++, trap ? npts * m * np : 1);
-  st.R32 = grow<float>(ctx, bi++, trap ? npts * m * np : 1);
-  st.lam = grow<float>(ctx, bi++, (npts + 1) * np);
-  st.lamb = grow<float>(ctx, bi++, (npts + 1) * np);
-  st.y = grow<float>(ctx, bi++, (size_t)(npts + 1) * st.ystride);
-  st.yR = grow<float>(ctx, bi++, npts * st.mpad);
-  st.perm = grow<int>(ctx, bi++, npts);
-  st.setup_list = grow<int>(ctx, bi++, npts);
-  st.stage = grow<int>(ctx, bi++, npts);
-  st.esc = grow<int>(ctx, bi++, npts);
-  st.bT = grow<float>(ctx, bi++, npts);
-  st.bD = grow<float>(ctx, bi++, npts);
+  st.R64 = grow<double>(bufs, bi++, trap ? npts * m * np : 1);
+  st.R32 = grow<float>(bufs, bi++, trap ? npts * m * np : 1);
+  st.lam = grow<float>(bufs, bi++, (npts + 1) * np);
+  st.lamb = grow<float>(bufs, bi++, (npts + 1) * np);
+  st.y = grow<float>(bufs, bi++, (size_t)(npts + 1) * st.ystride);
+  st.yR = grow<float>(bufs, bi++, npts * st.mpad);
+  st.perm = grow<int>(bufs, bi++, npts);
+  st.setup_list = grow<int>(bufs, bi++, npts);
+  st.stage = grow<int>(bufs, bi++, npts);
+  st.esc = grow<int>(bufs, bi++, npts);
+  st.bT = grow<float>(bufs, bi++, npts);
+  st.bD = grow<float>(bufs, bi++, npts);
   st.log_pt = ctx->log_pt;
   st.log_T = ctx->log_T;
   st.log_lam = ctx->log_lam;
   st.log_cap = (int)std::min<long>(ctx->log_cap, 2000000000L);
-  st.counters = grow<int>(ctx, bi++, 4);
-  st.rowsum = grow<double>(ctx, bi++, 1);
+  st.counters = grow<int>(bufs, bi++, 4);
+  st.rowsum = grow<double>(bufs, bi++, 1);
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
-         st.sig && st.P && st.D && st.xf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
+         st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
          st.yR && st.perm && st.setup_list && st.stage && st.esc && st.bT && st.bD && st.counters && st.rowsum;
 }
 
@@ -613,6 +627,118 @@ SysView view(const SysTables &t) {
 
 }  // namespace
 
+namespace {
+
+// One system's share of a call: its points, kernels, point state and stream.
+struct Job {
+  int sid = 0;
+  const SysTables *tab = nullptr;
+  SysView S{};
+  pdhg_fn fp = nullptr, fp32_esc = nullptr;
+  cert_fn fc = nullptr;
+  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0;
+  PtState st{};
+  long npts = 0;
+  const int *idx = nullptr;      // device: job point -> caller's point (nullptr: identity)
+  hipStream_t s = nullptr;
+  unsigned ngrid = 0;
+  long rounds = 0, max_rounds = 0;
+  int *hcount = nullptr;         // pinned: active count of the last check of each group slot
+  hipEvent_t gev[2] = {nullptr, nullptr};   // completion of the two most recent round groups
+  int ngroups = 0, gdone = 0;    // groups issued / groups whose count was read
+  bool done = false;
+  MlpView mv{};
+  std::vector<hipEvent_t> kev;
+};
+
+constexpr int GROUP_ROUNDS = 4;   // rounds between active-count checks
+
+// Kernel choice and LDS sizes for one system at the requested precision.
+hopf_status plan_job(Ctx *ctx, Job &J) {
+  const SysTables &tab = *J.tab;
+  const hopf_opts &ho = ctx->opts;
+  const int NT = tab.n_pad / 16;
+  int MMc = 0;
+  // register-resident kernel where an instance exists (FP32/FP64, small m
+  // and n), the streaming kernel otherwise and for BF16 hi+lo
+  bool streaming = false;
+  if (ho.prec != HOPF_BF16X3) J.fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
+  if (!J.fp && ho.prec != HOPF_FP64) {
+    J.fp = stream_lookup(NT, ho.prec == HOPF_BF16X3 ? 1 : 0);
+    streaming = true;
+  }
+  J.fc = cert_lookup(NT);
+  if (!J.fp || !J.fc)
+    return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" +
+                                               std::to_string(tab.m) + " at this precision");
+  const size_t elt = ho.prec == HOPF_FP64 ? 8 : 4;
+  const int mpad = ((tab.m + 3) / 4) * 4;
+  const size_t lds_stream =
+      ((size_t)(WAVES - 1) * 4 * 4 * 64 + (size_t)NT * 4 * 64 + 32 * (size_t)tab.n_pad + 16 * (size_t)mpad) * 4;
+  if (streaming)   // cross-wave G chunks + broadcast of sigma*lam_bar + private-node scratch
+    J.lds_pdhg = lds_stream;
+  else             // double-buffered cross-wave G sums + the private-node scratch
+    J.lds_pdhg = (size_t)2 * WAVES * NT * 4 * 64 * elt + (size_t)(2 * 16 * tab.n_pad + 16 * MMc) * elt;
+  // certificate: G chunks, sigma sums, private-node scratch
+  J.lds_cert = (size_t)(WAVES - 1) * 2 * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 + (size_t)16 * tab.n_pad * 4 +
+               (size_t)16 * tab.n_pad * 8 + (size_t)16 * mpad * 8;
+  if (J.lds_pdhg > 150 * 1024 || J.lds_cert > 150 * 1024)
+    return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
+  if (ho.prec == HOPF_BF16X3 && !tab.Kd16h) return set_err(ctx, HOPF_ESTATE, "BF16 tables missing");
+  // BF16 hi+lo: points that stall are escalated to an FP32 kernel
+  if (ho.prec == HOPF_BF16X3) {
+    int mm2 = 0;
+    J.fp32_esc = pdhg_lookup(NT, tab.m, HOPF_FP32, &mm2);
+    if (J.fp32_esc) J.lds_esc = (size_t)2 * WAVES * NT * 4 * 64 * 4 + (size_t)(2 * 16 * tab.n_pad + 16 * mm2) * 4;
+    else {
+      J.fp32_esc = stream_lookup(NT, 0);
+      J.lds_esc = lds_stream;
+    }
+    HIPCHK(hipFuncSetAttribute((const void *)J.fp32_esc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_esc));
+  }
+  HIPCHK(hipFuncSetAttribute((const void *)J.fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_pdhg));
+  HIPCHK(hipFuncSetAttribute((const void *)J.fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_cert));
+  return HOPF_OK;
+}
+
+// Queue one group of rounds (setup, sort, iterations, certificate) and an
+// active-count check whose result lands in hcount[slot] when gev[slot] fires.
+hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
+  const hopf_opts &ho = ctx->opts;
+  const hipStream_t s = J.s;
+  for (int r = 0; r < GROUP_ROUNDS && J.rounds < J.max_rounds; ++r) {
+    k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
+    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, s));
+    if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
+    J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+    HIPCHK(hipEventRecord(b, s));
+    J.kev.push_back(a);
+    J.kev.push_back(b);
+    ctx->iter_launches++;
+    J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
+    ++J.rounds;
+  }
+  const int slot = J.ngroups & 1;
+  k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0);   // refresh the active count
+  HIPCHK(hipMemcpyAsync(J.hcount + slot, J.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(J.gev[slot], s));
+  ++J.ngroups;
+  return HOPF_OK;
+}
+
+}  // namespace
+
+// Solve every point of the call.  Points are grouped by system into jobs;
+// each job runs its own rounds (probe setup, tile formation, check_every
+// fused iterations, FP64 certificate and bisection step) until all of its
+// points are done.  A single-system call runs on the caller's stream; a
+// multi-system call runs its jobs on a pool of streams and interleaves their
+// rounds from this thread, keeping up to two round groups of each job in
+// flight so that the device does not wait for the host's checks.
 hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
                       const double *t_in, double *T_out, double *gap_out, double *philo_out,
                       double *phihi_out, double *lam_out, int *probes_out, int *iters_out,
@@ -623,154 +749,212 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   if (!status_out || !x) return set_err(ctx, HOPF_EINVAL, "x and pt_status are required");
   if (npts == 0) return HOPF_OK;
   if (npts > (1L << 26)) return set_err(ctx, HOPF_EINVAL, "too many points in one call");
-  int sid = 0;
+  const int nsys = (int)ctx->sys.size();
+  hipStream_t base = user_stream ? user_stream : ctx->stream;
+  // ---- group the points by system (counting sort on the host)
+  std::vector<long> cnt(nsys, 0), off(nsys + 1, 0);
+  std::vector<int> ids;
   if (sys_id) {
-    std::vector<int> ids(npts);
-    HIPCHK(hipMemcpy(ids.data(), sys_id, npts * sizeof(int), hipMemcpyDeviceToHost));
-    sid = ids[0];
-    for (long i = 1; i < npts; ++i)
-      if (ids[i] != sid) return set_err(ctx, HOPF_EUNSUPPORTED, "all points of one call must share a system in this build");
-    if (sid < 0 || sid >= (int)ctx->sys.size()) return set_err(ctx, HOPF_EINVAL, "sys_id out of range");
-  }
-  const SysTables &tab = ctx->sys[sid];
-  const SysView S = view(tab);
-  const hopf_opts &ho = ctx->opts;
-  const int NT = tab.n_pad / 16;
-  int MMc = 0;
-  // register-resident kernel where an instance exists (FP32/FP64, m <= 16,
-  // n <= 128), the streaming kernel otherwise and for BF16 hi+lo
-  pdhg_fn fp = nullptr;
-  bool streaming = false;
-  if (ho.prec != HOPF_BF16X3) fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
-  if (!fp && ho.prec != HOPF_FP64) {
-    fp = stream_lookup(NT, ho.prec == HOPF_BF16X3 ? 1 : 0);
-    streaming = true;
-  }
-  cert_fn fc = cert_lookup(NT);
-  if (!fp || !fc)
-    return set_err(ctx, HOPF_EUNSUPPORTED, "no kernel instance for n=" + std::to_string(tab.n) + ", m=" +
-                                               std::to_string(tab.m) + " at this precision");
-  const size_t elt = ho.prec == HOPF_FP64 ? 8 : 4;
-  const int mpad = ((tab.m + 3) / 4) * 4;
-  size_t lds_pdhg;
-  if (streaming)   // cross-wave G chunks + broadcast of sigma*lam_bar + private-node scratch
-    lds_pdhg = ((size_t)(WAVES - 1) * 4 * 4 * 64 + (size_t)NT * 4 * 64 + 32 * (size_t)tab.n_pad + 16 * (size_t)mpad) * 4;
-  else             // double-buffered cross-wave G sums + the private-node scratch
-    lds_pdhg = (size_t)2 * WAVES * NT * 4 * 64 * elt + (size_t)(2 * 16 * tab.n_pad + 16 * MMc) * elt;
-  // certificate: G chunks, sigma sums, private-node scratch
-  const size_t lds_cert = (size_t)(WAVES - 1) * 2 * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 +
-                          (size_t)16 * tab.n_pad * 4 + (size_t)16 * tab.n_pad * 8 + (size_t)16 * mpad * 8;
-  if (lds_pdhg > 150 * 1024 || lds_cert > 150 * 1024)
-    return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
-  if (ho.prec == HOPF_BF16X3 && !tab.Kd16h)
-    return set_err(ctx, HOPF_ESTATE, "BF16 tables missing");
-  // BF16 hi+lo: points that stall are escalated to an FP32 kernel
-  pdhg_fn fp32_esc = nullptr;
-  size_t lds_esc = 0;
-  if (ho.prec == HOPF_BF16X3) {
-    int mm2 = 0;
-    fp32_esc = pdhg_lookup(NT, tab.m, HOPF_FP32, &mm2);
-    if (fp32_esc) lds_esc = (size_t)2 * WAVES * NT * 4 * 64 * 4 + (size_t)(2 * 16 * tab.n_pad + 16 * mm2) * 4;
-    else {
-      fp32_esc = stream_lookup(NT, 0);
-      lds_esc = ((size_t)(WAVES - 1) * 4 * 4 * 64 + (size_t)NT * 4 * 64 + 32 * (size_t)tab.n_pad + 16 * (size_t)mpad) * 4;
+    ids.resize(npts);
+    HIPCHK(hipMemcpyAsync(ids.data(), sys_id, npts * sizeof(int), hipMemcpyDeviceToHost, base));
+    HIPCHK(hipStreamSynchronize(base));
+    for (long i = 0; i < npts; ++i) {
+      if (ids[i] < 0 || ids[i] >= nsys) return set_err(ctx, HOPF_EINVAL, "sys_id out of range");
+      cnt[ids[i]]++;
     }
-    HIPCHK(hipFuncSetAttribute((const void *)fp32_esc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_esc));
+  } else {
+    cnt[0] = npts;
   }
-  HIPCHK(hipFuncSetAttribute((const void *)fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pdhg));
-  HIPCHK(hipFuncSetAttribute((const void *)fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cert));
-  hipStream_t s = user_stream ? user_stream : ctx->stream;
-  const int np = tab.n_pad;
-  PtState st{};
-  if (!make_state(ctx, tab, npts, st)) return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
-  int *hcount = nullptr;
-  if (!st.x0 || !st.status || !st.y || !st.R64 || !st.R32 || !st.perm || !st.rowsum)
-    return set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
-  HIPCHK(hipHostMalloc((void **)&hcount, 4 * sizeof(int), hipHostMallocDefault));
-
-  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000};
-  hipEvent_t e0, e1;
+  int xs = 0;      // row stride of x and lam: the largest n among the systems used
+  std::vector<int> used;
+  for (int k = 0; k < nsys; ++k)
+    if (cnt[k] > 0) {
+      used.push_back(k);
+      xs = std::max(xs, ctx->sys[k].n);
+    }
+  for (int k = 0; k < nsys; ++k) off[k + 1] = off[k] + cnt[k];
+  const int nj = (int)used.size();
+  int *d_idx = nullptr;
+  if (nj > 1) {
+    std::vector<int> order(npts);
+    std::vector<long> pos(off.begin(), off.end() - 1);
+    for (long i = 0; i < npts; ++i) order[pos[ids[i]]++] = (int)i;
+    if ((int)ctx->jbufs.size() < nj + 1) ctx->jbufs.resize(nj + 1);
+    d_idx = grow<int>(ctx->jbufs[nj], 0, npts);
+    if (!d_idx) return set_err(ctx, HOPF_ENOMEM, "index buffer");
+    HIPCHK(hipMemcpyAsync(d_idx, order.data(), npts * sizeof(int), hipMemcpyHostToDevice, base));
+    HIPCHK(hipStreamSynchronize(base));
+  }
+  // ---- streams: the caller's for one job, the pool (and the caller's) otherwise
+  const int NPOOL = 4;
+  if (nj > 1)
+    while ((int)ctx->pool.size() < NPOOL) {
+      hipStream_t ps = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+      ctx->pool.push_back(ps);
+    }
+  const hopf_opts &ho = ctx->opts;
+  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000,
+         ho.root, ho.newton_after, ho.newton_rho};
+  const int max_probes = POW_BITS + 40;
+  hipEvent_t e0, e1, ebase;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  std::vector<hipEvent_t> kev;
-  HIPCHK(hipEventRecord(e0, s));
-  HIPCHK(hipMemsetAsync(st.rows, 0, npts * sizeof(int), s));
-  HIPCHK(hipMemsetAsync(st.rowsum, 0, sizeof(double), s));
-  HIPCHK(hipMemsetAsync(st.partial, 0, npts * sizeof(int), s));
-  HIPCHK(hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s));
-  HIPCHK(hipMemsetAsync(st.stage, 0, npts * sizeof(int), s));
-  HIPCHK(hipMemsetAsync(st.esc, 0, npts * sizeof(int), s));
-  HIPCHK(hipMemsetAsync(st.bT, 0, npts * sizeof(float), s));
-  HIPCHK(hipMemsetAsync(st.bD, 0, npts * sizeof(float), s));
-  MlpView mv{};
-  if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM) && sid < (int)ctx->mlp.size() &&
-      ctx->mlp[sid].valid) {
-    const MlpState &w = ctx->mlp[sid];
-    mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
-  }
-  {
-    const long tot = npts * np;
-    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, npts, tab.n, np);
-    k_init<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(S, st, mode, t_in);
-  }
-  const int max_probes = POW_BITS + 40;
-  const long max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
-  const unsigned ngrid = (unsigned)((npts + PTS_TILE - 1) / PTS_TILE);
-  long rounds = 0;
+  HIPCHK(hipEventCreate(&ebase));
+  HIPCHK(hipEventRecord(e0, base));
+  HIPCHK(hipEventRecord(ebase, base));
+  std::vector<Job> jobs(nj);
+  int *hcount = nullptr;
+  HIPCHK(hipHostMalloc((void **)&hcount, 2 * nj * sizeof(int), hipHostMallocDefault));
+  hopf_status rc = HOPF_OK;
   ctx->iter_launches = 0;
-  for (;;) {
-    k_setup<<<(unsigned)std::min<long>(npts, 2048), 256, 0, s>>>(S, st, o, mv);
-    k_sort<<<1, 1024, 0, s>>>(st, tab.N, 1);
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    HIPCHK(hipEventRecord(a, s));
-    if (fp32_esc) fp32_esc<<<ngrid, THREADS, lds_esc, s>>>(S, st, ho.check_every, 0);   // escalated points
-    fp<<<ngrid, THREADS, lds_pdhg, s>>>(S, st, ho.check_every, fp32_esc ? 1 : 2);
-    HIPCHK(hipEventRecord(b, s));
-    kev.push_back(a);
-    kev.push_back(b);
-    ctx->iter_launches++;
-    fc<<<ngrid, THREADS, lds_cert, s>>>(S, st, o, mode);
-    ++rounds;
-    if (rounds % 4 == 0 || rounds >= max_rounds) {
-      k_sort<<<1, 1024, 0, s>>>(st, tab.N, 0);   // refresh the active count
-      HIPCHK(hipMemcpyAsync(hcount, st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (hcount[0] == 0 || rounds >= max_rounds) break;
+  for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
+    Job &J = jobs[j];
+    J.sid = used[j];
+    J.tab = &ctx->sys[J.sid];
+    J.S = view(*J.tab);
+    J.npts = cnt[J.sid];
+    J.idx = nj > 1 ? d_idx + off[J.sid] : nullptr;
+    J.s = nj > 1 ? ctx->pool[j % NPOOL] : base;
+    J.ngrid = (unsigned)((J.npts + PTS_TILE - 1) / PTS_TILE);
+    J.max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
+    J.hcount = hcount + 2 * j;
+    if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
+    if (!make_state(ctx, j, *J.tab, J.npts, J.st)) {
+      rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
+      break;
+    }
+    for (int k = 0; k < 2 && rc == HOPF_OK; ++k)
+      if (hipEventCreateWithFlags(&J.gev[k], hipEventDisableTiming) != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "event");
+    if (rc != HOPF_OK) break;
+    if (J.s != base && hipStreamWaitEvent(J.s, ebase, 0) != hipSuccess) {
+      rc = set_err(ctx, HOPF_EDEVICE, "stream wait");
+      break;
+    }
+    if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM) && J.sid < (int)ctx->mlp.size() &&
+        ctx->mlp[J.sid].valid) {
+      const MlpState &w = ctx->mlp[J.sid];
+      J.mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
+    }
+    const PtState &st = J.st;
+    const long np_ = J.npts;
+    const hipStream_t s = J.s;
+    bool ok = hipMemsetAsync(st.rows, 0, np_ * sizeof(int), s) == hipSuccess &&
+              hipMemsetAsync(st.rowsum, 0, sizeof(double), s) == hipSuccess &&
+              hipMemsetAsync(st.partial, 0, np_ * sizeof(int), s) == hipSuccess &&
+              hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s) == hipSuccess &&
+              hipMemsetAsync(st.stage, 0, np_ * sizeof(int), s) == hipSuccess &&
+              hipMemsetAsync(st.esc, 0, np_ * sizeof(int), s) == hipSuccess &&
+              hipMemsetAsync(st.bT, 0, np_ * sizeof(float), s) == hipSuccess &&
+              hipMemsetAsync(st.bD, 0, np_ * sizeof(float), s) == hipSuccess;
+    if (!ok) {
+      rc = set_err(ctx, HOPF_EDEVICE, "hipMemsetAsync failed");
+      break;
+    }
+    const long tot = np_ * J.tab->n_pad;
+    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad,
+                                                         nj > 1 ? xs : J.tab->n, J.idx);
+    k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, mode, t_in, J.idx);
+  }
+  // ---- interleaved rounds: each job keeps up to two groups in flight
+  long live = rc == HOPF_OK ? nj : 0;
+  while (rc == HOPF_OK && live > 0) {
+    bool progressed = false;
+    for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
+      Job &J = jobs[j];
+      if (J.done) continue;
+      // read the oldest outstanding check if it has completed
+      if (J.gdone < J.ngroups) {
+        const hipError_t q = hipEventQuery(J.gev[J.gdone & 1]);
+        if (q == hipSuccess) {
+          const int c = J.hcount[J.gdone & 1];
+          ++J.gdone;
+          progressed = true;
+          if (c == 0 || J.rounds >= J.max_rounds) {
+            J.done = true;
+            --live;
+            continue;
+          }
+        } else if (q != hipErrorNotReady) {
+          rc = set_err(ctx, HOPF_EDEVICE, std::string("round check: ") + hipGetErrorString(q));
+          break;
+        }
+      }
+      if (J.ngroups - J.gdone < 2 && J.rounds < J.max_rounds) {
+        rc = issue_group(ctx, J, o, mode);
+        progressed = true;
+      }
+    }
+    if (rc != HOPF_OK) break;
+    if (!progressed) {   // every live job has two groups in flight: wait for the oldest check of one
+      for (int j = 0; j < nj; ++j)
+        if (!jobs[j].done && jobs[j].gdone < jobs[j].ngroups) {
+          if (hipEventSynchronize(jobs[j].gev[jobs[j].gdone & 1]) != hipSuccess)
+            rc = set_err(ctx, HOPF_EDEVICE, "round check failed");
+          break;
+        }
     }
   }
-  HIPCHK(hipGetLastError());
-  k_outputs<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(S, st, mode, T_out, gap_out, philo_out,
-                                                          phihi_out, lam_out, probes_out, iters_out, status_out);
-  HIPCHK(hipEventRecord(e1, s));
-  HIPCHK(hipStreamSynchronize(s));
+  if (rc == HOPF_OK) {
+    if (hipGetLastError() != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "kernel launch failed");
+  }
+  bool hit_limit = false;
+  double it_s = 0.0, rows_tot = 0.0, flops = 0.0;
+  for (int j = 0; j < nj; ++j) {
+    Job &J = jobs[j];
+    if (rc == HOPF_OK && J.st.x0) {
+      k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
+          J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,
+          J.idx, nj > 1 ? xs : J.tab->n);
+      hipEvent_t fin;
+      if (J.s != base && hipEventCreateWithFlags(&fin, hipEventDisableTiming) == hipSuccess) {
+        hipEventRecord(fin, J.s);
+        hipStreamWaitEvent(base, fin, 0);
+        hipEventDestroy(fin);
+      }
+    }
+    if (J.rounds >= J.max_rounds) hit_limit = true;
+  }
+  hipEventRecord(e1, base);
+  if (hipStreamSynchronize(base) != hipSuccess && rc == HOPF_OK) rc = set_err(ctx, HOPF_EDEVICE, "solve failed");
+  for (int j = 0; j < nj; ++j) {
+    Job &J = jobs[j];
+    for (size_t i = 0; i + 1 < J.kev.size(); i += 2) {
+      float km = 0.f;
+      if (rc == HOPF_OK) hipEventElapsedTime(&km, J.kev[i], J.kev[i + 1]);
+      it_s += km * 1e-3;
+      hipEventDestroy(J.kev[i]);
+      hipEventDestroy(J.kev[i + 1]);
+    }
+    if (rc == HOPF_OK && J.st.rowsum) {
+      double rs = 0.0;
+      hipMemcpy(&rs, J.st.rowsum, sizeof(double), hipMemcpyDeviceToHost);
+      // point-rows are summed once per round; each round runs check_every iterations
+      rows_tot += rs * ho.check_every;
+      flops += 4.0 * J.tab->m_user * J.tab->n * rs * ho.check_every;
+    }
+    if (rc == HOPF_OK && ctx->log_pt && j == 0) {
+      int lc = 0;
+      hipMemcpy(&lc, J.st.counters + 2, sizeof(int), hipMemcpyDeviceToHost);
+      ctx->log_count = std::min<long>(lc, ctx->log_cap);
+    }
+    for (int k = 0; k < 2; ++k)
+      if (J.gev[k]) hipEventDestroy(J.gev[k]);
+  }
   float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  if (rc == HOPF_OK) hipEventElapsedTime(&ms, e0, e1);
   ctx->t_total = ms * 1e-3;
-  double it_s = 0.0;
-  for (size_t i = 0; i + 1 < kev.size(); i += 2) {
-    float km = 0.f;
-    hipEventElapsedTime(&km, kev[i], kev[i + 1]);
-    it_s += km * 1e-3;
-    hipEventDestroy(kev[i]);
-    hipEventDestroy(kev[i + 1]);
-  }
   ctx->t_iter = it_s;
-  double rs = 0.0;
-  HIPCHK(hipMemcpy(&rs, st.rowsum, sizeof(double), hipMemcpyDeviceToHost));
-  // point-rows summed once per round; each round runs check_every iterations
-  ctx->point_rows = rs * ho.check_every;
-  if (ctx->log_pt) {
-    int lc = 0;
-    HIPCHK(hipMemcpy(&lc, st.counters + 2, sizeof(int), hipMemcpyDeviceToHost));
-    ctx->log_count = std::min<long>(lc, ctx->log_cap);
-  }
+  ctx->point_rows = rows_tot;
+  ctx->alg_flops = flops;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  hipEventDestroy(ebase);
+  if (nj > 1)
+    for (auto ps : ctx->pool) hipStreamSynchronize(ps);   // nothing of this call may outlive it
   hipHostFree(hcount);
-  if (rounds >= max_rounds) ctx->err = "round limit reached; unfinished points report NOCONV";
-  return HOPF_OK;
+  if (rc == HOPF_OK && hit_limit) ctx->err = "round limit reached; unfinished points report NOCONV";
+  return rc;
 }
 
 hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int *n_nodes, double *s_h,
@@ -801,7 +985,7 @@ hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int 
                    nullptr, nullptr);
     if (rc == HOPF_OK) {
       PtState st{};
-      if (!make_state(ctx, tab, 1, st)) rc = set_err(ctx, HOPF_ENOMEM, "point state");
+      if (!make_state(ctx, 0, tab, 1, st)) rc = set_err(ctx, HOPF_ENOMEM, "point state");
       else {
         k_traj<<<1, 256, 0, ctx->stream>>>(view(tab), st, T, ds, du, dxs, dp, dnn);
         if (hipStreamSynchronize(ctx->stream) != hipSuccess || hipGetLastError() != hipSuccess)
@@ -852,9 +1036,12 @@ static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, con
   if (mode == hopf::MODE_VALUE && !t) return hopf::set_err(c, HOPF_EINVAL, "t is required");
   if (npts == 0) return HOPF_OK;
   if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
-  int sid = sys_id ? sys_id[0] : 0;
-  if (sid < 0 || sid >= (int)c->sys.size()) return hopf::set_err(c, HOPF_EINVAL, "sys_id out of range");
-  const int n = c->sys[sid].n;
+  int n = 0;   // row stride of x and lam: the largest n among the systems used
+  for (long i = 0; i < (sys_id ? npts : 1); ++i) {
+    const int sid = sys_id ? sys_id[i] : 0;
+    if (sid < 0 || sid >= (int)c->sys.size()) return hopf::set_err(c, HOPF_EINVAL, "sys_id out of range");
+    n = std::max(n, c->sys[sid].n);
+  }
   if (mode == hopf::MODE_VALUE)
     for (long i = 0; i < npts; ++i)
       if (!(t[i] >= 0.0 && t[i] <= c->sys[sys_id ? sys_id[i] : 0].desc.t_max))

@@ -19,6 +19,7 @@ U_L2, U_BOX = 0, 1
 Q_TRAP, Q_LEFT = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
 WARM_COLD, WARM_CONT, WARM_MLP, WARM_MLP_LAM = 0, 1, 2, 3
+ROOT_BISECT, ROOT_NEWTON = 0, 1
 PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
 EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", "hopf_last_error",
@@ -38,7 +39,8 @@ class HopfSystem(C.Structure):
 class HopfOpts(C.Structure):
     _fields_ = [("c_tau", C.c_double), ("gap_tol", C.c_double), ("t_rel_tol", C.c_double),
                 ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
-                ("warm", C.c_int), ("prec", C.c_int)]
+                ("warm", C.c_int), ("prec", C.c_int), ("root", C.c_int), ("newton_after", C.c_int),
+                ("newton_rho", C.c_double)]
 
 
 class HopfError(RuntimeError):
@@ -71,7 +73,7 @@ def load(path: str = LIB_PATH):
     lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, ip, ip, ip]
     lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
-    lib.hopf_last_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_long), dp]
+    lib.hopf_last_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_long), dp, dp]
     fp = C.POINTER(C.c_float)
     lib.hopf_warm_init.argtypes = [vp, C.c_int, C.c_uint]
     lib.hopf_warm_params.argtypes = [vp, C.c_int, C.c_int, fp, C.c_long, fp]
@@ -165,15 +167,25 @@ class Solver:
                 v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(v, v)
             if k == "warm":
                 v = {"cold": WARM_COLD, "cont": WARM_CONT, "mlp": WARM_MLP, "mlp_lam": WARM_MLP_LAM}.get(v, v)
+            if k == "root":
+                v = {"bisect": ROOT_BISECT, "newton": ROOT_NEWTON}.get(v, v)
             setattr(o, k, v)
         self._check(self.lib.hopf_set_opts(self.h, C.byref(o)), "hopf_set_opts")
 
     # -------------------------------------------------------------- solves
+    def _stride(self, sid):
+        """Row width of x and lam: the largest n among the systems used."""
+        if sid is None or len(sid) == 0:
+            return self.n[0]
+        return max(self.n[int(k)] for k in np.unique(sid) if 0 <= int(k) < len(self.n))
+
     def value(self, x, t, sys_id=None):
         x = _f64(x)
         npts, n = x.shape
         t = _f64(np.broadcast_to(np.asarray(t, dtype=np.float64), (npts,)))
         sid = None if sys_id is None else np.ascontiguousarray(np.asarray(sys_id, dtype=np.int32))
+        if npts and n != self._stride(sid):
+            raise ValueError(f"x must have {self._stride(sid)} columns (the largest n of the systems used)")
         lo, hi = np.empty(npts), np.empty(npts)
         lam = np.empty((npts, n))
         iters = np.empty(npts, dtype=np.int32)
@@ -186,6 +198,8 @@ class Solver:
         x = _f64(x)
         npts, n = x.shape
         sid = None if sys_id is None else np.ascontiguousarray(np.asarray(sys_id, dtype=np.int32))
+        if npts and n != self._stride(sid):
+            raise ValueError(f"x must have {self._stride(sid)} columns (the largest n of the systems used)")
         T, gap = np.empty(npts), np.empty(npts)
         lam = np.empty((npts, n))
         probes = np.empty(npts, dtype=np.int32)
@@ -264,8 +278,9 @@ class Solver:
         return dict(epoch_loss=el[:epochs], pairs=pairs.value)
 
     def last_timing(self):
-        a, b, d = C.c_double(), C.c_double(), C.c_double()
+        a, b, d, f = C.c_double(), C.c_double(), C.c_double(), C.c_double()
         c = C.c_long()
-        self._check(self.lib.hopf_last_timing(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
-                    "hopf_last_timing")
-        return dict(total_s=a.value, iter_kernel_s=b.value, iter_launches=c.value, point_rows=d.value)
+        self._check(self.lib.hopf_last_timing(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
+                                              C.byref(f)), "hopf_last_timing")
+        return dict(total_s=a.value, iter_kernel_s=b.value, iter_launches=c.value, point_rows=d.value,
+                    alg_flops=f.value)

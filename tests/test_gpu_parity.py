@@ -241,3 +241,34 @@ def test_value_bf16_c3_shape(solver):
     for k in (0, 21, 63):
         pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=5.0))
         assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), (k, b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi)
+
+# ------------------------------------------------------------------ hybrid Newton-bisection
+
+@pytest.mark.parametrize("prec,case", [("fp64", "di"), ("fp32", "di"), ("fp32", "l2"), ("fp32", "box")])
+def test_min_time_newton_vs_oracle(solver, prec, case):
+    """Sec. IV hybrid on the device against the oracle's hybrid: same
+    statuses, |dT| <= 1e-4 T, gap <= 1e-6; fewer probes than bisection."""
+    say("case: min_time newton", prec, case)
+    if case == "di":
+        spec, c_tau = double_integrator(0.1, 100), 30.0
+        x = uniform_box_points(24, 2, -2.0, 2.0, seed=1)
+    else:
+        spec, c_tau = random_system(12, 2 if case == "l2" else 3, 50, case, seed=5, t_max=4.0), 1.0
+        x = gaussian_points(20, 12, 0.12, seed=8)
+    solver.set_systems([spec])
+    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont")
+    rb = solver.min_time(x)
+    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont", root="newton")
+    rn = solver.min_time(x)
+    say("probes bisect", rb["probes"].mean(), "newton", rn["probes"].mean(),
+        "iters", rb["iters"].mean(), rn["iters"].mean())
+    assert np.array_equal(rb["status"], rn["status"])
+    ok = rn["status"] == 0
+    assert rn["probes"][ok].mean() < rb["probes"][ok].mean()
+    assert np.all(rn["gap"][ok] <= GAP)
+    S = osys(spec)
+    for k in range(0, len(x), 4):
+        o = O.min_time(S, x[k], O.Options(c_tau=c_tau, warm="cont", root="newton"))
+        assert rn["status"][k] == o.status, (k, rn["status"][k], o.status)
+        if o.status == O.PT_OK:
+            assert abs(rn["T"][k] - o.T) <= 1e-4 * o.T, (k, rn["T"][k], o.T)

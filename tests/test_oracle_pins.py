@@ -364,3 +364,78 @@ def test_unreachable_and_inside_statuses():
     assert r.status == O.PT_INSIDE and r.T == 0.0
     r = O.min_time(S, np.array([np.nan, 0.0]))
     assert r.status == O.PT_NONFINITE
+
+
+# ------------------------------------------------------------------ hybrid Newton-bisection (Sec. IV)
+
+def test_value_slope_is_exact_left_rule_derivative():
+    """For the left rule the discrete value is differentiable between grid
+    points with d phi_N/dT = <A x_f, lam*> - sigma_C(K_M lam*) (envelope
+    theorem: only x_f and the last weight r depend on T).  Central finite
+    differences of tightly solved values must match the slope from lam*."""
+    spec = random_system(5, 2, 40, "l2", seed=14, t_max=4.0, quad="left")
+    S = sysobj(spec)
+    x = np.array([0.7, -0.4, 0.5, 0.2, -0.3])
+    opt = O.Options(gap_tol=1e-13, max_iter=3000000, check_every=50)
+    h = O.grid_step(S)
+    for T in (0.37 * 4.0 + 0.3 * h, 2.0 + 0.55 * h):
+        d = 1e-4 * h                   # stays between two grid points
+        a = O.solve_value(S, x, T - d, opt)
+        b = O.solve_value(S, x, T + d, opt)
+        mid = O.solve_value(S, x, T, opt)
+        fd = (-0.5 * (b.P + b.D) + 0.5 * (a.P + a.D)) / (2 * d)
+        s = O.value_slope(S, mid)
+        assert abs(fd - s) <= 1e-5 * max(1.0, abs(s)), (T, fd, s)
+
+
+def test_value_slope_sign_flip_fails():
+    """The slope is negative where the target is being approached: a flipped
+    sign of either term would break the Newton step (integrator closed form
+    d phi/dT = -(||x|| - T)/r^2 for the unit l2 ball)."""
+    r = 0.3
+    S = ball_system(3, r, O.L2, N=40, t_max=5.0)
+    x = np.array([0.9, -0.4, 0.2])
+    T = 0.5
+    pr = O.solve_value(S, x, T, O.Options(gap_tol=1e-12, max_iter=400000))
+    exact = -(np.linalg.norm(x) - T) / (r * r)
+    assert abs(O.value_slope(S, pr) - exact) <= 1e-5 * abs(exact)
+
+
+@pytest.mark.parametrize("x", [[0.9, -0.4, 0.2], [2.0, 1.0, 0.5], [1.1, 0.3, -0.7]])
+def test_newton_min_time_l2_ball_closed_form(x):
+    """Hybrid Newton-bisection finds T* = ||x|| - r within the stopping
+    tolerance, in fewer probes than bisection."""
+    r = 0.3
+    S = ball_system(3, r, O.L2, N=40, t_max=5.0)
+    exact = np.linalg.norm(x) - r
+    rn = O.min_time(S, np.array(x), O.Options(c_tau=1.0, root="newton", warm="cont"))
+    rb = O.min_time(S, np.array(x), O.Options(c_tau=1.0, warm="cont"))
+    assert rn.status == O.PT_OK and rn.lo <= exact + 1e-9 <= rn.hi + 2e-9
+    assert abs(rn.T - exact) <= 1e-4 * exact and rn.gap_n <= 1e-6
+    assert rn.probes < rb.probes
+
+
+def test_newton_double_integrator_vs_bang_bang():
+    """Same bang-bang anchors as bisection (Sec. VI-A system)."""
+    spec = double_integrator(0.1, 100)
+    S = sysobj(spec)
+    for x in [(1.0, 0.0), (-0.5, 1.0), (1.2, -0.8)]:
+        Tc = PH.di_min_time_ball(x[0], x[1], 0.1)
+        res = O.min_time(S, np.array(x), O.Options(c_tau=30.0, root="newton", warm="cont"))
+        assert res.status == O.PT_OK
+        assert abs(res.T - Tc) <= 3e-4 * Tc + 0.02 * O.grid_step(S) ** 2, (x, res.T, Tc)
+
+
+def test_newton_and_bisection_bracket_the_same_crossing():
+    """On a random system the two searches end on brackets of width <= tol
+    that overlap (the same sign change of phi_N)."""
+    spec = random_system(8, 2, 50, "l2", seed=5, t_max=4.0)
+    S = sysobj(spec)
+    from gen.workloads import planted_drift_points
+    xs, _ = planted_drift_points(spec, 4, 0.3, 2.5, seed=2)
+    for x in xs:
+        rb = O.min_time(S, x, O.Options(c_tau=1.0, warm="cont"))
+        rn = O.min_time(S, x, O.Options(c_tau=1.0, warm="cont", root="newton"))
+        assert rb.status == rn.status == O.PT_OK
+        assert max(rb.lo, rn.lo) <= min(rb.hi, rn.hi) + 1e-12
+        assert abs(rb.T - rn.T) <= 1e-4 * rb.T
