@@ -155,7 +155,7 @@ def main():
             step()
             print(f"[{mode}] warmup step {i + 1}/{nwarm} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        tk, launches, rows = 0.0, 0, 0.0
+        tk, launches, rows, ttail, tpts = 0.0, 0, 0.0, 0.0, 0
         t0 = time.perf_counter()
         for i in range(nsteps):
             step()
@@ -163,10 +163,13 @@ def main():
             tk += tm["iter_kernel_s"]
             launches += tm["iter_launches"]
             rows += tm["point_rows"]
+            ttail += tm["tail_kernel_s"]
+            tpts += tm["tail_points"]
             print(f"[{mode}] step {i + 1}/{nsteps}: device {tm['total_s']:.3f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = {"qps": npts * nsteps / dt, "ms": 1e3 * dt / nsteps, "tk": tk, "launches": launches, "rows": rows,
+               "ttail": ttail, "tpts": tpts,
                "status": status.cpu().numpy().copy(), "T": T.cpu().numpy().copy(), "gap": gap.cpu().numpy().copy(),
                "iters": iters.cpu().numpy().copy(), "probes": probes.cpu().numpy().copy()}
         return res
@@ -198,6 +201,8 @@ def main():
                        "max_iters": int(v["iters"].max()),
                        "iter_kernel_s": round(v["tk"] / max(1, args.steps), 3),
                        "iter_launches": int(v["launches"] // max(1, args.steps)),
+                       "tail_kernel_s": round(v["ttail"] / max(1, args.steps), 3),
+                       "tail_points": int(v["tpts"] // max(1, args.steps)),
                        "T_equal_to_cont_frac": round(float(same[okk].mean()) if okk.any() else 1.0, 5)}
     st, Tn, gn, itn = status_np, T_np, gap_np, it_np
     ok = st == 0

@@ -116,12 +116,18 @@ typedef struct {
  *                 before Newton steps start                                          [3]
  *   newton_rho    hybrid only: from probe newton_after on, a probe also runs until
  *                 P - D <= newton_rho |P + D| / 2 so the Newton step sees an accurate
- *                 value                                                              [0.5] */
+ *                 value                                                              [0.5]
+ *   tail_max      FP32 iterations: once at most tail_max of a system's points are
+ *                 still running, a per-point solver (one workgroup per point,
+ *                 matrix-vector iterations, certificate and search step in one
+ *                 launch) finishes them; 0 keeps every point on the 16-point tiles
+ *                 (at most 512)                                                      [0] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;
   int root, newton_after;
   double newton_rho;
+  int tail_max;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);
@@ -207,16 +213,31 @@ hopf_status hopf_warm_loss_grad(hopf_ctx *ctx, int sys_id, int nrows, const floa
 hopf_status hopf_warm_train(hopf_ctx *ctx, int sys_id, long npts, const double *x, int epochs, int batch,
                             float lr, unsigned seed, double *epoch_loss, long *pairs);
 
-/* Seconds spent on the device by the last solve call (HIP events around the
- * whole call on the caller's or the context's stream) and by the fused
- * iteration kernels alone (summed over launches; the launches of a
- * multi-system call run on several streams and can overlap), their launch
- * count, the point-rows they processed (one row = one quadrature node of one
- * point in one iteration) and the algorithmic flops, 4 m n per point-row
- * (K lam and K^T y), summed over the systems of the call; for throughput
- * and roofline reporting. */
-hopf_status hopf_last_timing(const hopf_ctx *ctx, double *total_s, double *iter_kernel_s,
-                             long *iter_launches, double *iter_point_rows, double *alg_flops);
+/* Device time and work of the last solve call, for throughput and roofline
+ * reporting.  A call runs rounds of tiled kernels (16 points per tile: probe
+ * setup, fused iteration kernel, FP64 certificate) and, once at most 512 of
+ * a system's points remain (FP32 iterations), a per-point tail solver that
+ * finishes them in one launch.
+ *   total_s          HIP events around the whole call
+ *   iter_kernel_s    the tiled iteration kernels alone, summed over launches
+ *                    (the launches of a multi-system call can overlap)
+ *   iter_launches    their launch count
+ *   iter_point_rows  point-rows they processed (one row = one quadrature node
+ *                    of one point in one iteration)
+ *   alg_flops        algorithmic flops of all iterations, 4 m n per point-row
+ *                    (K lam and K^T y), summed over the systems of the call
+ *   tail_kernel_s    the tail solver's launches (iterations, certificates and
+ *                    probe setups of the points it finished)
+ *   tail_point_rows  point-rows iterated by the tail solver
+ *   tail_points      points handed to it */
+typedef struct {
+  double total_s, iter_kernel_s;
+  long iter_launches;
+  double iter_point_rows, alg_flops, tail_kernel_s, tail_point_rows;
+  long tail_points;
+} hopf_timing;
+
+hopf_status hopf_last_timing(const hopf_ctx *ctx, hopf_timing *out);
 
 #ifdef __cplusplus
 }

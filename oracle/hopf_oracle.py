@@ -416,7 +416,11 @@ def value_slope(sys: System, pr: Probe):
     return float((sys.A @ pr.xf) @ lam - support(pr.Ks[-1] @ lam, sys.uset))
 
 
-def next_horizon(sys: System, opt: Options, pr: Probe, reached: bool, lo: float, hi: float):
+NEWTON_MAX_PROBES = 48     # from this probe on the hybrid takes midpoints only (termination)
+
+
+def next_horizon(sys: System, opt: Options, pr: Probe, reached: bool, lo: float, hi: float,
+                 probes: int = 0):
     """Next probe of the root search on the certified bracket [lo, hi].
 
     Bisection: the midpoint.  Hybrid (Sec. IV): the Newton step
@@ -424,14 +428,16 @@ def next_horizon(sys: System, opt: Options, pr: Probe, reached: bool, lo: float,
     its certified interval [-P, -D]; the step is moved 0.4 of the stopping
     tolerance towards the side of the root not yet bracketed (so that an
     accurate step closes the bracket in one probe), and is replaced by the
-    midpoint when it falls outside (lo, hi) or the slope is not negative.
+    midpoint when it falls outside (lo, hi), the slope is not negative, or
+    the probe count (including the probe just certified) has reached
+    NEWTON_MAX_PROBES, which bounds the search.
     Newton steps start once the probe count reaches newton_after (earlier
     probes are placed by bisection: where phi_N changes sign more than once,
     a Newton step from t_max heads for the last crossing), and those probes
     run until P - D <= newton_rho |P + D| / 2 so that the step sees an
     accurate value.  Returns (T_next, newton_used)."""
     mid = 0.5 * (lo + hi)
-    if opt.root != "newton" or not pr.tight:
+    if opt.root != "newton" or not pr.tight or probes >= NEWTON_MAX_PROBES:
         return mid, False
     s = value_slope(sys, pr)
     if not (s < 0.0) or not math.isfinite(s):
@@ -476,7 +482,7 @@ def min_time(sys: System, x0, opt: Options = Options()):
     lo, hi = 0.0, sys.t_max
     last, last_is_hi = pr, True
     while hi - lo > max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max):
-        nxt, _ = next_horizon(sys, opt, last, last_is_hi, lo, hi)
+        nxt, _ = next_horizon(sys, opt, last, last_is_hi, lo, hi, probes)
         if opt.warm == "cont":
             pr = make_probe(sys, x0, nxt, opt, last.lam, last.y)
         else:

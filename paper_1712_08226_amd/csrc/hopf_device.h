@@ -15,6 +15,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int WAVES = 4;
 constexpr int PTS_WAVE = 16;
 constexpr int PTS_WG = WAVES * PTS_WAVE;
+constexpr int NEWTON_MAX_PROBES = 48;   // hybrid search: bisection only from this probe on
 constexpr int PTS_TILE = 16;       // points per workgroup in the iteration and certificate kernels
 constexpr int THREADS = WAVES * 64;
 constexpr int LDS_BYTES = 76 * 1024;
@@ -413,6 +414,102 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 
 // ------------------------------------------------------------------ FP64 certificate + decisions
 
+// Certificate bookkeeping and the search step for point p (Sec. IV): the
+// certified interval [-P, -D] from the FP64 sums (sP = 1/2 lam^T W lam -
+// <x_f - c, lam>, wsig = sum_k w_k sigma_C(K_k lam), sJ = (x_T - c)^T W^-1
+// (x_T - c)), the sign or gap decision, the bracket update and the next
+// horizon (midpoint, hybrid Newton step with slope sAx - slast, or the
+// learned bracket).  Returns true when the point needs a probe setup at the
+// new horizon st.T[p].
+__device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long p, int np, double sP,
+                       double wsig, double sJ, double sAx, double slast) {
+  // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J)
+  const double Pv = fmin(sP + 0.5 + wsig, 0.5);
+  const double Dv = -0.5 * (sJ - 1.0);
+  st.P[p] = Pv;
+  st.D[p] = Dv;
+  const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
+  const int ph = st.phase[p];
+  const double T = st.T[p];
+  if (!isfinite(Pv) || !isfinite(Dv)) {
+    st.status[p] = HOPF_PT_NONFINITE;
+    st.phase[p] = PH_DONE;
+    return false;
+  }
+  if (ph == PH_FINAL) {
+    if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); return false; }
+    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
+    return false;
+  }
+  // probe: certified sign of phi_N(x, T); with the Newton hybrid, probes
+  // from newton_after on also need a value accurate to newton_rho relative
+  const bool tight = o.root == HOPF_ROOT_NEWTON && st.probes[p] >= o.newton_after;
+  const bool newton_ok = tight && st.probes[p] < NEWTON_MAX_PROBES;   // afterwards: bisection only
+  int outcome = -1;   // 1 reach, 0 unreach
+  if (gap <= o.gap_tol) outcome = (-Pv > 0.0) ? 0 : 1;
+  else if (tight && Pv - Dv > o.newton_rho * 0.5 * fabs(Pv + Dv)) outcome = -1;
+  else if (-Dv <= 0.0) outcome = 1;
+  else if (-Pv > 0.0) outcome = 0;
+  if (outcome < 0) {
+    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
+    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
+    return false;
+  }
+  log_probe(st, p, np);
+  const bool first = st.probes[p] == 1;
+  if (outcome == 0 && first) {       // unreachable at t_max
+    st.status[p] = HOPF_PT_UNREACH;
+    st.phase[p] = PH_DONE;
+    st.T[p] = INFINITY;
+    st.hi[p] = INFINITY;
+    return false;
+  }
+  double lo = st.lo[p], hi = st.hi[p];
+  if (outcome == 1) hi = T; else lo = T;
+  st.lo[p] = lo;
+  st.hi[p] = hi;
+  st.last_reach[p] = outcome;
+  if (hi - lo <= fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max)) {
+    st.phase[p] = PH_FINAL;
+    if (outcome == 1) {
+      if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); }   // already certified at T = hi
+    } else {
+      st.T[p] = hi;
+      return true;
+    }
+    return false;
+  }
+  // next probe: the midpoint; the Newton step of Sec. IV (hybrid); or
+  // (learned warm start) the network's proposed bracket ends right after the
+  // certified probe at t_max
+  double Tn = 0.5 * (lo + hi);
+  if (newton_ok) {
+    const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
+    if (slope < 0.0 && isfinite(slope)) {
+      const double phi = -0.5 * (Pv + Dv);
+      const double tl = fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max);
+      const double tn = T - phi / slope + (outcome == 1 ? -0.4 * tl : 0.4 * tl);
+      if (tn > lo && tn < hi) Tn = tn;
+    }
+  }
+  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.bT[p] > 0.0f) {
+    const int stg = st.stage[p];
+    if (first && outcome == 1) {
+      const double hi0 = (double)st.bT[p] * exp((double)st.bD[p]);
+      if (hi0 > lo && hi0 < hi) Tn = hi0;
+      st.stage[p] = 1;
+    } else if (stg == 1) {
+      const double lo0 = (double)st.bT[p] * exp(-(double)st.bD[p]);
+      if (lo0 > lo && lo0 < hi) Tn = lo0;
+      st.stage[p] = 0;
+    }
+  }
+  st.T[p] = Tn;
+  return true;
+}
+
+
 // Per point: P(lam) from K lam, D(y^) from K^T y^ with y^ the FP64
 // projection of the stored y onto w_k C (moved onto the boundary when within
 // 1e-5 of it; any point of w_k C gives a valid bound).  Then the sign / gap
@@ -689,89 +786,7 @@ __global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts
   wsig += __shfl_xor(wsig, 16); wsig += __shfl_xor(wsig, 32);
   if (!live || g != 0) return;
 
-  // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J)
-  const double Pv = fmin(sP + 0.5 + wsig, 0.5);
-  const double Dv = -0.5 * (sJ - 1.0);
-  st.P[p] = Pv;
-  st.D[p] = Dv;
-  const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
-  const int ph = st.phase[p];
-  const double T = st.T[p];
-  if (!isfinite(Pv) || !isfinite(Dv)) {
-    st.status[p] = HOPF_PT_NONFINITE;
-    st.phase[p] = PH_DONE;
-    return;
-  }
-  if (ph == PH_FINAL) {
-    if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); return; }
-    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
-    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
-    return;
-  }
-  // probe: certified sign of phi_N(x, T); with the Newton hybrid, probes
-  // from newton_after on also need a value accurate to newton_rho relative
-  const bool tight = o.root == HOPF_ROOT_NEWTON && st.probes[p] >= o.newton_after;
-  int outcome = -1;   // 1 reach, 0 unreach
-  if (gap <= o.gap_tol) outcome = (-Pv > 0.0) ? 0 : 1;
-  else if (tight && Pv - Dv > o.newton_rho * 0.5 * fabs(Pv + Dv)) outcome = -1;
-  else if (-Dv <= 0.0) outcome = 1;
-  else if (-Pv > 0.0) outcome = 0;
-  if (outcome < 0) {
-    if (st.iters_probe[p] >= o.max_iter) { st.status[p] = HOPF_PT_NOCONV; st.phase[p] = PH_DONE; }
-    else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
-    return;
-  }
-  log_probe(st, p, np);
-  const bool first = st.probes[p] == 1;
-  if (outcome == 0 && first) {       // unreachable at t_max
-    st.status[p] = HOPF_PT_UNREACH;
-    st.phase[p] = PH_DONE;
-    st.T[p] = INFINITY;
-    st.hi[p] = INFINITY;
-    return;
-  }
-  double lo = st.lo[p], hi = st.hi[p];
-  if (outcome == 1) hi = T; else lo = T;
-  st.lo[p] = lo;
-  st.hi[p] = hi;
-  st.last_reach[p] = outcome;
-  if (hi - lo <= fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max)) {
-    st.phase[p] = PH_FINAL;
-    if (outcome == 1) {
-      if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); }   // already certified at T = hi
-    } else {
-      st.T[p] = hi;
-      mark_setup(st, p);
-    }
-    return;
-  }
-  // next probe: the midpoint; the Newton step of Sec. IV (hybrid); or
-  // (learned warm start) the network's proposed bracket ends right after the
-  // certified probe at t_max
-  double Tn = 0.5 * (lo + hi);
-  if (tight) {
-    const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
-    if (slope < 0.0 && isfinite(slope)) {
-      const double phi = -0.5 * (Pv + Dv);
-      const double tl = fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max);
-      const double tn = T - phi / slope + (outcome == 1 ? -0.4 * tl : 0.4 * tl);
-      if (tn > lo && tn < hi) Tn = tn;
-    }
-  }
-  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.bT[p] > 0.0f) {
-    const int stg = st.stage[p];
-    if (first && outcome == 1) {
-      const double hi0 = (double)st.bT[p] * exp((double)st.bD[p]);
-      if (hi0 > lo && hi0 < hi) Tn = hi0;
-      st.stage[p] = 1;
-    } else if (stg == 1) {
-      const double lo0 = (double)st.bT[p] * exp(-(double)st.bD[p]);
-      if (lo0 > lo && lo0 < hi) Tn = lo0;
-      st.stage[p] = 0;
-    }
-  }
-  st.T[p] = Tn;
-  mark_setup(st, p);
+  if (decide(S, st, o, p, np, sP, wsig, sJ, sAx, slast)) mark_setup(st, p);
 }
 
 

@@ -69,7 +69,8 @@ struct Ctx {
   long log_count = 0;
   // timing of the last solve
   double t_total = 0.0, t_iter = 0.0, point_rows = 0.0, alg_flops = 0.0;
-  long iter_launches = 0;
+  double t_tail = 0.0, tail_rows = 0.0;
+  long iter_launches = 0, tail_points = 0;
   // point-state buffers of each job (one job per system in a call), grown on demand
   struct Buf { void *p = nullptr; size_t bytes = 0; };
   std::vector<std::vector<Buf>> jbufs;

@@ -376,6 +376,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->root = HOPF_ROOT_BISECT;
   o->newton_after = 3;
   o->newton_rho = 0.5;
+  o->tail_max = 0;
   return HOPF_OK;
 }
 
@@ -436,7 +437,8 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 2 ||
-      o->root < 0 || o->root > 1 || o->newton_after < 1 || !(o->newton_rho > 0.0))
+      o->root < 0 || o->root > 1 || o->newton_after < 1 || !(o->newton_rho > 0.0) ||
+      o->tail_max < 0 || o->tail_max > 512)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;
@@ -465,15 +467,17 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
   return HOPF_OK;
 }
 
-hopf_status hopf_last_timing(const hopf_ctx *h, double *total_s, double *iter_s, long *launches,
-                             double *point_rows, double *alg_flops) {
+hopf_status hopf_last_timing(const hopf_ctx *h, hopf_timing *out) {
   const Ctx *c = reinterpret_cast<const Ctx *>(h);
-  if (!c) return HOPF_EINVAL;
-  if (total_s) *total_s = c->t_total;
-  if (iter_s) *iter_s = c->t_iter;
-  if (launches) *launches = c->iter_launches;
-  if (point_rows) *point_rows = c->point_rows;
-  if (alg_flops) *alg_flops = c->alg_flops;
+  if (!c || !out) return HOPF_EINVAL;
+  out->total_s = c->t_total;
+  out->iter_kernel_s = c->t_iter;
+  out->iter_launches = c->iter_launches;
+  out->iter_point_rows = c->point_rows;
+  out->alg_flops = c->alg_flops;
+  out->tail_kernel_s = c->t_tail;
+  out->tail_point_rows = c->tail_rows;
+  out->tail_points = c->tail_points;
   return HOPF_OK;
 }
 

@@ -323,6 +323,307 @@ __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, Ml
   }
 }
 
+// ------------------------------------------------------------------ per-point tail solver
+
+// When few points remain, a 16-point MFMA tile is mostly empty and a round
+// (setup, sort, iteration and certificate launches) costs the same however
+// few points it carries.  The tail solver gives each remaining point a
+// workgroup of its own and runs the rest of its search inside one launch:
+// FP32 iterations as matrix-vector products (the node table streams from L2,
+// chunks of node blocks staged in LDS), the FP64 certificate and the search
+// step (decide) every check_every iterations, and the next probe's setup in
+// place.  The arithmetic is the same as the tiled path's (same tables, same
+// projections, same certificate); only the summation order differs.
+constexpr int TAIL_MAX_POINTS = 512;
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+
+// Dynamic LDS (bytes): bop 256 floats | vb 16*CB*m doubles | gp 256 doubles |
+// l64 256 doubles | red 5*256 doubles.
+__host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 64 ? 1 : (64 / m < 16 ? 64 / m : 16); }
+__host__ __device__ inline size_t tail_lds_bytes(int m) {
+  return 256 * 4 + (size_t)16 * tail_chunk_blocks(m) * m * 8 + 256 * 8 + 256 * 8 + 5 * 256 * 8;
+}
+
+__global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, MlpView mv) {
+  extern __shared__ __align__(16) unsigned char tl_raw[];
+  __shared__ int s_ctl;
+  if ((int)blockIdx.x >= st.counters[0]) return;
+  const long p = st.perm[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = S.m, np = S.n_pad, n = S.n;
+  const int CB = tail_chunk_blocks(m);
+  const int P2 = np <= 16 ? 16 : np <= 32 ? 32 : np <= 64 ? 64 : np <= 128 ? 128 : 256;
+  const int RG = 256 / P2, ig = tid % P2, rg = tid / P2;
+  float *bop = reinterpret_cast<float *>(tl_raw);
+  double *vb = reinterpret_cast<double *>(tl_raw + 256 * 4);
+  float *vbf = reinterpret_cast<float *>(vb);
+  double *gp = vb + 16 * CB * m;
+  float *gpf = reinterpret_cast<float *>(gp);
+  double *l64 = gp + 256;
+  double *red = l64 + 256;
+  float *yp = st.y + (size_t)p * st.ystride;
+  const int mp = st.mpad;
+  // every interval runs check_every iterations; the search ends within
+  // NEWTON_MAX_PROBES + 64 probes of at most max_iter iterations each
+  const long guard_max = (long)(NEWTON_MAX_PROBES + 64) * (o.max_iter / o.check_every + 2);
+  for (long guard = 0; guard < guard_max; ++guard) {
+    if (tid == 0) s_ctl = st.phase[p];
+    __syncthreads();
+    if (s_ctl == PH_DONE) break;
+    const int rows = st.rows[p], M = st.M[p], part = st.partial[p];
+    const double rr = st.r[p];
+    const int nkb = (rows + NODE_BLOCK - 1) / NODE_BLOCK;
+    const float tau = (float)st.tau[p], sig = (float)st.sig[p];
+    float lam_i = 0.f, xfc = 0.f, wd = 1.f;
+    if (tid < np) {
+      lam_i = st.lam[p * np + tid];
+      xfc = st.xfc32[p * np + tid];
+      wd = (float)S.Wd[tid];
+    }
+    bop[tid] = tid < np ? sig * st.lamb[p * np + tid] : 0.f;
+    // ---------------- check_every FP32 iterations
+    for (int it = 0; it < o.check_every; ++it) {
+      float gacc = 0.f;
+      __syncthreads();                       // bop of this iteration
+      for (int kb0 = 0; kb0 < nkb; kb0 += CB) {
+        const int cb = min(CB, nkb - kb0), nsl = cb * m;
+        {   // dual: V = K (sigma lam_bar), 16 lanes per (block, component) slab
+          const int gi = tid >> 4, kk = tid & 15;
+          for (int sl = gi; sl < nsl; sl += 16) {
+            const int kbl = sl / m, j = sl % m;
+            const float *a = S.K32T + ((size_t)((kb0 + kbl) * m + j) * np) * NODE_BLOCK + kk;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            for (int i = 0; i < np; i += 4) {
+              a0 += a[(size_t)i * NODE_BLOCK] * bop[i];
+              a1 += a[(size_t)(i + 1) * NODE_BLOCK] * bop[i + 1];
+              a2 += a[(size_t)(i + 2) * NODE_BLOCK] * bop[i + 2];
+              a3 += a[(size_t)(i + 3) * NODE_BLOCK] * bop[i + 3];
+            }
+            vbf[sl * NODE_BLOCK + kk] = (a0 + a1) + (a2 + a3);
+          }
+        }
+        __syncthreads();
+        if (tid < cb * NODE_BLOCK) {   // y_k = projection of y_k + V_k onto w_k C, one node per thread
+          const int kbl = tid >> 4, kk = tid & 15, k = (kb0 + kbl) * NODE_BLOCK + kk;
+          const float w = (k < rows) ? (float)node_weight(k, M, rr, S.h, S.quad) : 0.f;
+          float *yr = yp + (size_t)(kb0 + kbl) * m * NODE_BLOCK + kk;
+          float *vr = vbf + kbl * m * NODE_BLOCK + kk;
+          if (S.uset == HOPF_U_L2) {
+            float ss = 0.f;
+            for (int j = 0; j < m; ++j) {
+              const float v = yr[j * NODE_BLOCK] + vr[j * NODE_BLOCK];
+              vr[j * NODE_BLOCK] = v;
+              ss += v * v;
+            }
+            const float nv = sqrtf(ss);
+            const float sc = (nv > w) ? (nv > 0.f ? w / nv : 0.f) : 1.f;
+            for (int j = 0; j < m; ++j) {
+              const float v = vr[j * NODE_BLOCK] * sc;
+              vr[j * NODE_BLOCK] = v;
+              yr[j * NODE_BLOCK] = v;
+            }
+          } else {
+            for (int j = 0; j < m; ++j) {
+              const float v = fminf(fmaxf(yr[j * NODE_BLOCK] + vr[j * NODE_BLOCK], -w), w);
+              vr[j * NODE_BLOCK] = v;
+              yr[j * NODE_BLOCK] = v;
+            }
+          }
+        }
+        __syncthreads();
+        if (ig < np) {   // primal: G += K^T y over this chunk's rows
+          const float *a = S.K32 + (size_t)kb0 * m * NODE_BLOCK * np + ig;
+          const int nrow = nsl * NODE_BLOCK;
+          for (int row = rg; row < nrow; row += RG) gacc += a[(size_t)row * np] * vbf[row];
+        }
+        __syncthreads();
+      }
+      if (part) {   // the private node at tau = T with weight r/2
+        for (int j = wave; j < m; j += 4) {
+          const float *row = st.R32 + ((size_t)p * m + j) * np;
+          float acc = 0.f;
+          for (int i = lane; i < np; i += 64) acc += row[i] * bop[i];
+          acc = wave_sum_f(acc);
+          if (lane == 0) vbf[j] = st.yR[(size_t)p * mp + j] + acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          const float wR = (float)(0.5 * rr);
+          if (S.uset == HOPF_U_L2) {
+            float ss = 0.f;
+            for (int j = 0; j < m; ++j) ss += vbf[j] * vbf[j];
+            const float nv = sqrtf(ss);
+            const float sc = (nv > wR) ? (nv > 0.f ? wR / nv : 0.f) : 1.f;
+            for (int j = 0; j < m; ++j) vbf[j] *= sc;
+          } else {
+            for (int j = 0; j < m; ++j) vbf[j] = fminf(fmaxf(vbf[j], -wR), wR);
+          }
+          for (int j = 0; j < m; ++j) st.yR[(size_t)p * mp + j] = vbf[j];
+        }
+        __syncthreads();
+        if (rg == 0 && ig < np)
+          for (int j = 0; j < m; ++j) gacc += st.R32[((size_t)p * m + j) * np + ig] * vbf[j];
+      }
+      gpf[tid] = gacc;
+      __syncthreads();
+      if (tid < np) {   // lam+ = (lam - tau (K^T y - (x_f - c))) / (1 + tau W);  theta = 1
+        float gs = 0.f;
+        for (int r2 = 0; r2 < RG; ++r2) gs += gpf[r2 * P2 + tid];
+        const float ln = (lam_i - tau * (gs - xfc)) / (1.f + tau * wd);
+        bop[tid] = sig * (2.f * ln - lam_i);
+        lam_i = ln;
+      }
+    }
+    __syncthreads();
+    if (tid < np) {
+      st.lam[p * np + tid] = lam_i;
+      st.lamb[p * np + tid] = sig > 0.f ? bop[tid] / sig : 0.f;
+      l64[tid] = (double)lam_i;
+    }
+    if (tid == 0) {
+      st.iters_probe[p] += o.check_every;
+      st.iters_tot[p] += o.check_every;
+      atomicAdd(&st.rowsum[1], (double)(rows + part));
+    }
+    __syncthreads();
+    // ---------------- FP64 certificate from (lam, y)
+    double wsig = 0.0, slast = 0.0, g64 = 0.0;
+    for (int kb0 = 0; kb0 < nkb; kb0 += CB) {
+      const int cb = min(CB, nkb - kb0), nsl = cb * m;
+      {
+        const int gi = tid >> 4, kk = tid & 15;
+        for (int sl = gi; sl < nsl; sl += 16) {
+          const int kbl = sl / m, j = sl % m;
+          const double *a = S.K64T + ((size_t)((kb0 + kbl) * m + j) * np) * NODE_BLOCK + kk;
+          double a0 = 0.0, a1 = 0.0;
+          for (int i = 0; i < np; i += 2) {
+            a0 += a[(size_t)i * NODE_BLOCK] * l64[i];
+            a1 += a[(size_t)(i + 1) * NODE_BLOCK] * l64[i + 1];
+          }
+          vb[sl * NODE_BLOCK + kk] = a0 + a1;
+        }
+      }
+      __syncthreads();
+      if (tid < cb * NODE_BLOCK) {
+        const int kbl = tid >> 4, kk = tid & 15, k = (kb0 + kbl) * NODE_BLOCK + kk;
+        const double w = (k < rows) ? node_weight(k, M, rr, S.h, S.quad) : 0.0;
+        const float *yr = yp + (size_t)(kb0 + kbl) * m * NODE_BLOCK + kk;
+        double *ur = vb + kbl * m * NODE_BLOCK + kk;
+        double sg = 0.0, ysq = 0.0;
+        for (int j = 0; j < m; ++j) {
+          const double u = ur[j * NODE_BLOCK];
+          sg += (S.uset == HOPF_U_L2) ? u * u : fabs(u);
+          const double yv = (double)yr[j * NODE_BLOCK];
+          ysq += yv * yv;
+        }
+        if (S.uset == HOPF_U_L2) sg = sqrt(sg);
+        wsig += w * sg;
+        if (!part && k == rows - 1) slast = sg;
+        double ysc = 1.0;
+        if (S.uset == HOPF_U_L2) {
+          const double nv = sqrt(ysq);
+          if (w <= 0.0 || nv == 0.0) ysc = 0.0;
+          else if (nv >= (1.0 - 1e-5) * w) ysc = w / nv;
+        }
+        for (int j = 0; j < m; ++j) {   // y^ (replaces U in LDS)
+          double v = (double)yr[j * NODE_BLOCK];
+          if (S.uset == HOPF_U_L2) v *= ysc;
+          else {
+            v = fmin(fmax(v, -w), w);
+            if (w > 0.0 && fabs(v) >= (1.0 - 1e-5) * w) v = copysign(w, v);
+          }
+          ur[j * NODE_BLOCK] = v;
+        }
+      }
+      __syncthreads();
+      if (ig < np) {
+        const double *a = S.K64 + (size_t)kb0 * m * NODE_BLOCK * np + ig;
+        const int nrow = nsl * NODE_BLOCK;
+        for (int row = rg; row < nrow; row += RG) g64 += a[(size_t)row * np] * vb[row];
+      }
+      __syncthreads();
+    }
+    if (part) {
+      for (int j = wave; j < m; j += 4) {
+        const double *row = st.R64 + ((size_t)p * m + j) * np;
+        double acc = 0.0;
+        for (int i = lane; i < np; i += 64) acc += row[i] * l64[i];
+        acc = wave_sum_d(acc);
+        if (lane == 0) {
+          vb[j] = acc;                                    // U_R
+          vb[64 + j] = (double)st.yR[(size_t)p * mp + j];  // y_R
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double wR = 0.5 * rr;
+        double sg = 0.0, ysq = 0.0;
+        for (int j = 0; j < m; ++j) {
+          sg += (S.uset == HOPF_U_L2) ? vb[j] * vb[j] : fabs(vb[j]);
+          ysq += vb[64 + j] * vb[64 + j];
+        }
+        if (S.uset == HOPF_U_L2) sg = sqrt(sg);
+        wsig += wR * sg;
+        slast = sg;
+        double ysc = 1.0;
+        if (S.uset == HOPF_U_L2) {
+          const double nv = sqrt(ysq);
+          if (wR <= 0.0 || nv == 0.0) ysc = 0.0;
+          else if (nv >= (1.0 - 1e-5) * wR) ysc = wR / nv;
+        }
+        for (int j = 0; j < m; ++j) {
+          double v = vb[64 + j];
+          if (S.uset == HOPF_U_L2) v *= ysc;
+          else {
+            v = fmin(fmax(v, -wR), wR);
+            if (wR > 0.0 && fabs(v) >= (1.0 - 1e-5) * wR) v = copysign(wR, v);
+          }
+          vb[64 + j] = v;
+        }
+      }
+      __syncthreads();
+      if (rg == 0 && ig < np)
+        for (int j = 0; j < m; ++j) g64 += st.R64[((size_t)p * m + j) * np + ig] * vb[64 + j];
+    }
+    gp[tid] = g64;
+    __syncthreads();
+    double sP = 0.0, sJ = 0.0, sAx = 0.0;
+    if (tid < n) {
+      double G = 0.0;
+      for (int r2 = 0; r2 < RG; ++r2) G += gp[r2 * P2 + tid];
+      const double l = l64[tid], xf = st.xf[p * np + tid], cc = S.c[tid], wdd = S.Wd[tid];
+      sP = 0.5 * wdd * l * l - (xf - cc) * l;
+      const double d = xf - G - cc;      // x_T - c
+      sJ = d * d / wdd;
+      sAx = st.axf[p * np + tid] * l;
+    }
+    red[tid] = sP;
+    red[256 + tid] = sJ;
+    red[512 + tid] = sAx;
+    red[768 + tid] = wsig;
+    red[1024 + tid] = slast;
+    __syncthreads();
+    if (tid == 0) {
+      double a[5] = {0, 0, 0, 0, 0};
+      for (int q = 0; q < 5; ++q)
+        for (int t = 0; t < 256; ++t) a[q] += red[q * 256 + t];
+      s_ctl = decide(S, st, o, p, np, a[0], a[3], a[1], a[2], a[4]) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_ctl) setup_point(S, st, o, mv, p);
+  }
+}
+
 
 // ------------------------------------------------------------------ tile formation
 
@@ -361,7 +662,7 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
     }
     st.counters[0] = acc;
     st.counters[3] = nesc;
-    if (count_rows) st.rowsum[0] += rsum[0];
+    if (count_rows == 1) st.rowsum[0] += rsum[0];   // 2: list consumed before the tail solver
   }
   __syncthreads();
   for (long p = tid; p < st.npts; p += 1024) {
@@ -600,7 +901,7 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   st.log_lam = ctx->log_lam;
   st.log_cap = (int)std::min<long>(ctx->log_cap, 2000000000L);
   st.counters = grow<int>(bufs, bi++, 4);
-  st.rowsum = grow<double>(bufs, bi++, 1);
+  st.rowsum = grow<double>(bufs, bi++, 2);   // [0] tiled rounds, [1] tail solver
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
          st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
@@ -649,6 +950,10 @@ struct Job {
   bool done = false;
   MlpView mv{};
   std::vector<hipEvent_t> kev;
+  bool tail_ok = false;          // FP32 iterations: the tail solver may take over
+  int tail_group = -1;           // group index of the tail launch (-1: not issued)
+  long tail_points = 0;
+  hipEvent_t tev[2] = {nullptr, nullptr};
 };
 
 constexpr int GROUP_ROUNDS = 4;   // rounds between active-count checks
@@ -726,6 +1031,28 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
   k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0);   // refresh the active count
   HIPCHK(hipMemcpyAsync(J.hcount + slot, J.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(J.gev[slot], s));
+  ++J.ngroups;
+  return HOPF_OK;
+}
+
+// Hand the job's remaining points (at most `count`) to the per-point tail
+// solver: consume pending probe setups, sort, one k_tail launch.
+hopf_status issue_tail(Ctx *ctx, Job &J, const Opts &o, int count) {
+  const hipStream_t s = J.s;
+  k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
+  k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 2);
+  const size_t lds = tail_lds_bytes(J.tab->m);
+  HIPCHK(hipFuncSetAttribute((const void *)k_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  HIPCHK(hipEventCreate(&J.tev[0]));
+  HIPCHK(hipEventCreate(&J.tev[1]));
+  HIPCHK(hipEventRecord(J.tev[0], s));
+  k_tail<<<(unsigned)count, 256, lds, s>>>(J.S, J.st, o, J.mv);
+  HIPCHK(hipEventRecord(J.tev[1], s));
+  J.tail_points = count;
+  const int slot = J.ngroups & 1;
+  HIPCHK(hipMemcpyAsync(J.hcount + slot, J.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(J.gev[slot], s));
+  J.tail_group = J.ngroups;
   ++J.ngroups;
   return HOPF_OK;
 }
@@ -819,6 +1146,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.ngrid = (unsigned)((J.npts + PTS_TILE - 1) / PTS_TILE);
     J.max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
     J.hcount = hcount + 2 * j;
+    J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
     if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
     if (!make_state(ctx, j, *J.tab, J.npts, J.st)) {
       rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
@@ -840,7 +1168,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     const long np_ = J.npts;
     const hipStream_t s = J.s;
     bool ok = hipMemsetAsync(st.rows, 0, np_ * sizeof(int), s) == hipSuccess &&
-              hipMemsetAsync(st.rowsum, 0, sizeof(double), s) == hipSuccess &&
+              hipMemsetAsync(st.rowsum, 0, 2 * sizeof(double), s) == hipSuccess &&
               hipMemsetAsync(st.partial, 0, np_ * sizeof(int), s) == hipSuccess &&
               hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s) == hipSuccess &&
               hipMemsetAsync(st.stage, 0, np_ * sizeof(int), s) == hipSuccess &&
@@ -868,11 +1196,16 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
         const hipError_t q = hipEventQuery(J.gev[J.gdone & 1]);
         if (q == hipSuccess) {
           const int c = J.hcount[J.gdone & 1];
+          const bool was_tail = J.gdone == J.tail_group;
           ++J.gdone;
           progressed = true;
-          if (c == 0 || J.rounds >= J.max_rounds) {
+          if (was_tail || c == 0 || J.rounds >= J.max_rounds) {
             J.done = true;
             --live;
+            continue;
+          }
+          if (J.tail_ok && J.tail_group < 0 && c <= std::min(ho.tail_max, TAIL_MAX_POINTS)) {
+            rc = issue_tail(ctx, J, o, c);
             continue;
           }
         } else if (q != hipErrorNotReady) {
@@ -880,7 +1213,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
           break;
         }
       }
-      if (J.ngroups - J.gdone < 2 && J.rounds < J.max_rounds) {
+      if (J.tail_group < 0 && J.ngroups - J.gdone < 2 && J.rounds < J.max_rounds) {
         rc = issue_group(ctx, J, o, mode);
         progressed = true;
       }
@@ -899,7 +1232,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     if (hipGetLastError() != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "kernel launch failed");
   }
   bool hit_limit = false;
-  double it_s = 0.0, rows_tot = 0.0, flops = 0.0;
+  double it_s = 0.0, rows_tot = 0.0, flops = 0.0, tail_s = 0.0, tail_rows = 0.0;
+  long tail_pts = 0;
   for (int j = 0; j < nj; ++j) {
     Job &J = jobs[j];
     if (rc == HOPF_OK && J.st.x0) {
@@ -927,11 +1261,21 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       hipEventDestroy(J.kev[i + 1]);
     }
     if (rc == HOPF_OK && J.st.rowsum) {
-      double rs = 0.0;
-      hipMemcpy(&rs, J.st.rowsum, sizeof(double), hipMemcpyDeviceToHost);
-      // point-rows are summed once per round; each round runs check_every iterations
-      rows_tot += rs * ho.check_every;
-      flops += 4.0 * J.tab->m_user * J.tab->n * rs * ho.check_every;
+      double rs[2] = {0.0, 0.0};
+      hipMemcpy(rs, J.st.rowsum, 2 * sizeof(double), hipMemcpyDeviceToHost);
+      // point-rows are summed once per round (per interval in the tail
+      // solver); each runs check_every iterations
+      rows_tot += rs[0] * ho.check_every;
+      tail_rows += rs[1] * ho.check_every;
+      flops += 4.0 * J.tab->m_user * J.tab->n * (rs[0] + rs[1]) * ho.check_every;
+    }
+    if (J.tev[0]) {
+      float km = 0.f;
+      if (rc == HOPF_OK) hipEventElapsedTime(&km, J.tev[0], J.tev[1]);
+      tail_s += km * 1e-3;
+      tail_pts += J.tail_points;
+      hipEventDestroy(J.tev[0]);
+      hipEventDestroy(J.tev[1]);
     }
     if (rc == HOPF_OK && ctx->log_pt && j == 0) {
       int lc = 0;
@@ -947,6 +1291,9 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   ctx->t_iter = it_s;
   ctx->point_rows = rows_tot;
   ctx->alg_flops = flops;
+  ctx->t_tail = tail_s;
+  ctx->tail_rows = tail_rows;
+  ctx->tail_points = tail_pts;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipEventDestroy(ebase);

@@ -40,7 +40,13 @@ class HopfOpts(C.Structure):
     _fields_ = [("c_tau", C.c_double), ("gap_tol", C.c_double), ("t_rel_tol", C.c_double),
                 ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("warm", C.c_int), ("prec", C.c_int), ("root", C.c_int), ("newton_after", C.c_int),
-                ("newton_rho", C.c_double)]
+                ("newton_rho", C.c_double), ("tail_max", C.c_int)]
+
+
+class HopfTiming(C.Structure):
+    _fields_ = [("total_s", C.c_double), ("iter_kernel_s", C.c_double), ("iter_launches", C.c_long),
+                ("iter_point_rows", C.c_double), ("alg_flops", C.c_double), ("tail_kernel_s", C.c_double),
+                ("tail_point_rows", C.c_double), ("tail_points", C.c_long)]
 
 
 class HopfError(RuntimeError):
@@ -73,7 +79,7 @@ def load(path: str = LIB_PATH):
     lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, ip, ip, ip]
     lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
-    lib.hopf_last_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_long), dp, dp]
+    lib.hopf_last_timing.argtypes = [vp, C.POINTER(HopfTiming)]
     fp = C.POINTER(C.c_float)
     lib.hopf_warm_init.argtypes = [vp, C.c_int, C.c_uint]
     lib.hopf_warm_params.argtypes = [vp, C.c_int, C.c_int, fp, C.c_long, fp]
@@ -278,9 +284,8 @@ class Solver:
         return dict(epoch_loss=el[:epochs], pairs=pairs.value)
 
     def last_timing(self):
-        a, b, d, f = C.c_double(), C.c_double(), C.c_double(), C.c_double()
-        c = C.c_long()
-        self._check(self.lib.hopf_last_timing(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
-                                              C.byref(f)), "hopf_last_timing")
-        return dict(total_s=a.value, iter_kernel_s=b.value, iter_launches=c.value, point_rows=d.value,
-                    alg_flops=f.value)
+        t = HopfTiming()
+        self._check(self.lib.hopf_last_timing(self.h, C.byref(t)), "hopf_last_timing")
+        return dict(total_s=t.total_s, iter_kernel_s=t.iter_kernel_s, iter_launches=t.iter_launches,
+                    point_rows=t.iter_point_rows, alg_flops=t.alg_flops, tail_kernel_s=t.tail_kernel_s,
+                    tail_point_rows=t.tail_point_rows, tail_points=t.tail_points)

@@ -126,12 +126,15 @@ def test_min_time_integrator_closed_form(solver):
             assert abs(r["T"][k] - exact[k]) <= 1e-4 * exact[k], (k, r["T"][k], exact[k])
 
 
+@pytest.mark.parametrize("tail", [0, 512])
 @pytest.mark.parametrize("uset,n,m,N", [("l2", 12, 2, 50), ("box", 12, 3, 50)])
-def test_min_time_random_system_vs_oracle(solver, uset, n, m, N):
-    say("case: min_time random", uset, n, m, N)
+def test_min_time_random_system_vs_oracle(solver, uset, n, m, N, tail):
+    """tail=0: every round on the 16-point tiles; tail=512: the per-point
+    tail solver takes the points after the first round group."""
+    say("case: min_time random", uset, n, m, N, "tail", tail)
     spec = random_system(n, m, N, uset, seed=5, t_max=4.0)
     solver.set_systems([spec])
-    solver.set_opts(prec="fp32", c_tau=1.0)
+    solver.set_opts(prec="fp32", c_tau=1.0, tail_max=tail)
     x = gaussian_points(20, n, 0.12, seed=8)
     r = solver.min_time(x)
     S = osys(spec)
@@ -206,7 +209,7 @@ def test_value_streaming_and_bf16_vs_oracle(solver, prec, uset, n, m):
     say("case: value streaming", prec, uset, n, m)
     spec = random_system(n, m, 40, uset, seed=31, t_max=3.0)
     solver.set_systems([spec])
-    solver.set_opts(prec=prec, c_tau=1.0)
+    solver.set_opts(prec=prec, c_tau=1.0, tail_max=0)    # every iteration in the streaming kernel
     x = gaussian_points(40, n, 0.1, seed=6)
     t = np.linspace(0.2, 3.0, 40)
     r = solver.value(x, t)
@@ -272,3 +275,49 @@ def test_min_time_newton_vs_oracle(solver, prec, case):
         assert rn["status"][k] == o.status, (k, rn["status"][k], o.status)
         if o.status == O.PT_OK:
             assert abs(rn["T"][k] - o.T) <= 1e-4 * o.T, (k, rn["T"][k], o.T)
+
+
+
+# ------------------------------------------------------------------ per-point tail solver
+
+@pytest.mark.parametrize("mode,uset,quad", [("min_time", "l2", "trap"), ("min_time", "box", "trap"),
+                                            ("min_time", "l2", "left"), ("value", "l2", "trap"),
+                                            ("value", "box", "left")])
+def test_tail_solver_matches_tiles(solver, mode, uset, quad):
+    """The tail solver (matrix-vector FP32 iterations, in-kernel certificate,
+    search step and probe setup) against the tiled rounds on the same points:
+    identical statuses, certified results to the same tolerances; and it did
+    take the points."""
+    say("case: tail vs tiles", mode, uset, quad)
+    spec = random_system(24, 4, 60, uset, seed=77, t_max=4.0, quad=quad)
+    solver.set_systems([spec])
+    from gen.workloads import planted_drift_points
+    x, _ = planted_drift_points(spec, 70, 0.2, 3.0, seed=12)
+    t = np.linspace(0.1, 4.0, 70)
+    res = {}
+    for tail in (0, 512):
+        solver.set_opts(prec="fp32", c_tau=1.0, warm="cont", tail_max=tail)
+        res[tail] = solver.min_time(x) if mode == "min_time" else solver.value(x, t)
+        tm = solver.last_timing()
+        say("tail", tail, "points", tm["tail_points"], "rows", tm["tail_point_rows"], "s", tm["tail_kernel_s"])
+        assert (tm["tail_points"] > 0) == (tail > 0)
+    a, b = res[0], res[512]
+    assert np.array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    if mode == "min_time":
+        assert np.all(np.abs(a["T"][ok] - b["T"][ok]) <= 1e-4 * a["T"][ok])
+        assert np.all(b["gap"][ok] <= GAP)
+    else:
+        for k in np.flatnonzero(ok):
+            assert overlap(a["phi_lo"][k], a["phi_hi"][k], b["phi_lo"][k], b["phi_hi"][k]), k
+        assert np.all((b["phi_hi"] - b["phi_lo"])[ok] / np.maximum(1.0, np.abs(b["phi_hi"][ok])) <= GAP)
+    S = osys(spec)
+    for k in (0, 33, 69):
+        if mode == "min_time":
+            o = O.min_time(S, x[k], O.Options(c_tau=1.0, warm="cont"))
+            assert b["status"][k] == o.status, (k, b["status"][k], o.status)
+            if o.status == O.PT_OK:
+                assert abs(b["T"][k] - o.T) <= 1e-4 * o.T, (k, b["T"][k], o.T)
+        else:
+            pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=1.0, gap_tol=1e-9, max_iter=400000))
+            assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), k
