@@ -87,6 +87,8 @@ def main():
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call")
     ap.add_argument("--c4-scale", type=float, default=1.0, help="c4: fraction of each system's points")
+    ap.add_argument("--tail-max", type=int, default=None,
+                    help="points per system at which the per-point tail solver takes over (0: never)")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
                     help="iteration precision (default: the workload's, fp32)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -150,7 +152,8 @@ def main():
 
     def run_mode(mode, nsteps, nwarm):
         warm, _, root = mode.partition("+")
-        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=warm, root=root or "bisect")
+        extra = {} if args.tail_max is None else {"tail_max": args.tail_max}
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=warm, root=root or "bisect", **extra)
         for i in range(nwarm):
             step()
             print(f"[{mode}] warmup step {i + 1}/{nwarm} done", file=sys.stderr, flush=True)
@@ -222,6 +225,7 @@ def main():
            "config": {"workload": f"min-time, n={spec.n} m={spec.m} N={spec.N} l2 control, ellipsoid target, "
                                   f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points",
                       "npts": npts, "n": spec.n, "m": spec.m, "N": spec.N, "warm": best,
+                      "tail_max": args.tail_max or 0,
                       "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
            "results": {"ok": int(ok.sum()), "inside": int((st == 1).sum()), "unreachable": int((st == 2).sum()),
                        "noconv": int((st == 3).sum()), "nonfinite": int((st == 4).sum()),

@@ -121,7 +121,7 @@ typedef struct {
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
  *                 launch) finishes them; 0 keeps every point on the 16-point tiles
- *                 (at most 512)                                                      [0] */
+ *                 (at most 512: two workgroups per compute unit)                     [512] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;

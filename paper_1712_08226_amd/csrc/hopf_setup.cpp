@@ -376,7 +376,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->root = HOPF_ROOT_BISECT;
   o->newton_after = 3;
   o->newton_rho = 0.5;
-  o->tail_max = 0;
+  o->tail_max = 512;
   return HOPF_OK;
 }
 

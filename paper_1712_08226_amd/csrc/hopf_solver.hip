@@ -115,10 +115,13 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
 // e^{2^b delta A} and a short Taylor series for the remainder, then step
 // sizes and the warm or cold start.
 constexpr int SETUP_COLS = 8;
+// sv[3][256 * SETUP_COLS] | red[256] | network activations (4 x 260 floats)
+constexpr int SETUP_SCRATCH = 3 * 256 * SETUP_COLS + 256 + 520;
 
-__device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
-  __shared__ double sv[3][256 * SETUP_COLS];
-  __shared__ double red[256];
+// sm: LDS scratch of SETUP_SCRATCH doubles (the caller's; free during the call)
+__device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, double *sm) {
+  double (*sv)[256 * SETUP_COLS] = reinterpret_cast<double (*)[256 * SETUP_COLS]>(sm);
+  double *red = sm + 3 * 256 * SETUP_COLS;
   __syncthreads();
   const int tid = threadIdx.x;
   const int n = S.n, m = S.m, np = S.n_pad;
@@ -248,7 +251,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
   for (int j = tid; j < st.mpad; j += 256) st.yR[(size_t)p * st.mpad + j] = 0.0f;
   // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
   if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && mv.valid && mv.n == n && mv.H == 256) {
-    __shared__ float zin[260], ha[256], hb[256], outv[260];
+    float *zin = reinterpret_cast<float *>(red + 256), *ha = zin + 260, *hb = ha + 260, *outv = hb + 260;
     const int di = n + 1, dout = n + 2, H = 256;
     __syncthreads();
     for (int i = tid; i < di; i += 256)
@@ -315,10 +318,11 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p) {
 }
 
 __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, MlpView mv) {
+  __shared__ double sm[SETUP_SCRATCH];
   const int nset = st.counters[1];
   for (int li = blockIdx.x; li < nset; li += gridDim.x) {
     const long p = st.setup_list[li];
-    setup_point(S, st, o, mv, p);
+    setup_point(S, st, o, mv, p, sm);
     __syncthreads();
   }
 }
@@ -347,11 +351,79 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Dynamic LDS (bytes): bop 256 floats | vb 16*CB*m doubles | gp 256 doubles |
-// l64 256 doubles | red 5*256 doubles.
-__host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 64 ? 1 : (64 / m < 16 ? 64 / m : 16); }
+// Dual product of one chunk of node-block rows, V[r] = K[r,:] . b (rows of
+// the chunk contiguous in the dual table layout, n_pad values each): four
+// lanes per row, float4 (double2) loads, four rows in flight per quad.
+template <typename T, typename T4>
+__device__ __forceinline__ void tail_dual(const T *__restrict__ Kc, const T *__restrict__ b, T *__restrict__ V,
+                                          int nrow, int np, int tid) {
+  constexpr int EL = sizeof(T4) / sizeof(T);      // elements per vector load
+  const int q = tid & 3, quad = tid >> 2;
+  const int nv = np / EL;                           // vector loads per row (multiple of 4)
+  const T4 *K4 = reinterpret_cast<const T4 *>(Kc);
+  const T4 *b4 = reinterpret_cast<const T4 *>(b);
+  for (int r0 = quad; r0 < nrow; r0 += 4 * 64) {
+    T acc[4] = {0, 0, 0, 0};
+    const T4 *rp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 64 * u;
+      rp[u] = K4 + (size_t)(r < nrow ? r : r0) * nv;
+    }
+#pragma unroll 2
+    for (int c = q; c < nv; c += 4) {
+      const T4 bb = b4[c];
+      T4 a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = rp[u][c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if constexpr (EL == 4) acc[u] += a[u].x * bb.x + a[u].y * bb.y + a[u].z * bb.z + a[u].w * bb.w;
+        else acc[u] += a[u].x * bb.x + a[u].y * bb.y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      T v = acc[u];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      const int r = r0 + 64 * u;
+      if (q == 0 && r < nrow) V[r] = v;
+    }
+  }
+}
+
+// Primal product of one chunk, g += K[rows,:]^T y[rows]: lane (c, group)
+// owns column chunk c (EL columns) and the rows of its group; partial sums
+// stay in registers across chunks.
+template <typename T, typename T4>
+__device__ __forceinline__ void tail_primal(const T *__restrict__ Kc, const T *__restrict__ y, T4 &g, int nrow,
+                                            int np, int tid) {
+  constexpr int EL = sizeof(T4) / sizeof(T);
+  const int nv = np / EL, ngrp = 256 / nv;
+  const int c = tid % nv, grp = tid / nv;
+  if (grp >= ngrp) return;
+  const T4 *K4 = reinterpret_cast<const T4 *>(Kc) + c;
+#pragma unroll 8
+  for (int r = grp; r < nrow; r += ngrp) {
+    const T4 a = K4[(size_t)r * nv];
+    const T yv = y[r];
+    g.x += a.x * yv;
+    g.y += a.y * yv;
+    if constexpr (EL == 4) {
+      g.z += a.z * yv;
+      g.w += a.w * yv;
+    }
+  }
+}
+
+// Dynamic LDS of k_tail (the probe setup reuses the same bytes):
+//   bop 256 floats | l64 256 doubles | gp 256 x 16 B | red 5 x 4 doubles | vb CH doubles
+__host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 96 ? 1 : (96 / m < 16 ? 96 / m : 16); }
 __host__ __device__ inline size_t tail_lds_bytes(int m) {
-  return 256 * 4 + (size_t)16 * tail_chunk_blocks(m) * m * 8 + 256 * 8 + 256 * 8 + 5 * 256 * 8;
+  const size_t it = 256 * 4 + 256 * 8 + 256 * 16 + 20 * 8 + (size_t)16 * tail_chunk_blocks(m) * m * 8;
+  const size_t su = (size_t)SETUP_SCRATCH * 8;
+  return it > su ? it : su;
 }
 
 __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, MlpView mv) {
@@ -362,17 +434,19 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = S.m, np = S.n_pad, n = S.n;
   const int CB = tail_chunk_blocks(m);
-  const int P2 = np <= 16 ? 16 : np <= 32 ? 32 : np <= 64 ? 64 : np <= 128 ? 128 : 256;
-  const int RG = 256 / P2, ig = tid % P2, rg = tid / P2;
   float *bop = reinterpret_cast<float *>(tl_raw);
-  double *vb = reinterpret_cast<double *>(tl_raw + 256 * 4);
+  double *l64 = reinterpret_cast<double *>(tl_raw + 1024);
+  float4 *gpf4 = reinterpret_cast<float4 *>(tl_raw + 1024 + 2048);
+  double2 *gpd2 = reinterpret_cast<double2 *>(gpf4);
+  float *gpf = reinterpret_cast<float *>(gpf4);
+  double *gpd = reinterpret_cast<double *>(gpf4);
+  double *red = reinterpret_cast<double *>(tl_raw + 1024 + 2048 + 4096);
+  double *vb = red + 20;
   float *vbf = reinterpret_cast<float *>(vb);
-  double *gp = vb + 16 * CB * m;
-  float *gpf = reinterpret_cast<float *>(gp);
-  double *l64 = gp + 256;
-  double *red = l64 + 256;
+  double *sm = reinterpret_cast<double *>(tl_raw);        // probe setup scratch (aliases all of the above)
   float *yp = st.y + (size_t)p * st.ystride;
   const int mp = st.mpad;
+  const int nv4 = np / 4, ng4 = 256 / nv4, nv2 = np / 2, ng2 = 256 / nv2;
   // every interval runs check_every iterations; the search ends within
   // NEWTON_MAX_PROBES + 64 probes of at most max_iter iterations each
   const long guard_max = (long)(NEWTON_MAX_PROBES + 64) * (o.max_iter / o.check_every + 2);
@@ -393,25 +467,12 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
     bop[tid] = tid < np ? sig * st.lamb[p * np + tid] : 0.f;
     // ---------------- check_every FP32 iterations
     for (int it = 0; it < o.check_every; ++it) {
-      float gacc = 0.f;
+      float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f);
       __syncthreads();                       // bop of this iteration
       for (int kb0 = 0; kb0 < nkb; kb0 += CB) {
-        const int cb = min(CB, nkb - kb0), nsl = cb * m;
-        {   // dual: V = K (sigma lam_bar), 16 lanes per (block, component) slab
-          const int gi = tid >> 4, kk = tid & 15;
-          for (int sl = gi; sl < nsl; sl += 16) {
-            const int kbl = sl / m, j = sl % m;
-            const float *a = S.K32T + ((size_t)((kb0 + kbl) * m + j) * np) * NODE_BLOCK + kk;
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            for (int i = 0; i < np; i += 4) {
-              a0 += a[(size_t)i * NODE_BLOCK] * bop[i];
-              a1 += a[(size_t)(i + 1) * NODE_BLOCK] * bop[i + 1];
-              a2 += a[(size_t)(i + 2) * NODE_BLOCK] * bop[i + 2];
-              a3 += a[(size_t)(i + 3) * NODE_BLOCK] * bop[i + 3];
-            }
-            vbf[sl * NODE_BLOCK + kk] = (a0 + a1) + (a2 + a3);
-          }
-        }
+        const int cb = min(CB, nkb - kb0), nrow = cb * m * NODE_BLOCK;
+        const float *Kc = S.K32 + (size_t)kb0 * m * NODE_BLOCK * np;
+        tail_dual<float, float4>(Kc, bop, vbf, nrow, np, tid);   // V = K (sigma lam_bar)
         __syncthreads();
         if (tid < cb * NODE_BLOCK) {   // y_k = projection of y_k + V_k onto w_k C, one node per thread
           const int kbl = tid >> 4, kk = tid & 15, k = (kb0 + kbl) * NODE_BLOCK + kk;
@@ -441,11 +502,7 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
           }
         }
         __syncthreads();
-        if (ig < np) {   // primal: G += K^T y over this chunk's rows
-          const float *a = S.K32 + (size_t)kb0 * m * NODE_BLOCK * np + ig;
-          const int nrow = nsl * NODE_BLOCK;
-          for (int row = rg; row < nrow; row += RG) gacc += a[(size_t)row * np] * vbf[row];
-        }
+        tail_primal<float, float4>(Kc, vbf, g4, nrow, np, tid);   // g += K^T y
         __syncthreads();
       }
       if (part) {   // the private node at tau = T with weight r/2
@@ -471,14 +528,14 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
           for (int j = 0; j < m; ++j) st.yR[(size_t)p * mp + j] = vbf[j];
         }
         __syncthreads();
-        if (rg == 0 && ig < np)
-          for (int j = 0; j < m; ++j) gacc += st.R32[((size_t)p * m + j) * np + ig] * vbf[j];
       }
-      gpf[tid] = gacc;
+      if (tid / nv4 < ng4) gpf4[tid] = g4;     // column chunk tid % nv4 of group tid / nv4
       __syncthreads();
       if (tid < np) {   // lam+ = (lam - tau (K^T y - (x_f - c))) / (1 + tau W);  theta = 1
         float gs = 0.f;
-        for (int r2 = 0; r2 < RG; ++r2) gs += gpf[r2 * P2 + tid];
+        for (int r2 = 0; r2 < ng4; ++r2) gs += gpf[r2 * np + tid];
+        if (part)
+          for (int j = 0; j < m; ++j) gs += st.R32[((size_t)p * m + j) * np + tid] * vbf[j];
         const float ln = (lam_i - tau * (gs - xfc)) / (1.f + tau * wd);
         bop[tid] = sig * (2.f * ln - lam_i);
         lam_i = ln;
@@ -497,22 +554,12 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
     }
     __syncthreads();
     // ---------------- FP64 certificate from (lam, y)
-    double wsig = 0.0, slast = 0.0, g64 = 0.0;
+    double wsig = 0.0, slast = 0.0;
+    double2 g2 = make_double2(0.0, 0.0);
     for (int kb0 = 0; kb0 < nkb; kb0 += CB) {
-      const int cb = min(CB, nkb - kb0), nsl = cb * m;
-      {
-        const int gi = tid >> 4, kk = tid & 15;
-        for (int sl = gi; sl < nsl; sl += 16) {
-          const int kbl = sl / m, j = sl % m;
-          const double *a = S.K64T + ((size_t)((kb0 + kbl) * m + j) * np) * NODE_BLOCK + kk;
-          double a0 = 0.0, a1 = 0.0;
-          for (int i = 0; i < np; i += 2) {
-            a0 += a[(size_t)i * NODE_BLOCK] * l64[i];
-            a1 += a[(size_t)(i + 1) * NODE_BLOCK] * l64[i + 1];
-          }
-          vb[sl * NODE_BLOCK + kk] = a0 + a1;
-        }
-      }
+      const int cb = min(CB, nkb - kb0), nrow = cb * m * NODE_BLOCK;
+      const double *Kc = S.K64 + (size_t)kb0 * m * NODE_BLOCK * np;
+      tail_dual<double, double2>(Kc, l64, vb, nrow, np, tid);    // U = K lam
       __syncthreads();
       if (tid < cb * NODE_BLOCK) {
         const int kbl = tid >> 4, kk = tid & 15, k = (kb0 + kbl) * NODE_BLOCK + kk;
@@ -546,11 +593,7 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
         }
       }
       __syncthreads();
-      if (ig < np) {
-        const double *a = S.K64 + (size_t)kb0 * m * NODE_BLOCK * np + ig;
-        const int nrow = nsl * NODE_BLOCK;
-        for (int row = rg; row < nrow; row += RG) g64 += a[(size_t)row * np] * vb[row];
-      }
+      tail_primal<double, double2>(Kc, vb, g2, nrow, np, tid);   // K^T y^
       __syncthreads();
     }
     if (part) {
@@ -592,35 +635,34 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
         }
       }
       __syncthreads();
-      if (rg == 0 && ig < np)
-        for (int j = 0; j < m; ++j) g64 += st.R64[((size_t)p * m + j) * np + ig] * vb[64 + j];
     }
-    gp[tid] = g64;
+    if (tid / nv2 < ng2) gpd2[tid] = g2;
     __syncthreads();
     double sP = 0.0, sJ = 0.0, sAx = 0.0;
     if (tid < n) {
       double G = 0.0;
-      for (int r2 = 0; r2 < RG; ++r2) G += gp[r2 * P2 + tid];
+      for (int r2 = 0; r2 < ng2; ++r2) G += gpd[r2 * np + tid];
+      if (part)
+        for (int j = 0; j < m; ++j) G += st.R64[((size_t)p * m + j) * np + tid] * vb[64 + j];
       const double l = l64[tid], xf = st.xf[p * np + tid], cc = S.c[tid], wdd = S.Wd[tid];
       sP = 0.5 * wdd * l * l - (xf - cc) * l;
       const double d = xf - G - cc;      // x_T - c
       sJ = d * d / wdd;
       sAx = st.axf[p * np + tid] * l;
     }
-    red[tid] = sP;
-    red[256 + tid] = sJ;
-    red[512 + tid] = sAx;
-    red[768 + tid] = wsig;
-    red[1024 + tid] = slast;
+    {
+      const double v[5] = {wave_sum_d(sP), wave_sum_d(sJ), wave_sum_d(sAx), wave_sum_d(wsig), wave_sum_d(slast)};
+      if (lane == 0)
+        for (int q = 0; q < 5; ++q) red[q * 4 + wave] = v[q];
+    }
     __syncthreads();
     if (tid == 0) {
-      double a[5] = {0, 0, 0, 0, 0};
-      for (int q = 0; q < 5; ++q)
-        for (int t = 0; t < 256; ++t) a[q] += red[q * 256 + t];
+      double a[5];
+      for (int q = 0; q < 5; ++q) a[q] = (red[q * 4] + red[q * 4 + 1]) + (red[q * 4 + 2] + red[q * 4 + 3]);
       s_ctl = decide(S, st, o, p, np, a[0], a[3], a[1], a[2], a[4]) ? 1 : 0;
     }
     __syncthreads();
-    if (s_ctl) setup_point(S, st, o, mv, p);
+    if (s_ctl) setup_point(S, st, o, mv, p, sm);
   }
 }
 
