@@ -118,6 +118,23 @@ constexpr int SETUP_COLS = 8;
 // sv[3][256 * SETUP_COLS] | red[256] | network activations (4 x 260 floats)
 constexpr int SETUP_SCRATCH = 3 * 256 * SETUP_COLS + 256 + 520;
 
+// a[0..n) . b[0, stride, 2 stride, ...): four partial sums so that the loads
+// of consecutive terms are in flight together
+__device__ __forceinline__ double dot_strided(const double *__restrict__ a, const double *__restrict__ b,
+                                              int stride, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int l = 0;
+#pragma unroll 2
+  for (; l + 3 < n; l += 4) {
+    s0 += a[l] * b[l * stride];
+    s1 += a[l + 1] * b[(l + 1) * stride];
+    s2 += a[l + 2] * b[(l + 2) * stride];
+    s3 += a[l + 3] * b[(l + 3) * stride];
+  }
+  for (; l < n; ++l) s0 += a[l] * b[l * stride];
+  return (s0 + s1) + (s2 + s3);
+}
+
 // sm: LDS scratch of SETUP_SCRATCH doubles (the caller's; free during the call)
 __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, double *sm) {
   double (*sv)[256 * SETUP_COLS] = reinterpret_cast<double (*)[256 * SETUP_COLS]>(sm);
@@ -168,8 +185,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       const int nxt = cur ^ 1;
       for (int e = tid; e < n * cc; e += 256) {
         const int i = e / cc, cl = e % cc;
-        double acc = 0.0;
-        for (int l = 0; l < n; ++l) acc += E[(size_t)i * n + l] * sv[cur][l * SETUP_COLS + cl];
+        const double acc = dot_strided(E + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
         sv[nxt][i * SETUP_COLS + cl] = acc;
       }
       __syncthreads();
@@ -183,8 +199,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       for (int k = 1; k <= 8; ++k) {
         for (int e = tid; e < n * cc; e += 256) {
           const int i = e / cc, cl = e % cc;
-          double acc = 0.0;
-          for (int l = 0; l < n; ++l) acc += S.A[(size_t)i * n + l] * sv[tv][l * SETUP_COLS + cl];
+          const double acc = dot_strided(S.A + (size_t)i * n, &sv[tv][cl], SETUP_COLS, n);
           sv[other][i * SETUP_COLS + cl] = acc * (rho / k);
         }
         __syncthreads();
@@ -205,7 +220,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
         st.xfc32[p * np + i] = (float)(i < n ? v - S.c[i] : 0.0);
         double ax = 0.0;   // (A x_f)_i
         if (i < n)
-          for (int l = 0; l < n; ++l) ax += S.A[(size_t)i * n + l] * sv[cur][l * SETUP_COLS + cl];
+          ax = dot_strided(S.A + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
         st.axf[p * np + i] = ax;
       } else {
         const size_t o2 = ((size_t)p * m + (col - 1)) * np + i;
