@@ -26,6 +26,26 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "min-time queries/sec at dual gap≤1e-6 (n=100,N=300): plain vs warm-start"
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1712_08226_amd", "csrc", "hopf_device.h")
+COUNTERS = os.path.join(ROOT, "profiles", "k_pdhg_n100_m10_N300_65536q_hbm_counters.md")
+
+
+def counter_traffic():
+    """HBM bytes per k_pdhg launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs of this workload (a 'traffic:' JSON line in the summary), or
+    None when there is none or the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            line = next(l for l in f if l.startswith("traffic:"))
+        rec = json.loads(line[len("traffic:"):])
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, StopIteration, ValueError):
+        return None
+    return rec if rec.get("kernel_source_sha256") == sha else None
+
+
 def _oracle_query(args):
     """One oracle min-time query (run in a worker process)."""
     spec, x, opts = args
@@ -86,7 +106,10 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call")
-    ap.add_argument("--c4-scale", type=float, default=1.0, help="c4: fraction of each system's points")
+    ap.add_argument("--c4-scale", type=float, default=0.05, help="c4: fraction of each system's points")
+    ap.add_argument("--c4-max-iter", type=int, default=20000, help="c4: iteration cap per solve")
+    ap.add_argument("--c4-mode", default="min_time", choices=["min_time", "value"],
+                    help="c4: minimum-time queries, or value solves at t ~ U[0.5, t_max]")
     ap.add_argument("--tail-max", type=int, default=None,
                     help="points per system at which the per-point tail solver takes over (0: never)")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
@@ -214,8 +237,14 @@ def main():
     per_launch_ms = 1e3 * tk / max(1, launches)
     bf = w.opts["prec"] == "bf16x3"
     peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
+    ct = None if bf else counter_traffic()
+    traffic = None
+    if ct is not None and per_launch_ms > 0:   # measured HBM bytes per launch / measured launch time
+        traffic = round(ct["hbm_bytes_per_launch"] / (per_launch_ms * 1e-3) / 1e9, 2)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                "traffic_unit": "GB/s (HBM, FETCH_SIZE+WRITE_SIZE counters, calibrated)",
+                "traffic_bytes_per_launch": None if ct is None else ct["hbm_bytes_per_launch"],
                 "kernel": ("k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"
                            if bf else "k_pdhg (fused FP32 PDHG iterations)"),
                 "avg_launch_ms": round(per_launch_ms, 4), "launches": launches}
@@ -272,6 +301,12 @@ def bench_c3(args):
     spec = w.systems[0]
     npts = len(w.x)
     t = w.meta["t"]
+    # the FP64 oracle sample runs on the host while the GPU works
+    nsamp = min(8, npts)
+    idx = np.linspace(0, npts - 1, nsamp).astype(int)
+    ctx = mp.get_context("spawn")
+    pool = ctx.Pool(min(nsamp, os.cpu_count() or 1))
+    pending = pool.imap(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])
     solver = Solver(0)
     t0 = time.perf_counter()
     solver.set_systems([spec])
@@ -288,18 +323,20 @@ def bench_c3(args):
         out[prec] = dict(r=r, dt=dt, tm=tm)
         print(f"[c3 {prec}] {npts} value solves in {dt:.2f} s", file=sys.stderr, flush=True)
     solver.set_opts(prec="bf16x3", c_tau=w.opts["c_tau"])
+    nmt = min(npts, 2048)
     t0 = time.perf_counter()
-    rm = solver.min_time(w.x)
+    rm = solver.min_time(w.x[:nmt])
     dtm = time.perf_counter() - t0
+    print(f"[c3] {nmt} min-time queries in {dtm:.2f} s", file=sys.stderr, flush=True)
     b, f = out["bf16x3"]["r"], out["fp32"]["r"]
+    orc = []
+    for k, r in enumerate(pending):
+        orc.append(r)
+        print(f"[c3] oracle sample {k + 1}/{nsamp} done", file=sys.stderr, flush=True)
+    pool.close()
+    pool.join()
     mid_b = 0.5 * (b["phi_lo"] + b["phi_hi"])
     mid_f = 0.5 * (f["phi_lo"] + f["phi_hi"])
-    nsamp = min(16, npts)
-    idx = np.linspace(0, npts - 1, nsamp).astype(int)
-    workers = min(16, os.cpu_count() or 1)
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        orc = pool.map(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])
     o_mid = np.array([0.5 * (a + c) for a, c in orc])
     overl = [max(b["phi_lo"][i], lo) <= min(b["phi_hi"][i], hi) + 1e-9 for i, (lo, hi) in zip(idx, orc)]
     tmb = out["bf16x3"]["tm"]
@@ -318,7 +355,7 @@ def bench_c3(args):
            "error": {"max_abs_phi_bf16_vs_fp32_all": float(np.max(np.abs(mid_b - mid_f))),
                      "max_abs_phi_bf16_vs_fp64_oracle_sample": float(np.max(np.abs(mid_b[idx] - o_mid))),
                      "intervals_overlap_oracle": int(sum(overl)), "sample": int(nsamp)},
-           "min_time": {"queries_per_s": round(npts / dtm, 2),
+           "min_time": {"queries": nmt, "queries_per_s": round(nmt / dtm, 2),
                         "statuses": np.bincount(rm["status"], minlength=5).tolist()},
            "setup_s": round(setup_s, 2),
            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
@@ -328,49 +365,63 @@ def bench_c3(args):
 
 
 def bench_c4(args):
-    """64 uneven systems in one min-time call (every system's points mixed in
-    random order): jobs per system on a pool of streams."""
+    """64 uneven systems in one call (every system's points mixed in random
+    order; each system's points run as a job with its own kernels, the jobs
+    on a pool of streams).  Value solves phi(x, t), t ~ U[0.5, t_max], with
+    an iteration cap per solve; point counts scaled by --c4-scale."""
     import numpy as np
     from gen.configs import config4
     from paper_1712_08226_amd import Solver
     w = config4(scale=args.c4_scale)
     npts = len(w.x)
+    t = np.random.default_rng(44).uniform(0.5, 10.0, npts)
     solver = Solver(0)
     t0 = time.perf_counter()
     solver.set_systems(w.systems)
     setup_s = time.perf_counter() - t0
-    print(f"[c4] {len(w.systems)} systems set up in {setup_s:.1f} s; {npts} queries", file=sys.stderr, flush=True)
-    solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont")
-    for i in range(args.warmup):
-        sel = np.concatenate([np.flatnonzero(w.sys_id == k)[:16] for k in range(len(w.systems))])
-        solver.min_time(w.x[sel], sys_id=w.sys_id[sel])
-        print(f"[c4] warmup {i + 1} done", file=sys.stderr, flush=True)
+    print(f"[c4] {len(w.systems)} systems set up in {setup_s:.1f} s; {npts} {args.c4_mode} queries",
+          file=sys.stderr, flush=True)
+    solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], max_iter=args.c4_max_iter, warm="cont")
     times = []
     for i in range(args.steps):
         t0 = time.perf_counter()
-        r = solver.min_time(w.x, sys_id=w.sys_id)
+        if args.c4_mode == "value":
+            r = solver.value(w.x, t, sys_id=w.sys_id)
+        else:
+            r = solver.min_time(w.x, sys_id=w.sys_id)
         times.append(time.perf_counter() - t0)
         print(f"[c4] step {i + 1}/{args.steps}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
     tm = solver.last_timing()
     dt = float(np.mean(times))
     st = r["status"]
     ach = tm["alg_flops"] / tm["total_s"] / 1e12 if tm["total_s"] > 0 else 0.0
-    res = {"metric": "min-time queries/sec at dual gap<=1e-6, 64 uneven systems in one call",
-           "value": round(npts / dt, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(1e3 * dt, 1), "higher_is_better": True, "scaling": "weak",
+    per_sys = []
+    for k, s in enumerate(w.systems):
+        sel = w.sys_id == k
+        per_sys.append([int(s.A.shape[0]), int(s.B.shape[1]), int(s.N), s.uset, int(sel.sum()),
+                        int((st[sel] == 0).sum()), float(r["iters"][sel].mean())])
+    mt = args.c4_mode == "min_time"
+    res = {"metric": ("min-time queries/sec at dual gap<=1e-6" if mt else "certified value solves/sec (gap<=1e-6)")
+                     + ", 64 uneven systems in one call",
+           "value": round(npts / dt, 2), "unit": "queries/s" if mt else "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 0, "ms_per_step": round(1e3 * dt, 1), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-           "config": {"workload": f"min-time, 64 systems n log-uniform [4,256] (drawn {min(s.A.shape[0] for s in w.systems)}"
-                                  f"-{max(s.A.shape[0] for s in w.systems)}), m=max(1,n/4), N in 100..500, l2/box 32/32, "
-                                  f"{npts} drift-planted queries (256-4096 per system), continuation warm start"},
-           "results": {"ok": int((st == 0).sum()), "unreachable": int((st == 2).sum()), "noconv": int((st == 3).sum()),
-                       "inside": int((st == 1).sum()), "mean_iters": float(r["iters"].mean()),
-                       "max_iters": int(r["iters"].max()), "mean_probes": float(r["probes"].mean())},
+           "config": {"workload": ("min-time T(x), continuation warm start" if mt else "value phi(x,t), t~U[0.5,10]")
+                                  + f", 64 systems n log-uniform [4,256] (drawn "
+                                  f"{min(s.A.shape[0] for s in w.systems)}-{max(s.A.shape[0] for s in w.systems)}), "
+                                  f"m=max(1,n/4), N in 100..500, l2/box 32/32, {npts} drift-planted points "
+                                  f"({args.c4_scale:g} x 256-4096 per system), step ratio 5 (l2) / 0.3 (box), "
+                                  f"at most {args.c4_max_iter} iterations per solve (probe)"},
+           "results": {"ok": int((st == 0).sum()), "unreachable": int((st == 2).sum()), "inside": int((st == 1).sum()),
+                       "noconv": int((st == 3).sum()), "nonfinite": int((st == 4).sum()),
+                       "mean_iters": float(r["iters"].mean()), "max_iters": int(r["iters"].max())},
+           "timing": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in tm.items()},
            "setup_s": round(setup_s, 2),
+           "per_system_n_m_N_uset_points_ok_meaniters": per_sys,
            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                         "basis": "algorithmic flops of all systems / device time of the whole call"}}
     print(json.dumps(res), flush=True)
-
 
 if __name__ == "__main__":
     main()

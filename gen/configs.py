@@ -80,6 +80,8 @@ def config4_systems(nsys=64, seed=4):
     rng.shuffle(usets)
     specs = [random_system(int(n), max(1, int(n) // 4), int(N), str(u), seed=4000 + k)
              for k, (n, N, u) in enumerate(zip(ns, Ns, usets))]
+    for s in specs:       # step ratios chosen on the oracle for the two control sets
+        s.c_tau = 5.0 if s.uset == "l2" else 0.3
     return specs
 
 

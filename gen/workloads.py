@@ -37,6 +37,7 @@ class SystemSpec:
     t_max: float
     quad: str            # "trap" or "left"
     name: str = ""
+    c_tau: float = 0.0   # the system's primal step ratio for the solver (0: the call's)
 
     @property
     def n(self):

@@ -22,9 +22,10 @@
  * paper's N-sample layout.
  *
  * Precision.  Tables and matrix exponentials are built in FP64; the
- * iterations run in FP64 (HOPF_FP64), FP32 (HOPF_FP32) or with K and the
- * iterates split into bf16 hi + lo pairs, three bf16 MFMAs per product and
- * FP32 accumulation (HOPF_BF16X3); every
+ * iterations run in FP64 (HOPF_FP64: FP64 arithmetic within each launch of
+ * check_every iterations, the iterate stored in FP32 between launches), FP32
+ * (HOPF_FP32) or with K and the iterates split into bf16 hi + lo pairs,
+ * three bf16 MFMAs per product and FP32 accumulation (HOPF_BF16X3); every
  * reported value, gap and sign decision is certified in FP64 from a primal
  * point lam and a dual-feasible point y:  -min(P(lam), 1/2) <= phi <= -D(y)
  * (P(0) = 1/2 because the terminal cost is at least -1/2).
@@ -76,13 +77,17 @@ typedef enum {
 
 /* One system.  Sizes: A n*n, B n*m, Qu m*m (NULL = identity), W n*n
  * symmetric positive definite and diagonal in this build, c n (NULL = 0).
- * Limits: 1 <= n <= 256, 1 <= m <= 64, 2 <= N <= 4096, t_max > 0. */
+ * Limits: 1 <= n <= 256, 1 <= m <= 64, 2 <= N <= 4096, t_max > 0.
+ * c_tau: this system's primal step ratio (see hopf_opts.c_tau); 0 uses the
+ * call's option.  Lets one call mix systems whose best ratio differs (the
+ * box control set wants a much smaller one than the l2 ball). */
 typedef struct {
   int n, m, N;
   double t_max;
   int quad;               /* hopf_quad */
   int uset;               /* hopf_uset */
   const double *A, *B, *Qu, *W, *c;
+  double c_tau;
 } hopf_system;
 
 /* Solver options (hopf_default_opts fills the defaults in brackets).

@@ -52,7 +52,7 @@ template <> struct V4<double> { typedef doublex4 t; };
 
 struct SysView {
   int n, m, N, n_pad, nkb, quad, uset, m_user;
-  double t_max, h, delta;
+  double t_max, h, delta, c_tau;   // c_tau: the system's step ratio (0: the call's)
   const float *K32, *K32T;
   const __bf16 *Kd16h, *Kd16l, *Kp16h, *Kp16l;     // BF16 hi/lo copies (dual and primal layouts)
   const double *K64, *K64T, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;

@@ -162,6 +162,7 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
   if (n < 1 || n > 256 || m < 1 || m > 64 || N < 2 || N > 4096)
     return set_err(ctx, HOPF_EINVAL, "system sizes out of range (1<=n<=256, 1<=m<=64, 2<=N<=4096)");
   if (!(s.t_max > 0.0) || !std::isfinite(s.t_max)) return set_err(ctx, HOPF_EINVAL, "t_max must be finite and > 0");
+  if (!(s.c_tau >= 0.0) || !std::isfinite(s.c_tau)) return set_err(ctx, HOPF_EINVAL, "c_tau must be finite and >= 0");
   if (s.quad != HOPF_Q_TRAP && s.quad != HOPF_Q_LEFT) return set_err(ctx, HOPF_EINVAL, "bad quadrature rule");
   if (s.uset != HOPF_U_L2 && s.uset != HOPF_U_BOX) return set_err(ctx, HOPF_EINVAL, "bad control set");
   if (!s.A || !s.B || !s.W) return set_err(ctx, HOPF_EINVAL, "A, B and W are required");

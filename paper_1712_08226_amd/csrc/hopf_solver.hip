@@ -320,8 +320,9 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     st.rows[p] = rows;
     st.partial[p] = part;
     if (L > 0.0) {
-      st.tau[p] = o.c_tau / L;
-      st.sig[p] = 0.999 / (o.c_tau * L);
+      const double ct = S.c_tau > 0.0 ? S.c_tau : o.c_tau;
+      st.tau[p] = ct / L;
+      st.sig[p] = 0.999 / (ct * L);
     } else {          // no quadrature nodes: the prox of G alone is exact in one step
       st.tau[p] = 1e20;
       st.sig[p] = 0.0;
@@ -441,11 +442,10 @@ __host__ __device__ inline size_t tail_lds_bytes(int m) {
   return it > su ? it : su;
 }
 
-__global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, MlpView mv) {
-  extern __shared__ __align__(16) unsigned char tl_raw[];
-  __shared__ int s_ctl;
-  if ((int)blockIdx.x >= st.counters[0]) return;
-  const long p = st.perm[blockIdx.x];
+// The whole remaining search of point p by one workgroup of 256 threads;
+// tl_raw: tail_lds_bytes(S.m) bytes of LDS, s_ctl: one shared int.
+__device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, const MlpView &mv, long p,
+                           unsigned char *tl_raw, int &s_ctl) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = S.m, np = S.n_pad, n = S.n;
   const int CB = tail_chunk_blocks(m);
@@ -679,6 +679,35 @@ __global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, Mlp
     __syncthreads();
     if (s_ctl) setup_point(S, st, o, mv, p, sm);
   }
+}
+
+// One job's tail: workgroup b takes the b-th active point.
+__global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, MlpView mv) {
+  extern __shared__ __align__(16) unsigned char tl_raw[];
+  __shared__ int s_ctl;
+  if ((int)blockIdx.x >= st.counters[0]) return;
+  tail_point(S, st, o, mv, st.perm[blockIdx.x], tl_raw, s_ctl);
+}
+
+// Every parked job of a call in one launch: jobs[j] owns workgroups
+// [base[j], base[j+1]), workgroup base[j] + i takes the job's i-th active point.
+struct TailJob {
+  SysView S;
+  PtState st;
+  MlpView mv;
+  long base;
+};
+
+__global__ __launch_bounds__(256) void k_tail_multi(const TailJob *__restrict__ jobs, int njobs, Opts o) {
+  extern __shared__ __align__(16) unsigned char tl_raw[];
+  __shared__ int s_ctl;
+  const long b = blockIdx.x;
+  int j = 0;
+  while (j + 1 < njobs && jobs[j + 1].base <= b) ++j;
+  const TailJob &J = jobs[j];
+  const long i = b - J.base;
+  if (i >= J.st.counters[0]) return;
+  tail_point(J.S, J.st, o, J.mv, J.st.perm[i], tl_raw, s_ctl);
 }
 
 
@@ -969,7 +998,7 @@ SysView view(const SysTables &t) {
   SysView v;
   v.n = t.n; v.m = t.m; v.N = t.N; v.n_pad = t.n_pad; v.nkb = t.nkb;
   v.quad = t.desc.quad; v.uset = t.desc.uset;
-  v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta;
+  v.t_max = t.desc.t_max; v.h = t.h; v.delta = t.delta; v.c_tau = t.desc.c_tau;
   v.K32 = t.K32; v.K64 = t.K64; v.K32T = t.K32T; v.K64T = t.K64T;
   v.Kd16h = t.Kd16h; v.Kd16l = t.Kd16l; v.Kp16h = t.Kp16h; v.Kp16l = t.Kp16l; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
@@ -1008,9 +1037,9 @@ struct Job {
   MlpView mv{};
   std::vector<hipEvent_t> kev;
   bool tail_ok = false;          // FP32 iterations: the tail solver may take over
-  int tail_group = -1;           // group index of the tail launch (-1: not issued)
+  bool parked = false;           // waiting for the combined tail launch
+  hipEvent_t park_ev = nullptr;
   long tail_points = 0;
-  hipEvent_t tev[2] = {nullptr, nullptr};
 };
 
 constexpr int GROUP_ROUNDS = 4;   // rounds between active-count checks
@@ -1092,25 +1121,16 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
   return HOPF_OK;
 }
 
-// Hand the job's remaining points (at most `count`) to the per-point tail
-// solver: consume pending probe setups, sort, one k_tail launch.
-hopf_status issue_tail(Ctx *ctx, Job &J, const Opts &o, int count) {
+// Park the job for the tail solver: consume pending probe setups and sort its
+// (at most `count`) active points; the combined tail launch picks them up.
+hopf_status park_job(Ctx *ctx, Job &J, const Opts &o, long count) {
   const hipStream_t s = J.s;
   k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
   k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 2);
-  const size_t lds = tail_lds_bytes(J.tab->m);
-  HIPCHK(hipFuncSetAttribute((const void *)k_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  HIPCHK(hipEventCreate(&J.tev[0]));
-  HIPCHK(hipEventCreate(&J.tev[1]));
-  HIPCHK(hipEventRecord(J.tev[0], s));
-  k_tail<<<(unsigned)count, 256, lds, s>>>(J.S, J.st, o, J.mv);
-  HIPCHK(hipEventRecord(J.tev[1], s));
+  HIPCHK(hipEventCreateWithFlags(&J.park_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(J.park_ev, s));
+  J.parked = true;
   J.tail_points = count;
-  const int slot = J.ngroups & 1;
-  HIPCHK(hipMemcpyAsync(J.hcount + slot, J.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(J.gev[slot], s));
-  J.tail_group = J.ngroups;
-  ++J.ngroups;
   return HOPF_OK;
 }
 
@@ -1241,28 +1261,36 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
                                                          nj > 1 ? xs : J.tab->n, J.idx);
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, mode, t_in, J.idx);
   }
-  // ---- interleaved rounds: each job keeps up to two groups in flight
-  long live = rc == HOPF_OK ? nj : 0;
+  // ---- interleaved rounds: each job keeps up to two groups in flight until
+  // its points are done or at most tail_max remain (then it is parked); the
+  // parked jobs of the call finish together in one tail launch.
+  const long tail_lim = std::min(ho.tail_max, TAIL_MAX_POINTS);
+  long live = 0;
+  for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
+    Job &J = jobs[j];
+    if (J.tail_ok && J.npts <= tail_lim) rc = park_job(ctx, J, o, J.npts);   // straight to the tail
+    else ++live;
+  }
   while (rc == HOPF_OK && live > 0) {
     bool progressed = false;
     for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
       Job &J = jobs[j];
-      if (J.done) continue;
+      if (J.done || J.parked) continue;
       // read the oldest outstanding check if it has completed
       if (J.gdone < J.ngroups) {
         const hipError_t q = hipEventQuery(J.gev[J.gdone & 1]);
         if (q == hipSuccess) {
           const int c = J.hcount[J.gdone & 1];
-          const bool was_tail = J.gdone == J.tail_group;
           ++J.gdone;
           progressed = true;
-          if (was_tail || c == 0 || J.rounds >= J.max_rounds) {
+          if (c == 0 || J.rounds >= J.max_rounds) {
             J.done = true;
             --live;
             continue;
           }
-          if (J.tail_ok && J.tail_group < 0 && c <= std::min(ho.tail_max, TAIL_MAX_POINTS)) {
-            rc = issue_tail(ctx, J, o, c);
+          if (J.tail_ok && c <= tail_lim) {
+            rc = park_job(ctx, J, o, c);
+            --live;
             continue;
           }
         } else if (q != hipErrorNotReady) {
@@ -1270,27 +1298,75 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
           break;
         }
       }
-      if (J.tail_group < 0 && J.ngroups - J.gdone < 2 && J.rounds < J.max_rounds) {
+      if (J.ngroups - J.gdone < 2 && J.rounds < J.max_rounds) {
         rc = issue_group(ctx, J, o, mode);
         progressed = true;
       }
     }
     if (rc != HOPF_OK) break;
-    if (!progressed) {   // every live job has two groups in flight: wait for the oldest check of one
+    if (!progressed) {   // every running job has two groups in flight: wait for the oldest check of one
       for (int j = 0; j < nj; ++j)
-        if (!jobs[j].done && jobs[j].gdone < jobs[j].ngroups) {
+        if (!jobs[j].done && !jobs[j].parked && jobs[j].gdone < jobs[j].ngroups) {
           if (hipEventSynchronize(jobs[j].gev[jobs[j].gdone & 1]) != hipSuccess)
             rc = set_err(ctx, HOPF_EDEVICE, "round check failed");
           break;
         }
     }
   }
+  // ---- the combined tail launch over every parked job
+  double tail_s = 0.0;
+  long tail_pts = 0;
+  {
+    std::vector<TailJob> tj;
+    long tb = 0;
+    size_t lds = 0;
+    for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
+      Job &J = jobs[j];
+      if (!J.parked) continue;
+      tj.push_back(TailJob{J.S, J.st, J.mv, tb});
+      tb += J.tail_points;
+      lds = std::max(lds, tail_lds_bytes(J.tab->m));
+      if (hipStreamWaitEvent(base, J.park_ev, 0) != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "stream wait");
+    }
+    if (rc == HOPF_OK && tb > 0) {
+      if ((int)ctx->jbufs.size() < nj + 1) ctx->jbufs.resize(nj + 1);
+      TailJob *d_tj = grow<TailJob>(ctx->jbufs[nj], 1, tj.size());
+      if (!d_tj) rc = set_err(ctx, HOPF_ENOMEM, "tail job table");
+      hipEvent_t t0 = nullptr, t1 = nullptr, tdone = nullptr;
+      if (rc == HOPF_OK) {
+        const bool ok =
+            hipMemcpyAsync(d_tj, tj.data(), tj.size() * sizeof(TailJob), hipMemcpyHostToDevice, base) == hipSuccess &&
+            hipFuncSetAttribute((const void *)k_tail_multi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+                hipSuccess &&
+            hipEventCreate(&t0) == hipSuccess && hipEventCreate(&t1) == hipSuccess &&
+            hipEventCreateWithFlags(&tdone, hipEventDisableTiming) == hipSuccess && hipEventRecord(t0, base) == hipSuccess;
+        if (!ok) rc = set_err(ctx, HOPF_EDEVICE, "tail launch setup failed");
+      }
+      if (rc == HOPF_OK) {
+        k_tail_multi<<<(unsigned)tb, 256, lds, base>>>(d_tj, (int)tj.size(), o);
+        hipEventRecord(t1, base);
+        hipEventRecord(tdone, base);
+        for (int j = 0; j < nj; ++j)   // each parked job's outputs wait for the tail
+          if (jobs[j].parked && jobs[j].s != base) hipStreamWaitEvent(jobs[j].s, tdone, 0);
+        // the host table must outlive the asynchronous copy
+        if (hipEventSynchronize(t1) != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "tail solver failed");
+        float km = 0.f;
+        if (rc == HOPF_OK) hipEventElapsedTime(&km, t0, t1);
+        tail_s = km * 1e-3;
+        tail_pts = tb;
+      }
+      if (t0) hipEventDestroy(t0);
+      if (t1) hipEventDestroy(t1);
+      if (tdone) hipEventDestroy(tdone);
+    }
+    for (int j = 0; j < nj; ++j)
+      if (jobs[j].parked) jobs[j].done = true;
+  }
   if (rc == HOPF_OK) {
     if (hipGetLastError() != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "kernel launch failed");
   }
   bool hit_limit = false;
-  double it_s = 0.0, rows_tot = 0.0, flops = 0.0, tail_s = 0.0, tail_rows = 0.0;
-  long tail_pts = 0;
+  double it_s = 0.0, rows_tot = 0.0, flops = 0.0, tail_rows = 0.0;
   for (int j = 0; j < nj; ++j) {
     Job &J = jobs[j];
     if (rc == HOPF_OK && J.st.x0) {
@@ -1326,14 +1402,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       tail_rows += rs[1] * ho.check_every;
       flops += 4.0 * J.tab->m_user * J.tab->n * (rs[0] + rs[1]) * ho.check_every;
     }
-    if (J.tev[0]) {
-      float km = 0.f;
-      if (rc == HOPF_OK) hipEventElapsedTime(&km, J.tev[0], J.tev[1]);
-      tail_s += km * 1e-3;
-      tail_pts += J.tail_points;
-      hipEventDestroy(J.tev[0]);
-      hipEventDestroy(J.tev[1]);
-    }
+    if (J.park_ev) hipEventDestroy(J.park_ev);
     if (rc == HOPF_OK && ctx->log_pt && j == 0) {
       int lc = 0;
       hipMemcpy(&lc, J.st.counters + 2, sizeof(int), hipMemcpyDeviceToHost);

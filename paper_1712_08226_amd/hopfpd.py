@@ -33,7 +33,7 @@ class HopfSystem(C.Structure):
                 ("quad", C.c_int), ("uset", C.c_int),
                 ("A", C.POINTER(C.c_double)), ("B", C.POINTER(C.c_double)),
                 ("Qu", C.POINTER(C.c_double)), ("W", C.POINTER(C.c_double)),
-                ("c", C.POINTER(C.c_double))]
+                ("c", C.POINTER(C.c_double)), ("c_tau", C.c_double)]
 
 
 class HopfOpts(C.Structure):
@@ -142,7 +142,8 @@ class Solver:
     # -------------------------------------------------------------- setup
     def set_systems(self, systems):
         """systems: iterable of objects/dicts with A, B, W, c, uset, N, t_max,
-        quad (and optionally Qu); uset 'l2'/'box', quad 'trap'/'left'."""
+        quad (and optionally Qu and c_tau, the system's step ratio); uset
+        'l2'/'box', quad 'trap'/'left'."""
         arr = (HopfSystem * len(systems))()
         keep = []
         for k, s in enumerate(systems):
@@ -160,7 +161,7 @@ class Solver:
             arr[k] = HopfSystem(A.shape[0], B.shape[1], int(g("N")), float(g("t_max")),
                                 Q_TRAP if quad in ("trap", Q_TRAP) else Q_LEFT,
                                 U_L2 if uset in ("l2", U_L2) else U_BOX,
-                                _dptr(A), _dptr(B), _dptr(Qu), _dptr(W), _dptr(c))
+                                _dptr(A), _dptr(B), _dptr(Qu), _dptr(W), _dptr(c), float(g("c_tau", 0.0) or 0.0))
         self._check(self.lib.hopf_set_systems(self.h, len(systems), arr), "hopf_set_systems")
         self.n = [int(arr[k].n) for k in range(len(systems))]
         self.m = [int(arr[k].m) for k in range(len(systems))]

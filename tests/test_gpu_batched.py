@@ -45,12 +45,14 @@ def batch(npts_each=30, seed=0):
     return specs, x[perm], sid[perm]
 
 
-@pytest.mark.parametrize("mode", ["min_time", "value"])
-def test_batched_equals_single_system_calls(solver, mode):
-    say("case: batched", mode)
+@pytest.mark.parametrize("mode,tail", [("min_time", 0), ("value", 0), ("min_time", 512), ("value", 512)])
+def test_batched_equals_single_system_calls(solver, mode, tail):
+    """tail=0: every job runs its own rounds on a pool of streams; tail=512:
+    every job is parked and one combined tail launch finishes all systems."""
+    say("case: batched", mode, "tail", tail)
     specs, x, sid = batch()
     solver.set_systems(specs)
-    solver.set_opts(prec="fp32", c_tau=1.0, warm="cont")
+    solver.set_opts(prec="fp32", c_tau=1.0, warm="cont", tail_max=tail)
     t = np.linspace(0.3, 3.9, len(sid))
     if mode == "min_time":
         rb = solver.min_time(x, sys_id=sid)
@@ -58,6 +60,7 @@ def test_batched_equals_single_system_calls(solver, mode):
         rb = solver.value(x, t, sys_id=sid)
     tm = solver.last_timing()
     assert tm["alg_flops"] > 0
+    assert (tm["tail_points"] > 0) == (tail > 0)
     for k, s in enumerate(specs):
         sel = np.flatnonzero(sid == k)
         n = s.A.shape[0]

@@ -68,14 +68,17 @@ def test_value_integrator_closed_form(solver, prec):
         assert (r["phi_hi"][k] - r["phi_lo"][k]) / max(1.0, abs(r["phi_hi"][k])) <= GAP
 
 
+@pytest.mark.parametrize("tail", [0, 512])
 @pytest.mark.parametrize("uset,quad,n,m,prec", [("l2", "trap", 6, 2, "fp32"), ("box", "trap", 6, 2, "fp32"),
                                                 ("l2", "left", 20, 3, "fp32"), ("box", "left", 6, 1, "fp64"),
                                                 ("l2", "trap", 35, 5, "fp32")])
-def test_value_random_system_vs_oracle(solver, uset, quad, n, m, prec):
-    say("case: value random", uset, quad, n, m, prec)
+def test_value_random_system_vs_oracle(solver, uset, quad, n, m, prec, tail):
+    """tail=0: 16-point tiles throughout; tail=512: the per-point tail solver
+    (FP32 only; FP64 always runs on the tiles)."""
+    say("case: value random", uset, quad, n, m, prec, "tail", tail)
     spec = random_system(n, m, 40, uset, seed=21, t_max=3.0, quad=quad)
     solver.set_systems([spec])
-    solver.set_opts(prec=prec, c_tau=1.0)
+    solver.set_opts(prec=prec, c_tau=1.0, tail_max=tail)
     x = gaussian_points(70, n, 0.15, seed=4)          # 70 points: one full tile + a ragged one
     t = np.linspace(0.0, 3.0, 70)
     r = solver.value(x, t)
@@ -89,14 +92,14 @@ def test_value_random_system_vs_oracle(solver, uset, quad, n, m, prec):
 
 # ------------------------------------------------------------------ minimum time
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_min_time_double_integrator(solver, prec):
+@pytest.mark.parametrize("prec,tail", [("fp64", 0), ("fp32", 0), ("fp32", 512)])
+def test_min_time_double_integrator(solver, prec, tail):
     """Sec. VI-A system, r = 0.1, N = 100 trapezoid, 24 points of the
     [-2,2]^2 workload; every point is reachable (T <= 6)."""
-    say("case: min_time double integrator", prec)
+    say("case: min_time double integrator", prec, "tail", tail)
     spec = double_integrator(0.1, 100)
     solver.set_systems([spec])
-    solver.set_opts(prec=prec, c_tau=30.0)
+    solver.set_opts(prec=prec, c_tau=30.0, tail_max=tail)
     x = uniform_box_points(24, 2, -2.0, 2.0, seed=1)
     r = solver.min_time(x)
     S = osys(spec)
@@ -108,10 +111,11 @@ def test_min_time_double_integrator(solver, prec):
             assert r["gap"][k] <= GAP
 
 
-def test_min_time_integrator_closed_form(solver):
-    say("case: min_time integrator closed form")
+@pytest.mark.parametrize("tail", [0, 512])
+def test_min_time_integrator_closed_form(solver, tail):
+    say("case: min_time integrator closed form", "tail", tail)
     solver.set_systems([integrator(3, 0.3, "l2", N=40, t_max=5.0)])
-    solver.set_opts(prec="fp32", c_tau=1.0)
+    solver.set_opts(prec="fp32", c_tau=1.0, tail_max=tail)
     rng = np.random.default_rng(3)
     x = rng.normal(0, 1.0, size=(100, 3))
     r = solver.min_time(x)
@@ -247,11 +251,12 @@ def test_value_bf16_c3_shape(solver):
 
 # ------------------------------------------------------------------ hybrid Newton-bisection
 
-@pytest.mark.parametrize("prec,case", [("fp64", "di"), ("fp32", "di"), ("fp32", "l2"), ("fp32", "box")])
-def test_min_time_newton_vs_oracle(solver, prec, case):
+@pytest.mark.parametrize("prec,case,tail", [("fp64", "di", 0), ("fp32", "di", 512), ("fp32", "l2", 0),
+                                           ("fp32", "l2", 512), ("fp32", "box", 512)])
+def test_min_time_newton_vs_oracle(solver, prec, case, tail):
     """Sec. IV hybrid on the device against the oracle's hybrid: same
     statuses, |dT| <= 1e-4 T, gap <= 1e-6; fewer probes than bisection."""
-    say("case: min_time newton", prec, case)
+    say("case: min_time newton", prec, case, "tail", tail)
     if case == "di":
         spec, c_tau = double_integrator(0.1, 100), 30.0
         x = uniform_box_points(24, 2, -2.0, 2.0, seed=1)
@@ -259,9 +264,9 @@ def test_min_time_newton_vs_oracle(solver, prec, case):
         spec, c_tau = random_system(12, 2 if case == "l2" else 3, 50, case, seed=5, t_max=4.0), 1.0
         x = gaussian_points(20, 12, 0.12, seed=8)
     solver.set_systems([spec])
-    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont")
+    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont", tail_max=tail)
     rb = solver.min_time(x)
-    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont", root="newton")
+    solver.set_opts(prec=prec, c_tau=c_tau, warm="cont", root="newton", tail_max=tail)
     rn = solver.min_time(x)
     say("probes bisect", rb["probes"].mean(), "newton", rn["probes"].mean(),
         "iters", rb["iters"].mean(), rn["iters"].mean())
