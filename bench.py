@@ -107,6 +107,8 @@ def main():
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call")
     ap.add_argument("--c4-scale", type=float, default=0.05, help="c4: fraction of each system's points")
+    ap.add_argument("--c3-samples", type=int, default=0,
+                    help="c3: FP64 oracle value solves on the host for this many points (slow at N=400)")
     ap.add_argument("--c4-max-iter", type=int, default=20000, help="c4: iteration cap per solve")
     ap.add_argument("--c4-mode", default="min_time", choices=["min_time", "value"],
                     help="c4: minimum-time queries, or value solves at t ~ U[0.5, t_max]")
@@ -301,12 +303,16 @@ def bench_c3(args):
     spec = w.systems[0]
     npts = len(w.x)
     t = w.meta["t"]
-    # the FP64 oracle sample runs on the host while the GPU works
-    nsamp = min(8, npts)
+    # optional FP64 oracle sample on the host (running while the GPU works);
+    # the device intervals of 16 evenly spaced points are always reported so
+    # that the oracle can be run on them elsewhere
+    nsamp = min(args.c3_samples, npts)
     idx = np.linspace(0, npts - 1, nsamp).astype(int)
-    ctx = mp.get_context("spawn")
-    pool = ctx.Pool(min(nsamp, os.cpu_count() or 1))
-    pending = pool.imap(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])
+    pending = []
+    if nsamp:
+        ctx = mp.get_context("spawn")
+        pool = ctx.Pool(min(nsamp, os.cpu_count() or 1))
+        pending = pool.imap(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])
     solver = Solver(0)
     t0 = time.perf_counter()
     solver.set_systems([spec])
@@ -333,12 +339,15 @@ def bench_c3(args):
     for k, r in enumerate(pending):
         orc.append(r)
         print(f"[c3] oracle sample {k + 1}/{nsamp} done", file=sys.stderr, flush=True)
-    pool.close()
-    pool.join()
+    if nsamp:
+        pool.close()
+        pool.join()
+    rep = np.linspace(0, npts - 1, min(16, npts)).astype(int)
     mid_b = 0.5 * (b["phi_lo"] + b["phi_hi"])
     mid_f = 0.5 * (f["phi_lo"] + f["phi_hi"])
     o_mid = np.array([0.5 * (a + c) for a, c in orc])
     overl = [max(b["phi_lo"][i], lo) <= min(b["phi_hi"][i], hi) + 1e-9 for i, (lo, hi) in zip(idx, orc)]
+    err_o = float(np.max(np.abs(mid_b[idx] - o_mid))) if nsamp else None
     tmb = out["bf16x3"]["tm"]
     ach = tmb["alg_flops"] / tmb["iter_kernel_s"] / 1e12 if tmb["iter_kernel_s"] > 0 else 0.0
     res = {"metric": "value solves/sec at dual gap<=1e-6, BF16 hi+lo (n=200, m=20, N=400, box)",
@@ -353,8 +362,11 @@ def bench_c3(args):
            "mean_iters_bf16_fp32": [float(b["iters"].mean()), float(f["iters"].mean())],
            "max_gap_bf16": float(np.max((b["phi_hi"] - b["phi_lo"]) / np.maximum(1, np.abs(b["phi_hi"])))),
            "error": {"max_abs_phi_bf16_vs_fp32_all": float(np.max(np.abs(mid_b - mid_f))),
-                     "max_abs_phi_bf16_vs_fp64_oracle_sample": float(np.max(np.abs(mid_b[idx] - o_mid))),
+                     "max_abs_phi_bf16_vs_fp64_oracle_sample": err_o,
                      "intervals_overlap_oracle": int(sum(overl)), "sample": int(nsamp)},
+           "sample_intervals_idx_t_bf16lo_bf16hi_fp32lo_fp32hi": [
+               [int(i), float(t[i]), float(b["phi_lo"][i]), float(b["phi_hi"][i]), float(f["phi_lo"][i]),
+                float(f["phi_hi"][i])] for i in rep],
            "min_time": {"queries": nmt, "queries_per_s": round(nmt / dtm, 2),
                         "statuses": np.bincount(rm["status"], minlength=5).tolist()},
            "setup_s": round(setup_s, 2),

@@ -297,26 +297,31 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
           for (int q = 0; q < 4; ++q) V[j][q] = (Tv)src[acc_row<Tv>(g, q)];
         }
       }
-      // dual GEMM: V_j += K_j (sigma lam_bar), A = Kd[kb][j][node cl][16 t + acc_row(g, q)]
+      // dual GEMM: V_j += K_j (sigma lam_bar), A = Kd[kb][j][node cl][16 t + acc_row(g, q)];
+      // the operands of step t + 1 are loaded before the MFMAs of step t
       const Tv *kd = Kd + ((size_t)kb * m * NODE_BLOCK + cl) * np;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        Tv af[MM][4];
+      Tv af[2][MM][4];
+      auto load_af = [&](int t, Tv (&dst)[MM][4]) {
 #pragma unroll
         for (int j = 0; j < MM; ++j) {
           const Tv *a = kd + (size_t)j * NODE_BLOCK * np + 16 * t;
           if constexpr (sizeof(Tv) == 4) {
             const float4 f = *reinterpret_cast<const float4 *>(a + 4 * g);
-            af[j][0] = f.x; af[j][1] = f.y; af[j][2] = f.z; af[j][3] = f.w;
+            dst[j][0] = f.x; dst[j][1] = f.y; dst[j][2] = f.z; dst[j][3] = f.w;
           } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) af[j][q] = a[acc_row<Tv>(g, q)];
+            for (int q = 0; q < 4; ++q) dst[j][q] = a[acc_row<Tv>(g, q)];
           }
         }
+      };
+      load_af(0, af[0]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t + 1 < NT) load_af(t + 1, af[(t + 1) & 1]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int j = 0; j < MM; ++j) V[j] = mfma(af[j][q], bop[t][q], V[j]);
+          for (int j = 0; j < MM; ++j) V[j] = mfma(af[t & 1][j][q], bop[t][q], V[j]);
         __builtin_amdgcn_sched_barrier(0);
       }
       // projection onto w_k C per (node, point)
@@ -352,24 +357,28 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       }
       // primal GEMM: G += K_j^T Y_j, A = Kp[kb][j][16 t + cl][node acc_row(g, q)]
       const Tv *kp = Kp + (size_t)kb * m * np * NODE_BLOCK;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        Tv ap[NT][4];
+      Tv ap[2][NT][4];
+      auto load_ap = [&](int j, Tv (&dst)[NT][4]) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const Tv *a = kp + ((size_t)j * np + 16 * t + cl) * NODE_BLOCK;
           if constexpr (sizeof(Tv) == 4) {
             const float4 f = *reinterpret_cast<const float4 *>(a + 4 * g);
-            ap[t][0] = f.x; ap[t][1] = f.y; ap[t][2] = f.z; ap[t][3] = f.w;
+            dst[t][0] = f.x; dst[t][1] = f.y; dst[t][2] = f.z; dst[t][3] = f.w;
           } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ap[t][q] = a[acc_row<Tv>(g, q)];
+            for (int q = 0; q < 4; ++q) dst[t][q] = a[acc_row<Tv>(g, q)];
           }
         }
+      };
+      load_ap(0, ap[0]);
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        if (j + 1 < MM) load_ap(j + 1, ap[(j + 1) & 1]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int t = 0; t < NT; ++t) G[t] = mfma(ap[t][q], V[j][q], G[t]);
+          for (int t = 0; t < NT; ++t) G[t] = mfma(ap[j & 1][t][q], V[j][q], G[t]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }

@@ -1,7 +1,8 @@
 """Learned warm start on the GPU: the network's gradients against the FP64
-oracle, training reduces the loss, and warm-started minimum times are the
-certified results of the plain method (the network only changes where the
-iterations start)."""
+oracle, training reduces the loss, the trained network's lam_0 needs fewer
+iterations than the plain start lam_0 = 0, and warm-started minimum times are
+the certified results of the plain method (the network only changes where
+the iterations start)."""
 import sys
 
 import numpy as np
@@ -69,6 +70,8 @@ def test_training_and_warm_min_time(solver):
     assert res["pairs"] > 2048
     assert res["epoch_loss"][-1] < 0.5 * res["epoch_loss"][0]
     xte, _ = planted_drift_points(spec, 512, 0.2, 3.0, seed=2)
+    solver.set_opts(prec="fp32", c_tau=2.0, warm="cold")
+    cold = solver.min_time(xte)
     solver.set_opts(prec="fp32", c_tau=2.0, warm="cont")
     base = solver.min_time(xte)
     S = O.System(spec.A, spec.B, spec.W, spec.c, uset="l2", N=60, t_max=6.0)
@@ -78,6 +81,11 @@ def test_training_and_warm_min_time(solver):
         say(mode, "iters cont", base["iters"].mean(), "warm", warm["iters"].mean(),
             "probes", base["probes"].mean(), warm["probes"].mean())
         assert np.array_equal(base["status"], warm["status"])
+        if mode == "mlp_lam":
+            # what the trained network gains over the plain method: every probe
+            # starts from the network's lam_0 instead of lam_0 = 0
+            say("iters cold", cold["iters"].mean(), "network lam_0", warm["iters"].mean())
+            assert warm["iters"].mean() < 0.9 * cold["iters"].mean()
         ok = base["status"] == 0
         assert np.all(warm["gap"][ok] <= 1e-6)
         same = np.abs(warm["T"] - base["T"]) <= 1e-4 * base["T"] + 1e-9
