@@ -126,13 +126,20 @@ typedef struct {
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
  *                 launch) finishes them; 0 keeps every point on the 16-point tiles
- *                 (at most 512: two workgroups per compute unit)                     [512] */
+ *                 (at most 512: two workgroups per compute unit)                     [512]
+ *   adapt         tail solver: adapt each point's step ratio at restarts (not in the
+ *                 paper): when the certified gap has fallen to 0.2 of its value at the
+ *                 last restart (or to 0.8 and rises again), the primal weight
+ *                 omega = 1/c_tau moves to sqrt(omega * |dy| / |dlam|) (dy, dlam: the
+ *                 change of the iterates since that restart) and tau, sigma are
+ *                 rescaled with tau sigma fixed.  Results stay certified; only the
+ *                 iteration path changes                                              [1] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;
   int root, newton_after;
   double newton_rho;
-  int tail_max;
+  int tail_max, adapt;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);

@@ -78,6 +78,7 @@ struct PtState {
   int *counters;             // [0] active, [1] setup-list length, [2] probe-log length
   int *stage;                // [npts] warm-start bracket stage
   int *esc;                  // [npts] 1: iterate in FP32 (escalated from BF16 hi+lo)
+  float *lamref, *yref;      // tail solver: iterate at the last restart ([npts][n_pad], [npts][ystride])
   float *bT, *bD;            // [npts] predicted minimum time and log-bracket half-width
   int *log_pt;               // optional probe log: point, horizon, final lam of each probe
   float *log_T, *log_lam;
@@ -90,6 +91,7 @@ struct Opts {
   int max_iter, check_every, warm, prec, esc_iters;
   int root, newton_after;
   double newton_rho;
+  int adapt;
 };
 
 // point range of one iteration launch: 0 = FP32-escalated points

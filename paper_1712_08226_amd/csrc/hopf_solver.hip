@@ -465,13 +465,26 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
   // every interval runs check_every iterations; the search ends within
   // NEWTON_MAX_PROBES + 64 probes of at most max_iter iterations each
   const long guard_max = (long)(NEWTON_MAX_PROBES + 64) * (o.max_iter / o.check_every + 2);
+  // step adaptation: iterate and certified gap at the last restart (thread 0)
+  __shared__ int s_restart;
+  double gap_r = INFINITY, gap_prev = INFINITY;
+  bool need_ref = o.adapt != 0;
+  float *lref = st.lamref + (size_t)p * np, *yref = st.yref + (size_t)p * st.ystride;
   for (long guard = 0; guard < guard_max; ++guard) {
+    __syncthreads();   // every wave has read s_ctl of the previous interval
     if (tid == 0) s_ctl = st.phase[p];
     __syncthreads();
     if (s_ctl == PH_DONE) break;
     const int rows = st.rows[p], M = st.M[p], part = st.partial[p];
     const double rr = st.r[p];
     const int nkb = (rows + NODE_BLOCK - 1) / NODE_BLOCK;
+    if (need_ref) {   // a new probe (or entry): its starting iterate is the reference
+      for (int i = tid; i < np; i += 256) lref[i] = st.lam[p * np + i];
+      for (int e = tid; e < nkb * m * NODE_BLOCK; e += 256) yref[e] = yp[e];
+      gap_r = INFINITY;
+      gap_prev = INFINITY;
+      need_ref = false;
+    }
     const float tau = (float)st.tau[p], sig = (float)st.sig[p];
     float lam_i = 0.f, xfc = 0.f, wd = 1.f;
     if (tid < np) {
@@ -675,9 +688,53 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
       double a[5];
       for (int q = 0; q < 5; ++q) a[q] = (red[q * 4] + red[q * 4 + 1]) + (red[q * 4 + 2] + red[q * 4 + 3]);
       s_ctl = decide(S, st, o, p, np, a[0], a[3], a[1], a[2], a[4]) ? 1 : 0;
+      s_restart = 0;
+      if (o.adapt && !s_ctl && st.phase[p] != PH_DONE) {
+        const double Pv = st.P[p], Dv = st.D[p];
+        const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
+        s_restart = (gap <= 0.2 * gap_r || (gap <= 0.8 * gap_r && gap > gap_prev)) ? 1 : 0;
+        if (s_restart) gap_r = gap;
+        gap_prev = gap;
+      }
     }
     __syncthreads();
-    if (s_ctl) setup_point(S, st, o, mv, p, sm);
+    if (s_restart) {   // |dlam|^2, |dy|^2 since the last restart; the current iterate becomes the reference
+      double dl = 0.0, dy = 0.0;
+      for (int i = tid; i < np; i += 256) {
+        const float l = st.lam[p * np + i];
+        const double d = (double)l - (double)lref[i];
+        dl += d * d;
+        lref[i] = l;
+      }
+      for (int e = tid; e < nkb * m * NODE_BLOCK; e += 256) {
+        const float v = yp[e];
+        const double d = (double)v - (double)yref[e];
+        dy += d * d;
+        yref[e] = v;
+      }
+      dl = wave_sum_d(dl);
+      dy = wave_sum_d(dy);
+      if (lane == 0) {
+        red[wave] = dl;
+        red[4 + wave] = dy;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double dl2 = (red[0] + red[1]) + (red[2] + red[3]);
+        const double dy2 = (red[4] + red[5]) + (red[6] + red[7]);
+        const double ta = st.tau[p], sg = st.sig[p];
+        if (dl2 > 0.0 && dy2 > 0.0 && isfinite(dl2) && isfinite(dy2) && ta > 0.0 && sg > 0.0) {
+          const double w_old = sqrt(sg / (0.999 * ta));             // omega = 1 / c_tau
+          const double w_new = sqrt(w_old * sqrt(dy2 / dl2));      // geometric mean with |dy| / |dlam|
+          st.tau[p] = ta * (w_old / w_new);
+          st.sig[p] = sg * (w_new / w_old);
+        }
+      }
+    }
+    if (s_ctl) {
+      setup_point(S, st, o, mv, p, sm);
+      need_ref = o.adapt != 0;
+    }
   }
 }
 
@@ -980,6 +1037,8 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   st.setup_list = grow<int>(bufs, bi++, npts);
   st.stage = grow<int>(bufs, bi++, npts);
   st.esc = grow<int>(bufs, bi++, npts);
+  st.lamref = grow<float>(bufs, bi++, npts * np);
+  st.yref = grow<float>(bufs, bi++, (size_t)npts * st.ystride);
   st.bT = grow<float>(bufs, bi++, npts);
   st.bD = grow<float>(bufs, bi++, npts);
   st.log_pt = ctx->log_pt;
@@ -991,7 +1050,7 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
          st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
-         st.yR && st.perm && st.setup_list && st.stage && st.esc && st.bT && st.bD && st.counters && st.rowsum;
+         st.yR && st.perm && st.setup_list && st.stage && st.esc && st.lamref && st.yref && st.bT && st.bD && st.counters && st.rowsum;
 }
 
 SysView view(const SysTables &t) {
@@ -1199,7 +1258,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     }
   const hopf_opts &ho = ctx->opts;
   Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000,
-         ho.root, ho.newton_after, ho.newton_rho};
+         ho.root, ho.newton_after, ho.newton_rho, ho.adapt};
   const int max_probes = POW_BITS + 40;
   hipEvent_t e0, e1, ebase;
   HIPCHK(hipEventCreate(&e0));

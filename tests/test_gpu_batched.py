@@ -89,6 +89,12 @@ def test_batched_min_time_vs_oracle(solver):
         n = s.A.shape[0]
         for i in np.flatnonzero(sid == k)[:2]:
             o = O.min_time(S, x[i, :n], O.Options(c_tau=1.0, warm="cont"))
+            if o.status == O.PT_NOCONV:
+                # the fixed-step oracle ran out of iterations; the device result
+                # (adaptive steps) must still be certified if it claims one
+                assert r["status"][i] in (O.PT_OK, O.PT_NOCONV)
+                assert r["status"][i] != O.PT_OK or r["gap"][i] <= 1e-6
+                continue
             assert r["status"][i] == o.status, (k, i, r["status"][i], o.status)
             if o.status == O.PT_OK:
                 assert abs(r["T"][i] - o.T) <= 1e-4 * o.T, (k, i, r["T"][i], o.T)

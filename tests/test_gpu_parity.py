@@ -290,9 +290,9 @@ def test_min_time_newton_vs_oracle(solver, prec, case, tail):
                                             ("value", "box", "left")])
 def test_tail_solver_matches_tiles(solver, mode, uset, quad):
     """The tail solver (matrix-vector FP32 iterations, in-kernel certificate,
-    search step and probe setup) against the tiled rounds on the same points:
-    identical statuses, certified results to the same tolerances; and it did
-    take the points."""
+    search step and probe setup) against the tiled rounds on the same points,
+    both with fixed steps: identical statuses, certified results to the same
+    tolerances; and it did take the points."""
     say("case: tail vs tiles", mode, uset, quad)
     spec = random_system(24, 4, 60, uset, seed=77, t_max=4.0, quad=quad)
     solver.set_systems([spec])
@@ -301,7 +301,7 @@ def test_tail_solver_matches_tiles(solver, mode, uset, quad):
     t = np.linspace(0.1, 4.0, 70)
     res = {}
     for tail in (0, 512):
-        solver.set_opts(prec="fp32", c_tau=1.0, warm="cont", tail_max=tail)
+        solver.set_opts(prec="fp32", c_tau=1.0, warm="cont", tail_max=tail, adapt=0)
         res[tail] = solver.min_time(x) if mode == "min_time" else solver.value(x, t)
         tm = solver.last_timing()
         say("tail", tail, "points", tm["tail_points"], "rows", tm["tail_point_rows"], "s", tm["tail_kernel_s"])
@@ -326,3 +326,34 @@ def test_tail_solver_matches_tiles(solver, mode, uset, quad):
         else:
             pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=1.0, gap_tol=1e-9, max_iter=400000))
             assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), k
+
+
+
+@pytest.mark.parametrize("uset,quad,c_tau", [("box", "left", 1.0), ("box", "trap", 0.3), ("l2", "trap", 1.0)])
+def test_adaptive_steps_converge_at_least_as_often(solver, uset, quad, c_tau):
+    """Step adaptation in the tail solver (restarts with the primal-weight
+    update) changes only the iteration path: every point certified with fixed
+    steps is certified with adaptation too, the certified intervals overlap
+    each other and the oracle's, and no more points hit max_iter."""
+    say("case: adaptive steps", uset, quad, c_tau)
+    spec = random_system(24, 4, 60, uset, seed=77, t_max=4.0, quad=quad)
+    solver.set_systems([spec])
+    from gen.workloads import planted_drift_points
+    x, _ = planted_drift_points(spec, 70, 0.2, 3.0, seed=12)
+    t = np.linspace(0.1, 4.0, 70)
+    res = {}
+    for adapt in (0, 1):
+        solver.set_opts(prec="fp32", c_tau=c_tau, tail_max=512, adapt=adapt, max_iter=60000)
+        res[adapt] = solver.value(x, t)
+        say("adapt", adapt, "status", np.bincount(res[adapt]["status"], minlength=5), "iters", res[adapt]["iters"].mean())
+    a, b = res[0], res[1]
+    assert np.sum(b["status"] == 3) <= np.sum(a["status"] == 3)
+    assert np.all(b["status"][a["status"] == 0] == 0)
+    ok = b["status"] == 0
+    assert np.all((b["phi_hi"] - b["phi_lo"])[ok] / np.maximum(1.0, np.abs(b["phi_hi"][ok])) <= GAP)
+    for k in np.flatnonzero((a["status"] == 0) & ok):
+        assert overlap(a["phi_lo"][k], a["phi_hi"][k], b["phi_lo"][k], b["phi_hi"][k]), k
+    S = osys(spec)
+    for k in np.flatnonzero(ok)[::17]:
+        pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=c_tau, gap_tol=1e-9, max_iter=400000))
+        assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), k
