@@ -433,7 +433,7 @@ __device__ __forceinline__ void tail_primal(const T *__restrict__ Kc, const T *_
   }
 }
 
-// Dynamic LDS of k_tail (the probe setup reuses the same bytes):
+// Dynamic LDS of k_tail_multi (the probe setup reuses the same bytes):
 //   bop 256 floats | l64 256 doubles | gp 256 x 16 B | red 5 x 4 doubles | vb CH doubles
 __host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 96 ? 1 : (96 / m < 16 ? 96 / m : 16); }
 __host__ __device__ inline size_t tail_lds_bytes(int m) {
@@ -736,14 +736,6 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
       need_ref = o.adapt != 0;
     }
   }
-}
-
-// One job's tail: workgroup b takes the b-th active point.
-__global__ __launch_bounds__(256) void k_tail(SysView S, PtState st, Opts o, MlpView mv) {
-  extern __shared__ __align__(16) unsigned char tl_raw[];
-  __shared__ int s_ctl;
-  if ((int)blockIdx.x >= st.counters[0]) return;
-  tail_point(S, st, o, mv, st.perm[blockIdx.x], tl_raw, s_ctl);
 }
 
 // Every parked job of a call in one launch: jobs[j] owns workgroups
