@@ -96,9 +96,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--npts", type=int, default=65536)
     ap.add_argument("--variants", default="all",
-                    help="comma list of warm[+newton] variants (warm: cold, cont, mlp, mlp_lam; +newton: the "
+                    help="comma list of warm[+newton] variants (warm: cold, cont, mlp_first, mlp, mlp_lam; +newton: the "
                          "hybrid Newton-bisection of Sec. IV instead of bisection); 'all' times cont, "
-                         "cont+newton, mlp, mlp+newton, mlp_lam and cold and "
+                         "cont+newton, mlp_first, mlp, mlp+newton, mlp_lam and cold and "
                          "reports the best warm start as value")
     ap.add_argument("--train-npts", type=int, default=80000, help="training queries for the learned warm start")
     ap.add_argument("--epochs", type=int, default=8)
@@ -161,7 +161,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    modes = (["cont", "cont+newton", "mlp", "mlp+newton", "mlp_lam", "cold"] if args.variants == "all"
+    modes = (["cont", "cont+newton", "mlp_first", "mlp", "mlp+newton", "mlp_lam", "cold"] if args.variants == "all"
              else args.variants.split(","))
     train_info = None
     if any(m.startswith("mlp") for m in modes):

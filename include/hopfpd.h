@@ -22,10 +22,11 @@
  * paper's N-sample layout.
  *
  * Precision.  Tables and matrix exponentials are built in FP64; the
- * iterations run in FP64 (HOPF_FP64: FP64 arithmetic within each launch of
- * check_every iterations, the iterate stored in FP32 between launches), FP32
- * (HOPF_FP32) or with K and the iterates split into bf16 hi + lo pairs,
- * three bf16 MFMAs per product and FP32 accumulation (HOPF_BF16X3); every
+ * iterations run in FP64 (HOPF_FP64: the iterate stays in FP64 between
+ * launches; the FP64 certificate evaluates its FP32 rounding, which bounds phi
+ * as validly), FP32 (HOPF_FP32) or with K and the iterates split into bf16
+ * hi + lo pairs, three bf16 MFMAs per product and FP32 accumulation
+ * (HOPF_BF16X3); every
  * reported value, gap and sign decision is certified in FP64 from a primal
  * point lam and a dual-feasible point y:  -min(P(lam), 1/2) <= phi <= -D(y)
  * (P(0) = 1/2 because the terminal cost is at least -1/2).
@@ -63,7 +64,9 @@ typedef enum {
 typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
 typedef enum { HOPF_Q_TRAP = 0, HOPF_Q_LEFT = 1 } hopf_quad;
 typedef enum { HOPF_FP64 = 0, HOPF_FP32 = 1, HOPF_BF16X3 = 2 } hopf_prec;
-typedef enum { HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1, HOPF_WARM_MLP = 2, HOPF_WARM_MLP_LAM = 3 } hopf_warm;
+typedef enum {
+  HOPF_WARM_COLD = 0, HOPF_WARM_CONT = 1, HOPF_WARM_MLP = 2, HOPF_WARM_MLP_LAM = 3, HOPF_WARM_MLP_FIRST = 4
+} hopf_warm;
 typedef enum { HOPF_ROOT_BISECT = 0, HOPF_ROOT_NEWTON = 1 } hopf_root;
 
 /* per-point result status */
@@ -103,8 +106,11 @@ typedef struct {
  *                 HOPF_WARM_MLP: as CONT, and the system's trained network proposes
  *                 the two probes after t_max (its bracket [T e^-d, T e^d]);
  *                 HOPF_WARM_MLP_LAM: as MLP, and every probe starts from the
- *                 network's lam_0 (y from the previous probe).  Both fall back to
- *                 CONT where no trained network exists.  When phi(x,.) changes sign
+ *                 network's lam_0 (y from the previous probe);
+ *                 HOPF_WARM_MLP_FIRST: as CONT, and the first probe (at t_max, the
+ *                 only one that CONT starts cold) starts from the network's lam_0.
+ *                 The learned modes fall back to CONT where no trained network
+ *                 exists.  When phi(x,.) changes sign
  *                 more than once on [0, t_max] a different probe sequence can end
  *                 at a different certified crossing                              [COLD]
  *   prec          hopf_prec of the iterations; with HOPF_BF16X3 a probe that is not
@@ -131,9 +137,10 @@ typedef struct {
  *                 paper): when the certified gap has fallen to 0.2 of its value at the
  *                 last restart (or to 0.8 and rises again), the primal weight
  *                 omega = 1/c_tau moves to sqrt(omega * |dy| / |dlam|) (dy, dlam: the
- *                 change of the iterates since that restart) and tau, sigma are
- *                 rescaled with tau sigma fixed.  Results stay certified; only the
- *                 iteration path changes                                              [1] */
+ *                 change of the iterates since that restart), kept within 4x of the
+ *                 probe's starting weight, and tau, sigma are rescaled with tau sigma
+ *                 fixed; restarts are at least 4 certificates apart.  Results stay
+ *                 certified; only the iteration path changes                          [1] */
 typedef struct {
   double c_tau, gap_tol, t_rel_tol, t_abs_frac;
   int max_iter, check_every, warm, prec;

@@ -79,6 +79,11 @@ struct PtState {
   int *stage;                // [npts] warm-start bracket stage
   int *esc;                  // [npts] 1: iterate in FP32 (escalated from BF16 hi+lo)
   float *lamref, *yref;      // tail solver: iterate at the last restart ([npts][n_pad], [npts][ystride])
+  // FP64 iterations only (else null): the iterate in FP64 between launches, with
+  // s64[p] = 1 when it is current; lam/lamb/y/yR then hold its FP32 rounding,
+  // which the certificate and the read-out use
+  double *lam64, *lamb64, *y64, *yR64;
+  int *s64;
   float *bT, *bD;            // [npts] predicted minimum time and log-bracket half-width
   int *log_pt;               // optional probe log: point, horizon, final lam of each probe
   float *log_T, *log_lam;
@@ -190,16 +195,24 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
     M = st.M[p];
     rowsp = st.rows[p];
   }
+  // FP64 iterations continue from the FP64 iterate of the previous launch
+  const bool v64 = sizeof(Tv) == 8 && st.s64 != nullptr && live && st.s64[p] != 0;
   Tv lam[NT][4], bop[NT][4];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = 16 * t + acc_row<Tv>(g, q);
-      lam[t][q] = (Tv)st.lam[pd * np + i];
-      bop[t][q] = sig * (Tv)st.lamb[pd * np + i];
+      if (v64) {
+        lam[t][q] = (Tv)st.lam64[pd * np + i];
+        bop[t][q] = sig * (Tv)st.lamb64[pd * np + i];
+      } else {
+        lam[t][q] = (Tv)st.lam[pd * np + i];
+        bop[t][q] = sig * (Tv)st.lamb[pd * np + i];
+      }
     }
   float *yp = st.y + (size_t)pd * st.ystride;
+  double *yp64 = st.y64 ? st.y64 + (size_t)pd * st.ystride : nullptr;
 
   for (int it = 0; it < iters; ++it) {
     vec4 G[NT];
@@ -237,7 +250,8 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
             const Tv *row = Rr + ((size_t)P2 * m + j) * np;
             Tv acc = 0;
             for (int i = 0; i < np; ++i) acc += row[i] * lb_s[pp * np + i];
-            v = (Tv)st.yR[(size_t)P2 * st.mpad + j] + sig2 * acc;
+            const bool r64 = sizeof(Tv) == 8 && st.s64 != nullptr && st.s64[P2] != 0;
+            v = (r64 ? (Tv)st.yR64[(size_t)P2 * st.mpad + j] : (Tv)st.yR[(size_t)P2 * st.mpad + j]) + sig2 * acc;
           }
           vj[a] = v;
           ssq += v * v;
@@ -257,7 +271,10 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
         for (int a = 0; a < (MM + 3) / 4; ++a) {
           const int j = qq + 4 * a;
           if (j < MM) yr_s[pp * MM + j] = vj[a];
-          if (ppart && j < m) st.yR[(size_t)P2 * st.mpad + j] = (float)vj[a];
+          if (ppart && j < m) {
+            st.yR[(size_t)P2 * st.mpad + j] = (float)vj[a];
+            if (st.yR64) st.yR64[(size_t)P2 * st.mpad + j] = (double)vj[a];
+          }
         }
       }
       __syncthreads();
@@ -296,7 +313,9 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
           V[j] = vec4{(Tv)f.x, (Tv)f.y, (Tv)f.z, (Tv)f.w};
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) V[j][q] = (Tv)src[acc_row<Tv>(g, q)];
+          for (int q = 0; q < 4; ++q)
+            V[j][q] = v64 ? (Tv)yp64[(size_t)(kb * m + j) * NODE_BLOCK + acc_row<Tv>(g, q)]
+                          : (Tv)src[acc_row<Tv>(g, q)];
         }
       }
       // dual GEMM: V_j += K_j (sigma lam_bar), A = Kd[kb][j][node cl][16 t + acc_row(g, q)];
@@ -354,7 +373,10 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
           *reinterpret_cast<float4 *>(dst + 4 * g) = f;
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) dst[acc_row<Tv>(g, q)] = (float)V[j][q];
+          for (int q = 0; q < 4; ++q) {
+            dst[acc_row<Tv>(g, q)] = (float)V[j][q];
+            if (yp64) yp64[(size_t)(kb * m + j) * NODE_BLOCK + acc_row<Tv>(g, q)] = (double)V[j][q];
+          }
         }
       }
       // primal GEMM: G += K_j^T Y_j, A = Kp[kb][j][16 t + cl][node acc_row(g, q)]
@@ -415,10 +437,15 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
         const int i = 16 * t + acc_row<Tv>(g, q);
         st.lam[pd * np + i] = (float)lam[t][q];
         st.lamb[pd * np + i] = (float)(sig > 0 ? bop[t][q] / sig : (Tv)0);
+        if (sizeof(Tv) == 8 && st.lam64) {
+          st.lam64[pd * np + i] = (double)lam[t][q];
+          st.lamb64[pd * np + i] = (double)(sig > 0 ? bop[t][q] / sig : (Tv)0);
+        }
       }
     if (live && g == 0) {
       st.iters_probe[p] += iters;
       st.iters_tot[p] += iters;
+      if (sizeof(Tv) == 8 && st.s64) st.s64[p] = 1;
     }
   }
 }

@@ -438,7 +438,7 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
-      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 3 || o->prec < 0 || o->prec > 2 ||
+      o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
       o->root < 0 || o->root > 1 || o->newton_after < 1 || !(o->newton_rho > 0.0) ||
       o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1)
     return set_err(c, HOPF_EINVAL, "invalid solver options");

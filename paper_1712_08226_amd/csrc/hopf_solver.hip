@@ -246,13 +246,24 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
   // cold or warm start
   const int old_rows = st.rows[p];
   const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);   // CONT and MLP keep y
+  // FP64 iterations keep their own FP64 iterate (carried over when it is current)
+  const bool f64 = st.s64 != nullptr;
+  const bool had64 = f64 && st.s64[p] != 0;
   if (cold) {
     for (int i = tid; i < np; i += 256) {
       st.lam[p * np + i] = 0.0f;
       st.lamb[p * np + i] = 0.0f;
+      if (f64) { st.lam64[p * np + i] = 0.0; st.lamb64[p * np + i] = 0.0; }
     }
   } else {
-    for (int i = tid; i < np; i += 256) st.lamb[p * np + i] = st.lam[p * np + i];
+    for (int i = tid; i < np; i += 256) {
+      st.lamb[p * np + i] = st.lam[p * np + i];
+      if (f64) {
+        const double l = had64 ? st.lam64[p * np + i] : (double)st.lam[p * np + i];
+        st.lam64[p * np + i] = l;
+        st.lamb64[p * np + i] = l;
+      }
+    }
   }
   // The kernels read the node blocks of the tile's longest point, so every
   // row of the point's dual iterate must hold a finite value: rows this probe
@@ -261,11 +272,19 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
   const int keep = cold ? 0 : min(old_rows, rows);
   for (int e = tid; e < st.ystride; e += 256) {
     const int kb = e / (m * NODE_BLOCK), kk = e % NODE_BLOCK;
-    if (kb * NODE_BLOCK + kk >= keep) st.y[(size_t)p * st.ystride + e] = 0.0f;
+    const size_t ye = (size_t)p * st.ystride + e;
+    const bool zero = kb * NODE_BLOCK + kk >= keep;
+    if (zero) st.y[ye] = 0.0f;
+    if (f64) st.y64[ye] = zero ? 0.0 : (had64 ? st.y64[ye] : (double)st.y[ye]);
   }
-  for (int j = tid; j < st.mpad; j += 256) st.yR[(size_t)p * st.mpad + j] = 0.0f;
+  for (int j = tid; j < st.mpad; j += 256) {
+    st.yR[(size_t)p * st.mpad + j] = 0.0f;
+    if (f64) st.yR64[(size_t)p * st.mpad + j] = 0.0;
+  }
   // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
-  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && mv.valid && mv.n == n && mv.H == 256) {
+  const bool net_first = o.warm == HOPF_WARM_MLP_FIRST && st.probes[p] == 0;
+  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM || net_first) && mv.valid && mv.n == n &&
+      mv.H == 256) {
     float *zin = reinterpret_cast<float *>(red + 256), *ha = zin + 260, *hb = ha + 260, *outv = hb + 260;
     const int di = n + 1, dout = n + 2, H = 256;
     __syncthreads();
@@ -298,11 +317,12 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       outv[k] = a;
     }
     __syncthreads();
-    if (o.warm == HOPF_WARM_MLP_LAM) {
+    if (o.warm == HOPF_WARM_MLP_LAM || net_first) {
       for (int i = tid; i < np; i += 256) {
         const float l = i < n ? outv[i] * mv.lam_scale : 0.0f;
         st.lam[p * np + i] = l;
         st.lamb[p * np + i] = l;
+        if (f64) { st.lam64[p * np + i] = l; st.lamb64[p * np + i] = l; }
       }
     }
     if (tid == 0 && st.probes[p] == 0) {
@@ -330,6 +350,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     st.iters_probe[p] = 0;
     st.probes[p] += 1;
     st.flags[p] = 0;
+    if (f64) st.s64[p] = 1;
   }
 }
 
@@ -468,6 +489,8 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
   // step adaptation: iterate and certified gap at the last restart (thread 0)
   __shared__ int s_restart;
   double gap_r = INFINITY, gap_prev = INFINITY;
+  double w_base = 0.0;   // the probe's starting primal weight; adapted weights stay within 4x of it
+  int since = 0;         // certificates since the last restart
   bool need_ref = o.adapt != 0;
   float *lref = st.lamref + (size_t)p * np, *yref = st.yref + (size_t)p * st.ystride;
   for (long guard = 0; guard < guard_max; ++guard) {
@@ -483,6 +506,8 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
       for (int e = tid; e < nkb * m * NODE_BLOCK; e += 256) yref[e] = yp[e];
       gap_r = INFINITY;
       gap_prev = INFINITY;
+      since = 0;
+      w_base = (st.tau[p] > 0.0 && st.sig[p] > 0.0) ? sqrt(st.sig[p] / (0.999 * st.tau[p])) : 0.0;
       need_ref = false;
     }
     const float tau = (float)st.tau[p], sig = (float)st.sig[p];
@@ -692,8 +717,14 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
       if (o.adapt && !s_ctl && st.phase[p] != PH_DONE) {
         const double Pv = st.P[p], Dv = st.D[p];
         const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
-        s_restart = (gap <= 0.2 * gap_r || (gap <= 0.8 * gap_r && gap > gap_prev)) ? 1 : 0;
-        if (s_restart) gap_r = gap;
+        ++since;
+        // the first certificate of a probe always restarts; later ones at least 4 certificates apart
+        s_restart = (gap_r == INFINITY || (since >= 4 && (gap <= 0.2 * gap_r || (gap <= 0.8 * gap_r && gap > gap_prev))))
+                        ? 1 : 0;
+        if (s_restart) {
+          gap_r = gap;
+          since = 0;
+        }
         gap_prev = gap;
       }
     }
@@ -725,7 +756,8 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
         const double ta = st.tau[p], sg = st.sig[p];
         if (dl2 > 0.0 && dy2 > 0.0 && isfinite(dl2) && isfinite(dy2) && ta > 0.0 && sg > 0.0) {
           const double w_old = sqrt(sg / (0.999 * ta));             // omega = 1 / c_tau
-          const double w_new = sqrt(w_old * sqrt(dy2 / dl2));      // geometric mean with |dy| / |dlam|
+          double w_new = sqrt(w_old * sqrt(dy2 / dl2));            // geometric mean with |dy| / |dlam|
+          if (w_base > 0.0) w_new = fmin(fmax(w_new, 0.25 * w_base), 4.0 * w_base);
           st.tau[p] = ta * (w_old / w_new);
           st.sig[p] = sg * (w_new / w_old);
         }
@@ -872,8 +904,10 @@ __global__ __launch_bounds__(256) void k_traj(SysView S, PtState st, double T, d
     // y^ for this node
     if (tid < m) {
       double v;
-      if (isp) v = st.yR[tid];
-      else v = st.y[((size_t)(k / NODE_BLOCK) * m + tid) * NODE_BLOCK + (k % NODE_BLOCK)];
+      const bool u64 = st.s64 != nullptr && st.s64[0] != 0;
+      const size_t ye = ((size_t)(k / NODE_BLOCK) * m + tid) * NODE_BLOCK + (k % NODE_BLOCK);
+      if (isp) v = u64 ? st.yR64[tid] : st.yR[tid];
+      else v = u64 ? st.y64[ye] : st.y[ye];
       yh[tid] = v;
     }
     __syncthreads();
@@ -929,7 +963,7 @@ __global__ __launch_bounds__(256) void k_traj(SysView S, PtState st, double T, d
     __syncthreads();
   }
   // p* = e^{T A^T} lam
-  for (int i = tid; i < n; i += 256) z[i] = (double)st.lam[i];
+  for (int i = tid; i < n; i += 256) z[i] = (st.s64 != nullptr && st.s64[0] != 0) ? st.lam64[i] : (double)st.lam[i];
   __syncthreads();
   exp_apply(S, T, z, w2, term, true);
   for (int i = tid; i < n; i += 256) p_out[i] = z[i];
@@ -959,7 +993,9 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
   if (philo) philo[q] = -Pv;
   if (phihi) phihi[q] = -Dv;
   if (lam_out)
-    for (int i = 0; i < S.n; ++i) lam_out[q * ls + i] = (double)st.lam[p * S.n_pad + i];
+    for (int i = 0; i < S.n; ++i)
+      lam_out[q * ls + i] = (st.s64 != nullptr && st.s64[p] != 0) ? st.lam64[p * S.n_pad + i]
+                                                                 : (double)st.lam[p * S.n_pad + i];
   if (probes_out) probes_out[q] = st.probes[p];
   if (iters_out) iters_out[q] = st.iters_tot[p];
   status_out[q] = stt;
@@ -1030,6 +1066,18 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   st.stage = grow<int>(bufs, bi++, npts);
   st.esc = grow<int>(bufs, bi++, npts);
   st.lamref = grow<float>(bufs, bi++, npts * np);
+  if (ctx->opts.prec == HOPF_FP64) {   // the FP64 iterate (spare row included)
+    st.lam64 = grow<double>(bufs, bi++, (npts + 1) * np);
+    st.lamb64 = grow<double>(bufs, bi++, (npts + 1) * np);
+    st.y64 = grow<double>(bufs, bi++, (size_t)(npts + 1) * st.ystride);
+    st.yR64 = grow<double>(bufs, bi++, npts * st.mpad);
+    st.s64 = grow<int>(bufs, bi++, npts);
+    if (!st.lam64 || !st.lamb64 || !st.y64 || !st.yR64 || !st.s64) return false;
+  } else {
+    bi += 5;
+    st.lam64 = st.lamb64 = st.y64 = st.yR64 = nullptr;
+    st.s64 = nullptr;
+  }
   st.yref = grow<float>(bufs, bi++, (size_t)npts * st.ystride);
   st.bT = grow<float>(bufs, bi++, npts);
   st.bD = grow<float>(bufs, bi++, npts);
@@ -1287,7 +1335,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       rc = set_err(ctx, HOPF_EDEVICE, "stream wait");
       break;
     }
-    if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM) && J.sid < (int)ctx->mlp.size() &&
+    if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
+        J.sid < (int)ctx->mlp.size() &&
         ctx->mlp[J.sid].valid) {
       const MlpState &w = ctx->mlp[J.sid];
       J.mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
@@ -1299,6 +1348,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
               hipMemsetAsync(st.rowsum, 0, 2 * sizeof(double), s) == hipSuccess &&
               hipMemsetAsync(st.partial, 0, np_ * sizeof(int), s) == hipSuccess &&
               hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s) == hipSuccess &&
+              (st.s64 == nullptr || hipMemsetAsync(st.s64, 0, np_ * sizeof(int), s) == hipSuccess) &&
               hipMemsetAsync(st.stage, 0, np_ * sizeof(int), s) == hipSuccess &&
               hipMemsetAsync(st.esc, 0, np_ * sizeof(int), s) == hipSuccess &&
               hipMemsetAsync(st.bT, 0, np_ * sizeof(float), s) == hipSuccess &&

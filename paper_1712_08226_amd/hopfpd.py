@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libhopfpd.so")
 U_L2, U_BOX = 0, 1
 Q_TRAP, Q_LEFT = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
-WARM_COLD, WARM_CONT, WARM_MLP, WARM_MLP_LAM = 0, 1, 2, 3
+WARM_COLD, WARM_CONT, WARM_MLP, WARM_MLP_LAM, WARM_MLP_FIRST = 0, 1, 2, 3, 4
 ROOT_BISECT, ROOT_NEWTON = 0, 1
 PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
@@ -173,7 +173,8 @@ class Solver:
             if k == "prec":
                 v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(v, v)
             if k == "warm":
-                v = {"cold": WARM_COLD, "cont": WARM_CONT, "mlp": WARM_MLP, "mlp_lam": WARM_MLP_LAM}.get(v, v)
+                v = {"cold": WARM_COLD, "cont": WARM_CONT, "mlp": WARM_MLP, "mlp_lam": WARM_MLP_LAM,
+                     "mlp_first": WARM_MLP_FIRST}.get(v, v)
             if k == "root":
                 v = {"bisect": ROOT_BISECT, "newton": ROOT_NEWTON}.get(v, v)
             setattr(o, k, v)

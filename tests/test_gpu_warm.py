@@ -75,7 +75,7 @@ def test_training_and_warm_min_time(solver):
     solver.set_opts(prec="fp32", c_tau=2.0, warm="cont")
     base = solver.min_time(xte)
     S = O.System(spec.A, spec.B, spec.W, spec.c, uset="l2", N=60, t_max=6.0)
-    for mode in ("mlp", "mlp_lam"):
+    for mode in ("mlp", "mlp_lam", "mlp_first"):
         solver.set_opts(prec="fp32", c_tau=2.0, warm=mode)
         warm = solver.min_time(xte)
         say(mode, "iters cont", base["iters"].mean(), "warm", warm["iters"].mean(),
