@@ -129,6 +129,7 @@ def main():
     import torch
     from gen.configs import config5
     from paper_1712_08226_amd import Solver
+    from paper_1712_08226_amd.hopfpd import default_opts
 
     if args.workload == "c4":
         return bench_c4(args)
@@ -256,7 +257,7 @@ def main():
            "config": {"workload": f"min-time, n={spec.n} m={spec.m} N={spec.N} l2 control, ellipsoid target, "
                                   f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points",
                       "npts": npts, "n": spec.n, "m": spec.m, "N": spec.N, "warm": best,
-                      "tail_max": args.tail_max or 0,
+                      "tail_max": args.tail_max if args.tail_max is not None else default_opts().tail_max,
                       "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
            "results": {"ok": int(ok.sum()), "inside": int((st == 1).sum()), "unreachable": int((st == 2).sum()),
                        "noconv": int((st == 3).sum()), "nonfinite": int((st == 4).sum()),
