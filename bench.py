@@ -30,20 +30,35 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1712_08226_amd", "csrc", "hopf_device.h")
 COUNTERS = os.path.join(ROOT, "profiles", "k_pdhg_n100_m10_N300_65536q_hbm_counters.md")
 
 
-def counter_traffic():
+def counter_traffic(variant, check_every):
     """HBM bytes per k_pdhg launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs of this workload (a 'traffic:' JSON line in the summary), or
-    None when there is none or the kernel source changed since they were taken."""
+    counter runs of this workload ('traffic:' JSON lines in the summary, one
+    per profiled warm-start variant), or None when no record matches the
+    variant and iterations per launch of this run, or the kernel source has
+    changed since the counters were taken."""
     import hashlib
     try:
         with open(COUNTERS) as f:
-            line = next(l for l in f if l.startswith("traffic:"))
-        rec = json.loads(line[len("traffic:"):])
+            recs = [json.loads(l[len("traffic:"):]) for l in f if l.startswith("traffic:")]
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, StopIteration, ValueError):
+    except (OSError, ValueError):
         return None
-    return rec if rec.get("kernel_source_sha256") == sha else None
+    for rec in recs:
+        if (rec.get("kernel_source_sha256") == sha and rec.get("variant") == variant
+                and rec.get("check_every") == check_every):
+            return rec
+    return None
+
+
+def single_thread_workers():
+    """One BLAS/OpenMP thread in every oracle worker started after this call
+    (spawned workers read these at start-up).  Assigned, not defaulted: the
+    environment may already ask for one thread per core, and as many workers
+    as cores each spinning that many threads would measure contention, not
+    the oracle."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        os.environ[k] = "1"
 
 
 def _oracle_query(args):
@@ -62,9 +77,7 @@ def cpu_baseline(w, budget_s, workers, warm, root):
     the rate counts the queries finished within the budget.  Slow queries
     that do not finish are not counted, so this overstates the CPU rate."""
     import multiprocessing as mp
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
-    os.environ.setdefault("MKL_NUM_THREADS", "1")
+    single_thread_workers()
     opts = dict(w.opts, warm=warm, root=root)
     jobs = [(w.systems[0], w.x[i], opts) for i in range(min(len(w.x), 64 * workers))]
     ctx = mp.get_context("spawn")
@@ -103,15 +116,19 @@ def main():
     ap.add_argument("--train-npts", type=int, default=80000, help="training queries for the learned warm start")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=40.0, help="seconds of oracle wall time")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4"],
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
-                         "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call")
+                         "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call; "
+                         "tychastic: the paper's dimensional-scaling value solves, d = 2k sampled copies")
+    ap.add_argument("--dims", default="30,60,90,120", help="tychastic: state dimensions d to sweep")
     ap.add_argument("--c4-scale", type=float, default=0.05, help="c4: fraction of each system's points")
     ap.add_argument("--c3-samples", type=int, default=0,
                     help="c3: FP64 oracle value solves on the host for this many points (slow at N=400)")
     ap.add_argument("--c4-max-iter", type=int, default=20000, help="c4: iteration cap per solve")
     ap.add_argument("--c4-mode", default="min_time", choices=["min_time", "value"],
                     help="c4: minimum-time queries, or value solves at t ~ U[0.5, t_max]")
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="iterations between certificates (default: the library's)")
     ap.add_argument("--tail-max", type=int, default=None,
                     help="points per system at which the per-point tail solver takes over (0: never)")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
@@ -133,12 +150,16 @@ def main():
 
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "tychastic":
+        return bench_tychastic(args)
     if args.workload == "c3":
         return bench_c3(args)
 
     w = config5(npts=args.npts)
     if args.prec:
         w.opts["prec"] = args.prec
+    ce_run = args.check_every if args.check_every is not None else w.opts.get("check_every",
+                                                                              default_opts().check_every)
     spec = w.systems[0]
     dev = torch.device("cuda:0")
     solver = Solver(0)
@@ -168,7 +189,7 @@ def main():
     if any(m.startswith("mlp") for m in modes):
         # learned warm start: trained on separate drift-planted queries (not timed)
         wt = config5(npts=args.train_npts, seed=105)
-        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont")
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont", check_every=ce_run)
         t0 = time.perf_counter()
         tr = solver.warm_train(wt.x, epochs=args.epochs, batch=4096, lr=1e-3, seed=7)
         train_info = {"train_queries": args.train_npts, "pairs": tr["pairs"], "epochs": args.epochs,
@@ -179,6 +200,7 @@ def main():
     def run_mode(mode, nsteps, nwarm):
         warm, _, root = mode.partition("+")
         extra = {} if args.tail_max is None else {"tail_max": args.tail_max}
+        extra["check_every"] = ce_run
         solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=warm, root=root or "bisect", **extra)
         for i in range(nwarm):
             step()
@@ -240,7 +262,7 @@ def main():
     per_launch_ms = 1e3 * tk / max(1, launches)
     bf = w.opts["prec"] == "bf16x3"
     peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
-    ct = None if bf else counter_traffic()
+    ct = None if bf else counter_traffic(best, ce_run)
     traffic = None
     if ct is not None and per_launch_ms > 0:   # measured HBM bytes per launch / measured launch time
         traffic = round(ct["hbm_bytes_per_launch"] / (per_launch_ms * 1e-3) / 1e9, 2)
@@ -258,6 +280,7 @@ def main():
                                   f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points",
                       "npts": npts, "n": spec.n, "m": spec.m, "N": spec.N, "warm": best,
                       "tail_max": args.tail_max if args.tail_max is not None else default_opts().tail_max,
+                      "check_every": ce_run,
                       "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
            "results": {"ok": int(ok.sum()), "inside": int((st == 1).sum()), "unreachable": int((st == 2).sum()),
                        "noconv": int((st == 3).sum()), "nonfinite": int((st == 4).sum()),
@@ -290,6 +313,109 @@ def _oracle_value(args):
     return pr.phi_lo, pr.phi_hi
 
 
+def oracle_value_rate(spec, xs, t, c_tau, budget_s, workers):
+    """The oracle's value solves phi(x_i, t), in order, one per single-thread
+    worker process, for a wall-clock budget; returns (solves/s, seconds,
+    finished)."""
+    import multiprocessing as mp
+    single_thread_workers()
+    ctx = mp.get_context("spawn")
+    pool = ctx.Pool(workers)
+    done = 0
+    t0 = time.perf_counter()
+    try:
+        it = pool.imap(_oracle_value, [(spec, x, float(t), c_tau) for x in xs], chunksize=1)
+        while True:
+            left = budget_s - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                it.next(timeout=left)
+                done += 1
+            except (mp.TimeoutError, StopIteration):
+                break
+    finally:
+        el = time.perf_counter() - t0
+        pool.terminate()
+        pool.join()
+    return done / el, el, done
+
+
+def paper_scaling_ms(d):
+    """The paper's least-squares fit of its per-solve time (ms) against the
+    dimension d in the scaling experiment of Sec. VI-C (MATLAB, FP64, one
+    laptop CPU, residual stop 1e-4): context, not a target."""
+    return 2.382e-4 * d * d + 0.0414 * d + 2.598
+
+
+def bench_tychastic(args):
+    """The dimensional-scaling experiment of Sec. VI-C: value solves of the
+    k-copy double integrator (d = 2k, m = 1, N = 100 left-rule nodes, t = 2)
+    for every d of --dims, each over --npts points resident on the device.
+    `value` is the device rate at the largest d; the oracle's rate on the
+    host cores and the paper's fitted times are reported beside it."""
+    import numpy as np
+    from gen.configs import config_tychastic
+    from paper_1712_08226_amd import Solver
+    dims = [int(v) for v in args.dims.split(",")]
+    solver = Solver(0)
+    sweep = []
+    for d in dims:
+        w = config_tychastic(d, npts=args.npts)
+        spec, T, npts = w.systems[0], w.opts["t"], len(w.x)
+        t = np.full(npts, T)
+        solver.set_systems([spec])
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"])
+        for i in range(args.warmup):
+            solver.value(w.x[:4096], t[:4096])
+        t0 = time.perf_counter()
+        r = solver.value(w.x, t)
+        dt = time.perf_counter() - t0
+        tm = solver.last_timing()
+        gap = (r["phi_hi"] - r["phi_lo"]) / np.maximum(1.0, np.abs(r["phi_hi"]))
+        ach = tm["alg_flops"] / tm["iter_kernel_s"] / 1e12 if tm["iter_kernel_s"] > 0 else 0.0
+        pms = paper_scaling_ms(d)
+        row = {"d": d, "points": npts, "device_s": round(tm["total_s"], 4),
+               "solves_per_s": round(npts / tm["total_s"], 1),
+               "solves_per_s_host_call": round(npts / dt, 1),
+               "mean_iters": round(float(r["iters"].mean()), 1), "max_iters": int(r["iters"].max()),
+               "statuses": np.bincount(r["status"], minlength=5).tolist(), "max_gap": float(gap.max()),
+               "reached_frac": round(float(np.mean(r["phi_hi"] <= 0.0)), 4),
+               "k_pdhg_tflops": round(ach, 3), "k_pdhg_frac_fp32_mfma": round(ach / PEAK_FP32_MFMA_TFLOPS, 4),
+               "tail_s": round(tm["tail_kernel_s"], 4), "tail_points": tm["tail_points"],
+               "paper_ms_per_solve": round(pms, 3), "paper_solves_per_s": round(1e3 / pms, 1)}
+        sweep.append(row)
+        print(f"[tychastic d={d}] {npts} value solves: device {tm['total_s']:.3f} s, host call {dt:.3f} s, "
+              f"mean iters {row['mean_iters']}", file=sys.stderr, flush=True)
+    top = sweep[-1]
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on the host cores, value solves of the largest d, bounded
+        w = config_tychastic(dims[-1], npts=256)
+        workers = min(16, os.cpu_count() or 1)
+        rate, el, done = oracle_value_rate(w.systems[0], w.x, w.opts["t"], w.opts["c_tau"], args.cpu_budget, workers)
+        cpu = {"value": round(rate, 3), "unit": "solves/s", "cores": workers, "kind": "oracle",
+               "sample": f"d={dims[-1]} value solves in order on {workers} single-thread processes for "
+                         f"{args.cpu_budget:.0f} s wall; {done} finished"}
+        print(f"[tychastic] oracle: {done} solves in {el:.1f} s", file=sys.stderr, flush=True)
+    res = {"metric": f"value solves/sec at dual gap<=1e-6, sampled-copy double integrator (d={top['d']}, m=1, N=100)",
+           "value": top["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * top["device_s"], 2), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"value phi(x, t=2) of k = d/2 double integrators sharing one control in [-1,1], "
+                                  f"starts ~ N((1,0), 0.0667^2 I), mean-squared target 0.04, left rule N=100, "
+                                  f"{top['points']} points per d", "dims": dims, "c_tau": 0.5,
+                      "certificate": "fp64"},
+           "sweep": sweep,
+           "paper_context": "Sec. VI-C fit of MATLAB time per value solve on a laptop CPU (FP64, residual stop "
+                            "1e-4): paper_ms_per_solve; other hardware and a looser stop, not a target",
+           "roofline": {"bound": "mfma", "achieved": top["k_pdhg_tflops"], "peak": PEAK_FP32_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": top["k_pdhg_frac_fp32_mfma"], "traffic": None,
+                        "kernel": "k_pdhg<float, NT, 1> (algorithmic flops 4*m*n per point-row)"},
+           "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+
+
 def bench_c3(args):
     """Precision workload (n=200, m=20, N=400, box): value solves phi(x, t) of
     16384 points in BF16 hi+lo (FP32 accumulate, FP32 escalation of stalled
@@ -311,6 +437,7 @@ def bench_c3(args):
     idx = np.linspace(0, npts - 1, nsamp).astype(int)
     pending = []
     if nsamp:
+        single_thread_workers()
         ctx = mp.get_context("spawn")
         pool = ctx.Pool(min(nsamp, os.cpu_count() or 1))
         pending = pool.imap(_oracle_value, [(spec, w.x[i], float(t[i]), w.opts["c_tau"]) for i in idx])

@@ -9,6 +9,8 @@ without sharing any of the method.
 Workload shapes follow the paper's examples and the configurations the
 library is benchmarked on:
   * the double integrator of Sec. VI-A (n=2, m=1, |u| <= 1, ball target);
+  * its tychastic (sampled initial state) extension of Sec. VI-B/C: k copies
+    sharing one control, d = 2k, a mean-squared-error target;
   * random stable-ish linear systems: A = S diag(eig) S^{-1} with
     eig ~ U[-1, 0.2] and S_ij ~ N(0, 1/n), B_ij ~ N(0,1)/sqrt(n), an
     axis-aligned ellipsoid target W = diag(q), q ~ U[0.05, 0.2], and either
@@ -55,6 +57,32 @@ def double_integrator(r=0.1, N=100, t_max=10.0, quad="trap"):
     B = np.array([[0.0], [1.0]])
     W = (r * r) * np.eye(2)
     return SystemSpec(A, B, W, np.zeros(2), "box", N, t_max, quad, f"double_integrator_r{r}")
+
+
+def tychastic_double_integrator(k, ell=0.04, N=100, t_max=2.0, quad="left"):
+    """Sec. VI-B/C: k copies of the double integrator that share one scalar
+    control in [-1, 1] (state dimension d = 2k, A~ = I_k (x) A, B~ = 1_k (x) B),
+    with the terminal cost that bounds the mean squared distance of the k
+    terminal states from the origin by ell.  In the ellipsoid form used here,
+    {z : z^T W^-1 z <= 1}, that target is W = ell k I_d (the paper's shape
+    k I_d, scaled by the threshold).  With ell = r^2 and k equal copies the
+    problem is the single double integrator with a ball target of radius r."""
+    A2 = np.array([[0.0, 1.0], [0.0, 0.0]])
+    B2 = np.array([[0.0], [1.0]])
+    A = np.kron(np.eye(k), A2)
+    B = np.kron(np.ones((k, 1)), B2)
+    d = 2 * k
+    return SystemSpec(A, B, (ell * k) * np.eye(d), np.zeros(d), "box", N, t_max, quad,
+                      f"tychastic_double_integrator_k{k}")
+
+
+def tychastic_points(k, npts, mu, std, seed):
+    """Each query point stacks k independent samples chi_i ~ N(mu, std^2 I_2)
+    of the uncertain initial state (the randomly sampled variant of the
+    unscented construction)."""
+    rng = np.random.default_rng(seed)
+    return (np.asarray(mu, dtype=np.float64)[None, None, :]
+            + std * rng.normal(size=(npts, k, 2))).reshape(npts, 2 * k)
 
 
 def random_system(n, m, N, uset, seed, t_max=10.0, quad="trap",

@@ -100,7 +100,7 @@ typedef struct {
  *   t_rel_tol     bisection stops when hi - lo <= max(t_rel_tol*hi,
  *   t_abs_frac                                    t_abs_frac*t_max)                 [0.5e-4, 1e-6]
  *   max_iter      iterations per solve before HOPF_PT_NOCONV                         [200000]
- *   check_every   iterations between FP64 certificates                               [25]
+ *   check_every   iterations between FP64 certificates                               [50]
  *   warm          HOPF_WARM_COLD: every probe starts at lam = 0, y = 0;
  *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate;
  *                 HOPF_WARM_MLP: as CONT, and the system's trained network proposes

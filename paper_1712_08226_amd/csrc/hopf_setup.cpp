@@ -371,7 +371,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->t_rel_tol = 0.5e-4;
   o->t_abs_frac = 1e-6;
   o->max_iter = 200000;
-  o->check_every = 25;
+  o->check_every = 50;
   o->warm = HOPF_WARM_COLD;
   o->prec = HOPF_FP32;
   o->root = HOPF_ROOT_BISECT;

@@ -1,0 +1,108 @@
+"""GPU parity on the tychastic double integrator of Sec. VI-B/C (k copies of
+the double integrator sharing one control, d = 2k, mean-squared target): the
+HIP path through the C-ABI against the FP64 oracle.
+
+Small batches compare with the oracle's k-copy solves directly.  At the
+full workload size (d = 120, 65,536 points, the benchmark's launch) sampled
+points are checked against the oracle's two-dimensional solve at the sample
+mean plus the closed-form spread term, an identity that holds for the
+discrete problem at any k (all copies share the control, so each deviation
+from the mean evolves as e^{tA} delta_i)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from gen import double_integrator, tychastic_double_integrator, tychastic_points
+from gen.configs import config_tychastic
+from oracle import hopf_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+GAP = 1e-6
+ELL = 0.04
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_1712_08226_amd import Solver
+    s = Solver(0)
+    yield s
+    s.close()
+
+
+def osys(spec):
+    return O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+
+
+def overlap(a_lo, a_hi, b_lo, b_hi, tol=1e-9):
+    return max(a_lo, b_lo) <= min(a_hi, b_hi) + tol * max(1.0, abs(a_hi), abs(b_hi))
+
+
+@pytest.mark.parametrize("tail", [0, 512])
+@pytest.mark.parametrize("d", [30, 60])
+def test_tychastic_value_vs_oracle(solver, d, tail):
+    """70 points (a full tile and a ragged one), horizons from 0.4 to t_max
+    (partial node tables and the full one)."""
+    say("case: tychastic value d", d, "tail", tail)
+    k = d // 2
+    spec = tychastic_double_integrator(k, ell=ELL)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=0.5, tail_max=tail)
+    x = tychastic_points(k, 70, (1.0, 0.0), 0.0667, 31 + d)
+    t = np.linspace(0.4, 2.0, 70)
+    r = solver.value(x, t)
+    S = osys(spec)
+    for i in list(range(0, 70, 11)) + [69]:
+        pr = O.solve_value(S, x[i], t[i], O.Options(c_tau=0.5, gap_tol=1e-9, max_iter=400000))
+        assert r["status"][i] == 0, (i, r["status"][i])
+        assert overlap(r["phi_lo"][i], r["phi_hi"][i], pr.phi_lo, pr.phi_hi), \
+            (i, r["phi_lo"][i], r["phi_hi"][i], pr.phi_lo, pr.phi_hi)
+        assert (r["phi_hi"][i] - r["phi_lo"][i]) / max(1.0, abs(r["phi_hi"][i])) <= GAP
+
+
+def test_tychastic_min_time_vs_oracle(solver):
+    say("case: tychastic min time d 30")
+    k = 15
+    spec = tychastic_double_integrator(k, ell=ELL)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=0.5)
+    x = tychastic_points(k, 20, (1.0, 0.0), 0.0667, 77)
+    r = solver.min_time(x)
+    S = osys(spec)
+    for i in (0, 7, 19):
+        o = O.min_time(S, x[i], O.Options(c_tau=0.5))
+        assert r["status"][i] == o.status == O.PT_OK, (i, r["status"][i], o.status)
+        assert abs(r["T"][i] - o.T) <= 1e-4 * o.T + 1e-6 * spec.t_max, (i, r["T"][i], o.T)
+
+
+def test_tychastic_full_size_sampled(solver):
+    """The benchmark's d = 120 launch (65,536 value solves at t = t_max):
+    every solve certified, and sampled points equal the oracle's 2-D value at
+    the sample mean plus s(T) / (2 ell)."""
+    say("case: tychastic full size d 120")
+    w = config_tychastic(120)
+    spec = w.systems[0]
+    solver.set_systems([spec])
+    solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"])
+    T = w.opts["t"]
+    r = solver.value(w.x, np.full(len(w.x), T))
+    assert np.all(r["status"] == 0), np.unique(r["status"], return_counts=True)
+    gap = (r["phi_hi"] - r["phi_lo"]) / np.maximum(1.0, np.abs(r["phi_hi"]))
+    assert gap.max() <= GAP
+    S2 = osys(double_integrator(math.sqrt(ELL), spec.N, t_max=spec.t_max, quad=spec.quad))
+    E = np.array([[1.0, T], [0.0, 1.0]])
+    rng = np.random.default_rng(5)
+    for i in [0, len(w.x) - 1] + list(rng.integers(0, len(w.x), 6)):
+        chi = w.x[i].reshape(-1, 2)
+        mean = chi.mean(axis=0)
+        s = float(np.mean(np.sum(((chi - mean) @ E.T) ** 2, axis=1)))
+        b = O.solve_value(S2, mean, T, O.Options(c_tau=0.5, gap_tol=1e-10, max_iter=400000))
+        lo, hi = b.phi_lo + s / (2 * ELL), b.phi_hi + s / (2 * ELL)
+        assert overlap(r["phi_lo"][i], r["phi_hi"][i], lo, hi), (i, r["phi_lo"][i], r["phi_hi"][i], lo, hi)

@@ -8,7 +8,7 @@ import pytest
 from scipy.linalg import expm
 
 from oracle import hopf_oracle as O
-from gen import double_integrator, random_system
+from gen import double_integrator, random_system, tychastic_double_integrator, tychastic_points
 from tests import pin_helpers as PH
 
 
@@ -439,3 +439,45 @@ def test_newton_and_bisection_bracket_the_same_crossing():
         assert rb.status == rn.status == O.PT_OK
         assert max(rb.lo, rn.lo) <= min(rb.hi, rn.hi) + 1e-12
         assert abs(rb.T - rn.T) <= 1e-4 * rb.T
+
+
+# ------------------------------------------------------------------ tychastic double integrator (Sec. VI-B/C)
+
+@pytest.mark.slow
+def test_tychastic_identical_copies_reduce_to_double_integrator():
+    """k equal copies that share one control, with the mean-squared target
+    ell = r^2: the problem is the double integrator with the disk of radius
+    r, so the discrete minimum time matches one-switch bang-bang brute force
+    within the same quadrature bound as the single system."""
+    k, r = 3, 0.1
+    S = sysobj(tychastic_double_integrator(k, ell=r * r, N=100, t_max=10.0, quad="trap"))
+    res = O.min_time(S, np.tile([1.0, 0.0], k), O.Options(c_tau=30.0))
+    Tc = PH.di_min_time_ball(1.0, 0.0, r)
+    assert res.status == O.PT_OK
+    assert abs(res.T - Tc) <= 3e-4 * Tc + 0.02 * O.grid_step(S) ** 2, (res.T, Tc)
+
+
+def test_tychastic_value_splits_into_mean_and_spread():
+    """All copies share the control, so each copy's deviation delta_i from the
+    sample mean evolves as e^{tA} delta_i whatever the control.  With the
+    mean-squared target ell the value therefore splits exactly (also after
+    discretisation) into the double integrator's value at the mean, with the
+    disk of radius sqrt(ell), plus s(T) / (2 ell), s(T) = mean_i |e^{TA} delta_i|^2,
+    where e^{TA} = [[1, T], [0, 1]]."""
+    k, ell = 4, 0.04
+    S = sysobj(tychastic_double_integrator(k, ell=ell, N=100, t_max=2.0, quad="left"))
+    S2 = sysobj(double_integrator(math.sqrt(ell), 100, t_max=2.0, quad="left"))
+    opt = O.Options(c_tau=0.5, gap_tol=1e-10, max_iter=400000)
+    X = tychastic_points(k, 3, (1.0, 0.0), 0.0667, 21)
+    for x in X:
+        chi = x.reshape(k, 2)
+        mean = chi.mean(axis=0)
+        for T in (0.7, 2.0):
+            E = np.array([[1.0, T], [0.0, 1.0]])
+            s = float(np.mean(np.sum(((chi - mean) @ E.T) ** 2, axis=1)))
+            a = O.solve_value(S, x, T, opt)
+            b = O.solve_value(S2, mean, T, opt)
+            assert a.gap_n() <= 1e-10 and b.gap_n() <= 1e-10
+            lo, hi = b.phi_lo + s / (2 * ell), b.phi_hi + s / (2 * ell)
+            assert max(a.phi_lo, lo) <= min(a.phi_hi, hi) + 1e-9, (T, a.phi_lo, a.phi_hi, lo, hi)
+            assert abs(s / (2 * ell)) > 1e-3     # the spread term is not negligible
