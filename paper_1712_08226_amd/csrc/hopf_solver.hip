@@ -456,7 +456,7 @@ __device__ __forceinline__ void tail_primal(const T *__restrict__ Kc, const T *_
 
 // Dynamic LDS of k_tail_multi (the probe setup reuses the same bytes):
 //   bop 256 floats | l64 256 doubles | gp 256 x 16 B | red 5 x 4 doubles | vb CH doubles
-__host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 96 ? 1 : (96 / m < 16 ? 96 / m : 16); }
+__host__ __device__ inline int tail_chunk_blocks(int m) { return m >= 256 ? 1 : (256 / m < 16 ? 256 / m : 16); }
 __host__ __device__ inline size_t tail_lds_bytes(int m) {
   const size_t it = 256 * 4 + 256 * 8 + 256 * 16 + 20 * 8 + (size_t)16 * tail_chunk_blocks(m) * m * 8;
   const size_t su = (size_t)SETUP_SCRATCH * 8;
