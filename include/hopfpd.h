@@ -195,6 +195,16 @@ hopf_status hopf_min_time_dev(hopf_ctx *ctx, long npts, const int *sys_id, const
                               double *T, double *gap, double *lam, int *probes, int *iters,
                               int *pt_status, void *stream);
 
+/* Device-pointer twin of hopf_value: x, t, phi_lo, phi_hi, pt_status (and
+ * sys_id, lam, iters when given) are device memory with the layouts of
+ * hopf_value; the solve runs on `stream` (NULL: the context's stream).  The
+ * call copies t (and sys_id) to the host and checks them before any kernel
+ * runs (HOPF_EINVAL if a horizon lies outside [0, t_max] of its system), and
+ * returns when the results are in place. */
+hopf_status hopf_value_dev(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
+                           const double *t, double *phi_lo, double *phi_hi, double *lam,
+                           int *iters, int *pt_status, void *stream);
+
 /* Optimal control and trajectory at horizon T from x0 (Sec. IV eq. (27),
  * Sec. V eq. (33)).  Solves phi(x0,T) to gap_tol first.  Outputs, with
  * n_nodes <= N+1 written to *n_nodes, rows sorted by increasing physical

@@ -1601,6 +1601,37 @@ hopf_status hopf_min_time_dev(hopf_ctx *h, long npts, const int *sys_id, const d
                          probes, iters, pt_status, nullptr, (hipStream_t)stream);
 }
 
+hopf_status hopf_value_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *t,
+                           double *phi_lo, double *phi_hi, double *lam, int *iters, int *pt_status,
+                           void *stream) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (c->sys.empty()) return hopf::set_err(c, HOPF_ESTATE, "no systems set");
+  if (npts < 0 || !x || !t || !phi_lo || !phi_hi || !pt_status)
+    return hopf::set_err(c, HOPF_EINVAL, "x, t, phi_lo, phi_hi and pt_status are required");
+  if (npts == 0) return HOPF_OK;
+  if (npts > (1L << 26)) return hopf::set_err(c, HOPF_EINVAL, "too many points in one call");
+  if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+  // the horizons (and system ids) are checked on the host before any kernel
+  // runs: a horizon outside [0, t_max] would address nodes beyond the table
+  std::vector<double> th(npts);
+  std::vector<int> ih(sys_id ? npts : 0);
+  if (hipMemcpyAsync(th.data(), t, npts * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      (sys_id && hipMemcpyAsync(ih.data(), sys_id, npts * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return hopf::set_err(c, HOPF_EDEVICE, "reading t / sys_id from the device failed");
+  const int nsys = (int)c->sys.size();
+  for (long i = 0; i < npts; ++i) {
+    const int sid = sys_id ? ih[i] : 0;
+    if (sid < 0 || sid >= nsys) return hopf::set_err(c, HOPF_EINVAL, "sys_id out of range");
+    if (!(th[i] >= 0.0 && th[i] <= c->sys[sid].desc.t_max))
+      return hopf::set_err(c, HOPF_EINVAL, "t must lie in [0, t_max]");
+  }
+  return hopf::solve_dev(c, hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr, phi_lo, phi_hi, lam,
+                         nullptr, iters, pt_status, nullptr, s);
+}
+
 static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, const double *x,
                              const double *t, double *T, double *gap, double *philo, double *phihi,
                              double *lam, int *probes, int *iters, int *pt_status) {

@@ -23,7 +23,7 @@ ROOT_BISECT, ROOT_NEWTON = 0, 1
 PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
 EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", "hopf_last_error",
-           "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_min_time", "hopf_min_time_dev",
+           "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_value_dev", "hopf_min_time", "hopf_min_time_dev",
            "hopf_trajectory", "hopf_last_timing", "hopf_warm_init", "hopf_warm_params",
            "hopf_warm_loss_grad", "hopf_warm_train"]
 
@@ -63,6 +63,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise HopfError(f"{path} is not built: run `python -m paper_1712_08226_amd.build`")
+    # When PyTorch is installed its HIP runtime is loaded first, so the library
+    # binds to the same runtime and the device-pointer calls can share torch's
+    # tensors and streams; loaded the other way round, torch's own device
+    # initialisation fails later in the process ("No HIP GPUs are available").
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p
     lib.hopf_default_opts.argtypes = [C.POINTER(HopfOpts)]
@@ -78,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.hopf_value.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, dp, ip, ip]
     lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, ip, ip, ip]
     lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hopf_value_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
     lib.hopf_last_timing.argtypes = [vp, C.POINTER(HopfTiming)]
     fp = C.POINTER(C.c_float)
@@ -217,13 +226,50 @@ class Solver:
                                            _iptr(probes), _iptr(iters), _iptr(stat)), "hopf_min_time")
         return dict(T=T, gap=gap, lam=lam, probes=probes, iters=iters, status=stat)
 
+    def _dev_ptr(self, t, name, dtype, rows, cols=None):
+        """Pointer of a device tensor after checking what the library will
+        assume of it (device, dtype, contiguity, at least rows x cols items),
+        so that a mismatched tensor fails here instead of on the device."""
+        if t is None:
+            return None
+        if not (getattr(t, "is_cuda", False) and str(t.dtype) == dtype and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+        need = rows * (cols or 1)
+        if t.numel() < need or (cols is not None and (t.dim() != 2 or t.shape[1] != cols)):
+            raise ValueError(f"{name} must hold {rows} rows" + (f" of {cols} entries" if cols else ""))
+        return C.c_void_p(t.data_ptr())
+
+    def _dev_common(self, x, sys_id, stream):
+        if x.dim() != 2:
+            raise ValueError("x must be 2-D (points x n_max)")
+        npts, n = x.shape
+        if npts and n != self._stride(None if sys_id is None else sys_id.cpu().numpy()):
+            raise ValueError("x must have as many columns as the largest n of the systems used")
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        return npts, n, s
+
     def min_time_dev(self, x, T, gap, status, lam=None, probes=None, iters=None, sys_id=None, stream=None):
         """Device twin: torch CUDA tensors (float64 x/T/gap/lam, int32 others)."""
-        p = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
-        npts = x.shape[0]
-        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
-        self._check(self.lib.hopf_min_time_dev(self.h, npts, p(sys_id), p(x), p(T), p(gap), p(lam), p(probes),
-                                               p(iters), p(status), s), "hopf_min_time_dev")
+        npts, n, s = self._dev_common(x, sys_id, stream)
+        d = self._dev_ptr
+        self._check(self.lib.hopf_min_time_dev(
+            self.h, npts, d(sys_id, "sys_id", "torch.int32", npts), d(x, "x", "torch.float64", npts, n),
+            d(T, "T", "torch.float64", npts), d(gap, "gap", "torch.float64", npts),
+            d(lam, "lam", "torch.float64", npts, n), d(probes, "probes", "torch.int32", npts),
+            d(iters, "iters", "torch.int32", npts), d(status, "status", "torch.int32", npts), s),
+            "hopf_min_time_dev")
+
+    def value_dev(self, x, t, phi_lo, phi_hi, status, lam=None, iters=None, sys_id=None, stream=None):
+        """Device twin of value(): torch CUDA tensors (float64 x/t/phi/lam,
+        int32 others); results are in place when the call returns."""
+        npts, n, s = self._dev_common(x, sys_id, stream)
+        d = self._dev_ptr
+        self._check(self.lib.hopf_value_dev(
+            self.h, npts, d(sys_id, "sys_id", "torch.int32", npts), d(x, "x", "torch.float64", npts, n),
+            d(t, "t", "torch.float64", npts), d(phi_lo, "phi_lo", "torch.float64", npts),
+            d(phi_hi, "phi_hi", "torch.float64", npts), d(lam, "lam", "torch.float64", npts, n),
+            d(iters, "iters", "torch.int32", npts), d(status, "status", "torch.int32", npts), s),
+            "hopf_value_dev")
 
     def trajectory(self, x0, T, sys_id=0):
         """Control u(s) and state x(s) at the quadrature nodes (rows sorted by

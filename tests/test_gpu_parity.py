@@ -357,3 +357,38 @@ def test_adaptive_steps_converge_at_least_as_often(solver, uset, quad, c_tau):
     for k in np.flatnonzero(ok)[::17]:
         pr = O.solve_value(S, x[k], t[k], O.Options(c_tau=c_tau, gap_tol=1e-9, max_iter=400000))
         assert overlap(b["phi_lo"][k], b["phi_hi"][k], pr.phi_lo, pr.phi_hi), k
+
+
+def test_value_dev_matches_host_call(solver):
+    """hopf_value_dev (device buffers, caller's stream) gives the host call's
+    results; a horizon outside [0, t_max] is rejected before any kernel runs,
+    and a tensor of the wrong dtype is refused by the binding."""
+    import torch
+    from paper_1712_08226_amd.hopfpd import HopfError
+    say("case: value_dev vs value")
+    spec = random_system(20, 3, 40, "l2", seed=23, t_max=3.0)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=1.0)
+    x = gaussian_points(70, 20, 0.15, seed=6)
+    t = np.linspace(0.0, 3.0, 70)
+    r = solver.value(x, t)
+    dev = torch.device("cuda:0")
+    xd = torch.tensor(x, dtype=torch.float64, device=dev)
+    td = torch.tensor(t, dtype=torch.float64, device=dev)
+    lo = torch.empty(70, dtype=torch.float64, device=dev)
+    hi = torch.empty_like(lo)
+    lam = torch.empty(70, 20, dtype=torch.float64, device=dev)
+    it = torch.empty(70, dtype=torch.int32, device=dev)
+    st = torch.empty(70, dtype=torch.int32, device=dev)
+    solver.value_dev(xd, td, lo, hi, st, lam=lam, iters=it, stream=torch.cuda.current_stream(dev))
+    np.testing.assert_array_equal(st.cpu().numpy(), r["status"])
+    np.testing.assert_array_equal(it.cpu().numpy(), r["iters"])
+    np.testing.assert_allclose(lo.cpu().numpy(), r["phi_lo"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(hi.cpu().numpy(), r["phi_hi"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(lam.cpu().numpy(), r["lam"], rtol=1e-12, atol=1e-14)
+    bad = td.clone()
+    bad[5] = 3.5
+    with pytest.raises(HopfError):
+        solver.value_dev(xd, bad, lo, hi, st)
+    with pytest.raises(ValueError):
+        solver.value_dev(xd.float(), td, lo, hi, st)
