@@ -312,6 +312,21 @@ class Solver:
                                               None if nm is None else nm.ctypes.data_as(C.POINTER(C.c_float))),
                     "hopf_warm_params")
 
+    def warm_save(self, path, sys_id=0):
+        """Write the network of sys_id (parameters and input normalisation) to
+        an .npz file of plain arrays."""
+        th, nm = self.warm_get(sys_id)
+        np.savez(path, theta=th, norm=nm, n=np.int64(self.n[sys_id]))
+
+    def warm_load(self, path, sys_id=0):
+        """Load a network written by warm_save (no pickled objects are read)
+        into sys_id and mark it trained."""
+        with np.load(path, allow_pickle=False) as f:
+            if int(f["n"]) != self.n[sys_id]:
+                raise ValueError(f"{path} holds a network for n={int(f['n'])}, system {sys_id} has n={self.n[sys_id]}")
+            self.warm_init(sys_id)            # allocates the network; the parameters are replaced below
+            self.warm_set(f["theta"], f["norm"], sys_id)
+
     def warm_loss_grad(self, Z, Y, sys_id=0):
         Z = np.ascontiguousarray(Z, dtype=np.float32)
         Y = np.ascontiguousarray(Y, dtype=np.float32)

@@ -57,7 +57,7 @@ def test_mlp_gradient_matches_oracle(solver):
     assert rel <= 1e-3
 
 
-def test_training_and_warm_min_time(solver):
+def test_training_and_warm_min_time(solver, tmp_path):
     """Train on solver-generated pairs, then solve held-out points with the
     warm start: same certified times as the plain method (and the oracle)."""
     say("case: warm start train + min_time")
@@ -103,3 +103,20 @@ def test_training_and_warm_min_time(solver):
             before = O.solve_value(S, xte[k], Tw * (1 - 2e-4), O.Options(c_tau=2.0, gap_tol=1e-8, max_iter=400000))
             assert at.phi_lo <= 1e-6
             assert before.phi_hi >= -1e-6
+    # the trained network survives a save and a load into a fresh context
+    from paper_1712_08226_amd import Solver
+    path = str(tmp_path / "net.npz")
+    solver.warm_save(path)
+    s2 = Solver(0)
+    try:
+        s2.set_systems([spec])
+        s2.warm_load(path)
+        for a, b in zip(solver.warm_get(), s2.warm_get()):
+            assert np.array_equal(a, b)
+        solver.set_opts(prec="fp32", c_tau=2.0, warm="mlp_first")
+        s2.set_opts(prec="fp32", c_tau=2.0, warm="mlp_first")
+        r1, r2 = solver.min_time(xte[:64]), s2.min_time(xte[:64])
+        assert np.array_equal(r1["status"], r2["status"])
+        assert np.array_equal(r1["T"], r2["T"], equal_nan=True)
+    finally:
+        s2.close()
