@@ -128,3 +128,19 @@ def config_tychastic(d=30, npts=65536, seed=6):
     x = tychastic_points(k, npts, (1.0, 0.0), 0.0667, seed + d)
     return Workload(f"tychastic_d{d}", [spec], x, None, dict(prec="fp32", c_tau=0.5, t=2.0),
                     dict(points="k samples of N((1,0), 0.0667^2 I) per point"))
+
+
+def config_grid(per_axis=50):
+    """The level-set experiment of Sec. VI-A: the double integrator with
+    |u| <= 1 and the disk of radius 0.2 at the origin, value solves on a
+    per_axis x per_axis grid over [-1, 1]^2 (the paper's is 50 x 50) at
+    horizons spread over [0, T*], T* the minimum time from (1, 0); the
+    paper's own discretisation, left rule with N = 100 nodes per horizon.
+    The table's t_max (10) is only used to find T*; each horizon's solves
+    use a table built over [0, t]."""
+    spec = double_integrator(0.2, 100, t_max=10.0, quad="left")
+    g = np.linspace(-1.0, 1.0, per_axis)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    x = np.stack([X.ravel(), Y.ravel()], axis=1)
+    return Workload(f"double_integrator_grid_{per_axis}", [spec], x, None, dict(prec="fp64", c_tau=10.0),
+                    dict(points=f"{per_axis}x{per_axis} grid on [-1,1]^2"))

@@ -211,6 +211,20 @@ class Solver:
                                         _dptr(lam), _iptr(iters), _iptr(stat)), "hopf_value")
         return dict(phi_lo=lo, phi_hi=hi, lam=lam, iters=iters, status=stat)
 
+    def value_at_horizon(self, system, x, t):
+        """Value solves of many points at one shared horizon t in the paper's
+        per-horizon layout (Sec. III-A: the N nodes spread over [0, t]): the
+        system's node table is rebuilt over [0, t], which replaces the
+        context's systems, and every point is solved at t = t_max of that
+        table.  Level sets on a grid at a few horizons (Sec. VI-A) are the
+        intended use; for per-point horizons use value()."""
+        g = (lambda key, d=None: system.get(key, d) if isinstance(system, dict) else getattr(system, key, d))
+        sysd = {k: g(k) for k in ("A", "B", "W", "c", "Qu", "uset", "N", "quad", "c_tau")}
+        sysd["t_max"] = float(t)
+        self.set_systems([sysd])
+        x = _f64(x)
+        return self.value(x, np.full(x.shape[0], float(t)))
+
     def min_time(self, x, sys_id=None):
         x = _f64(x)
         npts, n = x.shape

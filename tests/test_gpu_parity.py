@@ -392,3 +392,28 @@ def test_value_dev_matches_host_call(solver):
         solver.value_dev(xd, bad, lo, hi, st)
     with pytest.raises(ValueError):
         solver.value_dev(xd.float(), td, lo, hi, st)
+
+
+def test_value_at_horizon_grid_vs_oracle(solver):
+    """The paper's per-horizon layout (Sec. III-A: N left-rule nodes spread
+    over [0, t]) on the Sec. VI-A level-set grid, FP64 iterations: every grid
+    point certified, sampled points against the oracle's solve on the same
+    nodes (which are i t / N, the paper's)."""
+    from gen.configs import config_grid
+    say("case: value at horizon, 50x50 grid")
+    w = config_grid(50)
+    spec = w.systems[0]
+    t = 1.2
+    solver.set_opts(prec="fp64", c_tau=10.0)
+    r = solver.value_at_horizon(spec, w.x, t)
+    assert np.all(r["status"] == 0), np.unique(r["status"], return_counts=True)
+    gap = (r["phi_hi"] - r["phi_lo"]) / np.maximum(1.0, np.abs(r["phi_hi"]))
+    assert gap.max() <= GAP
+    S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=t, quad=spec.quad)
+    tau, wts, _ = O.nodes_and_weights(S, t)
+    np.testing.assert_allclose(tau, np.arange(spec.N) * t / spec.N, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(wts, np.full(spec.N, t / spec.N), rtol=0, atol=1e-12)
+    for i in [0, 1224, 1275, 2499] + list(range(37, 2500, 401)):
+        pr = O.solve_value(S, w.x[i], t, O.Options(c_tau=10.0, gap_tol=1e-9, max_iter=400000))
+        assert overlap(r["phi_lo"][i], r["phi_hi"][i], pr.phi_lo, pr.phi_hi), \
+            (i, r["phi_lo"][i], r["phi_hi"][i], pr.phi_lo, pr.phi_hi)
