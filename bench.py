@@ -30,12 +30,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1712_08226_amd", "csrc", "hopf_device.h")
 COUNTERS = os.path.join(ROOT, "profiles", "k_pdhg_n100_m10_N300_65536q_hbm_counters.md")
 
 
-def counter_traffic(variant, check_every):
+def counter_traffic(variant, check_every, c_tau):
     """HBM bytes per k_pdhg launch from the committed FETCH_SIZE / WRITE_SIZE
     counter runs of this workload ('traffic:' JSON lines in the summary, one
     per profiled warm-start variant), or None when no record matches the
-    variant and iterations per launch of this run, or the kernel source has
-    changed since the counters were taken."""
+    variant, iterations per launch and step ratio of this run, or the kernel
+    source has changed since the counters were taken."""
     import hashlib
     try:
         with open(COUNTERS) as f:
@@ -46,7 +46,7 @@ def counter_traffic(variant, check_every):
         return None
     for rec in recs:
         if (rec.get("kernel_source_sha256") == sha and rec.get("variant") == variant
-                and rec.get("check_every") == check_every):
+                and rec.get("check_every") == check_every and rec.get("c_tau") == c_tau):
             return rec
     return None
 
@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--c4-max-iter", type=int, default=20000, help="c4: iteration cap per solve")
     ap.add_argument("--c4-mode", default="min_time", choices=["min_time", "value"],
                     help="c4: minimum-time queries, or value solves at t ~ U[0.5, t_max]")
+    ap.add_argument("--c-tau", type=float, default=None,
+                    help="primal step ratio c_tau (default: the workload's)")
     ap.add_argument("--check-every", type=int, default=None,
                     help="iterations between certificates (default: the library's)")
     ap.add_argument("--tail-max", type=int, default=None,
@@ -163,6 +165,8 @@ def main():
         w.opts["prec"] = args.prec
     ce_run = args.check_every if args.check_every is not None else w.opts.get("check_every",
                                                                               default_opts().check_every)
+    if args.c_tau is not None:
+        w.opts["c_tau"] = args.c_tau
     spec = w.systems[0]
     dev = torch.device("cuda:0")
     solver = Solver(0)
@@ -265,7 +269,7 @@ def main():
     per_launch_ms = 1e3 * tk / max(1, launches)
     bf = w.opts["prec"] == "bf16x3"
     peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
-    ct = None if bf else counter_traffic(best, ce_run)
+    ct = None if bf else counter_traffic(best, ce_run, w.opts["c_tau"])
     traffic = None
     if ct is not None and per_launch_ms > 0:   # measured HBM bytes per launch / measured launch time
         traffic = round(ct["hbm_bytes_per_launch"] / (per_launch_ms * 1e-3) / 1e9, 2)
