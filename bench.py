@@ -529,6 +529,8 @@ def bench_c3(args):
     from gen.configs import config3
     from paper_1712_08226_amd import Solver
     w = config3(npts=args.npts if args.npts != 65536 else 16384)
+    if args.c_tau is not None:
+        w.opts["c_tau"] = args.c_tau
     spec = w.systems[0]
     npts = len(w.x)
     t = w.meta["t"]

@@ -58,7 +58,7 @@ typedef enum {
   HOPF_ENOMEM = 2,        /* device or host allocation failed */
   HOPF_EDEVICE = 3,       /* HIP runtime error */
   HOPF_ESTATE = 4,        /* call out of order (e.g. solve before set_systems) */
-  HOPF_EUNSUPPORTED = 5   /* valid request this build does not handle */
+  HOPF_EUNSUPPORTED = 5   /* valid request the library does not handle */
 } hopf_status;
 
 typedef enum { HOPF_U_L2 = 0, HOPF_U_BOX = 1 } hopf_uset;
@@ -79,7 +79,7 @@ typedef enum {
 } hopf_pt;
 
 /* One system.  Sizes: A n*n, B n*m, Qu m*m (NULL = identity), W n*n
- * symmetric positive definite and diagonal in this build, c n (NULL = 0).
+ * symmetric positive definite and diagonal (the library handles diagonal targets), c n (NULL = 0).
  * Limits: 1 <= n <= 256, 1 <= m <= 64, 2 <= N <= 4096, t_max > 0.
  * c_tau: this system's primal step ratio (see hopf_opts.c_tau); 0 uses the
  * call's option.  Lets one call mix systems whose best ratio differs (the

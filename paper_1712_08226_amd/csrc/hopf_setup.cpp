@@ -196,7 +196,7 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
       const double v = t.W[(size_t)i * n + j];
       if (i == j && !(v > 0.0)) return set_err(ctx, HOPF_EINVAL, "W is not positive definite");
       if (i != j && v != 0.0)
-        return set_err(ctx, HOPF_EUNSUPPORTED, "this build needs a diagonal target matrix W");
+        return set_err(ctx, HOPF_EUNSUPPORTED, "the library needs a diagonal target matrix W");
     }
   t.desc.A = t.A.data(); t.desc.B = t.B.data(); t.desc.W = t.W.data();
   t.desc.Qu = t.Qu.data(); t.desc.c = t.c.data();
@@ -389,7 +389,7 @@ const char *hopf_strerror(hopf_status s) {
     case HOPF_ENOMEM: return "out of memory";
     case HOPF_EDEVICE: return "HIP device error";
     case HOPF_ESTATE: return "call out of order";
-    case HOPF_EUNSUPPORTED: return "unsupported by this build";
+    case HOPF_EUNSUPPORTED: return "not supported by the library";
   }
   return "unknown status";
 }

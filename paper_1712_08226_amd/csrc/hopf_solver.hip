@@ -1173,7 +1173,7 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   J.lds_cert = (size_t)(WAVES - 1) * 2 * 4 * 64 * 8 + (size_t)WAVES * 64 * 8 + (size_t)16 * tab.n_pad * 4 +
                (size_t)16 * tab.n_pad * 8 + (size_t)16 * mpad * 8;
   if (J.lds_pdhg > 150 * 1024 || J.lds_cert > 150 * 1024)
-    return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of this build");
+    return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of the kernels");
   if (ho.prec == HOPF_BF16X3 && !tab.Kd16h) return set_err(ctx, HOPF_ESTATE, "BF16 tables missing");
   // BF16 hi+lo: points that stall are escalated to an FP32 kernel
   if (ho.prec == HOPF_BF16X3) {
