@@ -481,3 +481,24 @@ def test_tychastic_value_splits_into_mean_and_spread():
             lo, hi = b.phi_lo + s / (2 * ell), b.phi_hi + s / (2 * ell)
             assert max(a.phi_lo, lo) <= min(a.phi_hi, hi) + 1e-9, (T, a.phi_lo, a.phi_hi, lo, hi)
             assert abs(s / (2 * ell)) > 1e-3     # the spread term is not negligible
+
+
+@pytest.mark.parametrize("T", [3.0, 1.37])
+def test_operator_norm_bound_against_singular_values(T):
+    """L (which sets both step sizes) is the spectral norm of the stacked K on
+    the table nodes, from the largest singular value of the stacked matrix
+    (a different computation from the oracle's eigenvalue of the Gram sum);
+    with an off-grid horizon the extra node's Frobenius term keeps L an upper
+    bound of ||K||."""
+    spec = random_system(6, 2, 30, "l2", seed=31, t_max=3.0)
+    S = sysobj(spec)
+    tau, w, partial = O.nodes_and_weights(S, T)
+    Ks = O.K_blocks(S, tau)
+    L = O.op_norm_bound(S, Ks, partial)
+    full = np.linalg.norm(Ks.reshape(-1, 6), 2)
+    if partial:
+        table = np.linalg.norm(Ks[:-1].reshape(-1, 6), 2)
+        assert full <= L + 1e-12
+        assert abs(L ** 2 - table ** 2 - np.sum(Ks[-1] ** 2)) <= 1e-10 * L ** 2
+    else:
+        assert abs(L - full) <= 1e-10 * full
