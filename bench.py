@@ -373,6 +373,8 @@ def bench_tychastic(args):
     sweep = []
     for d in dims:
         w = config_tychastic(d, npts=args.npts)
+        if args.c_tau is not None:
+            w.opts["c_tau"] = args.c_tau
         spec, T, npts = w.systems[0], w.opts["t"], len(w.x)
         solver.set_systems([spec])
         solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"])
@@ -425,7 +427,8 @@ def bench_tychastic(args):
            "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": f"value phi(x, t=2) of k = d/2 double integrators sharing one control in [-1,1], "
                                   f"starts ~ N((1,0), 0.0667^2 I), mean-squared target 0.04, left rule N=100, "
-                                  f"{top['points']} points per d", "dims": dims, "c_tau": 0.5,
+                                  f"{top['points']} points per d", "dims": dims,
+                      "c_tau": args.c_tau if args.c_tau is not None else config_tychastic(dims[-1], npts=1).opts["c_tau"],
                       "certificate": "fp64"},
            "sweep": sweep,
            "paper_context": "Sec. VI-C fit of MATLAB time per value solve on a laptop CPU (FP64, residual stop "
