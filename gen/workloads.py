@@ -2,9 +2,10 @@
 benchmark.
 
 This module only draws random systems and query points.  It contains none of
-the solver's arithmetic (no matrix exponential, quadrature, Hopf objective or
-primal-dual step), so the oracle and the HIP path can both read its output
-without sharing any of the method.
+the solver's arithmetic (no node table, quadrature, Hopf objective or
+primal-dual step); the one library matrix exponential here moves a start
+point under free motion (zero control) to plant it, so the oracle and the
+HIP path can both read its output without sharing any of the method.
 
 Workload shapes follow the paper's examples and the configurations the
 library is benchmarked on:
