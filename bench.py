@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=40.0, help="seconds of oracle wall time")
     ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
-                         "workload with its error against the FP64 oracle; c4: 64 uneven systems in one call; "
+                         "workload with its BF16 / FP32 difference; c4: 64 uneven systems in one call; "
                          "tychastic: the paper's dimensional-scaling value solves, d = 2k sampled copies; "
                          "grid: the paper's double-integrator level-set grid at ten horizons")
     ap.add_argument("--dims", default="30,60,90,120", help="tychastic: state dimensions d to sweep")
