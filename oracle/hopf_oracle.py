@@ -92,7 +92,13 @@ class System:
 class Options:
     """Solver settings.  Paper: theta = 1 and sigma = 1/(tau ||K||^2)
     (Sec. VI); here sigma carries a 0.999 factor so that the strict step
-    condition tau sigma ||K||^2 < 1 of Sec. III holds, and tau = c_tau/||K||."""
+    condition tau sigma ||K||^2 < 1 of Sec. III holds, and tau = c_tau/||K||.
+
+    Minimum-time search (Sec. IV: T* is the smallest horizon with
+    phi(x0, T) = 0): `scan` uniform horizons j t_max / scan, j = 1..scan, are
+    probed in ascending order until the first certified reach; the search then
+    refines the cell between the last certified-unreachable scan horizon and
+    that reach (bisection, or the Newton hybrid of Sec. IV)."""
     c_tau: float = 1.0
     gap_tol: float = 1e-6
     t_rel_tol: float = 0.5e-4
@@ -102,7 +108,8 @@ class Options:
     warm: str = "cold"          # "cold": lam0 = 0 at every probe; "cont": previous probe's iterate
     root: str = "bisect"        # "bisect": midpoint; "newton": Sec. IV hybrid Newton-bisection step
     newton_rho: float = 0.5     # hybrid: a probe also runs until gap <= rho |phi| (Newton accuracy)
-    newton_after: int = 1       # hybrid: probes (counting t_max) decided by bisection first
+    newton_after: int = 1       # hybrid: midpoint probes inside the cell before Newton steps start
+    scan: int = 32              # uniform scan horizons on (0, t_max] for the first crossing
 
 
 # ---------------------------------------------------------------- terminal data
@@ -363,26 +370,43 @@ def solve_value(sys: System, x0, T, opt: Options = Options(), lam0=None, y0=None
 REACH, UNREACH, NOCONV = "reach", "unreach", "noconv"
 
 
+def sign_decision(pr: Probe, opt: Options, tight: bool):
+    """Sign of phi_N(x, T) from the probe's current certified interval
+    [-P, -D] (Sec. IV: phi <= 0 means the target is reachable at T):
+    -D <= 0 certifies reachable, -P > 0 certifies unreachable, and a gap
+    below tolerance with neither counts as reachable (a zero of phi).  With
+    `tight` (the Newton hybrid) the interval must also be narrower than
+    newton_rho |phi| first.  Returns REACH, UNREACH or None (undecided)."""
+    if pr.gap_n() <= opt.gap_tol:
+        return UNREACH if -pr.P > 0.0 else REACH
+    if tight and pr.P - pr.D > opt.newton_rho * 0.5 * abs(pr.P + pr.D):
+        return None                     # the Newton step needs a tighter value
+    if -pr.D <= 0.0:
+        return REACH
+    if -pr.P > 0.0:
+        return UNREACH
+    return None
+
+
 def sign_probe(sys: System, pr: Probe, opt: Options, tight: bool = False):
-    """Run a probe until the sign of phi_N is certified (Sec. IV: phi < 0
-    means the target is reachable at T):  -D <= 0 certifies reachable, -P > 0
-    certifies unreachable, and a gap below tolerance with neither counts as
-    reachable (a zero of phi).  Returns REACH, UNREACH or NOCONV."""
+    """Run a probe until the sign of phi_N is certified.  The starting point
+    is certified before the first iteration (a probe continued from a nearby
+    horizon often already decides), then every check_every iterations.
+    Returns REACH, UNREACH or NOCONV."""
     if len(pr.tau) == 0:
         solve_value(sys, None, pr.T, opt, pr=pr)
         return REACH if -pr.D <= 0.0 else UNREACH
+    certify(sys, pr)
+    out = sign_decision(pr, opt, tight)
+    if out is not None:
+        return out
     while pr.iters < opt.max_iter:
         pdhg_iteration(sys, pr)
         if pr.iters % opt.check_every == 0:
             certify(sys, pr)
-            if pr.gap_n() <= opt.gap_tol:
-                return UNREACH if -pr.P > 0.0 else REACH
-            if tight and pr.P - pr.D > opt.newton_rho * 0.5 * abs(pr.P + pr.D):
-                continue                # the Newton step needs a tighter value
-            if -pr.D <= 0.0:
-                return REACH
-            if -pr.P > 0.0:
-                return UNREACH
+            out = sign_decision(pr, opt, tight)
+            if out is not None:
+                return out
     return NOCONV
 
 
@@ -400,6 +424,7 @@ class MinTimeResult:
     lo: float
     hi: float
     final: Probe | None = None
+    scan_probes: int = 0
 
 
 def value_slope(sys: System, pr: Probe):
@@ -416,49 +441,58 @@ def value_slope(sys: System, pr: Probe):
     return float((sys.A @ pr.xf) @ lam - support(pr.Ks[-1] @ lam, sys.uset))
 
 
-NEWTON_MAX_PROBES = 48     # from this probe on the hybrid takes midpoints only (termination)
+def scan_horizon(sys: System, opt: Options, j: int):
+    """j-th scan horizon j t_max / scan (the last one is t_max exactly)."""
+    return sys.t_max if j >= opt.scan else j * sys.t_max / opt.scan
 
 
-def next_horizon(sys: System, opt: Options, pr: Probe, reached: bool, lo: float, hi: float,
-                 probes: int = 0):
-    """Next probe of the root search on the certified bracket [lo, hi].
+def search_tol(sys: System, opt: Options, hi: float):
+    """Width at which the refinement stops (bracket [lo, hi], T = hi)."""
+    return max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max)
 
-    Bisection: the midpoint.  Hybrid (Sec. IV): the Newton step
-    T - phi/(d phi/dT) from the probe just certified, with phi the midpoint of
-    its certified interval [-P, -D]; the step is moved 0.4 of the stopping
-    tolerance towards the side of the root not yet bracketed (so that an
-    accurate step closes the bracket in one probe), and is replaced by the
-    midpoint when it falls outside (lo, hi), the slope is not negative, or
-    the probe count (including the probe just certified) has reached
-    NEWTON_MAX_PROBES, which bounds the search.
-    Newton steps start once the probe count reaches newton_after (earlier
-    probes are placed by bisection: where phi_N changes sign more than once,
-    a Newton step from t_max heads for the last crossing), and those probes
-    run until P - D <= newton_rho |P + D| / 2 so that the step sees an
-    accurate value.  Returns (T_next, newton_used)."""
-    mid = 0.5 * (lo + hi)
-    if opt.root != "newton" or not pr.tight or probes >= NEWTON_MAX_PROBES:
-        return mid, False
+
+def newton_proposal(sys: System, opt: Options, pr: Probe, lo: float, hi: float):
+    """The Sec. IV hybrid step from the probe just certified: T - phi/(d phi/dT)
+    with phi the midpoint of its certified interval [-P, -D] and the slope of
+    value_slope.  The probe is moved off that root estimate r towards the end
+    of the bracket farther from it (above r when hi - r > r - lo, else below),
+    by 0.4 of the stopping tolerance plus the estimate's own uncertainty, the
+    interval's half-width (P - D)/2 divided by |slope|: it then lands on that
+    side of the root, and with an accurate estimate the bracket closes on the
+    next probe.  None when the slope is not negative or the probe would leave
+    (lo, hi)."""
     s = value_slope(sys, pr)
     if not (s < 0.0) or not math.isfinite(s):
-        return mid, False
-    phi = -0.5 * (pr.P + pr.D)
-    tol = max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max)
-    t = pr.T - phi / s + (-0.4 * tol if reached else 0.4 * tol)
-    if lo < t < hi:
-        return t, True
-    return mid, False
+        return None
+    r = pr.T - (-0.5 * (pr.P + pr.D)) / s
+    shift = 0.4 * search_tol(sys, opt, hi) + 0.5 * (pr.P - pr.D) / abs(s)
+    t = r + shift if hi - r > r - lo else r - shift
+    return t if lo < t < hi else None
 
 
-def min_time(sys: System, x0, opt: Options = Options()):
-    """Minimum time to reach Omega (Sec. IV): the horizon where phi_N changes
-    sign, found on [0, t_max] with certified signs, by bisection or by the
-    hybrid Newton-bisection of Sec. IV (next_horizon).
+def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=None):
+    """Minimum time to reach Omega (Sec. IV): the smallest horizon where phi_N
+    falls to zero, searched with certified signs.
 
-    Steps: inside the target -> T = 0.  Probe t_max: certified unreachable ->
-    T = inf.  Otherwise probe inside the bracket until hi - lo <=
-    max(t_rel_tol hi, t_abs_tol_frac t_max); return T = hi and the solve at hi
-    continued to the gap tolerance."""
+    1. Inside the target (J(x0) <= 0): T = 0.
+    2. Scan: probe j t_max / scan for j = 1, 2, ... in ascending order until
+       the first certified reach.  Every scan horizon certified unreachable,
+       t_max included: T = +inf.  A reachable interval of horizons that lies
+       strictly between two neighbouring scan horizons is not seen.
+    3. Refine the cell [lo, hi] between the last certified-unreachable horizon
+       (0 when the first scan horizon already reaches) and the first certified
+       reach until hi - lo <= max(t_rel_tol hi, t_abs_tol_frac t_max):
+         - a caller's hint t_bracket = (a, b) is probed first: b, then a,
+           each only when it lies inside the current bracket;
+         - otherwise the midpoint, or with root = "newton" the hybrid step
+           (newton_proposal) once `newton_after` probes of the cell are done;
+           a Newton probe that leaves the bracket wider than half its width
+           before the step forces the next probe to the midpoint, so the width
+           halves at least every two probes (termination);
+       a certified reach moves hi, a certified unreachable moves lo.
+    4. T = hi; the solve at hi is continued to the gap tolerance.
+    Probes start at lam = 0 (warm = "cold") or from the previous probe's
+    iterate ("cont"); the first probe starts from lam0 when given."""
     x0 = np.asarray(x0, dtype=np.float64)
     if not np.all(np.isfinite(x0)):
         return MinTimeResult(math.nan, PT_NONFINITE, 0, 0, np.full(sys.n, math.nan), None,
@@ -468,52 +502,88 @@ def min_time(sys: System, x0, opt: Options = Options()):
         return MinTimeResult(0.0, PT_INSIDE, 0, 0, lam, None, J_star(sys, lam) - x0 @ lam,
                              -J(sys, x0), 0.0, 0.0, 0.0)
     probes, iters = 0, 0
-    pr = make_probe(sys, x0, sys.t_max, opt)
-    pr.tight = opt.root == "newton" and opt.newton_after <= 1
-    out = sign_probe(sys, pr, opt, pr.tight)
-    probes += 1
-    iters += pr.iters
-    if out == NOCONV:
-        return MinTimeResult(math.nan, PT_NOCONV, probes, iters, pr.lam, pr.y, pr.P, pr.D,
-                             pr.gap_n(), 0.0, sys.t_max, pr)
-    if out == UNREACH:
-        return MinTimeResult(math.inf, PT_UNREACH, probes, iters, pr.lam, pr.y, pr.P, pr.D,
-                             pr.gap_n(), sys.t_max, math.inf, pr)
-    lo, hi = 0.0, sys.t_max
-    last, last_is_hi = pr, True
-    while hi - lo > max(opt.t_rel_tol * hi, opt.t_abs_tol_frac * sys.t_max):
-        nxt, _ = next_horizon(sys, opt, last, last_is_hi, lo, hi, probes)
-        if opt.warm == "cont":
-            pr = make_probe(sys, x0, nxt, opt, last.lam, last.y)
+    last = None
+
+    def start(T, tight=False):
+        nonlocal probes
+        if last is None:
+            pr = make_probe(sys, x0, T, opt, lam0)
+        elif opt.warm == "cont":
+            pr = make_probe(sys, x0, T, opt, last.lam, last.y)
         else:
-            pr = make_probe(sys, x0, nxt, opt)
-        pr.tight = opt.root == "newton" and probes + 1 >= opt.newton_after
-        out = sign_probe(sys, pr, opt, pr.tight)
+            pr = make_probe(sys, x0, T, opt)
+        pr.tight = tight
         probes += 1
+        return pr
+
+    # ---- scan for the first certified reach
+    lo, hi = 0.0, math.inf
+    nscan = 0
+    for j in range(1, opt.scan + 1):
+        T = scan_horizon(sys, opt, j)
+        pr = start(T)
+        out = sign_probe(sys, pr, opt)
         iters += pr.iters
+        nscan += 1
+        last = pr
         if out == NOCONV:
             return MinTimeResult(math.nan, PT_NOCONV, probes, iters, pr.lam, pr.y, pr.P, pr.D,
-                                 pr.gap_n(), lo, hi, pr)
+                                 pr.gap_n(), lo, T, pr, nscan)
+        if out == REACH:
+            hi = T
+            break
+        lo = T
+    if not math.isfinite(hi):
+        return MinTimeResult(math.inf, PT_UNREACH, probes, iters, last.lam, last.y, last.P, last.D,
+                             last.gap_n(), lo, math.inf, last, nscan)
+
+    # ---- refine the first cell
+    hints = [] if t_bracket is None else [float(t_bracket[1]), float(t_bracket[0])]
+    last_is_hi = True
+    ncell = 0                 # probes inside the cell so far
+    guard_w = None            # bracket width before the last Newton probe
+    while hi - lo > search_tol(sys, opt, hi):
+        nxt, newton = 0.5 * (lo + hi), False
+        while hints:
+            t = hints.pop(0)
+            if lo < t < hi:
+                nxt = t
+                break
+        else:
+            if opt.root == "newton" and last.tight and guard_w is None:
+                t = newton_proposal(sys, opt, last, lo, hi)
+                if t is not None:
+                    nxt, newton = t, True
+        width = hi - lo
+        pr = start(nxt, tight=opt.root == "newton" and ncell + 1 >= opt.newton_after)
+        out = sign_probe(sys, pr, opt, pr.tight)
+        iters += pr.iters
+        ncell += 1
+        if out == NOCONV:
+            return MinTimeResult(math.nan, PT_NOCONV, probes, iters, pr.lam, pr.y, pr.P, pr.D,
+                                 pr.gap_n(), lo, hi, pr, nscan)
         if out == REACH:
             hi, last_is_hi = nxt, True
         else:
             lo, last_is_hi = nxt, False
         last = pr
+        if newton:
+            guard_w = width if hi - lo > 0.5 * width else None
+        else:
+            guard_w = None
+
+    # ---- the solve at T = hi to the gap tolerance
     if last_is_hi:
         fin = last
         before = fin.iters
     else:
-        if opt.warm == "cont":
-            fin = make_probe(sys, x0, hi, opt, last.lam, last.y)
-        else:
-            fin = make_probe(sys, x0, hi, opt)
-        probes += 1
+        fin = start(hi)
         before = 0
     solve_value(sys, x0, hi, opt, pr=fin)
     iters += fin.iters - before
     st = PT_OK if fin.gap_n() <= opt.gap_tol else PT_NOCONV
     return MinTimeResult(hi, st, probes, iters, fin.lam, fin.y, fin.P, fin.D, fin.gap_n(),
-                         lo, hi, fin)
+                         lo, hi, fin, nscan)
 
 
 def readout(sys: System, x0, pr: Probe):

@@ -62,3 +62,29 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([0.3, -2.0, 1e-3])
     th, m, v = M.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(th, -0.01 * np.sign(g), rtol=1e-4)
+
+
+def test_adam_bias_correction_over_several_steps():
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each step
+    moves a parameter by lr g / (|g| + eps): after t steps theta = -t lr g/(|g|+eps).
+    A correction with the wrong power of b1 or b2 breaks this from t = 2 on."""
+    g = np.array([0.3, -2.0, 1e-3, 5.0])
+    lr, eps = 0.01, 1e-8
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 8):
+        th, m, v = M.adam_step(th, g, m, v, t, lr, eps=eps)
+        np.testing.assert_allclose(th, -t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+
+
+def test_adam_second_step_by_hand():
+    """Gradients 1 then -1 (b1 = 0.9, b2 = 0.999, lr = 1): after step 2
+    m = 0.9*0.1 - 0.1 = -0.01, v = 0.999*0.001 + 0.001 = 0.001999, mh = -0.01/0.19,
+    vh = 0.001999/0.001999 = 1, so theta moves by +0.01/0.19 (+ the first step's -1)."""
+    th, m, v = M.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, 1.0, eps=0.0)
+    th, m, v = M.adam_step(th, -np.ones(1), m, v, 2, 1.0, eps=0.0)
+    np.testing.assert_allclose(m, [-0.01], rtol=1e-12)
+    np.testing.assert_allclose(v, [0.001999], rtol=1e-12)
+    np.testing.assert_allclose(th, [-1.0 + 0.01 / 0.19], rtol=1e-12)

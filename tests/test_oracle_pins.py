@@ -502,3 +502,169 @@ def test_operator_norm_bound_against_singular_values(T):
         assert abs(L ** 2 - table ** 2 - np.sum(Ks[-1] ** 2)) <= 1e-10 * L ** 2
     else:
         assert abs(L - full) <= 1e-10 * full
+
+
+# ------------------------------------------------------------------ first crossing (Sec. IV: the smallest T with phi = 0)
+
+def rotation_system(eps=0.05, r=0.5, N=200, t_max=10.0):
+    """Harmonic oscillator x1' = x2, x2' = -x1 (e^{tA} a rotation) with l2
+    control of radius eps in both coordinates and the disk of radius r at
+    c = (0, -2).  The free motion from (2, 0) is (2 cos t, -2 sin t): it
+    passes through the disk near t = pi/2 + 2 pi k and leaves it again."""
+    A = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    return O.System(A, eps * np.eye(2), (r * r) * np.eye(2), np.array([0.0, -2.0]), None,
+                    O.L2, N, t_max, O.TRAP)
+
+
+def rotation_first_crossing(eps=0.05, r=0.5):
+    """Closed form.  Because every e^{sA} is a rotation, the points reachable
+    at time t are the disk of radius eps t around the free motion, and so
+    are those of the quadrature form (sum_k w_k = t, every u_k can be turned
+    to the same direction).  The target is reached exactly when
+    |x_free(t) - c| = sqrt(8 - 8 sin t) <= r + eps t; T* is the first root."""
+    from scipy.optimize import brentq
+    f = lambda t: math.sqrt(max(8.0 - 8.0 * math.sin(t), 0.0)) - r - eps * t
+    return brentq(f, 0.5, math.pi / 2, xtol=1e-14)
+
+
+def test_rotation_reach_set_closed_form_sign_pattern():
+    """phi_N(x, t) <= 0 exactly where the closed form says the disk is
+    reached: twice in [0, 10] with an unreachable stretch in between and at
+    t_max, so a search that looks only at t_max misses the first crossing."""
+    S = rotation_system()
+    x = np.array([2.0, 0.0])
+    opt = O.Options(c_tau=1.0, max_iter=400000)
+    for t in (1.0, 1.6, 4.0, 7.85, 10.0):
+        dist = math.sqrt(max(8.0 - 8.0 * math.sin(t), 0.0))
+        reach = dist <= 0.5 + 0.05 * t
+        pr = O.make_probe(S, x, t, opt)
+        out = O.sign_probe(S, pr, opt)
+        assert out == (O.REACH if reach else O.UNREACH), (t, out, dist)
+
+
+@pytest.mark.parametrize("root", ["bisect", "newton"])
+def test_min_time_is_the_first_crossing(root):
+    """On the rotation system the search returns the first crossing of the
+    closed form (not +inf, which the value at t_max alone would suggest),
+    within the search tolerance and the trapezoid's exactness."""
+    S = rotation_system()
+    Tc = rotation_first_crossing()
+    res = O.min_time(S, np.array([2.0, 0.0]), O.Options(c_tau=1.0, warm="cont", root=root))
+    assert res.status == O.PT_OK
+    assert res.lo <= Tc + 1e-9 and abs(res.T - Tc) <= 1e-4 * Tc, (res.T, Tc)
+    assert res.gap_n <= 1e-6
+
+
+def test_min_time_unreachable_needs_every_scan_horizon():
+    """UNREACH only when every scan horizon is certified unreachable: a
+    start far from the target probes all of them."""
+    S = rotation_system(eps=0.01)
+    res = O.min_time(S, np.array([6.0, 0.0]), O.Options(c_tau=1.0, warm="cont", scan=16))
+    assert res.status == O.PT_UNREACH and math.isinf(res.T)
+    assert res.scan_probes == 16 and res.probes == 16
+
+
+def test_min_time_hint_inside_the_cell_is_probed_first():
+    """Hints t_bracket = (a, b) strictly inside the first cell are the first
+    probes after the scan; the answer is unchanged (single crossing)."""
+    S = rotation_system()
+    Tc = rotation_first_crossing()
+    a, b = Tc - 0.01, Tc + 0.01
+    plain = O.min_time(S, np.array([2.0, 0.0]), O.Options(c_tau=1.0, warm="cont"))
+    hinted = O.min_time(S, np.array([2.0, 0.0]), O.Options(c_tau=1.0, warm="cont"), t_bracket=(a, b))
+    assert hinted.status == O.PT_OK and abs(hinted.T - Tc) <= 1e-4 * Tc
+    assert hinted.probes < plain.probes
+
+
+@pytest.mark.slow
+def test_planted_points_of_the_n100_workload_reach_by_T0():
+    """The drift-planted start points of the n=100, m=10, N=300 workload hit
+    the target's boundary at T0 under zero control, so phi_N(x0, T0) <= 0
+    and the first crossing is at most T0.  Every one of them must come back
+    reached with T <= T0 (1 + 1e-4)."""
+    from gen.configs import config5
+    from gen.workloads import planted_drift_points
+    wl = config5(npts=8)
+    spec = wl.systems[0]
+    S = sysobj(spec)
+    x, T0 = planted_drift_points(spec, 6, 0.2, 1.2, 5)
+    for k in range(len(x)):
+        res = O.min_time(S, x[k], O.Options(c_tau=2.0, warm="cont"))
+        assert res.status == O.PT_OK, (k, res.status)
+        assert res.T <= T0[k] * (1 + 1e-4), (k, res.T, T0[k])
+
+
+# ------------------------------------------------------------------ read-out trajectory interior
+
+def test_trajectory_interior_matches_impulse_march():
+    """Every state of the read-out, not only the last, against an
+    independent forward march: the quadrature form applies the control at
+    node k as the impulse w_k B Qu u_k at physical time s_k and the state
+    moves freely in between, so x_j = e^{(s_j - s_{j-1}) A} x_{j-1} + w_j B Qu u_j
+    from x(0) = x0 (one matrix exponential per gap, no prefix sums)."""
+    spec = random_system(4, 2, 16, "box", seed=12, t_max=3.0)
+    S = O.System(spec.A, spec.B, spec.W, spec.c, np.diag([0.7, 1.3]), "box", 16, 3.0)
+    x = np.array([0.5, -0.3, 0.2, 0.4])
+    T = 1.37                        # off the grid: the extra node at tau = T is included
+    pr = O.solve_value(S, x, T, O.Options(gap_tol=1e-9, max_iter=400000, c_tau=0.3))
+    s, u, xs, p = O.readout(S, x, pr)
+    w_by_s = {round(T - t, 12): wk for t, wk in zip(pr.tau, pr.w)}
+    cur, s_prev = x.copy(), 0.0
+    for j in range(len(s)):
+        cur = expm((s[j] - s_prev) * spec.A) @ cur
+        wk = w_by_s[round(s[j], 12)]
+        cur = cur + wk * spec.B @ (u[j] if wk > 0 else np.zeros(2))
+        s_prev = s[j]
+        np.testing.assert_allclose(xs[j], cur, atol=1e-11)
+    np.testing.assert_allclose(xs[-1], O.terminal_state(S, pr.xf, pr.Ks, pr.y), atol=1e-11)
+
+
+def test_trajectory_converges_to_the_held_control_ode():
+    """As N grows the read-out approaches the exact solution of the ODE under
+    the same control held constant on each node's panel (zero-order hold,
+    integrated with the augmented-matrix exponential).  With the left rule
+    at T = t_max the node at physical time s_j closes the panel
+    [s_j - h, s_j], so the held-control state at s_j is compared with the
+    read-out state there; the gap is first order in h."""
+    A = np.array([[0.0, 1.0], [0.0, 0.0]])
+    B = np.array([[0.0], [1.0]])
+    errs = []
+    for N in (50, 200):
+        S = O.System(A, B, 0.01 * np.eye(2), None, None, O.BOX, N, 2.0, O.LEFT)
+        x = np.array([0.6, 0.1])
+        pr = O.solve_value(S, x, 2.0, O.Options(gap_tol=1e-10, max_iter=400000, c_tau=10.0))
+        s, u, xs, p = O.readout(S, x, pr)
+        h = 2.0 / N
+        assert abs(s[0] - h) < 1e-12
+        cur, err = x.copy(), 0.0
+        for j in range(len(s)):
+            Aug = np.zeros((3, 3))
+            Aug[:2, :2] = A
+            Aug[:2, 2] = (B @ u[j]).ravel()
+            E = expm(h * Aug)
+            cur = E[:2, :2] @ cur + E[:2, 2]          # state at s_j
+            err = max(err, float(np.max(np.abs(cur - xs[j]))))
+        errs.append(err)
+    assert errs[1] < 0.5 * errs[0] and errs[1] < 0.05, errs
+
+
+# ------------------------------------------------------------------ golden values against the oracle
+
+def test_oracle_min_time_against_golden_time_to_origin():
+    """The golden textbook times to the origin bound the oracle's minimum time
+    to a disk of radius r around it: T_r <= T_0, and since every point of the
+    disk reaches the origin within r + 2 sqrt(r + r^2/2),
+    T_r >= T_0 - r - 2 sqrt(r + r^2/2); the discrete search adds at most the
+    trapezoid error and its tolerance."""
+    r = 0.02
+    spec = double_integrator(r, 160, t_max=8.0)
+    S = sysobj(spec)
+    with open("tests/golden/double_integrator_origin.txt") as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    h = O.grid_step(S)
+    for p, v, T0 in rows:
+        res = O.min_time(S, np.array([float(p), float(v)]), O.Options(c_tau=30.0, warm="cont"))
+        T0 = float(T0)
+        assert res.status == O.PT_OK
+        slack = 0.02 * h * h + 1e-4 * T0
+        assert T0 - r - 2 * math.sqrt(r + r * r / 2) - slack <= res.T <= T0 + slack, (p, v, res.T, T0)
