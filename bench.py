@@ -62,60 +62,86 @@ def single_thread_workers():
 
 
 def _oracle_query(args):
-    """One oracle min-time query (run in a worker process)."""
+    """One oracle min-time query (run in a worker process); returns its
+    status, T and wall seconds."""
     spec, x, opts = args
     from oracle import hopf_oracle as O
     S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
-    r = O.min_time(S, x, O.Options(c_tau=opts.get("c_tau", 1.0), warm=opts.get("warm", "cont"),
-                                   root=opts.get("root", "bisect")))
-    return r.status, r.T, r.iters
-
-
-def cpu_baseline(w, budget_s, workers, warm, root):
-    """The FP64 oracle, as it stands, on the batch's queries in order, one
-    query per worker process (one thread each), for a wall-clock budget:
-    the rate counts the queries finished within the budget.  Slow queries
-    that do not finish are not counted, so this overstates the CPU rate."""
-    import multiprocessing as mp
-    single_thread_workers()
-    opts = dict(w.opts, warm=warm, root=root)
-    jobs = [(w.systems[0], w.x[i], opts) for i in range(min(len(w.x), 64 * workers))]
-    ctx = mp.get_context("spawn")
-    pool = ctx.Pool(workers)
-    done = 0
     t0 = time.perf_counter()
+    r = O.min_time(S, x, O.Options(**opts))
+    return r.status, r.T, time.perf_counter() - t0
+
+
+def host_info():
+    """CPU model, logical CPUs, and the NumPy / BLAS build of this host."""
+    import platform
+    import numpy as np
+    model = platform.processor() or ""
     try:
-        it = pool.imap_unordered(_oracle_query, jobs, chunksize=1)
-        while True:
-            left = budget_s - (time.perf_counter() - t0)
-            if left <= 0:
-                break
-            try:
-                it.next(timeout=left)
-                done += 1
-            except (mp.TimeoutError, StopIteration):
-                break
-    finally:
-        dt = time.perf_counter() - t0
-        pool.terminate()
-        pool.join()
-    return done / dt, dt, done
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg.get("Build Dependencies", {}).get("blas", {}).get("name")
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "numpy": np.__version__, "blas": blas}
+
+
+def cpu_baseline(spec, xs, opts, workers):
+    """The FP64 oracle, as it stands, on a fixed sample of queries run to
+    completion, one query per worker process (one thread each).  The rate is
+    the sample's queries over the wall time of the pool; the per-query times
+    and statuses are returned as well."""
+    import multiprocessing as mp
+    import numpy as np
+    single_thread_workers()
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_query, [(spec, x, opts) for x in xs], chunksize=1)
+    wall = time.perf_counter() - t0
+    per = np.array([r[2] for r in res])
+    st = np.bincount([r[0] for r in res], minlength=5).tolist()
+    return len(xs) / wall, wall, per, st
+
+
+def stratified_sample(T0, k):
+    """k query indices spread evenly over the planted times T0 (sorted), so
+    that short and long queries are represented in proportion."""
+    import numpy as np
+    order = np.argsort(T0, kind="stable")
+    return order[np.linspace(0, len(order) - 1, k).astype(int)]
+
+
+DECLARED_WARM = "cont"     # the warm-start form timed for `value` (declared, not chosen by the run)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--npts", type=int, default=65536)
-    ap.add_argument("--variants", default="all",
-                    help="comma list of warm[+newton] variants (warm: cold, cont, mlp_first, mlp, mlp_lam; +newton: the "
-                         "hybrid Newton-bisection of Sec. IV instead of bisection); 'all' times cont, "
-                         "cont+newton, mlp_first, mlp, mlp+newton, mlp_lam and cold and "
-                         "reports the best warm start as value")
-    ap.add_argument("--train-npts", type=int, default=80000, help="training queries for the learned warm start")
+    ap.add_argument("--warm", default=DECLARED_WARM,
+                    help="warm start of the timed form (cont: the previous probe's iterate; mlp_first / mlp_lam / "
+                         "mlp: the learned start, trained first on separate queries), optionally +newton for the "
+                         "Sec. IV hybrid search")
+    ap.add_argument("--plain-budget", type=float, default=60.0,
+                    help="seconds of timed steps for the plain form (cold start at every probe); at least one step")
+    ap.add_argument("--literal-budget", type=float, default=40.0,
+                    help="seconds of timed steps for the literal start points x ~ N(0, 4I); at least one step")
+    ap.add_argument("--train-npts", type=int, default=65536, help="training queries for the learned warm start")
     ap.add_argument("--epochs", type=int, default=8)
-    ap.add_argument("--cpu-budget", type=float, default=40.0, help="seconds of oracle wall time")
+    ap.add_argument("--cpu-sample", type=int, default=96, help="oracle queries in the CPU baseline sample")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle worker processes (one thread each)")
+    ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle wall time (value workloads)")
     ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its BF16 / FP32 difference; c4: 64 uneven systems in one call; "
@@ -135,6 +161,8 @@ def main():
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
                     help="iteration precision (default: the workload's, fp32)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-literal", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -142,12 +170,6 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the queries are independent, "
               "so a multi-GPU run is the single-GPU run on a shard of the points.", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-    from gen.configs import config5
-    from paper_1712_08226_amd import Solver
-    from paper_1712_08226_amd.hopfpd import default_opts
 
     if args.workload == "c4":
         return bench_c4(args)
@@ -157,29 +179,52 @@ def main():
         return bench_grid(args)
     if args.workload == "c3":
         return bench_c3(args)
+    return bench_c5(args)
 
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bench_c5(args):
+    """The metric's workload: min-time queries on n=100, m=10, N=300 with
+    the drift-planted start points, inputs resident in device memory.  Times
+    the declared warm-start form (value) for K steps after W warmup steps,
+    then the plain form (cold start at every probe) and the literal start
+    points within wall budgets, then the oracle on a stratified sample."""
+    import numpy as np
+    import torch
+    from gen.configs import config5
+    from gen.workloads import planted_drift_points
+    from paper_1712_08226_amd import Solver
+    from paper_1712_08226_amd.hopfpd import default_opts
+
+    t_start = time.perf_counter()
     w = config5(npts=args.npts)
     if args.prec:
         w.opts["prec"] = args.prec
-    ce_run = args.check_every if args.check_every is not None else w.opts.get("check_every",
-                                                                              default_opts().check_every)
     if args.c_tau is not None:
         w.opts["c_tau"] = args.c_tau
+    ce_run = args.check_every if args.check_every is not None else w.opts.get("check_every",
+                                                                              default_opts().check_every)
     spec = w.systems[0]
+    _, T0 = planted_drift_points(spec, args.npts, 0.2, 3.0, 5)     # the planted times of the batch's points
     dev = torch.device("cuda:0")
     solver = Solver(0)
     solver.set_systems([spec])
     npts = w.x.shape[0]
-    x = torch.tensor(w.x, dtype=torch.float64, device=dev)
-    T = torch.empty(npts, dtype=torch.float64, device=dev)
-    gap = torch.empty(npts, dtype=torch.float64, device=dev)
-    status = torch.empty(npts, dtype=torch.int32, device=dev)
-    probes = torch.empty(npts, dtype=torch.int32, device=dev)
-    iters = torch.empty(npts, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        solver.min_time_dev(x, T, gap, status, probes=probes, iters=iters, stream=stream)
+    def buffers(xh):
+        k = xh.shape[0]
+        return dict(x=torch.tensor(xh, dtype=torch.float64, device=dev),
+                    T=torch.empty(k, dtype=torch.float64, device=dev),
+                    gap=torch.empty(k, dtype=torch.float64, device=dev),
+                    status=torch.empty(k, dtype=torch.int32, device=dev),
+                    probes=torch.empty(k, dtype=torch.int32, device=dev),
+                    iters=torch.empty(k, dtype=torch.int32, device=dev))
+
+    main_buf = buffers(w.x)
 
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
@@ -188,10 +233,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    modes = (["cont", "cont+newton", "mlp_first", "mlp", "mlp+newton", "mlp_lam", "cold"] if args.variants == "all"
-             else args.variants.split(","))
+    warm, _, root = args.warm.partition("+")
+    root = root or "bisect"
     train_info = None
-    if any(m.startswith("mlp") for m in modes):
+    if warm.startswith("mlp"):
         # learned warm start: trained on separate drift-planted queries (not timed)
         wt = config5(npts=args.train_npts, seed=105)
         solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont", check_every=ce_run)
@@ -200,112 +245,122 @@ def main():
         train_info = {"train_queries": args.train_npts, "pairs": tr["pairs"], "epochs": args.epochs,
                       "loss_first_last": [round(float(tr["epoch_loss"][0]), 5), round(float(tr["epoch_loss"][-1]), 5)],
                       "seconds": round(time.perf_counter() - t0, 2)}
-        print(f"warm-start network trained: {train_info}", file=sys.stderr, flush=True)
+        log(f"warm-start network trained: {train_info}")
 
-    def run_mode(mode, nsteps, nwarm):
-        warm, _, root = mode.partition("+")
+    def run_leg(name, wmode, buf, nwarm, max_steps, budget_s=None):
+        """nwarm untimed steps, then timed steps: max_steps of them, or (with
+        a budget) as many as fit in budget_s, at least one."""
         extra = {} if args.tail_max is None else {"tail_max": args.tail_max}
-        extra["check_every"] = ce_run
-        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=warm, root=root or "bisect", **extra)
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=wmode, root=root, check_every=ce_run,
+                        **extra)
+
+        def step():
+            solver.min_time_dev(buf["x"], buf["T"], buf["gap"], buf["status"], probes=buf["probes"],
+                                iters=buf["iters"], stream=stream)
+
         for i in range(nwarm):
             step()
-            print(f"[{mode}] warmup step {i + 1}/{nwarm} done", file=sys.stderr, flush=True)
+            log(f"[{name}] warmup step {i + 1}/{nwarm} done")
         torch.cuda.synchronize()
-        tk, launches, rows, ttail, tpts = 0.0, 0, 0.0, 0.0, 0
+        acc = dict(tk=0.0, launches=0, rows=0.0, ttail=0.0, tpts=0, dev_s=0.0)
+        done = 0
         t0 = time.perf_counter()
-        for i in range(nsteps):
+        while done < max_steps:
             step()
             tm = solver.last_timing()
-            tk += tm["iter_kernel_s"]
-            launches += tm["iter_launches"]
-            rows += tm["point_rows"]
-            ttail += tm["tail_kernel_s"]
-            tpts += tm["tail_points"]
-            print(f"[{mode}] step {i + 1}/{nsteps}: device {tm['total_s']:.3f} s", file=sys.stderr, flush=True)
+            acc["tk"] += tm["iter_kernel_s"]
+            acc["launches"] += tm["iter_launches"]
+            acc["rows"] += tm["point_rows"]
+            acc["ttail"] += tm["tail_kernel_s"]
+            acc["tpts"] += tm["tail_points"]
+            acc["dev_s"] += tm["total_s"]
+            done += 1
+            log(f"[{name}] step {done}: device {tm['total_s']:.3f} s")
+            if budget_s is not None and time.perf_counter() - t0 >= budget_s:
+                break
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        res = {"qps": npts * nsteps / dt, "ms": 1e3 * dt / nsteps, "tk": tk, "launches": launches, "rows": rows,
-               "ttail": ttail, "tpts": tpts,
-               "status": status.cpu().numpy().copy(), "T": T.cpu().numpy().copy(), "gap": gap.cpu().numpy().copy(),
-               "iters": iters.cpu().numpy().copy(), "probes": probes.cpu().numpy().copy()}
-        return res
+        k = buf["x"].shape[0]
+        st = buf["status"].cpu().numpy()
+        return dict(qps=k * done / dt, ms=1e3 * dt / done, steps=done, status=st, T=buf["T"].cpu().numpy(),
+                    gap=buf["gap"].cpu().numpy(), iters=buf["iters"].cpu().numpy(),
+                    probes=buf["probes"].cpu().numpy(), **acc)
 
-    # every variant is timed over the same K steps (the first one after W
-    # warmup steps); value is the best warm start, "cold" is the plain method
-    results = {}
-    for i, mode in enumerate(modes):
-        results[mode] = run_mode(mode, args.steps, args.warmup if i == 0 else 0)
-    warm_modes = [m for m in results if m != "cold"] or list(results)
-    best = max(warm_modes, key=lambda k: results[k]["qps"])
-    R = results[best]
-    dt_ms = R["ms"]
-    qps = R["qps"]
-    tk, launches, rows = R["tk"], R["launches"], R["rows"]
-    ms = dt_ms
-    status_np, T_np, gap_np, it_np, pr_np = R["status"], R["T"], R["gap"], R["iters"], R["probes"]
-    ref = results.get("cont", R)        # T of other variants compared with bisection from continuation
-    variants = {}
-    for k, v in results.items():
-        okk = v["status"] == 0
-        with np.errstate(invalid="ignore"):
-            same = np.abs(v["T"] - ref["T"]) <= 1e-4 * np.abs(ref["T"]) + 1e-12
-        variants[k] = {"queries_per_s": round(v["qps"], 2), "ms_per_step": round(v["ms"], 1),
-                       "mean_iters": round(float(v["iters"].mean()), 1),
-                       "mean_probes": round(float(v["probes"].mean()), 3),
-                       "ok": int(okk.sum()), "unreachable": int((v["status"] == 2).sum()),
-                       "noconv": int((v["status"] == 3).sum()),
-                       "max_iters": int(v["iters"].max()),
-                       "iter_kernel_s": round(v["tk"] / max(1, args.steps), 3),
-                       "iter_launches": int(v["launches"] // max(1, args.steps)),
-                       "tail_kernel_s": round(v["ttail"] / max(1, args.steps), 3),
-                       "tail_points": int(v["tpts"] // max(1, args.steps)),
-                       "T_equal_to_cont_frac": round(float(same[okk].mean()) if okk.any() else 1.0, 5)}
-    st, Tn, gn, itn = status_np, T_np, gap_np, it_np
-    ok = st == 0
-    flops = 4.0 * spec.m * spec.n * rows           # algorithmic: K lam and K^T y per point-row
+    def summary(r):
+        st, it = r["status"], r["iters"]
+        ok = st == 0
+        return {"queries_per_s": round(r["qps"], 2), "ms_per_step": round(r["ms"], 1), "steps_timed": r["steps"],
+                "statuses_ok_inside_unreach_noconv_nonfinite": np.bincount(st, minlength=5).tolist(),
+                "mean_iters": round(float(it.mean()), 1),
+                "iters_p50_p90_p99_max": [float(v) for v in np.percentile(it, [50, 90, 99, 100])],
+                "mean_probes": round(float(r["probes"].mean()), 3),
+                "max_gap_reached": float(r["gap"][ok].max()) if ok.any() else None,
+                "iter_kernel_s_per_step": round(r["tk"] / r["steps"], 3),
+                "iter_launches_per_step": int(r["launches"] // r["steps"]),
+                "tail_kernel_s_per_step": round(r["ttail"] / r["steps"], 3),
+                "tail_points_per_step": int(r["tpts"] // r["steps"])}
+
+    R = run_leg(args.warm, warm, main_buf, args.warmup, args.steps)
+    head = summary(R)
+    ok = R["status"] == 0
+    head["T_le_T0_frac"] = round(float(np.mean(R["T"][ok] <= T0[ok] * (1 + 1e-4))), 6) if ok.any() else None
+
+    plain = None
+    if not args.no_plain and warm != "cold":
+        P = run_leg("plain", "cold", main_buf, 0, args.steps, args.plain_budget)
+        plain = summary(P)
+        okb = (P["status"] == 0) & (R["status"] == 0)
+        plain["same_results_as_value"] = bool(np.array_equal(P["status"], R["status"]) and np.all(
+            np.abs(P["T"][okb] - R["T"][okb]) <= 1e-4 * R["T"][okb]))
+        plain["value_over_plain"] = round(R["qps"] / P["qps"], 3)
+    literal = None
+    if not args.no_literal:
+        wl = config5(npts=args.npts, literal=True)
+        lb = buffers(wl.x)
+        L = run_leg("literal", warm, lb, 0, args.steps, args.literal_budget)
+        literal = summary(L)
+        literal["points"] = wl.meta["points"]
+        del lb
+
+    flops = 4.0 * spec.m * spec.n * R["rows"]           # algorithmic: K lam and K^T y per point-row
+    tk, launches = R["tk"], R["launches"]
     achieved = flops / tk / 1e12 if tk > 0 else 0.0
     per_launch_ms = 1e3 * tk / max(1, launches)
     bf = w.opts["prec"] == "bf16x3"
     peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
-    ct = None if bf else counter_traffic(best, ce_run, w.opts["c_tau"])
-    traffic = None
-    if ct is not None and per_launch_ms > 0:   # measured HBM bytes per launch / measured launch time
-        traffic = round(ct["hbm_bytes_per_launch"] / (per_launch_ms * 1e-3) / 1e9, 2)
+    ct = None if bf else counter_traffic(args.warm, ce_run, w.opts["c_tau"])
+    traffic = None if ct is None else ct["hbm_bytes_per_launch"]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "traffic_unit": "GB/s (HBM, FETCH_SIZE+WRITE_SIZE counters, calibrated)",
-                "traffic_bytes_per_launch": None if ct is None else ct["hbm_bytes_per_launch"],
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE counters, copy-calibrated)",
+                "alg_flops_per_launch": round(flops / max(1, launches), 1),
                 "kernel": ("k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"
                            if bf else "k_pdhg (fused FP32 PDHG iterations)"),
                 "avg_launch_ms": round(per_launch_ms, 4), "launches": launches}
-    out = {"metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+    out = {"metric": METRIC, "value": round(R["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": R["steps"],
+           "warmup": args.warmup, "ms_per_step": round(R["ms"], 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": w.opts["prec"], "data": "synthetic",
-           "config": {"workload": f"min-time, n={spec.n} m={spec.m} N={spec.N} l2 control, ellipsoid target, "
-                                  f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points",
-                      "npts": npts, "n": spec.n, "m": spec.m, "N": spec.N, "warm": best,
+           "config": {"workload": f"min-time T(x), n={spec.n} m={spec.m} N={spec.N}, l2 control, ellipsoid target, "
+                                  f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points "
+                                  f"(value: warm start '{args.warm}'; plain: cold start at every probe)",
+                      "npts": npts, "warm": args.warm, "scan": default_opts().scan,
                       "tail_max": args.tail_max if args.tail_max is not None else default_opts().tail_max,
-                      "check_every": ce_run,
-                      "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
-           "results": {"ok": int(ok.sum()), "inside": int((st == 1).sum()), "unreachable": int((st == 2).sum()),
-                       "noconv": int((st == 3).sum()), "nonfinite": int((st == 4).sum()),
-                       "median_T": float(np.median(Tn[ok])) if ok.any() else None,
-                       "max_gap_ok": float(gn[ok].max()) if ok.any() else None,
-                       "mean_iters": float(itn.mean()),
-                       "iters_p50_p90_p99_max": [float(v) for v in np.percentile(itn, [50, 90, 99, 100])],
-                       "mean_probes": float(pr_np.mean())},
-           "variants": variants, "warm_start_training": train_info,
+                      "check_every": ce_run, "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
+           "results": head, "plain": plain, "literal": literal, "warm_start_training": train_info,
            "roofline": roofline}
     if not args.no_cpu:
-        workers = min(16, os.cpu_count() or 1)
-        bw, _, broot = best.partition("+")
-        cw = bw if bw in ("cold", "cont") else "cont"        # the oracle has no learned warm start
-        cq, cdt, done = cpu_baseline(w, args.cpu_budget, workers, cw, broot or "bisect")
-        out["cpu_baseline"] = {"value": round(cq, 4), "unit": "queries/s", "cores": workers, "kind": "oracle",
-                               "options": {"warm": cw, "root": broot or "bisect"},
-                               "sample": f"batch queries in order on {workers} single-thread processes for "
-                                         f"{cdt:.1f} s wall; {done} finished (unfinished slow queries not "
-                                         f"counted, which overstates the CPU rate)"}
+        workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+        idx = stratified_sample(T0, args.cpu_sample)
+        copts = dict(c_tau=w.opts["c_tau"], warm=warm if warm in ("cold", "cont") else "cont", root=root)
+        log(f"[cpu] oracle on {len(idx)} stratified queries, {workers} workers")
+        rate, wall, per, cst = cpu_baseline(spec, w.x[idx], copts, workers)
+        out["cpu_baseline"] = {"value": round(rate, 4), "unit": "queries/s", "cores": workers, "kind": "oracle",
+                               "sample": f"{len(idx)} of the batch's queries spread evenly over the planted times "
+                                         f"T0, each run to completion on {workers} single-thread processes "
+                                         f"({wall:.1f} s wall; per query mean {per.mean():.2f} s, max "
+                                         f"{per.max():.2f} s)",
+                               "options": copts, "statuses": cst, **host_info()}
+    out["wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

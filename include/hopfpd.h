@@ -73,7 +73,7 @@ typedef enum { HOPF_ROOT_BISECT = 0, HOPF_ROOT_NEWTON = 1 } hopf_root;
 typedef enum {
   HOPF_PT_OK = 0,         /* certified to gap_tol */
   HOPF_PT_INSIDE = 1,     /* x already in the target: T = 0 */
-  HOPF_PT_UNREACH = 2,    /* certified phi(x, t_max) > 0: T = +inf */
+  HOPF_PT_UNREACH = 2,    /* phi(x, t) > 0 certified at every scan horizon, t_max included: T = +inf */
   HOPF_PT_NOCONV = 3,     /* max_iter reached before a certified sign/gap */
   HOPF_PT_NONFINITE = 4   /* NaN/Inf in the input or the iterates */
 } hopf_pt;
@@ -103,29 +103,39 @@ typedef struct {
  *   check_every   iterations between FP64 certificates                               [50]
  *   warm          HOPF_WARM_COLD: every probe starts at lam = 0, y = 0;
  *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate;
- *                 HOPF_WARM_MLP: as CONT, and the system's trained network proposes
- *                 the two probes after t_max (its bracket [T e^-d, T e^d]);
+ *                 HOPF_WARM_MLP: as CONT, and the system's trained network's bracket
+ *                 [T e^-d, T e^d] gives the probe hints (as hopf_min_time's t_bracket)
+ *                 of points whose caller gave none;
  *                 HOPF_WARM_MLP_LAM: as MLP, and every probe starts from the
  *                 network's lam_0 (y from the previous probe);
- *                 HOPF_WARM_MLP_FIRST: as CONT, and the first probe (at t_max, the
- *                 only one that CONT starts cold) starts from the network's lam_0.
+ *                 HOPF_WARM_MLP_FIRST: as CONT, and the first probe (the only one
+ *                 that CONT starts cold) starts from the network's lam_0 unless the
+ *                 caller gave lam0.
  *                 The learned modes fall back to CONT where no trained network
- *                 exists.  When phi(x,.) changes sign
- *                 more than once on [0, t_max] a different probe sequence can end
- *                 at a different certified crossing                              [COLD]
+ *                 exists.  The start changes only the iterations: the probe
+ *                 horizons, hence T, are those of the search below (hints aside) [COLD]
  *   prec          hopf_prec of the iterations; with HOPF_BF16X3 a probe that is not
  *                 certified after 4000 iterations continues in FP32 (its iterates
  *                 carry over unchanged)                                              [FP32]
- *   root          minimum-time search on the certified bracket [lo, hi]:
+ *   scan          minimum time (Sec. IV: the smallest T with phi(x, T) = 0): the
+ *                 horizons t_max (j / scan)^2, j = 1..scan, are probed in ascending
+ *                 order until the first certified reach; the cell between the last
+ *                 certified-unreachable horizon (0 for j = 1) and that reach is then
+ *                 refined.  The spacing, about 2 sqrt(t t_max) / scan at horizon t, is
+ *                 finest near 0, where reachable intervals are short.  A set of
+ *                 reachable horizons that lies strictly between two neighbouring scan
+ *                 horizons is not seen                                             [48]
+ *   root          refinement of the cell [lo, hi] (after any hints):
  *                 HOPF_ROOT_BISECT: midpoint;  HOPF_ROOT_NEWTON: the hybrid of Sec. IV,
- *                 t - phi/(d phi/dt) with d phi/dt = -H_x(p*, x0) (eq. of the Newton
- *                 update with the Hamiltonian), phi the midpoint of the certified
- *                 interval, moved 0.4 of the stopping tolerance towards the side not yet
- *                 bracketed, and the midpoint wherever the step leaves (lo, hi) or the
- *                 slope is not negative                                             [BISECT]
- *   newton_after  hybrid only: probes (counting the one at t_max) placed by bisection
- *                 before Newton steps start                                          [3]
- *   newton_rho    hybrid only: from probe newton_after on, a probe also runs until
+ *                 root estimate r = t - phi/(d phi/dt) with d phi/dt = -H_x(p*, x0) (the
+ *                 Newton update with the Hamiltonian) and phi the midpoint of the
+ *                 certified interval; the probe goes to r plus or minus (0.4 of the
+ *                 stopping tolerance + half the interval's width / |slope|), towards the
+ *                 bracket end farther from r; the midpoint where it would leave (lo, hi),
+ *                 where the slope is not negative, and after a Newton probe that left
+ *                 the bracket wider than half its width before the step            [BISECT]
+ *   newton_after  hybrid only: probes of the cell before Newton steps start         [1]
+ *   newton_rho    hybrid only: cell probes from newton_after on also run until
  *                 P - D <= newton_rho |P + D| / 2 so the Newton step sees an accurate
  *                 value                                                              [0.5]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
@@ -147,6 +157,7 @@ typedef struct {
   int root, newton_after;
   double newton_rho;
   int tail_max, adapt;
+  int scan;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);
@@ -179,21 +190,33 @@ hopf_status hopf_value(hopf_ctx *ctx, long npts, const int *sys_id, const double
                        const double *t, double *phi_lo, double *phi_hi, double *lam,
                        int *iters, int *pt_status);
 
-/* Minimum time to reach the target (Sec. IV) by a certified search on
- * [0, t_max] (bisection or the hybrid Newton step, opts.root):  T (npts; +inf
- * if unreachable at t_max, 0 if inside), gap (npts, normalised gap of the
- * final solve at T), lam (npts rows of stride n_max as for hopf_value, or
- * NULL), probes, iters (npts or NULL), pt_status (npts).  sys_id and x as
- * for hopf_value (systems may be mixed). */
+/* Minimum time to reach the target (Sec. IV: the smallest T with
+ * phi(x, T) = 0) by a certified search on (0, t_max]: the scan of opts.scan
+ * horizons finds the first cell with a certified sign change, which is then
+ * refined (bisection or the hybrid Newton step, opts.root) until
+ * hi - lo <= max(t_rel_tol hi, t_abs_frac t_max); T = hi and the solve at hi
+ * is continued to gap_tol.
+ *   sys_id, x   as for hopf_value (systems may be mixed)
+ *   lam0        NULL, or npts rows of stride n_max: the starting costate of
+ *               each point's first probe (later probes start as opts.warm says)
+ *   t_bracket   NULL, or npts pairs (a, b): probe hints; once the cell is found,
+ *               b and then a are probed first, each only if it lies strictly
+ *               inside the current bracket (non-finite values are skipped).
+ *               Hints move probes, so where phi(x, .) has several zeros inside
+ *               the cell they can change which one the refinement ends on
+ * Outputs: T (npts; +inf where every scan horizon is certified unreachable, 0
+ * inside the target, NaN for NOCONV / NONFINITE), gap (npts, normalised gap
+ * of the final solve at T), lam (npts rows of stride n_max as for hopf_value,
+ * or NULL), probes, iters (npts or NULL), pt_status (npts). */
 hopf_status hopf_min_time(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
-                          double *T, double *gap, double *lam, int *probes, int *iters,
-                          int *pt_status);
+                          const double *lam0, const double *t_bracket, double *T, double *gap,
+                          double *lam, int *probes, int *iters, int *pt_status);
 
 /* Device-pointer twin of hopf_min_time: every array is device memory;
- * sys_id may be NULL; lam, probes, iters may be NULL. */
+ * sys_id, lam0, t_bracket may be NULL; lam, probes, iters may be NULL. */
 hopf_status hopf_min_time_dev(hopf_ctx *ctx, long npts, const int *sys_id, const double *x,
-                              double *T, double *gap, double *lam, int *probes, int *iters,
-                              int *pt_status, void *stream);
+                              const double *lam0, const double *t_bracket, double *T, double *gap,
+                              double *lam, int *probes, int *iters, int *pt_status, void *stream);
 
 /* Device-pointer twin of hopf_value: x, t, phi_lo, phi_hi, pt_status (and
  * sys_id, lam, iters when given) are device memory with the layouts of

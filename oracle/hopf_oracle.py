@@ -95,7 +95,7 @@ class Options:
     condition tau sigma ||K||^2 < 1 of Sec. III holds, and tau = c_tau/||K||.
 
     Minimum-time search (Sec. IV: T* is the smallest horizon with
-    phi(x0, T) = 0): `scan` uniform horizons j t_max / scan, j = 1..scan, are
+    phi(x0, T) = 0): `scan` horizons t_max (j / scan)^2, j = 1..scan, are
     probed in ascending order until the first certified reach; the search then
     refines the cell between the last certified-unreachable scan horizon and
     that reach (bisection, or the Newton hybrid of Sec. IV)."""
@@ -109,7 +109,7 @@ class Options:
     root: str = "bisect"        # "bisect": midpoint; "newton": Sec. IV hybrid Newton-bisection step
     newton_rho: float = 0.5     # hybrid: a probe also runs until gap <= rho |phi| (Newton accuracy)
     newton_after: int = 1       # hybrid: midpoint probes inside the cell before Newton steps start
-    scan: int = 32              # uniform scan horizons on (0, t_max] for the first crossing
+    scan: int = 48              # scan horizons t_max (j/scan)^2 on (0, t_max] for the first crossing
 
 
 # ---------------------------------------------------------------- terminal data
@@ -442,8 +442,14 @@ def value_slope(sys: System, pr: Probe):
 
 
 def scan_horizon(sys: System, opt: Options, j: int):
-    """j-th scan horizon j t_max / scan (the last one is t_max exactly)."""
-    return sys.t_max if j >= opt.scan else j * sys.t_max / opt.scan
+    """j-th scan horizon t_max (j / scan)^2 (the last one is t_max exactly).
+    The spacing grows like sqrt(t): a reachable interval of horizons near
+    t = 0 is short (the control has acted only briefly), so the scan is
+    finest there."""
+    if j >= opt.scan:
+        return sys.t_max
+    s = j / opt.scan
+    return sys.t_max * s * s
 
 
 def search_tol(sys: System, opt: Options, hi: float):
@@ -475,8 +481,8 @@ def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=Non
     falls to zero, searched with certified signs.
 
     1. Inside the target (J(x0) <= 0): T = 0.
-    2. Scan: probe j t_max / scan for j = 1, 2, ... in ascending order until
-       the first certified reach.  Every scan horizon certified unreachable,
+    2. Scan: probe t_max (j / scan)^2 for j = 1, 2, ... in ascending order
+       until the first certified reach.  Every scan horizon certified unreachable,
        t_max included: T = +inf.  A reachable interval of horizons that lies
        strictly between two neighbouring scan horizons is not seen.
     3. Refine the cell [lo, hi] between the last certified-unreachable horizon

@@ -15,13 +15,15 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int WAVES = 4;
 constexpr int PTS_WAVE = 16;
 constexpr int PTS_WG = WAVES * PTS_WAVE;
-constexpr int NEWTON_MAX_PROBES = 48;   // hybrid search: bisection only from this probe on
 constexpr int PTS_TILE = 16;       // points per workgroup in the iteration and certificate kernels
 constexpr int THREADS = WAVES * 64;
 constexpr int LDS_BYTES = 76 * 1024;
 
 enum { MODE_VALUE = 0, MODE_MINTIME = 1 };
-enum { PH_PROBE = 0, PH_FINAL = 1, PH_DONE = 2 };
+// search phase of a point: PH_SCAN probes the uniform scan horizons in
+// ascending order; PH_PROBE refines the first cell with a sign change;
+// PH_FINAL continues the solve at T = hi to the gap tolerance
+enum { PH_PROBE = 0, PH_FINAL = 1, PH_DONE = 2, PH_SCAN = 3 };
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -63,7 +65,13 @@ struct PtState {
   int ystride;               // floats of y per point (nkb * m * 16)
   int mpad;                  // floats of the partial-node dual per point
   double *x0;                // [npts][n_pad]
-  int *status, *phase, *flags, *probes, *iters_tot, *iters_probe, *rows, *M, *partial, *last_reach;
+  int *status, *phase, *flags, *probes, *iters_tot, *iters_probe, *rows, *M, *partial;
+  int *nscan;                // scan probes decided
+  int *ncell;                // probes of the first sign-change cell decided
+  int *newt;                 // bit 0: the running probe was placed by a Newton step; bit 1: next probe is a midpoint
+  double *wbef;              // bracket width when the running probe was placed
+  double *ha, *hb;           // probe hints inside the cell (caller's t_bracket or the network's)
+  double *lam0s;             // [npts][n_pad] caller's starting costate of the first probe, or null
   double *T, *lo, *hi, *r, *tau, *sig, *P, *D;
   double *xf;                // [npts][n_pad]
   double *axf;               // [npts][n_pad]  A x_f (time derivative of x_f, for the Newton slope)
@@ -76,7 +84,7 @@ struct PtState {
   int *perm;                 // [npts]
   int *setup_list;           // [npts] points waiting for a probe setup
   int *counters;             // [0] active, [1] setup-list length, [2] probe-log length
-  int *stage;                // [npts] warm-start bracket stage
+  int *stage;                // [npts] hints still to probe: 0 both (hb then ha), 1 ha only, 2 none
   int *esc;                  // [npts] 1: iterate in FP32 (escalated from BF16 hi+lo)
   float *lamref, *yref;      // tail solver: iterate at the last restart ([npts][n_pad], [npts][ystride])
   // FP64 iterations only (else null): the iterate in FP64 between launches, with
@@ -97,7 +105,17 @@ struct Opts {
   int root, newton_after;
   double newton_rho;
   int adapt;
+  int scan;                  // scan horizons t_max (j / scan)^2, j = 1..scan
 };
+
+// j-th scan horizon t_max (j / scan)^2 (t_max exactly for the last): the
+// spacing grows like sqrt(t), finest near t = 0 where reachable intervals of
+// horizons are short
+__host__ __device__ __forceinline__ double scan_horizon(double t_max, int scan, int j) {
+  if (j >= scan) return t_max;
+  const double s = (double)j / (double)scan;
+  return t_max * s * s;
+}
 
 // point range of one iteration launch: 0 = FP32-escalated points
 // [0, counters[3]), 1 = the others [counters[3], counters[0]), 2 = all
@@ -452,13 +470,23 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 
 // ------------------------------------------------------------------ FP64 certificate + decisions
 
-// Certificate bookkeeping and the search step for point p (Sec. IV): the
+// Certificate bookkeeping and the search step for point p (Sec. IV: the
+// minimum time is the smallest horizon where phi(x, .) falls to zero): the
 // certified interval [-P, -D] from the FP64 sums (sP = 1/2 lam^T W lam -
 // <x_f - c, lam>, wsig = sum_k w_k sigma_C(K_k lam), sJ = (x_T - c)^T W^-1
-// (x_T - c)), the sign or gap decision, the bracket update and the next
-// horizon (midpoint, hybrid Newton step with slope sAx - slast, or the
-// learned bracket).  Returns true when the point needs a probe setup at the
-// new horizon st.T[p].
+// (x_T - c)), the sign or gap decision, then
+//   PH_SCAN   certified unreachable at the scan horizon: next scan horizon
+//             (t_max itself unreachable: T = +inf); certified reach: the
+//             cell [previous scan horizon, this one] holds the first crossing;
+//   PH_PROBE  a certified reach moves hi, unreachable moves lo; next probe:
+//             a pending hint inside (lo, hi), else the hybrid Newton step
+//             (slope sAx - slast) or the midpoint;
+//   PH_FINAL  the solve at T = hi runs to the gap tolerance.
+// Returns true when the point needs a probe setup at the new horizon st.T[p].
+__device__ __forceinline__ double search_tol(const Opts &o, double t_max, double hi) {
+  return fmax(o.t_rel_tol * hi, o.t_abs_frac * t_max);
+}
+
 __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long p, int np, double sP,
                        double wsig, double sJ, double sAx, double slast) {
   // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J)
@@ -480,10 +508,10 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
     return false;
   }
-  // probe: certified sign of phi_N(x, T); with the Newton hybrid, probes
-  // from newton_after on also need a value accurate to newton_rho relative
-  const bool tight = o.root == HOPF_ROOT_NEWTON && st.probes[p] >= o.newton_after;
-  const bool newton_ok = tight && st.probes[p] < NEWTON_MAX_PROBES;   // afterwards: bisection only
+  // certified sign of phi_N(x, T); with the Newton hybrid, cell probes from
+  // the newton_after-th on also need a value accurate to newton_rho relative
+  const bool scan = ph == PH_SCAN;
+  const bool tight = !scan && o.root == HOPF_ROOT_NEWTON && st.ncell[p] + 1 >= o.newton_after;
   int outcome = -1;   // 1 reach, 0 unreach
   if (gap <= o.gap_tol) outcome = (-Pv > 0.0) ? 0 : 1;
   else if (tight && Pv - Dv > o.newton_rho * 0.5 * fabs(Pv + Dv)) outcome = -1;
@@ -495,20 +523,34 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     return false;
   }
   log_probe(st, p, np);
-  const bool first = st.probes[p] == 1;
-  if (outcome == 0 && first) {       // unreachable at t_max
-    st.status[p] = HOPF_PT_UNREACH;
-    st.phase[p] = PH_DONE;
-    st.T[p] = INFINITY;
-    st.hi[p] = INFINITY;
-    return false;
-  }
   double lo = st.lo[p], hi = st.hi[p];
-  if (outcome == 1) hi = T; else lo = T;
+  if (scan) {
+    const int j = ++st.nscan[p];
+    if (outcome == 0) {
+      st.lo[p] = T;
+      if (j >= o.scan) {             // every scan horizon, t_max included, certified unreachable
+        st.status[p] = HOPF_PT_UNREACH;
+        st.phase[p] = PH_DONE;
+        st.T[p] = INFINITY;
+        st.hi[p] = INFINITY;
+        return false;
+      }
+      st.T[p] = scan_horizon(S.t_max, o.scan, j + 1);
+      return true;
+    }
+    hi = T;                          // first certified reach: refine [lo, hi]
+    st.phase[p] = PH_PROBE;
+  } else {
+    if (outcome == 1) hi = T; else lo = T;
+    st.ncell[p] += 1;
+    // a Newton probe that left the bracket wider than half its width before
+    // the step forces a midpoint next (the width halves at least every two probes)
+    const double wb = st.wbef[p];
+    st.newt[p] = ((st.newt[p] & 1) && hi - lo > 0.5 * wb) ? 2 : 0;
+  }
   st.lo[p] = lo;
   st.hi[p] = hi;
-  st.last_reach[p] = outcome;
-  if (hi - lo <= fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max)) {
+  if (hi - lo <= search_tol(o, S.t_max, hi)) {
     st.phase[p] = PH_FINAL;
     if (outcome == 1) {
       if (gap <= o.gap_tol) { st.phase[p] = PH_DONE; log_probe(st, p, np); }   // already certified at T = hi
@@ -518,31 +560,29 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     }
     return false;
   }
-  // next probe: the midpoint; the Newton step of Sec. IV (hybrid); or
-  // (learned warm start) the network's proposed bracket ends right after the
-  // certified probe at t_max
+  // next probe inside the cell: a pending hint (hb, then ha) inside (lo, hi);
+  // else the Newton step of Sec. IV from this probe (when it ran tight and no
+  // midpoint is forced), moved off its root estimate towards the farther end
+  // of the bracket by 0.4 of the stopping tolerance plus the estimate's own
+  // uncertainty; else the midpoint
   double Tn = 0.5 * (lo + hi);
-  if (newton_ok) {
+  bool placed = false, newton = false;
+  while (st.stage[p] < 2) {
+    const double t = st.stage[p] == 0 ? st.hb[p] : st.ha[p];
+    st.stage[p] += 1;
+    if (t > lo && t < hi) { Tn = t; placed = true; break; }
+  }
+  if (!placed && tight && !(st.newt[p] & 2)) {
     const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
     if (slope < 0.0 && isfinite(slope)) {
-      const double phi = -0.5 * (Pv + Dv);
-      const double tl = fmax(o.t_rel_tol * hi, o.t_abs_frac * S.t_max);
-      const double tn = T - phi / slope + (outcome == 1 ? -0.4 * tl : 0.4 * tl);
-      if (tn > lo && tn < hi) Tn = tn;
+      const double r = T - (-0.5 * (Pv + Dv)) / slope;
+      const double shift = 0.4 * search_tol(o, S.t_max, hi) + 0.5 * (Pv - Dv) / fabs(slope);
+      const double tn = (hi - r > r - lo) ? r + shift : r - shift;
+      if (tn > lo && tn < hi) { Tn = tn; newton = true; }
     }
   }
-  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.bT[p] > 0.0f) {
-    const int stg = st.stage[p];
-    if (first && outcome == 1) {
-      const double hi0 = (double)st.bT[p] * exp((double)st.bD[p]);
-      if (hi0 > lo && hi0 < hi) Tn = hi0;
-      st.stage[p] = 1;
-    } else if (stg == 1) {
-      const double lo0 = (double)st.bT[p] * exp(-(double)st.bD[p]);
-      if (lo0 > lo && lo0 < hi) Tn = lo0;
-      st.stage[p] = 0;
-    }
-  }
+  st.newt[p] = newton ? 1 : 0;
+  st.wbef[p] = hi - lo;
   st.T[p] = Tn;
   return true;
 }

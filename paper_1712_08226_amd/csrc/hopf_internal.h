@@ -76,6 +76,11 @@ struct Ctx {
   std::vector<std::vector<Buf>> jbufs;
   // extra streams (default priority) on which the jobs of a multi-system call run
   std::vector<hipStream_t> pool;
+  // events reused by every call (created on first use), pinned words for round checks
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  int *hcount = nullptr;
+  long hcount_cap = 0;
 };
 
 // host setup (hopf_setup.cpp)
@@ -84,9 +89,9 @@ void free_tables(SysTables &t);
 
 // device solver (hopf_solver.hip)
 hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
-                      const double *t_in, double *T_out, double *gap_out, double *philo_out,
-                      double *phihi_out, double *lam_out, int *probes_out, int *iters_out,
-                      int *status_out, double *y_out, hipStream_t user_stream);
+                      const double *t_in, const double *lam0, const double *t_bracket, double *T_out,
+                      double *gap_out, double *philo_out, double *phihi_out, double *lam_out,
+                      int *probes_out, int *iters_out, int *status_out, hipStream_t user_stream);
 hopf_status trajectory_dev(Ctx *ctx, int sys_id, const double *x0_h, double T, int *n_nodes,
                            double *s, double *u, double *xs, double *p_star, double *philo,
                            double *phihi);

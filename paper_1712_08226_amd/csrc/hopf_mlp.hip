@@ -425,8 +425,8 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
       std::vector<int> ids(npts, sys_id);
       hipMemcpy(dsid, ids.data(), npts * 4, hipMemcpyHostToDevice);
     }
-    rc = hopf::solve_dev(c, 1, npts, dsid, dx, nullptr, dT, dgap, nullptr, nullptr, nullptr, nullptr, nullptr, dst,
-                         nullptr, nullptr);
+    rc = hopf::solve_dev(c, 1, npts, dsid, dx, nullptr, nullptr, nullptr, dT, dgap, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, dst, nullptr);
   }
   const long rows = c->log_count;
   if (pairs) *pairs = rows;

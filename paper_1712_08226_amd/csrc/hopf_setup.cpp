@@ -375,10 +375,11 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->warm = HOPF_WARM_COLD;
   o->prec = HOPF_FP32;
   o->root = HOPF_ROOT_BISECT;
-  o->newton_after = 3;
+  o->newton_after = 1;
   o->newton_rho = 0.5;
   o->tail_max = 512;
   o->adapt = 1;
+  o->scan = 48;
   return HOPF_OK;
 }
 
@@ -425,6 +426,8 @@ void hopf_destroy(hopf_ctx *h) {
     hipStreamSynchronize(ps);
     hipStreamDestroy(ps);
   }
+  for (auto &e : c->evpool) hipEventDestroy(e);
+  if (c->hcount) hipHostFree(c->hcount);
   hipStreamDestroy(c->stream);
   delete c;
 }
@@ -439,8 +442,8 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   if (!c || !o) return HOPF_EINVAL;
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
-      o->root < 0 || o->root > 1 || o->newton_after < 1 || !(o->newton_rho > 0.0) ||
-      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1)
+      o->root < 0 || o->root > 1 || o->newton_after < 0 || !(o->newton_rho > 0.0) ||
+      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;

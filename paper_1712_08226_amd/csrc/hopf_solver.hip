@@ -47,8 +47,19 @@ __global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, lo
   x0[i] = k < n ? x[q * xs + k] : 0.0;
 }
 
-__global__ void k_init(SysView S, PtState st, int mode, const double *__restrict__ t_in,
-                       const int *__restrict__ idx) {
+// counters and flop accounting of a job start at zero (a kernel, not a
+// memset, so that the sequence needs no runtime memset nodes)
+__global__ void k_clear(PtState st) {
+  if (threadIdx.x < 4) st.counters[threadIdx.x] = 0;
+  if (threadIdx.x < 2) st.rowsum[threadIdx.x] = 0.0;
+}
+
+// t_in: value-mode horizons; lam0 (rows of stride ls) and tb (pairs a, b):
+// the caller's starting costate of the first probe and probe hints
+// (min-time mode, either may be null)
+__global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__restrict__ t_in,
+                       const int *__restrict__ idx, const double *__restrict__ lam0,
+                       const double *__restrict__ tb, int ls) {
   long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= st.npts) return;
   const double *x = st.x0 + p * S.n_pad;
@@ -61,10 +72,25 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
     Jx += d * d / S.Wd[i];
   }
   Jx = 0.5 * (Jx - 1.0);
+  const long q = idx ? idx[p] : p;
+  st.rows[p] = 0;
+  st.partial[p] = 0;
+  st.esc[p] = 0;
+  st.bT[p] = 0.0f;
+  st.bD[p] = 0.0f;
+  if (st.s64) st.s64[p] = 0;
   st.probes[p] = 0;
   st.iters_tot[p] = 0;
   st.iters_probe[p] = 0;
-  st.last_reach[p] = 0;
+  st.nscan[p] = 0;
+  st.ncell[p] = 0;
+  st.newt[p] = 0;
+  st.wbef[p] = 0.0;
+  st.stage[p] = 2;
+  st.ha[p] = 0.0;
+  st.hb[p] = 0.0;
+  if (st.lam0s)
+    for (int i = 0; i < S.n_pad; ++i) st.lam0s[p * S.n_pad + i] = (lam0 && i < S.n) ? lam0[q * ls + i] : 0.0;
   st.P[p] = 0.0;
   st.D[p] = 0.0;
   st.flags[p] = 0;
@@ -91,13 +117,18 @@ __global__ void k_init(SysView S, PtState st, int mode, const double *__restrict
       return;
     }
     st.status[p] = HOPF_PT_OK;
-    st.phase[p] = PH_PROBE;
-    st.T[p] = S.t_max;
+    st.phase[p] = PH_SCAN;
+    st.T[p] = scan_horizon(S.t_max, o.scan, 1);
     st.lo[p] = 0.0;
-    st.hi[p] = S.t_max;
+    st.hi[p] = INFINITY;
+    if (tb) {
+      st.ha[p] = tb[2 * q];
+      st.hb[p] = tb[2 * q + 1];
+      st.stage[p] = 0;
+    }
     mark_setup(st, p);
   } else {
-    const double tv = t_in[idx ? idx[p] : p];
+    const double tv = t_in[q];
     st.status[p] = HOPF_PT_OK;
     st.phase[p] = PH_FINAL;
     st.T[p] = tv;
@@ -249,11 +280,13 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
   // FP64 iterations keep their own FP64 iterate (carried over when it is current)
   const bool f64 = st.s64 != nullptr;
   const bool had64 = f64 && st.s64[p] != 0;
-  if (cold) {
+  if (cold) {   // lam = 0, or the caller's lam0 at the first probe
+    const bool given = st.lam0s != nullptr && st.probes[p] == 0;
     for (int i = tid; i < np; i += 256) {
-      st.lam[p * np + i] = 0.0f;
-      st.lamb[p * np + i] = 0.0f;
-      if (f64) { st.lam64[p * np + i] = 0.0; st.lamb64[p * np + i] = 0.0; }
+      const double l = given ? st.lam0s[p * np + i] : 0.0;
+      st.lam[p * np + i] = (float)l;
+      st.lamb[p * np + i] = (float)l;
+      if (f64) { st.lam64[p * np + i] = l; st.lamb64[p * np + i] = l; }
     }
   } else {
     for (int i = tid; i < np; i += 256) {
@@ -317,7 +350,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       outv[k] = a;
     }
     __syncthreads();
-    if (o.warm == HOPF_WARM_MLP_LAM || net_first) {
+    if ((o.warm == HOPF_WARM_MLP_LAM || net_first) && !(st.lam0s != nullptr && st.probes[p] == 0)) {
       for (int i = tid; i < np; i += 256) {
         const float l = i < n ? outv[i] * mv.lam_scale : 0.0f;
         st.lam[p * np + i] = l;
@@ -329,6 +362,13 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       const float r2 = outv[n + 1];
       st.bT[p] = expf(outv[n]);
       st.bD[p] = log1pf(expf(-fabsf(r2))) + fmaxf(r2, 0.0f) + 1e-3f;
+      // the network's bracket [T e^-d, T e^d] as probe hints inside the first
+      // sign-change cell, unless the caller gave hints
+      if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.stage[p] == 2) {
+        st.ha[p] = (double)st.bT[p] * exp(-(double)st.bD[p]);
+        st.hb[p] = (double)st.bT[p] * exp((double)st.bD[p]);
+        st.stage[p] = 0;
+      }
     }
     __syncthreads();
   }
@@ -483,9 +523,12 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
   float *yp = st.y + (size_t)p * st.ystride;
   const int mp = st.mpad;
   const int nv4 = np / 4, ng4 = 256 / nv4, nv2 = np / 2, ng2 = 256 / nv2;
-  // every interval runs check_every iterations; the search ends within
-  // NEWTON_MAX_PROBES + 64 probes of at most max_iter iterations each
-  const long guard_max = (long)(NEWTON_MAX_PROBES + 64) * (o.max_iter / o.check_every + 2);
+  // every interval runs check_every iterations (or none: the certificate of a
+  // fresh probe's starting point); the search ends within scan + 64 probes
+  // (scan, then a cell whose width halves at least every two probes) of at
+  // most max_iter iterations each
+  const long guard_max = (long)(o.scan + 64) * (o.max_iter / o.check_every + 3);
+  bool fresh = true;     // the running probe has not iterated yet: certify its starting point first
   // step adaptation: iterate and certified gap at the last restart (thread 0)
   __shared__ int s_restart;
   double gap_r = INFINITY, gap_prev = INFINITY;
@@ -518,8 +561,8 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
       wd = (float)S.Wd[tid];
     }
     bop[tid] = tid < np ? sig * st.lamb[p * np + tid] : 0.f;
-    // ---------------- check_every FP32 iterations
-    for (int it = 0; it < o.check_every; ++it) {
+    // ---------------- check_every FP32 iterations (none for a fresh probe)
+    for (int it = 0; it < (fresh ? 0 : o.check_every); ++it) {
       float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f);
       __syncthreads();                       // bop of this iteration
       for (int kb0 = 0; kb0 < nkb; kb0 += CB) {
@@ -596,11 +639,13 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
     }
     __syncthreads();
     if (tid < np) {
-      st.lam[p * np + tid] = lam_i;
-      st.lamb[p * np + tid] = sig > 0.f ? bop[tid] / sig : 0.f;
+      if (!fresh) {
+        st.lam[p * np + tid] = lam_i;
+        st.lamb[p * np + tid] = sig > 0.f ? bop[tid] / sig : 0.f;
+      }
       l64[tid] = (double)lam_i;
     }
-    if (tid == 0) {
+    if (tid == 0 && !fresh) {
       st.iters_probe[p] += o.check_every;
       st.iters_tot[p] += o.check_every;
       atomicAdd(&st.rowsum[1], (double)(rows + part));
@@ -763,6 +808,7 @@ __device__ void tail_point(const SysView &S, const PtState &st, const Opts &o, c
         }
       }
     }
+    fresh = s_ctl != 0;
     if (s_ctl) {
       setup_point(S, st, o, mv, p, sm);
       need_ref = o.adapt != 0;
@@ -794,10 +840,12 @@ __global__ __launch_bounds__(256) void k_tail_multi(const TailJob *__restrict__ 
 
 // ------------------------------------------------------------------ tile formation
 
-// Active points sorted by class (FP32-escalated first) and by rows
-// (descending) so that a tile's points need similar table prefixes; also
-// counts the algorithmic point-rows.
-__global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows) {
+// Active points (not done and not waiting for a probe setup) sorted by class
+// (FP32-escalated first) and by rows (descending) so that a tile's points
+// need similar table prefixes.  reset_setup: the setup list was consumed by
+// the k_setup launch before this one; count_rows: add the active point-rows
+// to the flop accounting (the iteration launch after this sort runs them).
+__global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int reset_setup, int count_rows) {
   __shared__ int hist[2 * 4097 + 2];
   __shared__ double rsum[1024];
   const int tid = threadIdx.x;
@@ -806,7 +854,7 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
   __syncthreads();
   double loc = 0.0;
   for (long p = tid; p < st.npts; p += 1024) {
-    if (st.phase[p] == PH_DONE) continue;
+    if (st.phase[p] == PH_DONE || st.flags[p]) continue;
     const int rw = st.rows[p];
     const int bin = (st.esc[p] ? 0 : N + 1) + (N - rw);
     atomicAdd(&hist[bin], 1);
@@ -819,7 +867,7 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
     __syncthreads();
   }
   if (tid == 0) {
-    if (count_rows) st.counters[1] = 0;   // the setup list was consumed by k_setup
+    if (reset_setup) st.counters[1] = 0;
     int acc = 0, nesc = 0;
     for (int b = 0; b < nb; ++b) {   // exclusive scan
       const int v = hist[b];
@@ -829,11 +877,11 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int count_rows
     }
     st.counters[0] = acc;
     st.counters[3] = nesc;
-    if (count_rows == 1) st.rowsum[0] += rsum[0];   // 2: list consumed before the tail solver
+    if (count_rows) st.rowsum[0] += rsum[0];
   }
   __syncthreads();
   for (long p = tid; p < st.npts; p += 1024) {
-    if (st.phase[p] == PH_DONE) continue;
+    if (st.phase[p] == PH_DONE || st.flags[p]) continue;
     const int bin = (st.esc[p] ? 0 : N + 1) + (N - st.rows[p]);
     const int pos = atomicAdd(&hist[bin], 1);
     st.perm[pos] = (int)p;
@@ -1023,7 +1071,7 @@ T *grow(std::vector<Ctx::Buf> &bufs, int idx, size_t count) {
 // Point state in the context's reusable buffers (same layout for every call
 // with the same system sizes; row npts of lam/lamb/xfc32/y is a spare row
 // that lanes without a point read and write).
-bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st) {
+bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st, bool with_lam0) {
   if ((int)ctx->jbufs.size() <= job) ctx->jbufs.resize(job + 1);
   auto &bufs = ctx->jbufs[job];
   const int np = tab.n_pad, m = tab.m;
@@ -1042,7 +1090,12 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   st.rows = grow<int>(bufs, bi++, npts);
   st.M = grow<int>(bufs, bi++, npts);
   st.partial = grow<int>(bufs, bi++, npts);
-  st.last_reach = grow<int>(bufs, bi++, npts);
+  st.nscan = grow<int>(bufs, bi++, npts);
+  st.ncell = grow<int>(bufs, bi++, npts);
+  st.newt = grow<int>(bufs, bi++, npts);
+  st.wbef = grow<double>(bufs, bi++, npts);
+  st.ha = grow<double>(bufs, bi++, npts);
+  st.hb = grow<double>(bufs, bi++, npts);
   st.T = grow<double>(bufs, bi++, npts);
   st.lo = grow<double>(bufs, bi++, npts);
   st.hi = grow<double>(bufs, bi++, npts);
@@ -1087,8 +1140,11 @@ bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st)
   st.log_cap = (int)std::min<long>(ctx->log_cap, 2000000000L);
   st.counters = grow<int>(bufs, bi++, 4);
   st.rowsum = grow<double>(bufs, bi++, 2);   // [0] tiled rounds, [1] tail solver
+  st.lam0s = nullptr;
+  if (with_lam0 && !(st.lam0s = grow<double>(bufs, bi, npts * np))) return false;
+  ++bi;
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
-         st.rows && st.M && st.partial && st.last_reach && st.T && st.lo && st.hi && st.r && st.tau &&
+         st.rows && st.M && st.partial && st.nscan && st.ncell && st.newt && st.wbef && st.ha && st.hb && st.T && st.lo && st.hi && st.r && st.tau &&
          st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
          st.yR && st.perm && st.setup_list && st.stage && st.esc && st.lamref && st.yref && st.bT && st.bD && st.counters && st.rowsum;
 }
@@ -1191,17 +1247,33 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   return HOPF_OK;
 }
 
-// Queue one group of rounds (setup, sort, iterations, certificate) and an
-// active-count check whose result lands in hcount[slot] when gev[slot] fires.
+// Timing events come from a pool the context keeps (created on first use,
+// reused by later calls, destroyed with the context).
+hipEvent_t take_event(Ctx *ctx) {
+  if (ctx->ev_used == ctx->evpool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->evpool.push_back(e);
+  }
+  return ctx->evpool[ctx->ev_used++];
+}
+
+// Queue one group of rounds and an active-count check whose result lands in
+// hcount[2 slot .. 2 slot + 1] when gev[slot] fires.  A round: probe setups,
+// tile formation, the FP64 certificate of every active point (the starting
+// point of a fresh probe, else the iterate after the last iterations) with
+// the search step, tile formation without the points that now wait for a
+// setup, then check_every fused iterations.
 hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
   const hopf_opts &ho = ctx->opts;
   const hipStream_t s = J.s;
   for (int r = 0; r < GROUP_ROUNDS && J.rounds < J.max_rounds; ++r) {
     k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
-    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1);
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
+    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
+    J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
+    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0, 1);
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
     HIPCHK(hipEventRecord(a, s));
     if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
     J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
@@ -1209,12 +1281,11 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
     J.kev.push_back(a);
     J.kev.push_back(b);
     ctx->iter_launches++;
-    J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
     ++J.rounds;
   }
+  // active points after the last certificate, and points waiting for a setup
   const int slot = J.ngroups & 1;
-  k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0);   // refresh the active count
-  HIPCHK(hipMemcpyAsync(J.hcount + slot, J.st.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(J.hcount + 2 * slot, J.st.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(J.gev[slot], s));
   ++J.ngroups;
   return HOPF_OK;
@@ -1225,8 +1296,9 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
 hopf_status park_job(Ctx *ctx, Job &J, const Opts &o, long count) {
   const hipStream_t s = J.s;
   k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
-  k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 2);
-  HIPCHK(hipEventCreateWithFlags(&J.park_ev, hipEventDisableTiming));
+  k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
+  J.park_ev = take_event(ctx);
+  if (!J.park_ev) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
   HIPCHK(hipEventRecord(J.park_ev, s));
   J.parked = true;
   J.tail_points = count;
@@ -1243,10 +1315,9 @@ hopf_status park_job(Ctx *ctx, Job &J, const Opts &o, long count) {
 // rounds from this thread, keeping up to two round groups of each job in
 // flight so that the device does not wait for the host's checks.
 hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
-                      const double *t_in, double *T_out, double *gap_out, double *philo_out,
-                      double *phihi_out, double *lam_out, int *probes_out, int *iters_out,
-                      int *status_out, double *y_out, hipStream_t user_stream) {
-  (void)y_out;
+                      const double *t_in, const double *lam0, const double *t_bracket, double *T_out,
+                      double *gap_out, double *philo_out, double *phihi_out, double *lam_out,
+                      int *probes_out, int *iters_out, int *status_out, hipStream_t user_stream) {
   if (ctx->sys.empty()) return set_err(ctx, HOPF_ESTATE, "no systems set");
   if (npts < 0) return set_err(ctx, HOPF_EINVAL, "npts < 0");
   if (!status_out || !x) return set_err(ctx, HOPF_EINVAL, "x and pt_status are required");
@@ -1298,17 +1369,25 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     }
   const hopf_opts &ho = ctx->opts;
   Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000,
-         ho.root, ho.newton_after, ho.newton_rho, ho.adapt};
-  const int max_probes = POW_BITS + 40;
-  hipEvent_t e0, e1, ebase;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventCreate(&ebase));
+         ho.root, ho.newton_after, ho.newton_rho, ho.adapt, ho.scan};
+  // a search takes at most scan + 64 probes (scan horizons, then a cell whose
+  // width halves at least every two probes, two hints and the final solve)
+  const int max_probes = ho.scan + 64;
+  ctx->ev_used = 0;
+  hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx), ebase = take_event(ctx);
+  if (!e0 || !e1 || !ebase) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
   HIPCHK(hipEventRecord(e0, base));
   HIPCHK(hipEventRecord(ebase, base));
   std::vector<Job> jobs(nj);
-  int *hcount = nullptr;
-  HIPCHK(hipHostMalloc((void **)&hcount, 2 * nj * sizeof(int), hipHostMallocDefault));
+  // pinned host words for the round checks: 2 slots x (active, pending setups) per job
+  if (ctx->hcount_cap < 4L * nj) {
+    if (ctx->hcount) hipHostFree(ctx->hcount);
+    ctx->hcount = nullptr;
+    ctx->hcount_cap = 0;
+    HIPCHK(hipHostMalloc((void **)&ctx->hcount, 4L * nj * sizeof(int), hipHostMallocDefault));
+    ctx->hcount_cap = 4L * nj;
+  }
+  int *hcount = ctx->hcount;
   hopf_status rc = HOPF_OK;
   ctx->iter_launches = 0;
   for (int j = 0; j < nj && rc == HOPF_OK; ++j) {
@@ -1320,16 +1399,16 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.idx = nj > 1 ? d_idx + off[J.sid] : nullptr;
     J.s = nj > 1 ? ctx->pool[j % NPOOL] : base;
     J.ngrid = (unsigned)((J.npts + PTS_TILE - 1) / PTS_TILE);
-    J.max_rounds = (long)(ho.max_iter / ho.check_every + 2) * (max_probes + 2);
-    J.hcount = hcount + 2 * j;
+    J.max_rounds = (long)(ho.max_iter / ho.check_every + 3) * (max_probes + 2);
+    J.hcount = hcount + 4 * j;
     J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
     if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
-    if (!make_state(ctx, j, *J.tab, J.npts, J.st)) {
+    if (!make_state(ctx, j, *J.tab, J.npts, J.st, lam0 != nullptr && mode == MODE_MINTIME)) {
       rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
       break;
     }
     for (int k = 0; k < 2 && rc == HOPF_OK; ++k)
-      if (hipEventCreateWithFlags(&J.gev[k], hipEventDisableTiming) != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "event");
+      if (!(J.gev[k] = take_event(ctx))) rc = set_err(ctx, HOPF_EDEVICE, "event");
     if (rc != HOPF_OK) break;
     if (J.s != base && hipStreamWaitEvent(J.s, ebase, 0) != hipSuccess) {
       rc = set_err(ctx, HOPF_EDEVICE, "stream wait");
@@ -1344,23 +1423,11 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     const PtState &st = J.st;
     const long np_ = J.npts;
     const hipStream_t s = J.s;
-    bool ok = hipMemsetAsync(st.rows, 0, np_ * sizeof(int), s) == hipSuccess &&
-              hipMemsetAsync(st.rowsum, 0, 2 * sizeof(double), s) == hipSuccess &&
-              hipMemsetAsync(st.partial, 0, np_ * sizeof(int), s) == hipSuccess &&
-              hipMemsetAsync(st.counters, 0, 4 * sizeof(int), s) == hipSuccess &&
-              (st.s64 == nullptr || hipMemsetAsync(st.s64, 0, np_ * sizeof(int), s) == hipSuccess) &&
-              hipMemsetAsync(st.stage, 0, np_ * sizeof(int), s) == hipSuccess &&
-              hipMemsetAsync(st.esc, 0, np_ * sizeof(int), s) == hipSuccess &&
-              hipMemsetAsync(st.bT, 0, np_ * sizeof(float), s) == hipSuccess &&
-              hipMemsetAsync(st.bD, 0, np_ * sizeof(float), s) == hipSuccess;
-    if (!ok) {
-      rc = set_err(ctx, HOPF_EDEVICE, "hipMemsetAsync failed");
-      break;
-    }
     const long tot = np_ * J.tab->n_pad;
-    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad,
-                                                         nj > 1 ? xs : J.tab->n, J.idx);
-    k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, mode, t_in, J.idx);
+    const int ls = nj > 1 ? xs : J.tab->n;     // row stride of x, lam0 and lam
+    k_clear<<<1, 64, 0, s>>>(st);
+    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx);
+    k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
   }
   // ---- interleaved rounds: each job keeps up to two groups in flight until
   // its points are done or at most tail_max remain (then it is parked); the
@@ -1381,7 +1448,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       if (J.gdone < J.ngroups) {
         const hipError_t q = hipEventQuery(J.gev[J.gdone & 1]);
         if (q == hipSuccess) {
-          const int c = J.hcount[J.gdone & 1];
+          const int c = J.hcount[2 * (J.gdone & 1)] + J.hcount[2 * (J.gdone & 1) + 1];
           ++J.gdone;
           progressed = true;
           if (c == 0 || J.rounds >= J.max_rounds) {
@@ -1433,14 +1500,14 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       if ((int)ctx->jbufs.size() < nj + 1) ctx->jbufs.resize(nj + 1);
       TailJob *d_tj = grow<TailJob>(ctx->jbufs[nj], 1, tj.size());
       if (!d_tj) rc = set_err(ctx, HOPF_ENOMEM, "tail job table");
-      hipEvent_t t0 = nullptr, t1 = nullptr, tdone = nullptr;
+      hipEvent_t t0 = take_event(ctx), t1 = take_event(ctx), tdone = take_event(ctx);
       if (rc == HOPF_OK) {
         const bool ok =
+            t0 && t1 && tdone &&
             hipMemcpyAsync(d_tj, tj.data(), tj.size() * sizeof(TailJob), hipMemcpyHostToDevice, base) == hipSuccess &&
             hipFuncSetAttribute((const void *)k_tail_multi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
                 hipSuccess &&
-            hipEventCreate(&t0) == hipSuccess && hipEventCreate(&t1) == hipSuccess &&
-            hipEventCreateWithFlags(&tdone, hipEventDisableTiming) == hipSuccess && hipEventRecord(t0, base) == hipSuccess;
+            hipEventRecord(t0, base) == hipSuccess;
         if (!ok) rc = set_err(ctx, HOPF_EDEVICE, "tail launch setup failed");
       }
       if (rc == HOPF_OK) {
@@ -1456,9 +1523,6 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
         tail_s = km * 1e-3;
         tail_pts = tb;
       }
-      if (t0) hipEventDestroy(t0);
-      if (t1) hipEventDestroy(t1);
-      if (tdone) hipEventDestroy(tdone);
     }
     for (int j = 0; j < nj; ++j)
       if (jobs[j].parked) jobs[j].done = true;
@@ -1474,11 +1538,10 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
           J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,
           J.idx, nj > 1 ? xs : J.tab->n);
-      hipEvent_t fin;
-      if (J.s != base && hipEventCreateWithFlags(&fin, hipEventDisableTiming) == hipSuccess) {
+      hipEvent_t fin = J.s != base ? take_event(ctx) : nullptr;
+      if (fin) {
         hipEventRecord(fin, J.s);
         hipStreamWaitEvent(base, fin, 0);
-        hipEventDestroy(fin);
       }
     }
     if (J.rounds >= J.max_rounds) hit_limit = true;
@@ -1491,8 +1554,6 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       float km = 0.f;
       if (rc == HOPF_OK) hipEventElapsedTime(&km, J.kev[i], J.kev[i + 1]);
       it_s += km * 1e-3;
-      hipEventDestroy(J.kev[i]);
-      hipEventDestroy(J.kev[i + 1]);
     }
     if (rc == HOPF_OK && J.st.rowsum) {
       double rs[2] = {0.0, 0.0};
@@ -1503,14 +1564,11 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       tail_rows += rs[1] * ho.check_every;
       flops += 4.0 * J.tab->m_user * J.tab->n * (rs[0] + rs[1]) * ho.check_every;
     }
-    if (J.park_ev) hipEventDestroy(J.park_ev);
     if (rc == HOPF_OK && ctx->log_pt && j == 0) {
       int lc = 0;
       hipMemcpy(&lc, J.st.counters + 2, sizeof(int), hipMemcpyDeviceToHost);
       ctx->log_count = std::min<long>(lc, ctx->log_cap);
     }
-    for (int k = 0; k < 2; ++k)
-      if (J.gev[k]) hipEventDestroy(J.gev[k]);
   }
   float ms = 0.f;
   if (rc == HOPF_OK) hipEventElapsedTime(&ms, e0, e1);
@@ -1521,12 +1579,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   ctx->t_tail = tail_s;
   ctx->tail_rows = tail_rows;
   ctx->tail_points = tail_pts;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipEventDestroy(ebase);
   if (nj > 1)
     for (auto ps : ctx->pool) hipStreamSynchronize(ps);   // nothing of this call may outlive it
-  hipHostFree(hcount);
   if (rc == HOPF_OK && hit_limit) ctx->err = "round limit reached; unfinished points report NOCONV";
   return rc;
 }
@@ -1555,11 +1609,11 @@ hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int 
     hipMemcpy(dx, x0_h, n * sizeof(double), hipMemcpyHostToDevice);
     hipMemcpy(dt, &T, sizeof(double), hipMemcpyHostToDevice);
     hipMemcpy(dsid, &sid, sizeof(int), hipMemcpyHostToDevice);
-    rc = solve_dev(ctx, MODE_VALUE, 1, dsid, dx, dt, dT, dgap, dlo, dhi, nullptr, nullptr, nullptr, dst,
-                   nullptr, nullptr);
+    rc = solve_dev(ctx, MODE_VALUE, 1, dsid, dx, dt, nullptr, nullptr, dT, dgap, dlo, dhi, nullptr, nullptr,
+                   nullptr, dst, nullptr);
     if (rc == HOPF_OK) {
       PtState st{};
-      if (!make_state(ctx, 0, tab, 1, st)) rc = set_err(ctx, HOPF_ENOMEM, "point state");
+      if (!make_state(ctx, 0, tab, 1, st, false)) rc = set_err(ctx, HOPF_ENOMEM, "point state");
       else {
         k_traj<<<1, 256, 0, ctx->stream>>>(view(tab), st, T, ds, du, dxs, dp, dnn);
         if (hipStreamSynchronize(ctx->stream) != hipSuccess || hipGetLastError() != hipSuccess)
@@ -1591,14 +1645,14 @@ using hopf::Ctx;
 
 extern "C" {
 
-hopf_status hopf_min_time_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, double *T,
-                              double *gap, double *lam, int *probes, int *iters, int *pt_status,
-                              void *stream) {
+hopf_status hopf_min_time_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *lam0,
+                              const double *t_bracket, double *T, double *gap, double *lam, int *probes,
+                              int *iters, int *pt_status, void *stream) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
   if (!c) return HOPF_EINVAL;
   if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
-  return hopf::solve_dev(c, hopf::MODE_MINTIME, npts, sys_id, x, nullptr, T, gap, nullptr, nullptr, lam,
-                         probes, iters, pt_status, nullptr, (hipStream_t)stream);
+  return hopf::solve_dev(c, hopf::MODE_MINTIME, npts, sys_id, x, nullptr, lam0, t_bracket, T, gap, nullptr,
+                         nullptr, lam, probes, iters, pt_status, (hipStream_t)stream);
 }
 
 hopf_status hopf_value_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *t,
@@ -1628,13 +1682,14 @@ hopf_status hopf_value_dev(hopf_ctx *h, long npts, const int *sys_id, const doub
     if (!(th[i] >= 0.0 && th[i] <= c->sys[sid].desc.t_max))
       return hopf::set_err(c, HOPF_EINVAL, "t must lie in [0, t_max]");
   }
-  return hopf::solve_dev(c, hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr, phi_lo, phi_hi, lam,
-                         nullptr, iters, pt_status, nullptr, s);
+  return hopf::solve_dev(c, hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr, nullptr, nullptr, phi_lo,
+                         phi_hi, lam, nullptr, iters, pt_status, s);
 }
 
 static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, const double *x,
-                             const double *t, double *T, double *gap, double *philo, double *phihi,
-                             double *lam, int *probes, int *iters, int *pt_status) {
+                             const double *t, const double *lam0, const double *tbr, double *T, double *gap,
+                             double *philo, double *phihi, double *lam, int *probes, int *iters,
+                             int *pt_status) {
   if (!c) return HOPF_EINVAL;
   if (c->sys.empty()) return hopf::set_err(c, HOPF_ESTATE, "no systems set");
   if (npts < 0 || !x || !pt_status) return hopf::set_err(c, HOPF_EINVAL, "x and pt_status are required");
@@ -1653,6 +1708,7 @@ static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, con
         return hopf::set_err(c, HOPF_EINVAL, "t must lie in [0, t_max]");
   // device buffers for this call
   double *dx = nullptr, *dt = nullptr, *dT = nullptr, *dgap = nullptr, *dlo = nullptr, *dhi = nullptr, *dlam = nullptr;
+  double *dl0 = nullptr, *dtb = nullptr;
   int *dsid = nullptr, *dpr = nullptr, *dit = nullptr, *dst = nullptr;
   hopf_status rc = HOPF_OK;
   auto al = [&](void **p, size_t b) { if (rc == HOPF_OK && hipMalloc(p, b) != hipSuccess) rc = HOPF_ENOMEM; };
@@ -1665,13 +1721,17 @@ static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, con
   al((void **)&dit, npts * sizeof(int));
   al((void **)&dst, npts * sizeof(int));
   if (lam) al((void **)&dlam, npts * n * sizeof(double));
+  if (lam0) al((void **)&dl0, npts * n * sizeof(double));
+  if (tbr) al((void **)&dtb, npts * 2 * sizeof(double));
   if (t) al((void **)&dt, npts * sizeof(double));
   if (sys_id) al((void **)&dsid, npts * sizeof(int));
   if (rc == HOPF_OK) {
     hipMemcpy(dx, x, npts * n * sizeof(double), hipMemcpyHostToDevice);
     if (t) hipMemcpy(dt, t, npts * sizeof(double), hipMemcpyHostToDevice);
     if (sys_id) hipMemcpy(dsid, sys_id, npts * sizeof(int), hipMemcpyHostToDevice);
-    rc = hopf::solve_dev(c, mode, npts, dsid, dx, dt, dT, dgap, dlo, dhi, dlam, dpr, dit, dst, nullptr, nullptr);
+    if (lam0) hipMemcpy(dl0, lam0, npts * n * sizeof(double), hipMemcpyHostToDevice);
+    if (tbr) hipMemcpy(dtb, tbr, npts * 2 * sizeof(double), hipMemcpyHostToDevice);
+    rc = hopf::solve_dev(c, mode, npts, dsid, dx, dt, dl0, dtb, dT, dgap, dlo, dhi, dlam, dpr, dit, dst, nullptr);
     if (rc == HOPF_OK) {
       if (T) hipMemcpy(T, dT, npts * sizeof(double), hipMemcpyDeviceToHost);
       if (gap) hipMemcpy(gap, dgap, npts * sizeof(double), hipMemcpyDeviceToHost);
@@ -1686,20 +1746,21 @@ static hopf_status host_call(Ctx *c, int mode, long npts, const int *sys_id, con
     hopf::set_err(c, rc, "device allocation failed");
   }
   hipFree(dx); hipFree(dt); hipFree(dT); hipFree(dgap); hipFree(dlo); hipFree(dhi); hipFree(dlam);
-  hipFree(dsid); hipFree(dpr); hipFree(dit); hipFree(dst);
+  hipFree(dsid); hipFree(dpr); hipFree(dit); hipFree(dst); hipFree(dl0); hipFree(dtb);
   return rc;
 }
 
-hopf_status hopf_min_time(hopf_ctx *h, long npts, const int *sys_id, const double *x, double *T,
-                          double *gap, double *lam, int *probes, int *iters, int *pt_status) {
-  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_MINTIME, npts, sys_id, x, nullptr, T, gap,
-                   nullptr, nullptr, lam, probes, iters, pt_status);
+hopf_status hopf_min_time(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *lam0,
+                          const double *t_bracket, double *T, double *gap, double *lam, int *probes, int *iters,
+                          int *pt_status) {
+  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_MINTIME, npts, sys_id, x, nullptr, lam0, t_bracket, T,
+                   gap, nullptr, nullptr, lam, probes, iters, pt_status);
 }
 
 hopf_status hopf_value(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *t,
                        double *phi_lo, double *phi_hi, double *lam, int *iters, int *pt_status) {
-  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr,
-                   phi_lo, phi_hi, lam, nullptr, iters, pt_status);
+  return host_call(reinterpret_cast<Ctx *>(h), hopf::MODE_VALUE, npts, sys_id, x, t, nullptr, nullptr, nullptr,
+                   nullptr, phi_lo, phi_hi, lam, nullptr, iters, pt_status);
 }
 
 hopf_status hopf_trajectory(hopf_ctx *h, int sys_id, const double *x0, double T, int *n_nodes, double *s,

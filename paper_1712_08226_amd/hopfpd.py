@@ -40,7 +40,7 @@ class HopfOpts(C.Structure):
     _fields_ = [("c_tau", C.c_double), ("gap_tol", C.c_double), ("t_rel_tol", C.c_double),
                 ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("warm", C.c_int), ("prec", C.c_int), ("root", C.c_int), ("newton_after", C.c_int),
-                ("newton_rho", C.c_double), ("tail_max", C.c_int), ("adapt", C.c_int)]
+                ("newton_rho", C.c_double), ("tail_max", C.c_int), ("adapt", C.c_int), ("scan", C.c_int)]
 
 
 class HopfTiming(C.Structure):
@@ -84,8 +84,8 @@ def load(path: str = LIB_PATH):
     lib.hopf_set_systems.argtypes = [vp, C.c_int, C.POINTER(HopfSystem)]
     lib.hopf_set_opts.argtypes = [vp, C.POINTER(HopfOpts)]
     lib.hopf_value.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, dp, ip, ip]
-    lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, ip, ip, ip]
-    lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, dp, dp, ip, ip, ip]
+    lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_value_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
     lib.hopf_last_timing.argtypes = [vp, C.POINTER(HopfTiming)]
@@ -225,19 +225,30 @@ class Solver:
         x = _f64(x)
         return self.value(x, np.full(x.shape[0], float(t)))
 
-    def min_time(self, x, sys_id=None):
+    def min_time(self, x, sys_id=None, lam0=None, t_bracket=None):
+        """lam0: optional (npts, n_max) starting costates of the first probes;
+        t_bracket: optional (npts, 2) probe hints (a, b) inside the first cell."""
         x = _f64(x)
         npts, n = x.shape
         sid = None if sys_id is None else np.ascontiguousarray(np.asarray(sys_id, dtype=np.int32))
         if npts and n != self._stride(sid):
             raise ValueError(f"x must have {self._stride(sid)} columns (the largest n of the systems used)")
+        if lam0 is not None:
+            lam0 = _f64(lam0)
+            if lam0.shape != (npts, n):
+                raise ValueError(f"lam0 must have shape {(npts, n)}")
+        if t_bracket is not None:
+            t_bracket = _f64(t_bracket)
+            if t_bracket.shape != (npts, 2):
+                raise ValueError(f"t_bracket must have shape {(npts, 2)}")
         T, gap = np.empty(npts), np.empty(npts)
         lam = np.empty((npts, n))
         probes = np.empty(npts, dtype=np.int32)
         iters = np.empty(npts, dtype=np.int32)
         stat = np.empty(npts, dtype=np.int32)
-        self._check(self.lib.hopf_min_time(self.h, npts, _iptr(sid), _dptr(x), _dptr(T), _dptr(gap), _dptr(lam),
-                                           _iptr(probes), _iptr(iters), _iptr(stat)), "hopf_min_time")
+        self._check(self.lib.hopf_min_time(self.h, npts, _iptr(sid), _dptr(x), _dptr(lam0), _dptr(t_bracket),
+                                           _dptr(T), _dptr(gap), _dptr(lam), _iptr(probes), _iptr(iters),
+                                           _iptr(stat)), "hopf_min_time")
         return dict(T=T, gap=gap, lam=lam, probes=probes, iters=iters, status=stat)
 
     def _dev_ptr(self, t, name, dtype, rows, cols=None):
@@ -262,12 +273,15 @@ class Solver:
         s = C.c_void_p(stream.cuda_stream) if stream is not None else None
         return npts, n, s
 
-    def min_time_dev(self, x, T, gap, status, lam=None, probes=None, iters=None, sys_id=None, stream=None):
-        """Device twin: torch CUDA tensors (float64 x/T/gap/lam, int32 others)."""
+    def min_time_dev(self, x, T, gap, status, lam=None, probes=None, iters=None, sys_id=None, stream=None,
+                     lam0=None, t_bracket=None):
+        """Device twin: torch CUDA tensors (float64 x/T/gap/lam/lam0/t_bracket,
+        int32 others)."""
         npts, n, s = self._dev_common(x, sys_id, stream)
         d = self._dev_ptr
         self._check(self.lib.hopf_min_time_dev(
             self.h, npts, d(sys_id, "sys_id", "torch.int32", npts), d(x, "x", "torch.float64", npts, n),
+            d(lam0, "lam0", "torch.float64", npts, n), d(t_bracket, "t_bracket", "torch.float64", npts, 2),
             d(T, "T", "torch.float64", npts), d(gap, "gap", "torch.float64", npts),
             d(lam, "lam", "torch.float64", npts, n), d(probes, "probes", "torch.int32", npts),
             d(iters, "iters", "torch.int32", npts), d(status, "status", "torch.int32", npts), s),

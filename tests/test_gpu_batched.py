@@ -88,13 +88,8 @@ def test_batched_min_time_vs_oracle(solver):
         S = O.System(s.A, s.B, s.W, s.c, uset=s.uset, N=s.N, t_max=s.t_max, quad=s.quad)
         n = s.A.shape[0]
         for i in np.flatnonzero(sid == k)[:2]:
-            o = O.min_time(S, x[i, :n], O.Options(c_tau=1.0, warm="cont"))
-            if o.status == O.PT_NOCONV:
-                # the fixed-step oracle ran out of iterations; the device result
-                # (adaptive steps) must still be certified if it claims one
-                assert r["status"][i] in (O.PT_OK, O.PT_NOCONV)
-                assert r["status"][i] != O.PT_OK or r["gap"][i] <= 1e-6
-                continue
+            # the oracle keeps fixed steps, so it gets a larger iteration budget
+            o = O.min_time(S, x[i, :n], O.Options(c_tau=1.0, warm="cont", max_iter=2000000))
             assert r["status"][i] == o.status, (k, i, r["status"][i], o.status)
             if o.status == O.PT_OK:
                 assert abs(r["T"][i] - o.T) <= 1e-4 * o.T, (k, i, r["T"][i], o.T)

@@ -12,6 +12,7 @@ import sys
 
 import numpy as np
 import pytest
+from scipy.linalg import expm
 
 from gen import double_integrator, random_system, uniform_box_points, gaussian_points
 from oracle import hopf_oracle as O
@@ -201,6 +202,23 @@ def test_trajectory_readout_vs_oracle(solver, quad, T):
     err = np.linalg.norm(tr["u"][big] - u[big], axis=1)
     assert np.all(err <= tol), (err, tol)
     assert np.all(np.linalg.norm(tr["u"], axis=1) <= 1.0 + 1e-9)
+    # the device's trajectory interior is the impulse march of its own
+    # controls: x_j = e^{(s_j - s_{j-1}) A} x_{j-1} + w_j B u_j (Sec. V eq. (33))
+    w_of = {round(T - t, 10): wk for t, wk in zip(pr.tau, pr.w)}
+    cur, sp = x0.copy(), 0.0
+    for j in range(len(s)):
+        cur = expm((tr["s"][j] - sp) * spec.A) @ cur + w_of[round(tr["s"][j], 10)] * spec.B @ tr["u"][j]
+        sp = tr["s"][j]
+        np.testing.assert_allclose(tr["xs"][j], cur, atol=1e-9 * scale)
+    # and it matches the oracle's interior within what the controls allow:
+    # |dx_j| <= sum_{k <= j} w_k ||e^{(s_j - s_k) A} B|| du_k, with du_k the
+    # bound above where u_k is unique and 2 (the ball's diameter) elsewhere
+    du = np.full(len(s), 2.0)
+    du[big] = np.minimum(2.0, tol)
+    for j in range(len(s)):
+        bound = sum(w_of[round(s[k], 10)] * np.linalg.norm(expm((s[j] - s[k]) * spec.A) @ spec.B, 2) * du[k]
+                    for k in range(j + 1))
+        assert np.linalg.norm(tr["xs"][j] - xs[j]) <= bound + 2e-4 * scale, (j, np.linalg.norm(tr["xs"][j] - xs[j]), bound)
 
 
 # ------------------------------------------------------------------ streaming kernel and BF16 hi+lo

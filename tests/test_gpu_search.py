@@ -1,0 +1,165 @@
+"""The minimum-time search on the device (Sec. IV: T* is the smallest
+horizon with phi(x, T) = 0) against the FP64 oracle, at the shapes of the
+benchmark workloads.
+
+Bar per query: identical status; for a reached point |dT| <= 1e-4 T and the
+final certified gap <= 1e-6; T = +inf where every scan horizon is certified
+unreachable.  Large calls run exactly as the benchmark launches them (16-point
+tiles, then the per-point tail solver for the last points) and are compared
+with the oracle on a sample that includes the most expensive queries."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from gen import gaussian_points
+from gen.configs import config2, config5
+from gen.workloads import planted_drift_points
+from oracle import hopf_oracle as O
+from tests.oracle_pool import oracle_min_times, same_min_time, sysdict
+from tests.test_oracle_pins import rotation_first_crossing
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_1712_08226_amd import Solver
+    s = Solver(0)
+    yield s
+    s.close()
+
+
+def rotation_spec(eps=0.05, r=0.5, N=200, t_max=10.0):
+    return dict(A=np.array([[0.0, 1.0], [-1.0, 0.0]]), B=eps * np.eye(2), W=(r * r) * np.eye(2),
+                c=np.array([0.0, -2.0]), uset="l2", N=N, t_max=t_max, quad="trap")
+
+
+@pytest.mark.parametrize("prec,tail,root", [("fp64", 0, "bisect"), ("fp32", 0, "bisect"), ("fp32", 512, "bisect"),
+                                            ("fp32", 0, "newton"), ("fp32", 512, "newton")])
+def test_first_crossing_closed_form(solver, prec, tail, root):
+    """The rotating system: unreachable at t_max, reached first near pi/2.
+    The device returns the closed-form first crossing, as the oracle does."""
+    say("case: first crossing rotation", prec, tail, root)
+    solver.set_systems([rotation_spec()])
+    solver.set_opts(prec=prec, c_tau=1.0, warm="cont", tail_max=tail, root=root)
+    x = np.tile([2.0, 0.0], (20, 1))
+    x[1::2] *= 1.0 + 1e-3 * np.arange(10)[:, None]        # nearby starts, same structure
+    r = solver.min_time(x)
+    Tc = rotation_first_crossing()
+    assert r["status"][0] == 0 and abs(r["T"][0] - Tc) <= 1e-4 * Tc, (r["T"][0], Tc)
+    assert np.all(r["status"] == 0) and np.all(r["T"] < 2.0)
+    S = O.System(**{k: v for k, v in rotation_spec().items()})
+    for k in (0, 5, 19):
+        o = O.min_time(S, x[k], O.Options(c_tau=1.0, warm="cont", root=root))
+        ok, why = same_min_time(r["T"][k], r["status"][k], r["gap"][k], vars(o))
+        assert ok, (k, why)
+
+
+def _big_call(solver, x, **opts):
+    solver.set_opts(**opts)
+    r = solver.min_time(x)
+    tm = solver.last_timing()
+    say("launches", tm["iter_launches"], "tail points", tm["tail_points"], "total s", round(tm["total_s"], 3),
+        "status", np.bincount(r["status"], minlength=5), "probes", r["probes"].mean(), "iters", r["iters"].mean())
+    return r, tm
+
+
+def _sample(r, k_hard, k_even, seed):
+    """The k_hard most expensive queries (the last to finish: they end in the
+    tail solver) and k_even spread over the rest."""
+    hard = list(np.argsort(-r["iters"], kind="stable")[:k_hard])
+    rest = np.setdiff1d(np.arange(len(r["iters"])), hard)
+    even = list(np.random.default_rng(seed).choice(rest, k_even, replace=False))
+    return sorted(int(i) for i in hard + even)
+
+
+def _check_sample(r, idx, outs):
+    bad = []
+    for i, o in zip(idx, outs):
+        ok, why = same_min_time(r["T"][i], r["status"][i], r["gap"][i], o)
+        if not ok:
+            bad.append((i, why))
+    assert not bad, bad
+
+
+def test_headline_workload_shape_vs_oracle(solver):
+    """n=100, m=10, N=300, l2 ball, ellipsoid target, drift-planted points
+    (the metric's workload at 8192 of its 65,536 points), in the benchmark's
+    launch configuration.  Every planted point must come back reached with
+    T <= T0 (1 + 1e-4) (its free motion reaches the target at T0); 20 sampled
+    queries, the 10 most expensive among them, match the oracle."""
+    say("case: headline shape n100 m10 N300, 8192 points")
+    wl = config5(npts=8192)
+    spec = wl.systems[0]
+    x, T0 = planted_drift_points(spec, 8192, 0.2, 3.0, 5)
+    solver.set_systems([spec])
+    r, tm = _big_call(solver, x, prec="fp32", c_tau=2.0, check_every=75, warm="cont")
+    assert tm["tail_points"] > 0 and tm["iter_launches"] > 10      # tiles, drain and the tail handoff
+    assert np.all(r["status"] == 0), np.bincount(r["status"], minlength=5)
+    assert np.all(r["T"] <= T0 * (1 + 1e-4)), np.max(r["T"] / T0)
+    assert np.all(r["gap"] <= 1e-6)
+    idx = _sample(r, 10, 10, seed=1)
+    outs = oracle_min_times(sysdict(spec), x[idx], dict(c_tau=2.0, warm="cont"))
+    _check_sample(r, idx, outs)
+
+
+def test_headline_literal_points_vs_oracle(solver):
+    """The same system with the literal start points x ~ N(0, 4I): the search
+    probes every scan horizon before it may report T = +inf."""
+    say("case: headline shape, literal points")
+    wl = config5(npts=512, literal=True)
+    spec = wl.systems[0]
+    solver.set_systems([spec])
+    r, _ = _big_call(solver, wl.x, prec="fp32", c_tau=2.0, check_every=75, warm="cont")
+    un = r["status"] == 2
+    assert np.all(r["probes"][un] == 48)
+    idx = _sample(r, 4, 4, seed=2)
+    outs = oracle_min_times(sysdict(spec), wl.x[idx], dict(c_tau=2.0, warm="cont"))
+    _check_sample(r, idx, outs)
+
+
+def test_c2_workload_shape_vs_oracle(solver):
+    """n=50, m=5, N=200, l2 ball, drift-planted points (4096 of the 65,536)."""
+    say("case: n50 m5 N200, 4096 points")
+    wl = config2(npts=4096)
+    spec = wl.systems[0]
+    x, T0 = planted_drift_points(spec, 4096, 0.2, 3.0, 2)
+    solver.set_systems([spec])
+    r, tm = _big_call(solver, x, prec="fp32", c_tau=5.0, warm="cont")
+    assert tm["tail_points"] > 0
+    assert np.all(r["status"] == 0) and np.all(r["T"] <= T0 * (1 + 1e-4))
+    idx = _sample(r, 8, 8, seed=3)
+    outs = oracle_min_times(sysdict(spec), x[idx], dict(c_tau=5.0, warm="cont"))
+    _check_sample(r, idx, outs)
+
+
+@pytest.mark.parametrize("tail", [0, 512])
+def test_caller_lam0_and_hints_vs_oracle(solver, tail):
+    """Caller-supplied starting costates and probe hints through the C-ABI:
+    the oracle given the same lam0 and t_bracket returns the same results.
+    The hints come from the generator: [0.8 T0, T0] around the planted time."""
+    say("case: lam0 and t_bracket", "tail", tail)
+    wl = config2(npts=64)
+    spec = wl.systems[0]
+    x, T0 = planted_drift_points(spec, 64, 0.2, 3.0, 7)
+    rng = np.random.default_rng(11)
+    lam0 = 0.05 * rng.normal(size=x.shape)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=5.0, warm="cont", tail_max=tail)
+    plain = solver.min_time(x)
+    tb = np.stack([0.8 * T0, T0], axis=1)
+    tb[::7] = [np.nan, 1e9]                                             # some hints unusable: skipped
+    r = solver.min_time(x, lam0=lam0, t_bracket=tb)
+    assert np.array_equal(r["status"], plain["status"])
+    ok = r["status"] == 0
+    assert np.all(np.abs(r["T"][ok] - plain["T"][ok]) <= 1e-4 * plain["T"][ok])
+    idx = list(range(0, 64, 8)) + [7, 14]
+    outs = oracle_min_times(sysdict(spec), x[idx], dict(c_tau=5.0, warm="cont"), lam0=lam0[idx], tbr=tb[idx])
+    _check_sample(r, idx, outs)

@@ -59,7 +59,12 @@ def test_mlp_gradient_matches_oracle(solver):
 
 def test_training_and_warm_min_time(solver, tmp_path):
     """Train on solver-generated pairs, then solve held-out points with the
-    warm start: same certified times as the plain method (and the oracle)."""
+    warm start.  Every learned mode must return the plain search's results on
+    every point (same status, |dT| <= 1e-4 T, gap <= 1e-6): the network only
+    moves where the iterations start, or (mode "mlp") adds probe hints inside
+    the first sign-change cell.  Sampled points also match the oracle.  The
+    iteration counts of cold, continuation and the learned starts are
+    reported; the network's lam_0 must beat the cold start."""
     say("case: warm start train + min_time")
     spec = random_system(20, 3, 60, "l2", seed=12, t_max=6.0)
     solver.set_systems([spec])
@@ -74,35 +79,27 @@ def test_training_and_warm_min_time(solver, tmp_path):
     cold = solver.min_time(xte)
     solver.set_opts(prec="fp32", c_tau=2.0, warm="cont")
     base = solver.min_time(xte)
+    assert np.array_equal(cold["status"], base["status"])
+    ok = base["status"] == 0
+    assert np.all(np.abs(cold["T"][ok] - base["T"][ok]) <= 1e-4 * base["T"][ok])
     S = O.System(spec.A, spec.B, spec.W, spec.c, uset="l2", N=60, t_max=6.0)
+    for k in np.flatnonzero(ok)[:3]:
+        o = O.min_time(S, xte[k], O.Options(c_tau=2.0))
+        assert o.status == O.PT_OK and abs(base["T"][k] - o.T) <= 1e-4 * o.T
+    iters = {"cold": cold["iters"].mean(), "cont": base["iters"].mean()}
     for mode in ("mlp", "mlp_lam", "mlp_first"):
         solver.set_opts(prec="fp32", c_tau=2.0, warm=mode)
         warm = solver.min_time(xte)
-        say(mode, "iters cont", base["iters"].mean(), "warm", warm["iters"].mean(),
-            "probes", base["probes"].mean(), warm["probes"].mean())
-        assert np.array_equal(base["status"], warm["status"])
-        if mode == "mlp_lam":
-            # what the trained network gains over the plain method: every probe
-            # starts from the network's lam_0 instead of lam_0 = 0
-            say("iters cold", cold["iters"].mean(), "network lam_0", warm["iters"].mean())
-            assert warm["iters"].mean() < 0.9 * cold["iters"].mean()
-        ok = base["status"] == 0
-        assert np.all(warm["gap"][ok] <= 1e-6)
-        same = np.abs(warm["T"] - base["T"]) <= 1e-4 * base["T"] + 1e-9
-        assert same[ok].mean() > 0.95
-        for k in np.flatnonzero(ok)[:3]:
-            o = O.min_time(S, xte[k], O.Options(c_tau=2.0))
-            if same[k]:
-                assert abs(warm["T"][k] - o.T) <= 1e-4 * o.T
-        # where the two probe sequences ended at different crossings of
-        # phi(x, .) = 0, the warm result must itself be a certified crossing:
-        # reachable at T, not reachable slightly before T (oracle value solves)
-        for k in np.flatnonzero(ok & ~same)[:2]:
-            Tw = warm["T"][k]
-            at = O.solve_value(S, xte[k], Tw, O.Options(c_tau=2.0, gap_tol=1e-8, max_iter=400000))
-            before = O.solve_value(S, xte[k], Tw * (1 - 2e-4), O.Options(c_tau=2.0, gap_tol=1e-8, max_iter=400000))
-            assert at.phi_lo <= 1e-6
-            assert before.phi_hi >= -1e-6
+        iters[mode] = warm["iters"].mean()
+        say(mode, "iters", iters[mode], "probes cont", base["probes"].mean(), "warm", warm["probes"].mean())
+        assert np.array_equal(base["status"], warm["status"]), mode
+        assert np.all(warm["gap"][ok] <= 1e-6), mode
+        assert np.all(np.abs(warm["T"][ok] - base["T"][ok]) <= 1e-4 * base["T"][ok]), mode
+        assert np.all(np.isinf(warm["T"][base["status"] == 2])), mode
+    say("mean iterations per query:", {k: round(float(v), 1) for k, v in iters.items()},
+        "gain of the network's lam_0 over continuation:", round(float(iters["cont"] / iters["mlp_lam"]), 3),
+        "of the network's first-probe start:", round(float(iters["cont"] / iters["mlp_first"]), 3))
+    assert iters["mlp_lam"] < 0.9 * iters["cold"]
     # the trained network survives a save and a load into a fresh context
     from paper_1712_08226_amd import Solver
     path = str(tmp_path / "net.npz")
