@@ -95,10 +95,11 @@ class Options:
     condition tau sigma ||K||^2 < 1 of Sec. III holds, and tau = c_tau/||K||.
 
     Minimum-time search (Sec. IV: T* is the smallest horizon with
-    phi(x0, T) = 0): `scan` horizons t_max (j / scan)^2, j = 1..scan, are
-    probed in ascending order until the first certified reach; the search then
-    refines the cell between the last certified-unreachable scan horizon and
-    that reach (bisection, or the Newton hybrid of Sec. IV)."""
+    phi(x0, T) = 0): the table nodes nearest to t_max (j / scan)^2,
+    j = 1..scan, are probed in ascending order until the first certified
+    reach; the search then refines the cell between the last
+    certified-unreachable scan horizon and that reach (bisection over the
+    table nodes inside it, then bisection or the Newton hybrid of Sec. IV)."""
     c_tau: float = 1.0
     gap_tol: float = 1e-6
     t_rel_tol: float = 0.5e-4
@@ -109,7 +110,7 @@ class Options:
     root: str = "bisect"        # "bisect": midpoint; "newton": Sec. IV hybrid Newton-bisection step
     newton_rho: float = 0.5     # hybrid: a probe also runs until gap <= rho |phi| (Newton accuracy)
     newton_after: int = 1       # hybrid: midpoint probes inside the cell before Newton steps start
-    scan: int = 48              # scan horizons t_max (j/scan)^2 on (0, t_max] for the first crossing
+    scan: int = 48              # scan horizons: table nodes nearest t_max (j/scan)^2, j = 1..scan
 
 
 # ---------------------------------------------------------------- terminal data
@@ -441,15 +442,51 @@ def value_slope(sys: System, pr: Probe):
     return float((sys.A @ pr.xf) @ lam - support(pr.Ks[-1] @ lam, sys.uset))
 
 
-def scan_horizon(sys: System, opt: Options, j: int):
-    """j-th scan horizon t_max (j / scan)^2 (the last one is t_max exactly).
+def last_node(sys: System):
+    """Index K of the table node at t_max (K h = t_max)."""
+    return sys.N - 1 if sys.quad == TRAP else sys.N
+
+
+def node_horizon(sys: System, k: int):
+    """Horizon of table node k (t_max exactly for the last node)."""
+    return sys.t_max if k >= last_node(sys) else k * grid_step(sys)
+
+
+def scan_nodes(sys: System, opt: Options):
+    """The scan horizons as table nodes, ascending: node round(K (j/scan)^2)
+    (at least 1) for j = 1..scan, repeats dropped, the last one K (t_max).
     The spacing grows like sqrt(t): a reachable interval of horizons near
     t = 0 is short (the control has acted only briefly), so the scan is
-    finest there."""
-    if j >= opt.scan:
-        return sys.t_max
-    s = j / opt.scan
-    return sys.t_max * s * s
+    finest there.  At a table node the quadrature needs no extra node."""
+    K = last_node(sys)
+    out = []
+    for j in range(1, opt.scan + 1):
+        if j == opt.scan:
+            k = K
+        else:
+            s = j / opt.scan
+            k = min(K, max(1, int(round(K * s * s))))
+        if not out or k > out[-1]:
+            out.append(k)
+    return out
+
+
+def node_floor(sys: System, t: float):
+    """(k, exact): the table node at t when t is one (within 1e-12 relative,
+    the snapping of split_horizon), else the node just below t."""
+    q = t / grid_step(sys)
+    qr = round(q)
+    if abs(q - qr) <= 1e-12 * max(1.0, q):
+        return int(qr), True
+    return int(math.floor(q)), False
+
+
+def inner_nodes(sys: System, lo: float, hi: float):
+    """First and last table node strictly inside (lo, hi) (empty if ka > kb)."""
+    ka = node_floor(sys, lo)[0] + 1
+    kh, exact = node_floor(sys, hi)
+    kb = min(kh - 1 if exact else kh, last_node(sys))
+    return ka, kb
 
 
 def search_tol(sys: System, opt: Options, hi: float):
@@ -481,8 +518,8 @@ def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=Non
     falls to zero, searched with certified signs.
 
     1. Inside the target (J(x0) <= 0): T = 0.
-    2. Scan: probe t_max (j / scan)^2 for j = 1, 2, ... in ascending order
-       until the first certified reach.  Every scan horizon certified unreachable,
+    2. Scan: probe the scan nodes (scan_nodes) in ascending order until the
+       first certified reach.  Every scan horizon certified unreachable,
        t_max included: T = +inf.  A reachable interval of horizons that lies
        strictly between two neighbouring scan horizons is not seen.
     3. Refine the cell [lo, hi] between the last certified-unreachable horizon
@@ -490,11 +527,14 @@ def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=Non
        reach until hi - lo <= max(t_rel_tol hi, t_abs_tol_frac t_max):
          - a caller's hint t_bracket = (a, b) is probed first: b, then a,
            each only when it lies inside the current bracket;
-         - otherwise the midpoint, or with root = "newton" the hybrid step
-           (newton_proposal) once `newton_after` probes of the cell are done;
-           a Newton probe that leaves the bracket wider than half its width
-           before the step forces the next probe to the midpoint, so the width
-           halves at least every two probes (termination);
+         - then, while table nodes lie strictly inside the bracket, the
+           middle one of them (bisection over the nodes);
+         - then the midpoint, or with root = "newton" the hybrid step
+           (newton_proposal) from a probe that ran to the Newton accuracy
+           (probes between nodes, from the newton_after-th probe of the cell
+           on); a Newton probe that leaves the bracket wider than half its
+           width before the step forces the next probe to the midpoint, so
+           the width halves at least every two probes (termination);
        a certified reach moves hi, a certified unreachable moves lo.
     4. T = hi; the solve at hi is continued to the gap tolerance.
     Probes start at lam = 0 (warm = "cold") or from the previous probe's
@@ -525,8 +565,8 @@ def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=Non
     # ---- scan for the first certified reach
     lo, hi = 0.0, math.inf
     nscan = 0
-    for j in range(1, opt.scan + 1):
-        T = scan_horizon(sys, opt, j)
+    for k in scan_nodes(sys, opt):
+        T = node_horizon(sys, k)
         pr = start(T)
         out = sign_probe(sys, pr, opt)
         iters += pr.iters
@@ -549,19 +589,22 @@ def min_time(sys: System, x0, opt: Options = Options(), lam0=None, t_bracket=Non
     ncell = 0                 # probes inside the cell so far
     guard_w = None            # bracket width before the last Newton probe
     while hi - lo > search_tol(sys, opt, hi):
-        nxt, newton = 0.5 * (lo + hi), False
+        nxt, newton, cont = 0.5 * (lo + hi), False, True
         while hints:
             t = hints.pop(0)
             if lo < t < hi:
                 nxt = t
                 break
         else:
-            if opt.root == "newton" and last.tight and guard_w is None:
+            ka, kb = inner_nodes(sys, lo, hi)
+            if ka <= kb:                      # table nodes inside: bisect over them
+                nxt, cont = node_horizon(sys, (ka + kb) // 2), False
+            elif opt.root == "newton" and last.tight and guard_w is None:
                 t = newton_proposal(sys, opt, last, lo, hi)
                 if t is not None:
                     nxt, newton = t, True
         width = hi - lo
-        pr = start(nxt, tight=opt.root == "newton" and ncell + 1 >= opt.newton_after)
+        pr = start(nxt, tight=opt.root == "newton" and cont and ncell + 1 >= opt.newton_after)
         out = sign_probe(sys, pr, opt, pr.tight)
         iters += pr.iters
         ncell += 1

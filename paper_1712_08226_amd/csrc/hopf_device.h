@@ -55,6 +55,9 @@ template <> struct V4<double> { typedef doublex4 t; };
 struct SysView {
   int n, m, N, n_pad, nkb, quad, uset, m_user;
   double t_max, h, delta, c_tau;   // c_tau: the system's step ratio (0: the call's)
+  int n_hbin;
+  double dr, anorm;
+  const double *hbin, *rdig;       // probe-setup powers (see SysTables)
   const float *K32, *K32T;
   const __bf16 *Kd16h, *Kd16l, *Kp16h, *Kp16l;     // BF16 hi/lo copies (dual and primal layouts)
   const double *K64, *K64T, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
@@ -68,7 +71,8 @@ struct PtState {
   int *status, *phase, *flags, *probes, *iters_tot, *iters_probe, *rows, *M, *partial;
   int *nscan;                // scan probes decided
   int *ncell;                // probes of the first sign-change cell decided
-  int *newt;                 // bit 0: the running probe was placed by a Newton step; bit 1: next probe is a midpoint
+  int *newt;                 // bit 0: the running probe was placed by a Newton step; bit 1: no Newton step next;
+                             // bit 2: the running probe runs to the Newton accuracy
   double *wbef;              // bracket width when the running probe was placed
   double *ha, *hb;           // probe hints inside the cell (caller's t_bracket or the network's)
   double *lam0s;             // [npts][n_pad] caller's starting costate of the first probe, or null
@@ -105,16 +109,30 @@ struct Opts {
   int root, newton_after;
   double newton_rho;
   int adapt;
-  int scan;                  // scan horizons t_max (j / scan)^2, j = 1..scan
+  int scan;                  // scan horizons: table nodes nearest t_max (j / scan)^2, j = 1..scan
 };
 
-// j-th scan horizon t_max (j / scan)^2 (t_max exactly for the last): the
-// spacing grows like sqrt(t), finest near t = 0 where reachable intervals of
-// horizons are short
-__host__ __device__ __forceinline__ double scan_horizon(double t_max, int scan, int j) {
-  if (j >= scan) return t_max;
+// Table nodes as probe horizons.  K = index of the node at t_max; the scan
+// probes the node nearest to t_max (j / scan)^2 (at least node 1) for
+// j = 1..scan, repeats skipped, the last one K: the spacing grows like
+// sqrt(t), finest near t = 0 where reachable intervals of horizons are
+// short, and a node needs no extra quadrature node.
+__host__ __device__ __forceinline__ int last_node(int N, int quad) { return quad == HOPF_Q_TRAP ? N - 1 : N; }
+__host__ __device__ __forceinline__ double node_horizon(double t_max, double h, int K, int k) {
+  return k >= K ? t_max : (double)k * h;
+}
+__host__ __device__ __forceinline__ int scan_node(int K, int scan, int j) {
+  if (j >= scan) return K;
   const double s = (double)j / (double)scan;
-  return t_max * s * s;
+  const int k = (int)rint((double)K * s * s);
+  return k < 1 ? 1 : (k > K ? K : k);
+}
+// the table node at t when t is one (within 1e-12 relative), else the node below
+__host__ __device__ __forceinline__ int node_floor(double t, double h, bool &exact) {
+  const double q = t / h;
+  const double qr = rint(q);
+  exact = fabs(q - qr) <= 1e-12 * fmax(1.0, q);
+  return exact ? (int)qr : (int)floor(q);
 }
 
 // point range of one iteration launch: 0 = FP32-escalated points
@@ -508,10 +526,11 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     else if (o.prec == HOPF_BF16X3 && st.iters_probe[p] >= o.esc_iters) st.esc[p] = 1;   // finish in FP32
     return false;
   }
-  // certified sign of phi_N(x, T); with the Newton hybrid, cell probes from
-  // the newton_after-th on also need a value accurate to newton_rho relative
+  // certified sign of phi_N(x, T); a probe placed for the Newton hybrid
+  // (between table nodes, from the newton_after-th probe of the cell on) also
+  // needs a value accurate to newton_rho relative
   const bool scan = ph == PH_SCAN;
-  const bool tight = !scan && o.root == HOPF_ROOT_NEWTON && st.ncell[p] + 1 >= o.newton_after;
+  const bool tight = !scan && (st.newt[p] & 4);
   int outcome = -1;   // 1 reach, 0 unreach
   if (gap <= o.gap_tol) outcome = (-Pv > 0.0) ? 0 : 1;
   else if (tight && Pv - Dv > o.newton_rho * 0.5 * fabs(Pv + Dv)) outcome = -1;
@@ -524,18 +543,22 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
   }
   log_probe(st, p, np);
   double lo = st.lo[p], hi = st.hi[p];
+  const int K = last_node(S.N, S.quad);
   if (scan) {
-    const int j = ++st.nscan[p];
     if (outcome == 0) {
       st.lo[p] = T;
-      if (j >= o.scan) {             // every scan horizon, t_max included, certified unreachable
+      int j = st.nscan[p];
+      const int kc = scan_node(K, o.scan, j);
+      if (kc >= K) {                 // every scan horizon, t_max included, certified unreachable
         st.status[p] = HOPF_PT_UNREACH;
         st.phase[p] = PH_DONE;
         st.T[p] = INFINITY;
         st.hi[p] = INFINITY;
         return false;
       }
-      st.T[p] = scan_horizon(S.t_max, o.scan, j + 1);
+      while (scan_node(K, o.scan, j) <= kc) ++j;
+      st.nscan[p] = j;
+      st.T[p] = node_horizon(S.t_max, S.h, K, scan_node(K, o.scan, j));
       return true;
     }
     hi = T;                          // first certified reach: refine [lo, hi]
@@ -546,7 +569,7 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     // a Newton probe that left the bracket wider than half its width before
     // the step forces a midpoint next (the width halves at least every two probes)
     const double wb = st.wbef[p];
-    st.newt[p] = ((st.newt[p] & 1) && hi - lo > 0.5 * wb) ? 2 : 0;
+    st.newt[p] = ((st.newt[p] & 1) && hi - lo > 0.5 * wb) ? 2 : 0;   // the tight bit was read above
   }
   st.lo[p] = lo;
   st.hi[p] = hi;
@@ -561,27 +584,38 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
     return false;
   }
   // next probe inside the cell: a pending hint (hb, then ha) inside (lo, hi);
-  // else the Newton step of Sec. IV from this probe (when it ran tight and no
-  // midpoint is forced), moved off its root estimate towards the farther end
-  // of the bracket by 0.4 of the stopping tolerance plus the estimate's own
+  // else the middle table node strictly inside (lo, hi); else the Newton
+  // step of Sec. IV from this probe (when it ran tight and no midpoint is
+  // forced), moved off its root estimate towards the farther end of the
+  // bracket by 0.4 of the stopping tolerance plus the estimate's own
   // uncertainty; else the midpoint
   double Tn = 0.5 * (lo + hi);
-  bool placed = false, newton = false;
+  bool placed = false, newton = false, cont = true;
   while (st.stage[p] < 2) {
     const double t = st.stage[p] == 0 ? st.hb[p] : st.ha[p];
     st.stage[p] += 1;
     if (t > lo && t < hi) { Tn = t; placed = true; break; }
   }
-  if (!placed && tight && !(st.newt[p] & 2)) {
-    const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
-    if (slope < 0.0 && isfinite(slope)) {
-      const double r = T - (-0.5 * (Pv + Dv)) / slope;
-      const double shift = 0.4 * search_tol(o, S.t_max, hi) + 0.5 * (Pv - Dv) / fabs(slope);
-      const double tn = (hi - r > r - lo) ? r + shift : r - shift;
-      if (tn > lo && tn < hi) { Tn = tn; newton = true; }
+  if (!placed) {
+    bool ex_lo, ex_hi;
+    const int ka = node_floor(lo, S.h, ex_lo) + 1;
+    const int kh = node_floor(hi, S.h, ex_hi);
+    const int kb = min(ex_hi ? kh - 1 : kh, K);
+    if (ka <= kb) {                                  // bisection over the table nodes inside
+      Tn = node_horizon(S.t_max, S.h, K, (ka + kb) / 2);
+      cont = false;
+    } else if (tight && !(st.newt[p] & 2)) {
+      const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
+      if (slope < 0.0 && isfinite(slope)) {
+        const double r = T - (-0.5 * (Pv + Dv)) / slope;
+        const double shift = 0.4 * search_tol(o, S.t_max, hi) + 0.5 * (Pv - Dv) / fabs(slope);
+        const double tn = (hi - r > r - lo) ? r + shift : r - shift;
+        if (tn > lo && tn < hi) { Tn = tn; newton = true; }
+      }
     }
   }
-  st.newt[p] = newton ? 1 : 0;
+  const bool tight_next = o.root == HOPF_ROOT_NEWTON && cont && st.ncell[p] + 1 >= o.newton_after;
+  st.newt[p] = (newton ? 1 : 0) | (tight_next ? 4 : 0);
   st.wbef[p] = hi - lo;
   st.T[p] = Tn;
   return true;

@@ -13,6 +13,7 @@ namespace hopf {
 constexpr int NODE_BLOCK = 16;     // table nodes per MFMA row tile
 constexpr int POW_LEVELS = 21;     // binary powers e^{2^b delta A}, delta = t_max / 2^20
 constexpr int POW_BITS = 20;
+constexpr int RDIG_LEVELS = 3;     // base-16 digits of r / dr below one node step
 
 // Host copy of one system plus its device tables.
 struct SysTables {
@@ -25,6 +26,13 @@ struct SysTables {
   std::vector<double> phi;     // [N][m][n] node blocks Phi_k = -Qu^T B^T e^{k h A^T}
   std::vector<double> lpref;   // [N+1] upper bound of ||Phi_{0..j-1}||_2^2
   std::vector<double> epow;    // [POW_LEVELS][n][n] e^{2^b delta A}
+  // probe setup: x_f = e^{T A} x0 and the extra node's block for T = M h + r,
+  // r = q dr + rho, as e^{rho A} e^{q dr A} e^{M h A}
+  int n_hbin = 0;              // binary node powers e^{2^b h A}, b < n_hbin (2^n_hbin > last node)
+  std::vector<double> hbin;    // [n_hbin][n][n]
+  std::vector<double> rdig;    // [RDIG_LEVELS][15][n][n] e^{d 16^b dr A}, d = 1..15
+  double dr = 0.0;             // h / 16^RDIG_LEVELS
+  double anorm = 0.0;          // max(||A||_1, ||A||_inf): Taylor term count of e^{rho A}
   // device tables
   float *K32 = nullptr;        // [nkb][m][16][n_pad]   dual-operand layout
   double *K64 = nullptr;       // [nkb][m][16][n_pad]
@@ -34,6 +42,8 @@ struct SysTables {
   __bf16 *Kp16h = nullptr, *Kp16l = nullptr;   // BF16 hi/lo split, primal layout
   double *lpref_d = nullptr;   // [N+1]
   double *epow_d = nullptr;    // [POW_LEVELS][n][n]
+  double *hbin_d = nullptr;    // [n_hbin][n][n]
+  double *rdig_d = nullptr;    // [RDIG_LEVELS][15][n][n]
   double *A_d = nullptr;       // [n][n]
   double *BQ_d = nullptr;      // [n][m]   -B Qu
   double *Wd_d = nullptr;      // [n_pad]  diag W (1 in the padding)

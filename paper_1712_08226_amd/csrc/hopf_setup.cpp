@@ -148,6 +148,8 @@ bool all_finite(const double *p, size_t k) {
 
 void free_tables(SysTables &t) {
   hipFree(t.K32); hipFree(t.K64); hipFree(t.K32T); hipFree(t.K64T); hipFree(t.lpref_d); hipFree(t.epow_d);
+  hipFree(t.hbin_d); hipFree(t.rdig_d);
+  t.hbin_d = t.rdig_d = nullptr;
   hipFree(t.Kd16h); hipFree(t.Kd16l); hipFree(t.Kp16h); hipFree(t.Kp16l);
   t.K32T = nullptr; t.K64T = nullptr;
   t.Kd16h = t.Kd16l = t.Kp16h = t.Kp16l = nullptr;
@@ -302,6 +304,41 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
       return set_err(ctx, HOPF_EINVAL, "e^{t A} overflows on [0, t_max]");
   }
 
+  // probe-setup powers: e^{2^b h A} by squaring e^{h A}; e^{d 16^b dr A}
+  // (d = 1..15) from e^{dr A} by products, dr = h / 16^RDIG_LEVELS
+  {
+    const int K = (s.quad == HOPF_Q_TRAP) ? N - 1 : N;
+    t.n_hbin = 1;
+    while ((1 << t.n_hbin) <= K) ++t.n_hbin;
+    const size_t nn = (size_t)n * n;
+    t.hbin.assign((size_t)t.n_hbin * nn, 0.0);
+    std::copy(Eh.begin(), Eh.end(), t.hbin.begin());
+    for (int b = 1; b < t.n_hbin; ++b)
+      matmul(&t.hbin[(b - 1) * nn], &t.hbin[(b - 1) * nn], &t.hbin[b * nn], n, n, n);
+    t.dr = std::ldexp(t.h, -4 * RDIG_LEVELS);
+    Mat base;
+    if (!expm(t.A, t.dr, base, n)) return set_err(ctx, HOPF_EINVAL, "matrix exponential failed");
+    t.rdig.assign((size_t)RDIG_LEVELS * 15 * nn, 0.0);
+    Mat unit(base);   // e^{16^b dr A}
+    for (int b = 0; b < RDIG_LEVELS; ++b) {
+      double *lev = &t.rdig[(size_t)b * 15 * nn];
+      std::copy(unit.begin(), unit.end(), lev);
+      for (int d = 2; d <= 15; ++d) matmul(&lev[(d - 2) * nn], unit.data(), &lev[(d - 1) * nn], n, n, n);
+      Mat next(nn);
+      matmul(&lev[14 * nn], unit.data(), next.data(), n, n, n);   // e^{16^{b+1} dr A}
+      unit.swap(next);
+    }
+    double ninf = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < n; ++j) r += std::fabs(t.A[(size_t)i * n + j]);
+      ninf = std::max(ninf, r);
+    }
+    t.anorm = std::max(norm1(t.A, n), ninf);
+    if (!all_finite(t.hbin.data(), t.hbin.size()) || !all_finite(t.rdig.data(), t.rdig.size()))
+      return set_err(ctx, HOPF_EINVAL, "e^{t A} overflows on [0, t_max]");
+  }
+
   // device copies in the kernels' layout: K[kb][j][kk][i] = Phi_{16 kb + kk}[j][i]
   const size_t kel = (size_t)t.nkb * mk * NODE_BLOCK * t.n_pad;
   std::vector<float> K32(kel, 0.0f), K32T(kel, 0.0f);
@@ -344,6 +381,8 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
             up((void **)&t.Kp16l, Kpl.data(), kel * sizeof(__bf16)) &&
             up((void **)&t.lpref_d, t.lpref.data(), t.lpref.size() * sizeof(double)) &&
             up((void **)&t.epow_d, t.epow.data(), t.epow.size() * sizeof(double)) &&
+            up((void **)&t.hbin_d, t.hbin.data(), t.hbin.size() * sizeof(double)) &&
+            up((void **)&t.rdig_d, t.rdig.data(), t.rdig.size() * sizeof(double)) &&
             up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&
             up((void **)&t.BQ_d, mBQ.data(), mBQ.size() * sizeof(double)) &&
             up((void **)&t.Wd_d, Wd.data(), Wd.size() * sizeof(double)) &&

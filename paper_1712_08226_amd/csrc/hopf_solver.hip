@@ -118,7 +118,8 @@ __global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__
     }
     st.status[p] = HOPF_PT_OK;
     st.phase[p] = PH_SCAN;
-    st.T[p] = scan_horizon(S.t_max, o.scan, 1);
+    st.nscan[p] = 1;
+    st.T[p] = node_horizon(S.t_max, S.h, last_node(S.N, S.quad), scan_node(last_node(S.N, S.quad), o.scan, 1));
     st.lo[p] = 0.0;
     st.hi[p] = INFINITY;
     if (tb) {
@@ -192,42 +193,68 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     if (rows > S.N) rows = S.N;
     part = 0;
   }
-  // binary split of T for e^{T A}: T = qq delta + rho
-  const double qd = T / S.delta;
-  long qq = (long)floor(qd);
-  if (qq > (1L << POW_BITS)) qq = 1L << POW_BITS;
-  if (qq < 0) qq = 0;
-  const double rho = T - qq * S.delta;
-
+  // x_f = e^{T A} x0 and (trapezoid, r > 0) the extra node's block
+  // R = -Qu^T B^T e^{T A^T} = K_M e^{r A^T}, for T = M h + r:
+  //   1. x_M = e^{M h A} x0 by the binary node powers (one column);
+  //   2. e^{r A} applied to [x_M | rows of K_M] (columns of one LDS block):
+  //      r = q dr + rho, the base-16 digits of q pick powers e^{d 16^b dr A},
+  //      then a Taylor series for rho < dr with as many terms as
+  //      (rho ||A||)^k / k! needs to fall below 1e-17.
   const int ncols = 1 + (part ? m : 0);
+  const long qd = (r > 0.0) ? (long)floor(r / S.dr) : 0;
+  const long qdig = qd > 4095 ? 4095 : (qd < 0 ? 0 : qd);
+  const double rho = (r > 0.0) ? r - (double)qdig * S.dr : 0.0;
+  int kt = 0;
+  if (rho > 0.0) {
+    const double a = rho * S.anorm;
+    double term = 1.0;
+    while (kt < 30) {
+      ++kt;
+      term *= a / kt;
+      if (term < 1e-17) break;
+    }
+  }
   double Rfro = 0.0;
+  int cur = 0;
+  // 1. x_M into column 0 of sv[cur]
+  for (int i = tid; i < n; i += 256) sv[0][i * SETUP_COLS] = st.x0[p * np + i];
+  __syncthreads();
+  for (int b = 0; b < S.n_hbin; ++b) {
+    if (!((M >> b) & 1)) continue;
+    const double *E = S.hbin + (size_t)b * n * n;
+    const int nxt = cur ^ 1;
+    for (int i = tid; i < n; i += 256) sv[nxt][i * SETUP_COLS] = dot_strided(E + (size_t)i * n, &sv[cur][0], SETUP_COLS, n);
+    __syncthreads();
+    cur = nxt;
+  }
+  const int kb_M = M / NODE_BLOCK, kk_M = M % NODE_BLOCK;
   for (int c0 = 0; c0 < ncols; c0 += SETUP_COLS) {
     const int cc = min(SETUP_COLS, ncols - c0);
-    // load columns: col 0 = x0 (first chunk), others = -B Qu columns
+    // columns: x_M (first block, already in place), then rows j of K_M
     for (int e = tid; e < n * cc; e += 256) {
       const int i = e / cc, cl = e % cc, col = c0 + cl;
-      sv[0][i * SETUP_COLS + cl] = (col == 0) ? st.x0[p * np + i] : S.BQ[i * m + (col - 1)];
+      if (col > 0)
+        sv[cur][i * SETUP_COLS + cl] = S.K64[(((size_t)kb_M * m + (col - 1)) * NODE_BLOCK + kk_M) * np + i];
     }
     __syncthreads();
-    int cur = 0;
-    for (int b = 0; b <= POW_BITS; ++b) {
-      if (!((qq >> b) & 1L)) continue;
-      const double *E = S.epow + (size_t)b * n * n;
+    for (int lv = 0; lv < RDIG_LEVELS; ++lv) {
+      const int d = (int)((qdig >> (4 * lv)) & 15);
+      if (!d) continue;
+      const double *E = S.rdig + ((size_t)lv * 15 + (d - 1)) * n * n;
       const int nxt = cur ^ 1;
       for (int e = tid; e < n * cc; e += 256) {
         const int i = e / cc, cl = e % cc;
-        const double acc = dot_strided(E + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
-        sv[nxt][i * SETUP_COLS + cl] = acc;
+        sv[nxt][i * SETUP_COLS + cl] = dot_strided(E + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
       }
       __syncthreads();
       cur = nxt;
     }
-    if (rho > 0.0) {   // e^{rho A} v by Taylor: rho ||A|| is below 2^-20 t_max ||A||
+    if (kt > 0) {   // e^{rho A} v = v + sum_k (rho A)^k v / k!
       const int tv = 2;   // sv[2] holds the running term
       for (int e = tid; e < n * cc; e += 256) sv[tv][(e / cc) * SETUP_COLS + e % cc] = sv[cur][(e / cc) * SETUP_COLS + e % cc];
       __syncthreads();
       const int other = cur ^ 1;
-      for (int k = 1; k <= 8; ++k) {
+      for (int k = 1; k <= kt; ++k) {
         for (int e = tid; e < n * cc; e += 256) {
           const int i = e / cc, cl = e % cc;
           const double acc = dot_strided(S.A + (size_t)i * n, &sv[tv][cl], SETUP_COLS, n);
@@ -1158,6 +1185,7 @@ SysView view(const SysTables &t) {
   v.Kd16h = t.Kd16h; v.Kd16l = t.Kd16l; v.Kp16h = t.Kp16h; v.Kp16l = t.Kp16l; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
   v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
+  v.n_hbin = t.n_hbin; v.dr = t.dr; v.anorm = t.anorm; v.hbin = t.hbin_d; v.rdig = t.rdig_d;
   return v;
 }
 

@@ -119,7 +119,8 @@ def test_headline_literal_points_vs_oracle(solver):
     solver.set_systems([spec])
     r, _ = _big_call(solver, wl.x, prec="fp32", c_tau=2.0, check_every=75, warm="cont")
     un = r["status"] == 2
-    assert np.all(r["probes"][un] == 48)
+    S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+    assert np.all(r["probes"][un] == len(O.scan_nodes(S, O.Options())))
     idx = _sample(r, 4, 4, seed=2)
     outs = oracle_min_times(sysdict(spec), wl.x[idx], dict(c_tau=2.0, warm="cont"))
     _check_sample(r, idx, outs)

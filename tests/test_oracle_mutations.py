@@ -63,8 +63,8 @@ def _J_with_W(sys, x):
     return 0.5 * (d @ sys.W @ d - 1.0)
 
 
-def _scan_t_max_only(sys, opt, j):
-    return sys.t_max
+def _scan_t_max_only(sys, opt):
+    return [O.last_node(sys)]
 
 
 def _trap_full_end_weight(sys, T):
@@ -94,7 +94,7 @@ MUTATIONS = {
     "transposed matrix exponential in K": (O, "K_blocks", _K_transposed),
     "quadrature weights dropped from P": (O, "primal_obj", _primal_no_weights),
     "W in place of W^-1 in the terminal cost": (O, "J", _J_with_W),
-    "search that looks at t_max only": (O, "scan_horizon", _scan_t_max_only),
+    "search that looks at t_max only": (O, "scan_nodes", _scan_t_max_only),
     "full trapezoid weight at tau = 0": (O, "nodes_and_weights", _trap_full_end_weight),
     "Adam bias correction with power 1": (M, "adam_step", _adam_first_power),
     "free motion e^{-TA} x0 in place of e^{TA} x0": (O, "make_probe", _xf_wrong_sign),

@@ -559,9 +559,27 @@ def test_min_time_unreachable_needs_every_scan_horizon():
     """UNREACH only when every scan horizon is certified unreachable: a
     start far from the target probes all of them."""
     S = rotation_system(eps=0.01)
-    res = O.min_time(S, np.array([6.0, 0.0]), O.Options(c_tau=1.0, warm="cont", scan=16))
+    opt = O.Options(c_tau=1.0, warm="cont", scan=16)
+    res = O.min_time(S, np.array([6.0, 0.0]), opt)
     assert res.status == O.PT_UNREACH and math.isinf(res.T)
+    nodes = O.scan_nodes(S, opt)
+    assert nodes[-1] == S.N - 1 and len(nodes) == 16 and all(np.diff(nodes) > 0)
     assert res.scan_probes == 16 and res.probes == 16
+
+
+def test_scan_nodes_and_node_bisection_bookkeeping():
+    """Scan horizons are table nodes, strictly ascending, ending at t_max;
+    the nodes strictly inside a bracket are found exactly at node horizons
+    and between them."""
+    S = rotation_system(N=300)
+    h = O.grid_step(S)
+    nodes = O.scan_nodes(S, O.Options(scan=48))
+    assert nodes[0] == 1 and nodes[-1] == 299 and all(np.diff(nodes) > 0)
+    assert O.node_horizon(S, 299) == S.t_max
+    assert O.inner_nodes(S, 5 * h, 9 * h) == (6, 8)
+    assert O.inner_nodes(S, 5.5 * h, 9.2 * h) == (6, 9)
+    ka, kb = O.inner_nodes(S, 5 * h, 6 * h)
+    assert ka > kb
 
 
 def test_min_time_hint_inside_the_cell_is_probed_first():
