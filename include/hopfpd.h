@@ -218,6 +218,22 @@ hopf_status hopf_min_time_dev(hopf_ctx *ctx, long npts, const int *sys_id, const
                               const double *lam0, const double *t_bracket, double *T, double *gap,
                               double *lam, int *probes, int *iters, int *pt_status, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): hopf_min_time_dev for the points
+ * of one system `sys`, with the per-point solver state in a fixed device
+ * scratch of 64 MiB that each GPU holds for the life of the process.  The
+ * call makes no device, pinned-host or event allocation and creates no
+ * stream; it checks the active count synchronously between rounds and
+ * records no timing (hopf_last_timing reads zeros).  A call whose state does
+ * not fit (about 43 KB per point for n = 100, m = 10, N = 300: some 1,500
+ * points) returns HOPF_EINVAL with the size it needed.  Calls that overlap
+ * on one GPU share the scratch and race: issue them one after another.
+ * Arguments as for hopf_min_time_dev (lam0, t_bracket, lam, probes, iters
+ * may be NULL; stream NULL: the context's). */
+hopf_status hopf_min_time_dev_noalloc(hopf_ctx *ctx, long npts, int sys, const double *x, const double *lam0,
+                                      const double *t_bracket, double *T, double *gap, double *lam, int *probes,
+                                      int *iters, int *pt_status, void *stream);
+
 /* Device-pointer twin of hopf_value: x, t, phi_lo, phi_hi, pt_status (and
  * sys_id, lam, iters when given) are device memory with the layouts of
  * hopf_value; the solve runs on `stream` (NULL: the context's stream).  The

@@ -91,6 +91,7 @@ struct Ctx {
   size_t ev_used = 0;
   int *hcount = nullptr;
   long hcount_cap = 0;
+  void *scratch = nullptr;         // this device's no-allocation scratch (hipGetSymbolAddress)
 };
 
 // host setup (hopf_setup.cpp)
@@ -107,5 +108,8 @@ hopf_status trajectory_dev(Ctx *ctx, int sys_id, const double *x0_h, double T, i
                            double *phihi);
 
 hopf_status set_err(Ctx *ctx, hopf_status st, const std::string &msg);
+
+// the device scratch of the no-allocation entry point (hopf_solver.hip)
+hopf_status scratch_init(int device, void **out);
 
 }  // namespace hopf

@@ -448,6 +448,12 @@ hopf_status hopf_create(int device, hopf_ctx **out) {
     return HOPF_EDEVICE;
   }
   hopf_default_opts(&c->opts);
+  // the no-allocation entry point's scratch: its address on this device
+  if (hopf::scratch_init(device, &c->scratch) != HOPF_OK) {
+    hipStreamDestroy(c->stream);
+    delete c;
+    return HOPF_EDEVICE;
+  }
   *out = reinterpret_cast<hopf_ctx *>(c);
   return HOPF_OK;
 }

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1095,85 +1096,107 @@ T *grow(std::vector<Ctx::Buf> &bufs, int idx, size_t count) {
   return reinterpret_cast<T *>(b.p);
 }
 
-// Point state in the context's reusable buffers (same layout for every call
-// with the same system sizes; row npts of lam/lamb/xfc32/y is a spare row
-// that lanes without a point read and write).
-bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st, bool with_lam0) {
-  if ((int)ctx->jbufs.size() <= job) ctx->jbufs.resize(job + 1);
-  auto &bufs = ctx->jbufs[job];
+// Per-point state layout (same for every call with the same system sizes;
+// row npts of lam/lamb/xfc32/y is a spare row that lanes without a point
+// read and write).  The allocator hands out typed arrays in a fixed order:
+// GrowAlloc from the context's reusable buffers (grown with hipMalloc when a
+// call needs more), ArenaAlloc from one fixed block without allocating.
+struct GrowAlloc {
+  std::vector<Ctx::Buf> &bufs;
+  int bi = 0;
+  template <typename T> T *get(size_t count) { return grow<T>(bufs, bi++, count); }
+};
+struct ArenaAlloc {
+  unsigned char *base;           // nullptr: only count the bytes (the arrays are never touched)
+  size_t cap, used = 0;
+  template <typename T> T *get(size_t count) {
+    const size_t bytes = (std::max<size_t>(count * sizeof(T), 1) + 255) & ~(size_t)255;
+    if (used + bytes > cap) { used = cap + 1; return nullptr; }
+    static T dummy;
+    T *p = base ? reinterpret_cast<T *>(base + used) : &dummy;
+    used += bytes;
+    return p;
+  }
+};
+
+template <class Alloc>
+bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool with_lam0, bool fp64) {
   const int np = tab.n_pad, m = tab.m;
   st = PtState{};
   st.npts = npts;
   st.ystride = tab.nkb * m * NODE_BLOCK;
   st.mpad = ((m + 3) / 4) * 4;
-  int bi = 0;
-  st.x0 = grow<double>(bufs, bi++, npts * np);
-  st.status = grow<int>(bufs, bi++, npts);
-  st.phase = grow<int>(bufs, bi++, npts);
-  st.flags = grow<int>(bufs, bi++, npts);
-  st.probes = grow<int>(bufs, bi++, npts);
-  st.iters_tot = grow<int>(bufs, bi++, npts);
-  st.iters_probe = grow<int>(bufs, bi++, npts);
-  st.rows = grow<int>(bufs, bi++, npts);
-  st.M = grow<int>(bufs, bi++, npts);
-  st.partial = grow<int>(bufs, bi++, npts);
-  st.nscan = grow<int>(bufs, bi++, npts);
-  st.ncell = grow<int>(bufs, bi++, npts);
-  st.newt = grow<int>(bufs, bi++, npts);
-  st.wbef = grow<double>(bufs, bi++, npts);
-  st.ha = grow<double>(bufs, bi++, npts);
-  st.hb = grow<double>(bufs, bi++, npts);
-  st.T = grow<double>(bufs, bi++, npts);
-  st.lo = grow<double>(bufs, bi++, npts);
-  st.hi = grow<double>(bufs, bi++, npts);
-  st.r = grow<double>(bufs, bi++, npts);
-  st.tau = grow<double>(bufs, bi++, npts);
-  st.sig = grow<double>(bufs, bi++, npts);
-  st.P = grow<double>(bufs, bi++, npts);
-  st.D = grow<double>(bufs, bi++, npts);
-  st.xf = grow<double>(bufs, bi++, npts * np);
-  st.axf = grow<double>(bufs, bi++, npts * np);
-  st.xfc32 = grow<float>(bufs, bi++, (npts + 1) * np);
+  st.x0 = al.template get<double>(npts * np);
+  st.status = al.template get<int>(npts);
+  st.phase = al.template get<int>(npts);
+  st.flags = al.template get<int>(npts);
+  st.probes = al.template get<int>(npts);
+  st.iters_tot = al.template get<int>(npts);
+  st.iters_probe = al.template get<int>(npts);
+  st.rows = al.template get<int>(npts);
+  st.M = al.template get<int>(npts);
+  st.partial = al.template get<int>(npts);
+  st.nscan = al.template get<int>(npts);
+  st.ncell = al.template get<int>(npts);
+  st.newt = al.template get<int>(npts);
+  st.wbef = al.template get<double>(npts);
+  st.ha = al.template get<double>(npts);
+  st.hb = al.template get<double>(npts);
+  st.T = al.template get<double>(npts);
+  st.lo = al.template get<double>(npts);
+  st.hi = al.template get<double>(npts);
+  st.r = al.template get<double>(npts);
+  st.tau = al.template get<double>(npts);
+  st.sig = al.template get<double>(npts);
+  st.P = al.template get<double>(npts);
+  st.D = al.template get<double>(npts);
+  st.xf = al.template get<double>(npts * np);
+  st.axf = al.template get<double>(npts * np);
+  st.xfc32 = al.template get<float>((npts + 1) * np);
   const bool trap = tab.desc.quad == HOPF_Q_TRAP;
-  st.R64 = grow<double>(bufs, bi++, trap ? npts * m * np : 1);
-  st.R32 = grow<float>(bufs, bi++, trap ? npts * m * np : 1);
-  st.lam = grow<float>(bufs, bi++, (npts + 1) * np);
-  st.lamb = grow<float>(bufs, bi++, (npts + 1) * np);
-  st.y = grow<float>(bufs, bi++, (size_t)(npts + 1) * st.ystride);
-  st.yR = grow<float>(bufs, bi++, npts * st.mpad);
-  st.perm = grow<int>(bufs, bi++, npts);
-  st.setup_list = grow<int>(bufs, bi++, npts);
-  st.stage = grow<int>(bufs, bi++, npts);
-  st.esc = grow<int>(bufs, bi++, npts);
-  st.lamref = grow<float>(bufs, bi++, npts * np);
-  if (ctx->opts.prec == HOPF_FP64) {   // the FP64 iterate (spare row included)
-    st.lam64 = grow<double>(bufs, bi++, (npts + 1) * np);
-    st.lamb64 = grow<double>(bufs, bi++, (npts + 1) * np);
-    st.y64 = grow<double>(bufs, bi++, (size_t)(npts + 1) * st.ystride);
-    st.yR64 = grow<double>(bufs, bi++, npts * st.mpad);
-    st.s64 = grow<int>(bufs, bi++, npts);
+  st.R64 = al.template get<double>(trap ? npts * m * np : 1);
+  st.R32 = al.template get<float>(trap ? npts * m * np : 1);
+  st.lam = al.template get<float>((npts + 1) * np);
+  st.lamb = al.template get<float>((npts + 1) * np);
+  st.y = al.template get<float>((size_t)(npts + 1) * st.ystride);
+  st.yR = al.template get<float>(npts * st.mpad);
+  st.perm = al.template get<int>(npts);
+  st.setup_list = al.template get<int>(npts);
+  st.stage = al.template get<int>(npts);
+  st.esc = al.template get<int>(npts);
+  st.lamref = al.template get<float>(npts * np);
+  if (fp64) {   // the FP64 iterate (spare row included)
+    st.lam64 = al.template get<double>((npts + 1) * np);
+    st.lamb64 = al.template get<double>((npts + 1) * np);
+    st.y64 = al.template get<double>((size_t)(npts + 1) * st.ystride);
+    st.yR64 = al.template get<double>(npts * st.mpad);
+    st.s64 = al.template get<int>(npts);
     if (!st.lam64 || !st.lamb64 || !st.y64 || !st.yR64 || !st.s64) return false;
-  } else {
-    bi += 5;
-    st.lam64 = st.lamb64 = st.y64 = st.yR64 = nullptr;
-    st.s64 = nullptr;
   }
-  st.yref = grow<float>(bufs, bi++, (size_t)npts * st.ystride);
-  st.bT = grow<float>(bufs, bi++, npts);
-  st.bD = grow<float>(bufs, bi++, npts);
+  st.yref = al.template get<float>((size_t)npts * st.ystride);
+  st.bT = al.template get<float>(npts);
+  st.bD = al.template get<float>(npts);
+  st.counters = al.template get<int>(4);
+  st.rowsum = al.template get<double>(2);   // [0] tiled rounds, [1] tail solver
+  st.lam0s = nullptr;
+  if (with_lam0 && !(st.lam0s = al.template get<double>(npts * np))) return false;
+  return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
+         st.rows && st.M && st.partial && st.nscan && st.ncell && st.newt && st.wbef && st.ha && st.hb && st.T &&
+         st.lo && st.hi && st.r && st.tau && st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 &&
+         st.R32 && st.lam && st.lamb && st.y && st.yR && st.perm && st.setup_list && st.stage && st.esc &&
+         st.lamref && st.yref && st.bT && st.bD && st.counters && st.rowsum;
+}
+
+// Point state of job `job` in the context's reusable buffers.
+bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st, bool with_lam0) {
+  if ((int)ctx->jbufs.size() <= job) ctx->jbufs.resize(job + 1);
+  GrowAlloc al{ctx->jbufs[job]};
+  if (!layout_state(al, tab, npts, st, with_lam0, ctx->opts.prec == HOPF_FP64)) return false;
   st.log_pt = ctx->log_pt;
   st.log_T = ctx->log_T;
   st.log_lam = ctx->log_lam;
   st.log_cap = (int)std::min<long>(ctx->log_cap, 2000000000L);
-  st.counters = grow<int>(bufs, bi++, 4);
-  st.rowsum = grow<double>(bufs, bi++, 2);   // [0] tiled rounds, [1] tail solver
-  st.lam0s = nullptr;
-  if (with_lam0 && !(st.lam0s = grow<double>(bufs, bi, npts * np))) return false;
-  ++bi;
-  return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
-         st.rows && st.M && st.partial && st.nscan && st.ncell && st.newt && st.wbef && st.ha && st.hb && st.T && st.lo && st.hi && st.r && st.tau &&
-         st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 && st.R32 && st.lam && st.lamb && st.y &&
-         st.yR && st.perm && st.setup_list && st.stage && st.esc && st.lamref && st.yref && st.bT && st.bD && st.counters && st.rowsum;
+  return true;
 }
 
 SysView view(const SysTables &t) {
@@ -1223,6 +1246,7 @@ struct Job {
   bool parked = false;           // waiting for the combined tail launch
   hipEvent_t park_ev = nullptr;
   long tail_points = 0;
+  bool timed = true;             // timing events and the asynchronous round checks (off: no runtime objects made)
 };
 
 constexpr int GROUP_ROUNDS = 4;   // rounds between active-count checks
@@ -1300,17 +1324,24 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
     J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0, 1);
-    hipEvent_t a = take_event(ctx), b = take_event(ctx);
-    if (!a || !b) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
-    HIPCHK(hipEventRecord(a, s));
+    hipEvent_t a = nullptr, b = nullptr;
+    if (J.timed) {
+      a = take_event(ctx);
+      b = take_event(ctx);
+      if (!a || !b) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
+      HIPCHK(hipEventRecord(a, s));
+    }
     if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
     J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
-    HIPCHK(hipEventRecord(b, s));
-    J.kev.push_back(a);
-    J.kev.push_back(b);
+    if (J.timed) {
+      HIPCHK(hipEventRecord(b, s));
+      J.kev.push_back(a);
+      J.kev.push_back(b);
+    }
     ctx->iter_launches++;
     ++J.rounds;
   }
+  if (!J.timed) return HOPF_OK;   // the caller reads the counters itself
   // active points after the last certificate, and points waiting for a setup
   const int slot = J.ngroups & 1;
   HIPCHK(hipMemcpyAsync(J.hcount + 2 * slot, J.st.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1325,9 +1356,11 @@ hopf_status park_job(Ctx *ctx, Job &J, const Opts &o, long count) {
   const hipStream_t s = J.s;
   k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
   k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
-  J.park_ev = take_event(ctx);
-  if (!J.park_ev) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
-  HIPCHK(hipEventRecord(J.park_ev, s));
+  if (J.timed) {
+    J.park_ev = take_event(ctx);
+    if (!J.park_ev) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(J.park_ev, s));
+  }
   J.parked = true;
   J.tail_points = count;
   return HOPF_OK;
@@ -1613,6 +1646,114 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   return rc;
 }
 
+// ------------------------------------------------------------------ minimum time without allocations
+
+// Device scratch for callers that cannot allocate (graph capture, serving
+// loops): the per-point state of hopf_min_time_dev_noalloc lives here.  Each
+// GPU the library runs on holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress gives
+// on that device (scratch_init), never through the array's name.
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+hopf_status scratch_init(int device, void **out) {
+  static std::mutex mu;
+  static std::vector<void *> addr;      // per device
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HOPF_EDEVICE;
+    addr[device] = ptr;
+  }
+  *out = addr[device];
+  return HOPF_OK;
+}
+
+size_t scratch_bytes() { return SCRATCH_BYTES; }
+
+// One system's minimum-time call with every array of the point state carved
+// from the device scratch: no device, pinned-host or event allocation, no
+// extra streams; round checks read the active count synchronously.  The
+// kernels and the search are those of solve_dev.
+hopf_status solve_noalloc(Ctx *ctx, int sid, long npts, const double *x, const double *lam0, const double *tb,
+                          double *T_out, double *gap_out, double *lam_out, int *probes_out, int *iters_out,
+                          int *status_out, hipStream_t s) {
+  if (ctx->sys.empty()) return set_err(ctx, HOPF_ESTATE, "no systems set");
+  if (sid < 0 || sid >= (int)ctx->sys.size()) return set_err(ctx, HOPF_EINVAL, "sys out of range");
+  if (npts < 0 || !x || !status_out) return set_err(ctx, HOPF_EINVAL, "x and pt_status are required");
+  if (npts == 0) return HOPF_OK;
+  if (!ctx->scratch) return set_err(ctx, HOPF_ESTATE, "device scratch not initialised");
+  const hopf_opts &ho = ctx->opts;
+  Job J;
+  J.sid = sid;
+  J.tab = &ctx->sys[sid];
+  J.S = view(*J.tab);
+  J.npts = npts;
+  J.s = s;
+  J.timed = false;
+  J.ngrid = (unsigned)((npts + PTS_TILE - 1) / PTS_TILE);
+  J.max_rounds = (long)(ho.max_iter / ho.check_every + 3) * (ho.scan + 64 + 2);
+  J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
+  hopf_status rc = plan_job(ctx, J);
+  if (rc != HOPF_OK) return rc;
+  // the point state and the tail solver's job entry, in the scratch
+  ArenaAlloc need{nullptr, ~(size_t)0};
+  PtState probe_st;
+  layout_state(need, *J.tab, npts, probe_st, lam0 != nullptr, ho.prec == HOPF_FP64);
+  const size_t bytes = need.used + ((sizeof(TailJob) + 255) & ~(size_t)255);
+  if (bytes > SCRATCH_BYTES)
+    return set_err(ctx, HOPF_EINVAL, "this call needs " + std::to_string(bytes) + " bytes of scratch, more than the " +
+                                         std::to_string(SCRATCH_BYTES) + " the no-allocation entry point holds; "
+                                         "split the points over several calls");
+  ArenaAlloc ar{reinterpret_cast<unsigned char *>(ctx->scratch), SCRATCH_BYTES};
+  if (!layout_state(ar, *J.tab, npts, J.st, lam0 != nullptr, ho.prec == HOPF_FP64))
+    return set_err(ctx, HOPF_EINVAL, "scratch layout failed");
+  TailJob *d_tj = ar.template get<TailJob>(1);
+  if (!d_tj) return set_err(ctx, HOPF_EINVAL, "scratch layout failed");
+  if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
+      sid < (int)ctx->mlp.size() && ctx->mlp[sid].valid) {
+    const MlpState &w = ctx->mlp[sid];
+    J.mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
+  }
+  Opts o{ho.c_tau, ho.gap_tol, ho.t_rel_tol, ho.t_abs_frac, ho.max_iter, ho.check_every, ho.warm, ho.prec, 4000,
+         ho.root, ho.newton_after, ho.newton_rho, ho.adapt, ho.scan};
+  const int n = J.tab->n;
+  const long tot = npts * J.tab->n_pad;
+  k_clear<<<1, 64, 0, s>>>(J.st);
+  k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, J.st.x0, npts, n, J.tab->n_pad, n, nullptr);
+  k_init<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(J.S, J.st, o, MODE_MINTIME, nullptr, nullptr, lam0, tb, n);
+  ctx->iter_launches = 0;
+  const long tail_lim = std::min(ho.tail_max, TAIL_MAX_POINTS);
+  int cnt[2] = {0, 0};
+  while (J.rounds < J.max_rounds) {
+    if ((rc = issue_group(ctx, J, o, MODE_MINTIME)) != HOPF_OK) return rc;
+    HIPCHK(hipMemcpyAsync(cnt, J.st.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const long act = (long)cnt[0] + cnt[1];
+    if (act == 0) break;
+    if (J.tail_ok && act <= tail_lim) {
+      if ((rc = park_job(ctx, J, o, act)) != HOPF_OK) return rc;
+      const TailJob tj{J.S, J.st, J.mv, 0};
+      HIPCHK(hipMemcpyAsync(d_tj, &tj, sizeof(TailJob), hipMemcpyHostToDevice, s));
+      HIPCHK(hipFuncSetAttribute((const void *)k_tail_multi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)tail_lds_bytes(J.tab->m)));
+      k_tail_multi<<<(unsigned)act, 256, tail_lds_bytes(J.tab->m), s>>>(d_tj, 1, o);
+      HIPCHK(hipStreamSynchronize(s));    // the host copy of the job entry lives until here
+      break;
+    }
+  }
+  k_outputs<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(J.S, J.st, MODE_MINTIME, T_out, gap_out, nullptr,
+                                                          nullptr, lam_out, probes_out, iters_out, status_out,
+                                                          nullptr, n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->t_total = ctx->t_iter = ctx->point_rows = ctx->alg_flops = ctx->t_tail = ctx->tail_rows = 0.0;
+  ctx->tail_points = 0;
+  if (J.rounds >= J.max_rounds) ctx->err = "round limit reached; unfinished points report NOCONV";
+  return HOPF_OK;
+}
+
 hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int *n_nodes, double *s_h,
                            double *u_h, double *xs_h, double *p_h, double *philo, double *phihi) {
   if (ctx->sys.empty()) return set_err(ctx, HOPF_ESTATE, "no systems set");
@@ -1681,6 +1822,16 @@ hopf_status hopf_min_time_dev(hopf_ctx *h, long npts, const int *sys_id, const d
   if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
   return hopf::solve_dev(c, hopf::MODE_MINTIME, npts, sys_id, x, nullptr, lam0, t_bracket, T, gap, nullptr,
                          nullptr, lam, probes, iters, pt_status, (hipStream_t)stream);
+}
+
+hopf_status hopf_min_time_dev_noalloc(hopf_ctx *h, long npts, int sys, const double *x, const double *lam0,
+                                      const double *t_bracket, double *T, double *gap, double *lam, int *probes,
+                                      int *iters, int *pt_status, void *stream) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c) return HOPF_EINVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return hopf::set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
+  return hopf::solve_noalloc(c, sys, npts, x, lam0, t_bracket, T, gap, lam, probes, iters, pt_status,
+                             stream ? (hipStream_t)stream : c->stream);
 }
 
 hopf_status hopf_value_dev(hopf_ctx *h, long npts, const int *sys_id, const double *x, const double *t,

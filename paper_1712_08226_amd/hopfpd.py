@@ -24,6 +24,7 @@ PT_OK, PT_INSIDE, PT_UNREACH, PT_NOCONV, PT_NONFINITE = 0, 1, 2, 3, 4
 
 EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", "hopf_last_error",
            "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_value_dev", "hopf_min_time", "hopf_min_time_dev",
+           "hopf_min_time_dev_noalloc",
            "hopf_trajectory", "hopf_last_timing", "hopf_warm_init", "hopf_warm_params",
            "hopf_warm_loss_grad", "hopf_warm_train"]
 
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.hopf_min_time.argtypes = [vp, C.c_long, ip, dp, dp, dp, dp, dp, dp, ip, ip, ip]
     lib.hopf_min_time_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_value_dev.argtypes = [vp, C.c_long, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hopf_min_time_dev_noalloc.argtypes = [vp, C.c_long, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hopf_trajectory.argtypes = [vp, C.c_int, dp, C.c_double, ip, dp, dp, dp, dp, dp, dp]
     lib.hopf_last_timing.argtypes = [vp, C.POINTER(HopfTiming)]
     fp = C.POINTER(C.c_float)
@@ -286,6 +288,25 @@ class Solver:
             d(lam, "lam", "torch.float64", npts, n), d(probes, "probes", "torch.int32", npts),
             d(iters, "iters", "torch.int32", npts), d(status, "status", "torch.int32", npts), s),
             "hopf_min_time_dev")
+
+    def min_time_dev_noalloc(self, x, T, gap, status, lam=None, probes=None, iters=None, sys=0, stream=None,
+                             lam0=None, t_bracket=None):
+        """min_time_dev for the points of one system with the solver state in
+        the library's fixed device scratch (no allocation in the call)."""
+        if x.dim() != 2:
+            raise ValueError("x must be 2-D (points x n)")
+        npts, n = x.shape
+        if npts and n != self.n[sys]:
+            raise ValueError(f"x must have {self.n[sys]} columns")
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        d = self._dev_ptr
+        self._check(self.lib.hopf_min_time_dev_noalloc(
+            self.h, npts, int(sys), d(x, "x", "torch.float64", npts, n),
+            d(lam0, "lam0", "torch.float64", npts, n), d(t_bracket, "t_bracket", "torch.float64", npts, 2),
+            d(T, "T", "torch.float64", npts), d(gap, "gap", "torch.float64", npts),
+            d(lam, "lam", "torch.float64", npts, n), d(probes, "probes", "torch.int32", npts),
+            d(iters, "iters", "torch.int32", npts), d(status, "status", "torch.int32", npts), s),
+            "hopf_min_time_dev_noalloc")
 
     def value_dev(self, x, t, phi_lo, phi_hi, status, lam=None, iters=None, sys_id=None, stream=None):
         """Device twin of value(): torch CUDA tensors (float64 x/t/phi/lam,
