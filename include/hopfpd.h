@@ -79,7 +79,10 @@ typedef enum {
 } hopf_pt;
 
 /* One system.  Sizes: A n*n, B n*m, Qu m*m (NULL = identity), W n*n
- * symmetric positive definite and diagonal (the library handles diagonal targets), c n (NULL = 0).
+ * symmetric positive definite (HOPF_EINVAL otherwise; a W that is not
+ * diagonal is diagonalised once, W = U diag(d) U^T, and the system is solved
+ * in the rotated state U^T x: x, lam0 are rotated in and lam, x(s), p*
+ * rotated back, so every call keeps the caller's coordinates), c n (NULL = 0).
  * Limits: 1 <= n <= 256, 1 <= m <= 64, 2 <= N <= 4096, t_max > 0.
  * c_tau: this system's primal step ratio (see hopf_opts.c_tau); 0 uses the
  * call's option.  Lets one call mix systems whose best ratio differs (the
@@ -99,7 +102,9 @@ typedef struct {
  *   gap_tol       stop when (P - D) / max(1, |D|) <= gap_tol                         [1e-6]
  *   t_rel_tol     bisection stops when hi - lo <= max(t_rel_tol*hi,
  *   t_abs_frac                                    t_abs_frac*t_max)                 [0.5e-4, 1e-6]
- *   max_iter      iterations per solve before HOPF_PT_NOCONV                         [200000]
+ *   max_iter      iteration cap per solve (probe): a solve still undecided at a
+ *                 certificate after max_iter or more iterations ends its query with
+ *                 HOPF_PT_NOCONV (certificates come every check_every iterations) [200000]
  *   check_every   iterations between FP64 certificates                               [50]
  *   warm          HOPF_WARM_COLD: every probe starts at lam = 0, y = 0;
  *                 HOPF_WARM_CONT: every probe starts from the previous probe's iterate;
@@ -138,6 +143,9 @@ typedef struct {
  *   newton_rho    hybrid only: cell probes from newton_after on also run until
  *                 P - D <= newton_rho |P + D| / 2 so the Newton step sees an accurate
  *                 value                                                              [0.5]
+ *   wide_min      FP32 iterations run on 64-point workgroups that share one LDS copy
+ *                 of each node block of the table while at least wide_min of a
+ *                 system's points are active (then on 16-point tiles); 0: never  [16384]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
@@ -158,6 +166,7 @@ typedef struct {
   double newton_rho;
   int tail_max, adapt;
   int scan;
+  int wide_min;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);
@@ -275,6 +284,16 @@ hopf_status hopf_trajectory(hopf_ctx *ctx, int sys_id, const double *x0, double 
  *                       epoch_loss (epochs, may be NULL) gets the mean loss per
  *                       epoch and *pairs the number of training rows */
 hopf_status hopf_warm_init(hopf_ctx *ctx, int sys_id, unsigned seed);
+/* hopf_warm_save     write the trained network of sys_id to `path` (HOPF_ESTATE if
+ *                    it has none)
+ * hopf_warm_load     read a network written by hopf_warm_save into sys_id and mark
+ *                    it trained; HOPF_EINVAL (nothing replaced) when the file is
+ *                    missing, truncated, for another n or width, or non-finite
+ * File format, little-endian: the 8 bytes "HOPFWARM", u32 version (1), u32 n,
+ * u32 width H, u64 parameter count, f32 t_scale, f32 lam_scale, f32 x_mean[n],
+ * f32 x_std[n], f32 parameters[count] (the flat vector of hopf_warm_params). */
+hopf_status hopf_warm_save(hopf_ctx *ctx, int sys_id, const char *path);
+hopf_status hopf_warm_load(hopf_ctx *ctx, int sys_id, const char *path);
 hopf_status hopf_warm_params(hopf_ctx *ctx, int sys_id, int set, float *theta, long count, float *norm);
 hopf_status hopf_warm_loss_grad(hopf_ctx *ctx, int sys_id, int nrows, const float *Z, const float *Y,
                                 double *loss, float *grad);

@@ -58,6 +58,7 @@ struct SysView {
   int n_hbin;
   double dr, anorm;
   const double *hbin, *rdig;       // probe-setup powers (see SysTables)
+  const double *U;                 // [n][n] x = U x' for a rotated system (non-diagonal W), else null
   const float *K32, *K32T;
   const __bf16 *Kd16h, *Kd16l, *Kp16h, *Kp16l;     // BF16 hi/lo copies (dual and primal layouts)
   const double *K64, *K64T, *lpref, *epow, *A, *BQ, *Wd, *c, *Eh, *Qu;
@@ -483,6 +484,229 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       st.iters_tot[p] += iters;
       if (sizeof(Tv) == 8 && st.s64) st.s64[p] = 1;
     }
+  }
+}
+
+// ------------------------------------------------------------------ wide FP32 iterations (64 points, K staged in LDS)
+
+// The same iteration as k_pdhg for FP32 with a workgroup of 64 points: wave
+// w owns points 16 w .. 16 w + 15 of the workgroup's slots and runs every
+// node block for them, so its G = K^T Y needs no cross-wave sum.  Each
+// 16-node block of the table (dual layout, one row of n_pad values per
+// (component, node)) is copied once into LDS and read by all four waves:
+// one global read of K serves 64 points instead of 16.  Operand reads from
+// LDS: dual GEMM A = K_j[node cl][16 t + 4 g .. +3] (one 16-byte read),
+// primal GEMM A = K_j[node 4 g + q][16 t + cl]; the row stride n_pad + 4
+// spreads the rows of a 16-byte read over the banks.  The extra node at
+// tau = T (trapezoid, T off the grid) is applied per point in registers:
+// the four lanes of a point hold all of its lambda_bar rows, reduce R lam_bar
+// with two shuffles, project, and add R^T y_R to their rows of G.
+constexpr int WIDE_PTS = 64;
+__host__ __device__ constexpr int wide_row_stride(int NT) { return 16 * NT + 4; }
+
+template <int NT, int MM>
+__global__ __launch_bounds__(THREADS, 2) void k_pdhg_wide(SysView S, PtState st, int iters, int part) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  constexpr int np = 16 * NT;
+  constexpr int KS = wide_row_stride(NT);
+  constexpr int m = MM;
+  float *ks = reinterpret_cast<float *>(lds_raw);           // [MM][16][KS]
+  int beg, nact;
+  launch_range(st, part, beg, nact);
+  const int wg0 = beg + blockIdx.x * WIDE_PTS;
+  if (wg0 >= nact) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int slot = wg0 + wave * PTS_WAVE + cl;
+  const bool live = slot < nact;
+  const long p = live ? st.perm[slot] : -1;
+  const long pd = live ? p : st.npts;
+  const int rows_max = st.rows[st.perm[wg0]];     // slots are sorted by rows, descending
+  const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
+
+  float tau = 0.f, sig = 0.f, rr = 0.f;
+  int M = -1, rowsp = 0;
+  bool ppart = false;
+  if (live) {
+    tau = (float)st.tau[p];
+    sig = (float)st.sig[p];
+    rr = (float)st.r[p];
+    M = st.M[p];
+    rowsp = st.rows[p];
+    ppart = st.partial[p] != 0;
+  }
+  const bool wave_part = __any(ppart);
+  const float wR = ppart ? 0.5f * rr : 0.f;
+  const float hw = (float)S.h;
+  // sigma lam_bar stays in registers (operand of the dual GEMM); lam itself
+  // is read and written in memory once per iteration, at the prox step
+  float bop[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bop[t][q] = sig * st.lamb[pd * np + 16 * t + 4 * g + q];
+  float *lamp = st.lam + pd * np;
+  float *yp = st.y + (size_t)pd * st.ystride;
+  const float *Rp = ppart ? st.R32 + (size_t)p * m * np : nullptr;
+  const int nchunk = m * NODE_BLOCK * (np / 4);               // float4 chunks of one node block
+
+  for (int it = 0; it < iters; ++it) {
+    floatx4 G[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) G[t] = floatx4{0, 0, 0, 0};
+
+    // ---- extra node at tau = T, in registers
+    if (wave_part) {
+      float yr[MM];
+      float ssq = 0.f;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        float acc = 0.f;
+        if (ppart) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float4 rv = *reinterpret_cast<const float4 *>(Rp + (size_t)j * np + 16 * t + 4 * g);
+            acc += rv.x * bop[t][0] + rv.y * bop[t][1] + rv.z * bop[t][2] + rv.w * bop[t][3];
+          }
+        }
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        const float v = ppart ? st.yR[(size_t)p * st.mpad + j] + acc : 0.f;
+        yr[j] = v;
+        ssq += v * v;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (S.uset == HOPF_U_L2) {
+        const float nv = sqrtf(ssq);
+        const float sc = (nv > wR) ? (nv > 0.f ? wR / nv : 0.f) : 1.f;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) yr[j] *= sc;
+      } else {
+#pragma unroll
+        for (int j = 0; j < MM; ++j) yr[j] = fminf(fmaxf(yr[j], -wR), wR);
+      }
+      if (ppart && g == 0)
+#pragma unroll
+        for (int j = 0; j < MM; ++j) st.yR[(size_t)p * st.mpad + j] = yr[j];
+      if (ppart) {
+#pragma unroll
+        for (int j = 0; j < MM; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const float4 rv = *reinterpret_cast<const float4 *>(Rp + (size_t)j * np + 16 * t + 4 * g);
+            G[t][0] += rv.x * yr[j];
+            G[t][1] += rv.y * yr[j];
+            G[t][2] += rv.z * yr[j];
+            G[t][3] += rv.w * yr[j];
+          }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+
+    for (int kb = 0; kb < nkb; ++kb) {
+      // ---- stage node block kb of the dual table in LDS
+      __syncthreads();                                    // every wave is done with the previous block
+      const float4 *src = reinterpret_cast<const float4 *>(S.K32 + (size_t)kb * m * NODE_BLOCK * np);
+      for (int e = threadIdx.x; e < nchunk; e += THREADS) {
+        const int row = e / (np / 4), c4 = e - row * (np / 4);
+        *reinterpret_cast<float4 *>(ks + row * KS + 4 * c4) = src[e];
+      }
+      __syncthreads();
+      // ---- dual GEMM: V_j = Y_j + K_j (sigma lam_bar)
+      floatx4 V[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        const float4 f = *reinterpret_cast<const float4 *>(yp + (size_t)(kb * m + j) * NODE_BLOCK + 4 * g);
+        V[j] = floatx4{f.x, f.y, f.z, f.w};
+      }
+      // operands of step s + 1 are read from LDS before the MFMAs of step s
+      // (s = 4 t + q), so the LDS latency hides behind the matrix core
+      {
+        float a[2][MM];
+        const float *kd = ks + cl * KS + 4 * g;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) a[0][j] = kd[j * NODE_BLOCK * KS];
+#pragma unroll
+        for (int sidx = 0; sidx < 4 * NT; ++sidx) {
+          const int t = sidx >> 2, q = sidx & 3;
+          if (sidx + 1 < 4 * NT) {
+            const int t1 = (sidx + 1) >> 2, q1 = (sidx + 1) & 3;
+#pragma unroll
+            for (int j = 0; j < MM; ++j) a[(sidx + 1) & 1][j] = kd[j * NODE_BLOCK * KS + 16 * t1 + q1];
+          }
+#pragma unroll
+          for (int j = 0; j < MM; ++j) V[j] = mfma(a[sidx & 1][j], bop[t][q], V[j]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      // ---- projection onto w_k C per (node, point), rows 4 g + q
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb * NODE_BLOCK + 4 * g + q;
+        const float w = (k < rowsp) ? (float)node_weight(k, M, (double)rr, (double)hw, S.quad) : 0.f;
+        if (S.uset == HOPF_U_L2) {
+          float ss = 0.f;
+#pragma unroll
+          for (int j = 0; j < MM; ++j) ss += V[j][q] * V[j][q];
+          const float nv = sqrtf(ss);
+          const float sc = (nv > w) ? (nv > 0.f ? w / nv : 0.f) : 1.f;
+#pragma unroll
+          for (int j = 0; j < MM; ++j) V[j][q] *= sc;
+        } else {
+#pragma unroll
+          for (int j = 0; j < MM; ++j) V[j][q] = fminf(fmaxf(V[j][q], -w), w);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        float4 f;
+        f.x = V[j][0]; f.y = V[j][1]; f.z = V[j][2]; f.w = V[j][3];
+        *reinterpret_cast<float4 *>(yp + (size_t)(kb * m + j) * NODE_BLOCK + 4 * g) = f;
+      }
+      // ---- primal GEMM: G_t += K_j^T Y_j, A = K_j[node 4 g + q][16 t + cl]
+      {
+        float b[2][NT];
+        const float *kp = ks + 4 * g * KS + cl;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[0][t] = kp[16 * t];
+#pragma unroll
+        for (int sidx = 0; sidx < 4 * MM; ++sidx) {
+          const int j = sidx >> 2, q = sidx & 3;
+          if (sidx + 1 < 4 * MM) {
+            const int j1 = (sidx + 1) >> 2, q1 = (sidx + 1) & 3;
+            const float *row = kp + (j1 * NODE_BLOCK + q1) * KS;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[(sidx + 1) & 1][t] = row[16 * t];
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) G[t] = mfma(b[sidx & 1][t], V[j][q], G[t]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // ---- prox of G and extrapolation (theta = 1), rows 16 t + 4 g + q
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float4 l4 = *reinterpret_cast<const float4 *>(lamp + 16 * t + 4 * g);
+      const float4 x4 = *reinterpret_cast<const float4 *>(st.xfc32 + pd * np + 16 * t + 4 * g);
+      const float l0[4] = {l4.x, l4.y, l4.z, l4.w}, xc[4] = {x4.x, x4.y, x4.z, x4.w};
+      float ln[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float wd = (float)S.Wd[16 * t + 4 * g + q];
+        ln[q] = (l0[q] - tau * (G[t][q] - xc[q])) / (1.0f + tau * wd);
+        bop[t][q] = sig * (2.0f * ln[q] - l0[q]);
+      }
+      *reinterpret_cast<float4 *>(lamp + 16 * t + 4 * g) = make_float4(ln[0], ln[1], ln[2], ln[3]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + 4 * g + q] = sig > 0.f ? bop[t][q] / sig : 0.f;
+  if (live && g == 0) {
+    st.iters_probe[p] += iters;
+    st.iters_tot[p] += iters;
   }
 }
 
@@ -1246,6 +1470,7 @@ typedef void (*cert_fn)(SysView, PtState, Opts, int);
 
 // kernel instances, one lookup per NT (hopf_inst_nt*.hip); nullptr if absent
 pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM_out);
+pdhg_fn wide_lookup(int NT, int m);
 cert_fn cert_lookup(int NT);
 pdhg_fn stream_lookup(int NT, int bf16);
 

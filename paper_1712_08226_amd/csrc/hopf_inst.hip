@@ -53,6 +53,32 @@ pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
 #endif
 }
 
+pdhg_fn HOPF_CAT(wide_lookup_nt, HOPF_NT)(int m) {
+#if HOPF_NT > 8
+  (void)m;
+  return nullptr;
+#else
+  int MM = 0;
+  for (int v : kMM)
+    if (v >= m) { MM = v; break; }
+  // one node block of the table in LDS, two workgroups per compute unit
+  if ((size_t)NODE_BLOCK * MM * wide_row_stride(HOPF_NT) * 4 > 76 * 1024) return nullptr;
+  switch (MM) {
+    case 1: return k_pdhg_wide<HOPF_NT, 1>;
+    case 2: return k_pdhg_wide<HOPF_NT, 2>;
+    case 3: return k_pdhg_wide<HOPF_NT, 3>;
+    case 4: return k_pdhg_wide<HOPF_NT, 4>;
+    case 5: return k_pdhg_wide<HOPF_NT, 5>;
+    case 6: return k_pdhg_wide<HOPF_NT, 6>;
+    case 8: return k_pdhg_wide<HOPF_NT, 8>;
+    case 10: return k_pdhg_wide<HOPF_NT, 10>;
+    case 12: return k_pdhg_wide<HOPF_NT, 12>;
+    case 16: return k_pdhg_wide<HOPF_NT, 16>;
+    default: return nullptr;
+  }
+#endif
+}
+
 pdhg_fn HOPF_CAT(stream_lookup_nt, HOPF_NT)(int bf16) {
   return bf16 ? k_pdhg_stream<HOPF_NT, true> : k_pdhg_stream<HOPF_NT, false>;
 }

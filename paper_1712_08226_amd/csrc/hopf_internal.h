@@ -18,7 +18,9 @@ constexpr int RDIG_LEVELS = 3;     // base-16 digits of r / dr below one node st
 // Host copy of one system plus its device tables.
 struct SysTables {
   hopf_system desc{};
-  std::vector<double> A, B, Qu, W, c;   // host copies (row-major)
+  std::vector<double> A, B, Qu, W, c;   // host copies (row-major), in the solver's coordinates
+  bool rotated = false;                 // W was not diagonal: the solver works in x' = U^T x
+  std::vector<double> U;                // [n][n] orthogonal, W = U diag(d) U^T (rotated only)
   int n = 0, m = 0, N = 0, n_pad = 0, nkb = 0;
   int m_user = 0;                      // the caller's m; m >= m_user is the padded kernel size
   double h = 0.0, delta = 0.0;
@@ -44,6 +46,7 @@ struct SysTables {
   double *epow_d = nullptr;    // [POW_LEVELS][n][n]
   double *hbin_d = nullptr;    // [n_hbin][n][n]
   double *rdig_d = nullptr;    // [RDIG_LEVELS][15][n][n]
+  double *U_d = nullptr;       // [n][n] (rotated systems only)
   double *A_d = nullptr;       // [n][n]
   double *BQ_d = nullptr;      // [n][m]   -B Qu
   double *Wd_d = nullptr;      // [n_pad]  diag W (1 in the padding)

@@ -14,6 +14,10 @@
 // Parameters are one flat FP32 vector [W1 (n+1,H), b1, W2, b2, W3, b3, W4 (H,n+2), b4].
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -352,6 +356,70 @@ hopf_status hopf_warm_params(hopf_ctx *h, int sys_id, int set, float *theta, lon
   return HOPF_OK;
 }
 
+// Checkpoint file of one network (little-endian): "HOPFWARM", u32 version 1,
+// u32 n, u32 H, u64 parameter count, f32 t_scale, f32 lam_scale, then f32
+// x_mean[n], x_std[n], theta[count].  Load checks every header field against
+// the system's network before it replaces anything.
+hopf_status hopf_warm_save(hopf_ctx *h, int sys_id, const char *path) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !path) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->mlp.size() || !c->mlp[sys_id].theta || !c->mlp[sys_id].valid)
+    return set_err(c, HOPF_ESTATE, "no trained warm-start network for this system");
+  hopf::MlpState &w = c->mlp[sys_id];
+  hipSetDevice(c->device);
+  std::vector<float> th(w.nparam), xm(w.n), xs(w.n);
+  if (hipMemcpy(th.data(), w.theta, w.nparam * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(xm.data(), w.xm, w.n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(xs.data(), w.xs, w.n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return set_err(c, HOPF_EDEVICE, "reading the network from the device failed");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return set_err(c, HOPF_EINVAL, std::string("cannot open ") + path + " for writing");
+  const uint32_t hdr[3] = {1u, (uint32_t)w.n, (uint32_t)w.H};
+  const uint64_t cnt = w.nparam;
+  const float sc[2] = {w.t_scale, w.lam_scale};
+  bool ok = std::fwrite("HOPFWARM", 1, 8, f) == 8 && std::fwrite(hdr, 4, 3, f) == 3 &&
+            std::fwrite(&cnt, 8, 1, f) == 1 && std::fwrite(sc, 4, 2, f) == 2 &&
+            std::fwrite(xm.data(), 4, w.n, f) == (size_t)w.n && std::fwrite(xs.data(), 4, w.n, f) == (size_t)w.n &&
+            std::fwrite(th.data(), 4, w.nparam, f) == w.nparam;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? HOPF_OK : set_err(c, HOPF_EINVAL, std::string("writing ") + path + " failed");
+}
+
+hopf_status hopf_warm_load(hopf_ctx *h, int sys_id, const char *path) {
+  Ctx *c = reinterpret_cast<Ctx *>(h);
+  if (!c || !path) return HOPF_EINVAL;
+  if (sys_id < 0 || sys_id >= (int)c->sys.size()) return set_err(c, HOPF_EINVAL, "sys_id out of range");
+  hipSetDevice(c->device);
+  if ((int)c->mlp.size() < (int)c->sys.size()) c->mlp.resize(c->sys.size());
+  hopf::MlpState &w = c->mlp[sys_id];
+  hopf_status st = hopf::mlp_ensure(c, sys_id, w);
+  if (st != HOPF_OK) return st;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return set_err(c, HOPF_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  uint32_t hdr[3];
+  uint64_t cnt = 0;
+  float sc[2];
+  std::vector<float> xm(w.n), xs(w.n), th(w.nparam);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "HOPFWARM", 8) == 0 &&
+            std::fread(hdr, 4, 3, f) == 3 && hdr[0] == 1u && hdr[1] == (uint32_t)w.n && hdr[2] == (uint32_t)w.H &&
+            std::fread(&cnt, 8, 1, f) == 1 && cnt == (uint64_t)w.nparam && std::fread(sc, 4, 2, f) == 2 &&
+            std::fread(xm.data(), 4, w.n, f) == (size_t)w.n && std::fread(xs.data(), 4, w.n, f) == (size_t)w.n &&
+            std::fread(th.data(), 4, w.nparam, f) == w.nparam;
+  std::fclose(f);
+  if (!ok) return set_err(c, HOPF_EINVAL, std::string(path) + " is not a warm-start checkpoint of this system's network");
+  for (float v : th)
+    if (!std::isfinite(v)) return set_err(c, HOPF_EINVAL, std::string(path) + " holds non-finite parameters");
+  if (hipMemcpy(w.theta, th.data(), w.nparam * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(w.xm, xm.data(), w.n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(w.xs, xs.data(), w.n * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return set_err(c, HOPF_EDEVICE, "copying the network to the device failed");
+  w.t_scale = sc[0];
+  w.lam_scale = sc[1];
+  w.valid = 1;
+  return HOPF_OK;
+}
+
 hopf_status hopf_warm_loss_grad(hopf_ctx *h, int sys_id, int nrows, const float *Z, const float *Y, double *loss,
                                 float *grad) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
@@ -388,11 +456,24 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
   }
   const hopf::SysTables &tab = c->sys[sys_id];
   const int n = tab.n, np = tab.n_pad;
+  // the network sees the start point in the solver's coordinates (rotated
+  // when the target matrix is not diagonal), as the probe setup does
+  std::vector<double> xr;
+  const double *xf = x;
+  if (tab.rotated) {
+    xr.assign((size_t)npts * n, 0.0);
+    for (long p = 0; p < npts; ++p)
+      for (int j = 0; j < n; ++j) {
+        const double v = x[p * n + j];
+        for (int i = 0; i < n; ++i) xr[(size_t)p * n + i] += tab.U[(size_t)j * n + i] * v;
+      }
+    xf = xr.data();
+  }
   // input normalisation from the training points
   std::vector<float> xm(n, 0.0f), xs(n, 1.0f);
   for (int i = 0; i < n; ++i) {
     double s = 0.0, s2 = 0.0;
-    for (long p = 0; p < npts; ++p) { const double v = x[p * n + i]; s += v; s2 += v * v; }
+    for (long p = 0; p < npts; ++p) { const double v = xf[p * n + i]; s += v; s2 += v * v; }
     const double mu = s / npts, var = std::max(s2 / npts - mu * mu, 1e-24);
     xm[i] = (float)mu;
     xs[i] = (float)std::sqrt(var);
@@ -402,11 +483,12 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
   w.t_scale = (float)tab.desc.t_max;
   // 1. solve the training points with the probe log on
   const long cap = npts * 48;
-  double *dx = nullptr, *dT = nullptr, *dgap = nullptr;
+  double *dx = nullptr, *dxf = nullptr, *dT = nullptr, *dgap = nullptr;
   int *dst = nullptr, *dsid = nullptr;
   hopf_status rc = HOPF_OK;
   auto al = [&](void **p, size_t b) { if (rc == HOPF_OK && hipMalloc(p, b) != hipSuccess) rc = HOPF_ENOMEM; };
   al((void **)&dx, (size_t)npts * n * 8);
+  if (tab.rotated) al((void **)&dxf, (size_t)npts * n * 8);
   al((void **)&dT, npts * 8);
   al((void **)&dgap, npts * 8);
   al((void **)&dst, npts * 4);
@@ -421,6 +503,7 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
     c->log_cap = cap;
     c->log_count = 0;
     hipMemcpy(dx, x, (size_t)npts * n * 8, hipMemcpyHostToDevice);
+    if (dxf) hipMemcpy(dxf, xf, (size_t)npts * n * 8, hipMemcpyHostToDevice);
     if (dsid) {
       std::vector<int> ids(npts, sys_id);
       hipMemcpy(dsid, ids.data(), npts * 4, hipMemcpyHostToDevice);
@@ -461,7 +544,8 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
       long seen = 0;
       for (long s0 = 0; s0 + Bn <= rows || (s0 == 0 && rows < Bn); s0 += Bn) {
         const int nb = (int)std::min<long>(Bn, rows - s0);
-        hopf::k_make_rows<<<nb, 128, 0, c->stream>>>(didx + s0, nb, c->log_pt, c->log_T, c->log_lam, np, dx, dT, dst,
+        hopf::k_make_rows<<<nb, 128, 0, c->stream>>>(didx + s0, nb, c->log_pt, c->log_T, c->log_lam, np,
+                                                     dxf ? dxf : dx, dT, dst,
                                                      n, w.xm, w.xs, w.t_scale, w.lam_scale, b.Z, b.Y);
         hopf::loss_grad(c->stream, w.theta, b, nb, n, w.H);
         w.step += 1;
@@ -481,7 +565,7 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
     else w.valid = 1;
   }
   b.free_all();
-  hipFree(didx); hipFree(dss); hipFree(dx); hipFree(dT); hipFree(dgap); hipFree(dst); hipFree(dsid);
+  hipFree(didx); hipFree(dss); hipFree(dx); hipFree(dxf); hipFree(dT); hipFree(dgap); hipFree(dst); hipFree(dsid);
   hipFree(c->log_pt); hipFree(c->log_T); hipFree(c->log_lam);
   c->log_pt = nullptr; c->log_T = nullptr; c->log_lam = nullptr;
   c->log_cap = 0;

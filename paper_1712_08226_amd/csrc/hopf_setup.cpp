@@ -138,6 +138,50 @@ bool expm(const Mat &A, double t, Mat &out, int n) {
   return true;
 }
 
+// Symmetric eigendecomposition W = U diag(d) U^T by cyclic Jacobi rotations
+// (U orthogonal, row-major; column k is the eigenvector of d[k]).
+void sym_eig(const Mat &W, int n, Mat &U, std::vector<double> &d) {
+  Mat a(W);
+  U.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = c * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = c * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
+          U[(size_t)k * n + p] = c * ukp - sn * ukq;
+          U[(size_t)k * n + q] = sn * ukp + c * ukq;
+        }
+      }
+  }
+  d.resize(n);
+  for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
+}
+
 bool all_finite(const double *p, size_t k) {
   for (size_t i = 0; i < k; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -148,8 +192,8 @@ bool all_finite(const double *p, size_t k) {
 
 void free_tables(SysTables &t) {
   hipFree(t.K32); hipFree(t.K64); hipFree(t.K32T); hipFree(t.K64T); hipFree(t.lpref_d); hipFree(t.epow_d);
-  hipFree(t.hbin_d); hipFree(t.rdig_d);
-  t.hbin_d = t.rdig_d = nullptr;
+  hipFree(t.hbin_d); hipFree(t.rdig_d); hipFree(t.U_d);
+  t.hbin_d = t.rdig_d = t.U_d = nullptr;
   hipFree(t.Kd16h); hipFree(t.Kd16l); hipFree(t.Kp16h); hipFree(t.Kp16l);
   t.K32T = nullptr; t.K64T = nullptr;
   t.Kd16h = t.Kd16l = t.Kp16h = t.Kp16l = nullptr;
@@ -193,13 +237,49 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
       !all_finite(t.W.data(), t.W.size()) || !all_finite(t.Qu.data(), t.Qu.size()) ||
       !all_finite(t.c.data(), t.c.size()))
     return set_err(ctx, HOPF_EINVAL, "non-finite system data");
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      const double v = t.W[(size_t)i * n + j];
-      if (i == j && !(v > 0.0)) return set_err(ctx, HOPF_EINVAL, "W is not positive definite");
-      if (i != j && v != 0.0)
-        return set_err(ctx, HOPF_EUNSUPPORTED, "the library needs a diagonal target matrix W");
+  // W must be symmetric positive definite.  A diagonal W is used as is; any
+  // other is diagonalised, W = U diag(d) U^T, and the system is solved in the
+  // rotated state x' = U^T x (A' = U^T A U, B' = U^T B, c' = U^T c, W' = diag(d)):
+  // an orthogonal change of coordinates leaves phi, T*, u and the certified
+  // gap unchanged, and the library rotates x in and lam, x(s), p* out.
+  {
+    double wmax = 0.0;
+    bool diag = true;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        wmax = std::max(wmax, std::fabs(t.W[(size_t)i * n + j]));
+        if (i != j && t.W[(size_t)i * n + j] != 0.0) diag = false;
+      }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(t.W[(size_t)i * n + j] - t.W[(size_t)j * n + i]) > 1e-12 * wmax)
+          return set_err(ctx, HOPF_EINVAL, "W is not symmetric");
+    t.rotated = !diag;
+    t.U.clear();
+    if (diag) {
+      for (int i = 0; i < n; ++i)
+        if (!(t.W[(size_t)i * n + i] > 0.0)) return set_err(ctx, HOPF_EINVAL, "W is not positive definite");
+    } else {
+      std::vector<double> d;
+      sym_eig(t.W, n, t.U, d);
+      for (int i = 0; i < n; ++i)
+        if (!(d[i] > 1e-14 * wmax)) return set_err(ctx, HOPF_EINVAL, "W is not positive definite");
+      Mat Ut((size_t)n * n), AU((size_t)n * n), Ar((size_t)n * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ut[(size_t)i * n + j] = t.U[(size_t)j * n + i];
+      matmul(t.A.data(), t.U.data(), AU.data(), n, n, n);
+      matmul(Ut.data(), AU.data(), Ar.data(), n, n, n);
+      std::vector<double> Br((size_t)n * m), cr(n, 0.0);
+      matmul(Ut.data(), t.B.data(), Br.data(), n, n, m);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) cr[i] += Ut[(size_t)i * n + j] * t.c[j];
+      t.A.swap(Ar);
+      t.B.swap(Br);
+      t.c.swap(cr);
+      t.W.assign((size_t)n * n, 0.0);
+      for (int i = 0; i < n; ++i) t.W[(size_t)i * n + i] = d[i];
     }
+  }
   t.desc.A = t.A.data(); t.desc.B = t.B.data(); t.desc.W = t.W.data();
   t.desc.Qu = t.Qu.data(); t.desc.c = t.c.data();
 
@@ -388,7 +468,8 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
             up((void **)&t.Wd_d, Wd.data(), Wd.size() * sizeof(double)) &&
             up((void **)&t.c_d, cc.data(), cc.size() * sizeof(double)) &&
             up((void **)&t.Eh_d, Eh.data(), Eh.size() * sizeof(double)) &&
-            up((void **)&t.Qu_d, t.Qu.data(), t.Qu.size() * sizeof(double));
+            up((void **)&t.Qu_d, t.Qu.data(), t.Qu.size() * sizeof(double)) &&
+            (!t.rotated || up((void **)&t.U_d, t.U.data(), t.U.size() * sizeof(double)));
   if (!ok) {
     free_tables(t);
     return set_err(ctx, HOPF_ENOMEM, "device allocation/copy of the node tables failed");
@@ -419,6 +500,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->tail_max = 512;
   o->adapt = 1;
   o->scan = 48;
+  o->wide_min = 16384;
   return HOPF_OK;
 }
 
@@ -488,7 +570,7 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
       o->root < 0 || o->root > 1 || o->newton_after < 0 || !(o->newton_rho > 0.0) ||
-      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096)
+      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;

@@ -37,15 +37,20 @@ namespace hopf {
 
 // ------------------------------------------------------------------ init
 
-// x0[p] = row idx[p] (or p) of the caller's x, whose rows are xs doubles apart
+// x0[p] = row idx[p] (or p) of the caller's x, whose rows are xs doubles
+// apart; for a rotated system x0 = U^T x (the solver's coordinates)
 __global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int n, int n_pad,
-                       int xs, const int *__restrict__ idx) {
+                       int xs, const int *__restrict__ idx, const double *__restrict__ U) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npts * n_pad) return;
   long p = i / n_pad;
   int k = (int)(i % n_pad);
   const long q = idx ? idx[p] : p;
-  x0[i] = k < n ? x[q * xs + k] : 0.0;
+  if (k >= n) { x0[i] = 0.0; return; }
+  if (!U) { x0[i] = x[q * xs + k]; return; }
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) acc += U[(size_t)j * n + k] * x[q * xs + j];
+  x0[i] = acc;
 }
 
 // counters and flop accounting of a job start at zero (a kernel, not a
@@ -91,7 +96,16 @@ __global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__
   st.ha[p] = 0.0;
   st.hb[p] = 0.0;
   if (st.lam0s)
-    for (int i = 0; i < S.n_pad; ++i) st.lam0s[p * S.n_pad + i] = (lam0 && i < S.n) ? lam0[q * ls + i] : 0.0;
+    for (int i = 0; i < S.n_pad; ++i) {
+      double v = 0.0;
+      if (lam0 && i < S.n) {
+        if (S.U)
+          for (int j = 0; j < S.n; ++j) v += S.U[(size_t)j * S.n + i] * lam0[q * ls + j];   // U^T lam0
+        else
+          v = lam0[q * ls + i];
+      }
+      st.lam0s[p * S.n_pad + i] = v;
+    }
   st.P[p] = 0.0;
   st.D[p] = 0.0;
   st.flags[p] = 0;
@@ -378,7 +392,18 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       outv[k] = a;
     }
     __syncthreads();
-    if ((o.warm == HOPF_WARM_MLP_LAM || net_first) && !(st.lam0s != nullptr && st.probes[p] == 0)) {
+    // a network output that is not finite, or a costate more than 1000 times
+    // the training costates' scale, is not used (the start stays cold or
+    // continued): a damaged network can slow a solve down, not change it
+    if (tid == 0) {
+      int bad = !(isfinite(mv.lam_scale) && mv.lam_scale > 0.0f);
+      for (int k = 0; k < dout; ++k) bad |= !isfinite(outv[k] * (k < n ? mv.lam_scale : 1.0f));
+      for (int k = 0; k < n; ++k) bad |= fabsf(outv[k]) > 1e3f;
+      reinterpret_cast<int *>(outv)[dout] = bad;
+    }
+    __syncthreads();
+    const bool net_bad = reinterpret_cast<const int *>(outv)[dout] != 0;
+    if ((o.warm == HOPF_WARM_MLP_LAM || net_first) && !net_bad && !(st.lam0s != nullptr && st.probes[p] == 0)) {
       for (int i = tid; i < np; i += 256) {
         const float l = i < n ? outv[i] * mv.lam_scale : 0.0f;
         st.lam[p * np + i] = l;
@@ -386,7 +411,7 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
         if (f64) { st.lam64[p * np + i] = l; st.lamb64[p * np + i] = l; }
       }
     }
-    if (tid == 0 && st.probes[p] == 0) {
+    if (tid == 0 && st.probes[p] == 0 && !net_bad) {
       const float r2 = outv[n + 1];
       st.bT[p] = expf(outv[n]);
       st.bD[p] = log1pf(expf(-fabsf(r2))) + fmaxf(r2, 0.0f) + 1e-3f;
@@ -1068,10 +1093,18 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
   if (gap_out) gap_out[q] = (Pv - Dv) / fmax(1.0, fabs(Dv));
   if (philo) philo[q] = -Pv;
   if (phihi) phihi[q] = -Dv;
-  if (lam_out)
-    for (int i = 0; i < S.n; ++i)
-      lam_out[q * ls + i] = (st.s64 != nullptr && st.s64[p] != 0) ? st.lam64[p * S.n_pad + i]
-                                                                 : (double)st.lam[p * S.n_pad + i];
+  if (lam_out) {
+    const bool f64 = st.s64 != nullptr && st.s64[p] != 0;
+    for (int i = 0; i < S.n; ++i) {
+      double v = 0.0;
+      if (S.U)   // lam = U lam' (back to the caller's coordinates)
+        for (int j = 0; j < S.n; ++j)
+          v += S.U[(size_t)i * S.n + j] * (f64 ? st.lam64[p * S.n_pad + j] : (double)st.lam[p * S.n_pad + j]);
+      else
+        v = f64 ? st.lam64[p * S.n_pad + i] : (double)st.lam[p * S.n_pad + i];
+      lam_out[q * ls + i] = v;
+    }
+  }
   if (probes_out) probes_out[q] = st.probes[p];
   if (iters_out) iters_out[q] = st.iters_tot[p];
   status_out[q] = stt;
@@ -1209,6 +1242,7 @@ SysView view(const SysTables &t) {
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
   v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
   v.n_hbin = t.n_hbin; v.dr = t.dr; v.anorm = t.anorm; v.hbin = t.hbin_d; v.rdig = t.rdig_d;
+  v.U = t.rotated ? t.U_d : nullptr;
   return v;
 }
 
@@ -1228,8 +1262,10 @@ struct Job {
   const SysTables *tab = nullptr;
   SysView S{};
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
+  pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
   cert_fn fc = nullptr;
-  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0;
+  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0;
+  long last_active = 0;          // active points at the last check read (picks the iteration kernel)
   PtState st{};
   long npts = 0;
   const int *idx = nullptr;      // device: job point -> caller's point (nullptr: identity)
@@ -1283,6 +1319,13 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   if (J.lds_pdhg > 150 * 1024 || J.lds_cert > 150 * 1024)
     return set_err(ctx, HOPF_EUNSUPPORTED, "system too large for the LDS tiling of the kernels");
   if (ho.prec == HOPF_BF16X3 && !tab.Kd16h) return set_err(ctx, HOPF_ESTATE, "BF16 tables missing");
+  if (ho.prec == HOPF_FP32 && !streaming && ho.wide_min > 0) {
+    J.fw = wide_lookup(NT, tab.m);
+    if (J.fw) {
+      J.lds_wide = (size_t)NODE_BLOCK * MMc * wide_row_stride(NT) * sizeof(float);
+      HIPCHK(hipFuncSetAttribute((const void *)J.fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_wide));
+    }
+  }
   // BF16 hi+lo: points that stall are escalated to an FP32 kernel
   if (ho.prec == HOPF_BF16X3) {
     int mm2 = 0;
@@ -1332,7 +1375,12 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
       HIPCHK(hipEventRecord(a, s));
     }
     if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
-    J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+    if (J.fw && J.last_active >= ho.wide_min) {
+      const unsigned wgrid = (unsigned)((J.npts + WIDE_PTS - 1) / WIDE_PTS);
+      J.fw<<<wgrid, THREADS, J.lds_wide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+    } else {
+      J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+    }
     if (J.timed) {
       HIPCHK(hipEventRecord(b, s));
       J.kev.push_back(a);
@@ -1460,6 +1508,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.idx = nj > 1 ? d_idx + off[J.sid] : nullptr;
     J.s = nj > 1 ? ctx->pool[j % NPOOL] : base;
     J.ngrid = (unsigned)((J.npts + PTS_TILE - 1) / PTS_TILE);
+    J.last_active = J.npts;
     J.max_rounds = (long)(ho.max_iter / ho.check_every + 3) * (max_probes + 2);
     J.hcount = hcount + 4 * j;
     J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
@@ -1487,7 +1536,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     const long tot = np_ * J.tab->n_pad;
     const int ls = nj > 1 ? xs : J.tab->n;     // row stride of x, lam0 and lam
     k_clear<<<1, 64, 0, s>>>(st);
-    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx);
+    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
   }
   // ---- interleaved rounds: each job keeps up to two groups in flight until
@@ -1510,6 +1559,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
         const hipError_t q = hipEventQuery(J.gev[J.gdone & 1]);
         if (q == hipSuccess) {
           const int c = J.hcount[2 * (J.gdone & 1)] + J.hcount[2 * (J.gdone & 1) + 1];
+          J.last_active = c;
           ++J.gdone;
           progressed = true;
           if (c == 0 || J.rounds >= J.max_rounds) {
@@ -1693,6 +1743,7 @@ hopf_status solve_noalloc(Ctx *ctx, int sid, long npts, const double *x, const d
   J.s = s;
   J.timed = false;
   J.ngrid = (unsigned)((npts + PTS_TILE - 1) / PTS_TILE);
+  J.last_active = npts;
   J.max_rounds = (long)(ho.max_iter / ho.check_every + 3) * (ho.scan + 64 + 2);
   J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
   hopf_status rc = plan_job(ctx, J);
@@ -1721,7 +1772,7 @@ hopf_status solve_noalloc(Ctx *ctx, int sid, long npts, const double *x, const d
   const int n = J.tab->n;
   const long tot = npts * J.tab->n_pad;
   k_clear<<<1, 64, 0, s>>>(J.st);
-  k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, J.st.x0, npts, n, J.tab->n_pad, n, nullptr);
+  k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, J.st.x0, npts, n, J.tab->n_pad, n, nullptr, J.S.U);
   k_init<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(J.S, J.st, o, MODE_MINTIME, nullptr, nullptr, lam0, tb, n);
   ctx->iter_launches = 0;
   const long tail_lim = std::min(ho.tail_max, TAIL_MAX_POINTS);
@@ -1731,6 +1782,7 @@ hopf_status solve_noalloc(Ctx *ctx, int sid, long npts, const double *x, const d
     HIPCHK(hipMemcpyAsync(cnt, J.st.counters, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const long act = (long)cnt[0] + cnt[1];
+    J.last_active = act;
     if (act == 0) break;
     if (J.tail_ok && act <= tail_lim) {
       if ((rc = park_job(ctx, J, o, act)) != HOPF_OK) return rc;
@@ -1797,6 +1849,19 @@ hopf_status trajectory_dev(Ctx *ctx, int sid, const double *x0_h, double T, int 
       hipMemcpy(u_h, du, (size_t)nn * mu * sizeof(double), hipMemcpyDeviceToHost);
       hipMemcpy(xs_h, dxs, (size_t)nn * n * sizeof(double), hipMemcpyDeviceToHost);
       hipMemcpy(p_h, dp, n * sizeof(double), hipMemcpyDeviceToHost);
+      if (tab.rotated) {   // states and costate back to the caller's coordinates: v = U v'
+        std::vector<double> tmp(n);
+        auto rot = [&](double *v) {
+          for (int i = 0; i < n; ++i) {
+            double a = 0.0;
+            for (int j = 0; j < n; ++j) a += tab.U[(size_t)i * n + j] * v[j];
+            tmp[i] = a;
+          }
+          std::copy(tmp.begin(), tmp.end(), v);
+        };
+        for (int j = 0; j < nn; ++j) rot(xs_h + (size_t)j * n);
+        rot(p_h);
+      }
       if (philo) hipMemcpy(philo, dlo, sizeof(double), hipMemcpyDeviceToHost);
       if (phihi) hipMemcpy(phihi, dhi, sizeof(double), hipMemcpyDeviceToHost);
     }
@@ -1955,6 +2020,7 @@ namespace hopf {
 
 #define HOPF_DECL(k)                                   \
   pdhg_fn pdhg_lookup_nt##k(int m, int prec, int *MM); \
+  pdhg_fn wide_lookup_nt##k(int m);                    \
   pdhg_fn stream_lookup_nt##k(int bf16);               \
   cert_fn cert_lookup_nt##k();
 HOPF_DECL(1) HOPF_DECL(2) HOPF_DECL(3) HOPF_DECL(4) HOPF_DECL(5) HOPF_DECL(6) HOPF_DECL(7) HOPF_DECL(8)
@@ -1974,6 +2040,12 @@ HOPF_DECL(9) HOPF_DECL(10) HOPF_DECL(11) HOPF_DECL(12) HOPF_DECL(13) HOPF_DECL(1
 
 pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM) {
 #define E(k) pdhg_lookup_nt##k(m, prec, MM)
+  HOPF_SW(E)
+#undef E
+}
+
+pdhg_fn wide_lookup(int NT, int m) {
+#define E(k) wide_lookup_nt##k(m)
   HOPF_SW(E)
 #undef E
 }

@@ -26,7 +26,7 @@ EXPORTS = ["hopf_default_opts", "hopf_create", "hopf_destroy", "hopf_strerror", 
            "hopf_set_systems", "hopf_set_opts", "hopf_value", "hopf_value_dev", "hopf_min_time", "hopf_min_time_dev",
            "hopf_min_time_dev_noalloc",
            "hopf_trajectory", "hopf_last_timing", "hopf_warm_init", "hopf_warm_params",
-           "hopf_warm_loss_grad", "hopf_warm_train"]
+           "hopf_warm_loss_grad", "hopf_warm_train", "hopf_warm_save", "hopf_warm_load"]
 
 
 class HopfSystem(C.Structure):
@@ -41,7 +41,8 @@ class HopfOpts(C.Structure):
     _fields_ = [("c_tau", C.c_double), ("gap_tol", C.c_double), ("t_rel_tol", C.c_double),
                 ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("warm", C.c_int), ("prec", C.c_int), ("root", C.c_int), ("newton_after", C.c_int),
-                ("newton_rho", C.c_double), ("tail_max", C.c_int), ("adapt", C.c_int), ("scan", C.c_int)]
+                ("newton_rho", C.c_double), ("tail_max", C.c_int), ("adapt", C.c_int), ("scan", C.c_int),
+                ("wide_min", C.c_int)]
 
 
 class HopfTiming(C.Structure):
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.hopf_last_timing.argtypes = [vp, C.POINTER(HopfTiming)]
     fp = C.POINTER(C.c_float)
     lib.hopf_warm_init.argtypes = [vp, C.c_int, C.c_uint]
+    lib.hopf_warm_save.argtypes = [vp, C.c_int, C.c_char_p]
+    lib.hopf_warm_load.argtypes = [vp, C.c_int, C.c_char_p]
     lib.hopf_warm_params.argtypes = [vp, C.c_int, C.c_int, fp, C.c_long, fp]
     lib.hopf_warm_loss_grad.argtypes = [vp, C.c_int, C.c_int, fp, fp, dp, fp]
     lib.hopf_warm_train.argtypes = [vp, C.c_int, C.c_long, dp, C.c_int, C.c_int, C.c_float, C.c_uint, dp,
@@ -362,19 +365,13 @@ class Solver:
                     "hopf_warm_params")
 
     def warm_save(self, path, sys_id=0):
-        """Write the network of sys_id (parameters and input normalisation) to
-        an .npz file of plain arrays."""
-        th, nm = self.warm_get(sys_id)
-        np.savez(path, theta=th, norm=nm, n=np.int64(self.n[sys_id]))
+        """Write the trained network of sys_id to a checkpoint file
+        (hopf_warm_save; format in include/hopfpd.h)."""
+        self._check(self.lib.hopf_warm_save(self.h, sys_id, os.fsencode(path)), "hopf_warm_save")
 
     def warm_load(self, path, sys_id=0):
-        """Load a network written by warm_save (no pickled objects are read)
-        into sys_id and mark it trained."""
-        with np.load(path, allow_pickle=False) as f:
-            if int(f["n"]) != self.n[sys_id]:
-                raise ValueError(f"{path} holds a network for n={int(f['n'])}, system {sys_id} has n={self.n[sys_id]}")
-            self.warm_init(sys_id)            # allocates the network; the parameters are replaced below
-            self.warm_set(f["theta"], f["norm"], sys_id)
+        """Read a checkpoint written by warm_save into sys_id (hopf_warm_load)."""
+        self._check(self.lib.hopf_warm_load(self.h, sys_id, os.fsencode(path)), "hopf_warm_load")
 
     def warm_loss_grad(self, Z, Y, sys_id=0):
         Z = np.ascontiguousarray(Z, dtype=np.float32)

@@ -164,3 +164,45 @@ def test_caller_lam0_and_hints_vs_oracle(solver, tail):
     idx = list(range(0, 64, 8)) + [7, 14]
     outs = oracle_min_times(sysdict(spec), x[idx], dict(c_tau=5.0, warm="cont"), lam0=lam0[idx], tbr=tb[idx])
     _check_sample(r, idx, outs)
+
+
+@pytest.mark.parametrize("mode", ["min_time", "value"])
+@pytest.mark.parametrize("shape", [("c5", 100, 10, 300, "l2"), ("box", 40, 8, 120, "box"), ("c2", 50, 5, 200, "l2")])
+def test_wide_kernel_matches_16_point_tiles(solver, mode, shape):
+    """The 64-point LDS-staged iteration kernel against the 16-point tiles on
+    the same points, every round on one of them (no tail solver): identical
+    statuses and results to the parity bar, and sampled points against the
+    oracle.  Horizons off the table grid exercise the extra node."""
+    from gen import random_system
+    name, n, m, N, uset = shape
+    say("case: wide kernel vs tiles", mode, name)
+    if name == "c5":
+        spec = config5(npts=8).systems[0]
+    elif name == "c2":
+        spec = config2(npts=8).systems[0]
+    else:
+        spec = random_system(n, m, N, uset, seed=91, t_max=4.0)
+    c_tau = {"c5": 2.0, "c2": 5.0, "box": 0.3}[name]
+    x, _ = planted_drift_points(spec, 700, 0.2, min(3.0, spec.t_max * 0.7), 13)
+    t = np.linspace(0.05, 0.3 * spec.t_max, 700)     # horizons where fixed steps converge within max_iter
+    solver.set_systems([spec])
+    res = {}
+    for wide in (0, 1):
+        solver.set_opts(prec="fp32", c_tau=c_tau, warm="cont", tail_max=0, wide_min=wide)
+        res[wide] = solver.min_time(x) if mode == "min_time" else solver.value(x, t)
+        say("wide_min", wide, "status", np.bincount(res[wide]["status"], minlength=5))
+    a, b = res[0], res[1]
+    assert np.array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    if mode == "min_time":
+        assert np.all(np.abs(a["T"][ok] - b["T"][ok]) <= 1e-4 * a["T"][ok])
+        assert np.all(b["gap"][ok] <= 1e-6)
+        idx = [0, 1, 350, 699]
+        outs = oracle_min_times(sysdict(spec), x[idx], dict(c_tau=c_tau, warm="cont"))
+        _check_sample(b, idx, outs)
+    else:
+        gap = (b["phi_hi"] - b["phi_lo"]) / np.maximum(1.0, np.abs(b["phi_hi"]))
+        assert np.all(gap[ok] <= 1e-6)
+        lo = np.maximum(a["phi_lo"], b["phi_lo"])
+        hi = np.minimum(a["phi_hi"], b["phi_hi"])
+        assert np.all(lo[ok] <= hi[ok] + 1e-9 * np.maximum(1.0, np.abs(hi[ok])))
