@@ -555,51 +555,58 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg_wide(SysView S, PtState st,
 #pragma unroll
     for (int t = 0; t < NT; ++t) G[t] = floatx4{0, 0, 0, 0};
 
-    // ---- extra node at tau = T, in registers
+    // ---- extra node at tau = T, in registers, one pass over R: for each
+    // component j, v_j = y_R,j + R_j . (sigma lam_bar) (the four lanes of a
+    // point reduce with two shuffles) and the primal term R_j^T (.) is added
+    // to G with the same loaded row: the clamped v_j for the box; for the l2
+    // ball v_j itself, G being scaled by the projection factor afterwards
+    // (G holds only this term at that point)
     if (wave_part) {
-      float yr[MM];
       float ssq = 0.f;
+      const bool box = S.uset != HOPF_U_L2;
+      float *yRp = ppart ? st.yR + (size_t)p * st.mpad : nullptr;
+      // row j + 1 of R is loaded while row j is used
+      float4 rn[NT];
 #pragma unroll
-      for (int j = 0; j < MM; ++j) {
+      for (int t = 0; t < NT; ++t)
+        rn[t] = ppart ? *reinterpret_cast<const float4 *>(Rp + 16 * t + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 1
+      for (int j = 0; j < m; ++j) {
+        float4 rv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) rv[t] = rn[t];
+        if (j + 1 < m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            rn[t] = ppart ? *reinterpret_cast<const float4 *>(Rp + (size_t)(j + 1) * np + 16 * t + 4 * g)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
         float acc = 0.f;
-        if (ppart) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const float4 rv = *reinterpret_cast<const float4 *>(Rp + (size_t)j * np + 16 * t + 4 * g);
-            acc += rv.x * bop[t][0] + rv.y * bop[t][1] + rv.z * bop[t][2] + rv.w * bop[t][3];
-          }
-        }
+        for (int t = 0; t < NT; ++t)
+          acc += rv[t].x * bop[t][0] + rv[t].y * bop[t][1] + rv[t].z * bop[t][2] + rv[t].w * bop[t][3];
         acc += __shfl_xor(acc, 16);
         acc += __shfl_xor(acc, 32);
-        const float v = ppart ? st.yR[(size_t)p * st.mpad + j] + acc : 0.f;
-        yr[j] = v;
+        float v = ppart ? yRp[j] + acc : 0.f;
+        if (box) v = fminf(fmaxf(v, -wR), wR);
         ssq += v * v;
-        __builtin_amdgcn_sched_barrier(0);
+        if (ppart && g == 0) yRp[j] = v;           // the l2 ball's scale is applied below
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          G[t][0] += rv[t].x * v;
+          G[t][1] += rv[t].y * v;
+          G[t][2] += rv[t].z * v;
+          G[t][3] += rv[t].w * v;
+        }
       }
-      if (S.uset == HOPF_U_L2) {
+      if (!box) {
         const float nv = sqrtf(ssq);
         const float sc = (nv > wR) ? (nv > 0.f ? wR / nv : 0.f) : 1.f;
+        if (ppart && g == 0)
+          for (int j = 0; j < m; ++j) yRp[j] *= sc;
 #pragma unroll
-        for (int j = 0; j < MM; ++j) yr[j] *= sc;
-      } else {
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int j = 0; j < MM; ++j) yr[j] = fminf(fmaxf(yr[j], -wR), wR);
-      }
-      if (ppart && g == 0)
-#pragma unroll
-        for (int j = 0; j < MM; ++j) st.yR[(size_t)p * st.mpad + j] = yr[j];
-      if (ppart) {
-#pragma unroll
-        for (int j = 0; j < MM; ++j)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const float4 rv = *reinterpret_cast<const float4 *>(Rp + (size_t)j * np + 16 * t + 4 * g);
-            G[t][0] += rv.x * yr[j];
-            G[t][1] += rv.y * yr[j];
-            G[t][2] += rv.z * yr[j];
-            G[t][3] += rv.w * yr[j];
-          }
-        __builtin_amdgcn_sched_barrier(0);
+          for (int q = 0; q < 4; ++q) G[t][q] *= sc;
       }
     }
 
