@@ -27,15 +27,16 @@ METRIC = "min-time queries/sec at dual gap≤1e-6 (n=100,N=300): plain vs warm-s
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1712_08226_amd", "csrc", "hopf_device.h")
-COUNTERS = os.path.join(ROOT, "profiles", "k_pdhg_n100_m10_N300_65536q_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "pdhg_n100_m10_N300_65536q_hbm_counters.md")
 
 
-def counter_traffic(variant, check_every, c_tau):
-    """HBM bytes per k_pdhg launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs of this workload ('traffic:' JSON lines in the summary, one
-    per profiled warm-start variant), or None when no record matches the
-    variant, iterations per launch and step ratio of this run, or the kernel
-    source has changed since the counters were taken."""
+def counter_traffic(variant, check_every, c_tau, kernel):
+    """HBM bytes per launch of an iteration kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs of this workload ('traffic:' JSON
+    lines in the summary, one per profiled kernel and warm-start variant), or
+    None when no record matches the kernel, variant, iterations per launch and
+    step ratio of this run, or the kernel source has changed since the
+    counters were taken."""
     import hashlib
     try:
         with open(COUNTERS) as f:
@@ -45,7 +46,7 @@ def counter_traffic(variant, check_every, c_tau):
     except (OSError, ValueError):
         return None
     for rec in recs:
-        if (rec.get("kernel_source_sha256") == sha and rec.get("variant") == variant
+        if (rec.get("kernel_source_sha256") == sha and rec.get("kernel") == kernel and rec.get("variant") == variant
                 and rec.get("check_every") == check_every and rec.get("c_tau") == c_tau):
             return rec
     return None
@@ -266,7 +267,7 @@ def bench_c5(args):
             step()
             log(f"[{name}] warmup step {i + 1}/{nwarm} done")
         torch.cuda.synchronize()
-        acc = dict(tk=0.0, launches=0, rows=0.0, ttail=0.0, tpts=0, dev_s=0.0)
+        acc = dict(tk=0.0, launches=0, rows=0.0, ttail=0.0, tpts=0, dev_s=0.0, tw=0.0, nw=0, rw=0.0)
         done = 0
         t0 = time.perf_counter()
         while done < max_steps:
@@ -278,6 +279,9 @@ def bench_c5(args):
             acc["ttail"] += tm["tail_kernel_s"]
             acc["tpts"] += tm["tail_points"]
             acc["dev_s"] += tm["total_s"]
+            acc["tw"] += tm["wide_kernel_s"]
+            acc["nw"] += tm["wide_launches"]
+            acc["rw"] += tm["wide_point_rows"]
             done += 1
             log(f"[{name}] step {done}: device {tm['total_s']:.3f} s")
             if budget_s is not None and time.perf_counter() - t0 >= budget_s:
@@ -326,21 +330,33 @@ def bench_c5(args):
         literal["points"] = wl.meta["points"]
         del lb
 
-    flops = 4.0 * spec.m * spec.n * R["rows"]           # algorithmic: K lam and K^T y per point-row
-    tk, launches = R["tk"], R["launches"]
-    achieved = flops / tk / 1e12 if tk > 0 else 0.0
-    per_launch_ms = 1e3 * tk / max(1, launches)
+    # algorithmic flops: K lam and K^T y per point-row, 4 m n
+    fpr = 4.0 * spec.m * spec.n
     bf = w.opts["prec"] == "bf16x3"
     peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
-    ct = None if bf else counter_traffic(args.warm, ce_run, w.opts["c_tau"])
+    kern = {"k_pdhg_wide": (R["tw"], R["nw"], R["rw"]),
+            "k_pdhg": (R["tk"] - R["tw"], R["launches"] - R["nw"], R["rows"] - R["rw"])}
+    if bf:
+        kern = {"k_pdhg_stream": (R["tk"], R["launches"], R["rows"])}
+    dom = max(kern, key=lambda k: kern[k][0])
+    tk, launches, rows = kern[dom]
+    flops = fpr * rows
+    achieved = flops / tk / 1e12 if tk > 0 else 0.0
+    ct = None if bf else counter_traffic(args.warm, ce_run, w.opts["c_tau"], dom)
     traffic = None if ct is None else ct["hbm_bytes_per_launch"]
+    desc = {"k_pdhg_wide": "k_pdhg_wide (fused FP32 PDHG iterations, 64 points per workgroup)",
+            "k_pdhg": "k_pdhg (fused FP32 PDHG iterations, 16-point tiles)",
+            "k_pdhg_stream": "k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"}
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE counters, copy-calibrated)",
                 "alg_flops_per_launch": round(flops / max(1, launches), 1),
-                "kernel": ("k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"
-                           if bf else "k_pdhg (fused FP32 PDHG iterations)"),
-                "avg_launch_ms": round(per_launch_ms, 4), "launches": launches}
+                "kernel": desc[dom], "avg_launch_ms": round(1e3 * tk / max(1, launches), 4), "launches": launches,
+                "iteration_kernels": {k: {"s_per_step": round(v[0] / R["steps"], 4),
+                                          "launches_per_step": int(v[1] // R["steps"]),
+                                          "avg_launch_ms": round(1e3 * v[0] / max(1, v[1]), 4),
+                                          "tflops": round(fpr * v[2] / v[0] / 1e12, 3) if v[0] > 0 else None}
+                                      for k, v in kern.items()}}
     out = {"metric": METRIC, "value": round(R["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": R["steps"],
            "warmup": args.warmup, "ms_per_step": round(R["ms"], 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": w.opts["prec"], "data": "synthetic",

@@ -316,12 +316,19 @@ hopf_status hopf_warm_train(hopf_ctx *ctx, int sys_id, long npts, const double *
  *   tail_kernel_s    the tail solver's launches (iterations, certificates and
  *                    probe setups of the points it finished)
  *   tail_point_rows  point-rows iterated by the tail solver
- *   tail_points      points handed to it */
+ *   tail_points      points handed to it
+ *   wide_kernel_s, wide_launches, wide_point_rows
+ *                    the share of iter_kernel_s, iter_launches and
+ *                    iter_point_rows that ran on the 64-point iteration kernel
+ *                    (rounds with at least hopf_opts.wide_min active points) */
 typedef struct {
   double total_s, iter_kernel_s;
   long iter_launches;
   double iter_point_rows, alg_flops, tail_kernel_s, tail_point_rows;
   long tail_points;
+  double wide_kernel_s;
+  long wide_launches;
+  double wide_point_rows;
 } hopf_timing;
 
 hopf_status hopf_last_timing(const hopf_ctx *ctx, hopf_timing *out);

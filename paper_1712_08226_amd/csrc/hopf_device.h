@@ -57,7 +57,7 @@ struct SysView {
   double t_max, h, delta, c_tau;   // c_tau: the system's step ratio (0: the call's)
   int n_hbin;
   double dr, anorm;
-  const double *hbin, *rdig;       // probe-setup powers (see SysTables)
+  const double *hbin, *rdig, *At;  // probe-setup powers and A, stored by columns (see SysTables)
   const double *U;                 // [n][n] x = U x' for a rotated system (non-diagonal W), else null
   const float *K32, *K32T;
   const __bf16 *Kd16h, *Kd16l, *Kp16h, *Kp16l;     // BF16 hi/lo copies (dual and primal layouts)

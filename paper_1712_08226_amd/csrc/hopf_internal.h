@@ -44,8 +44,11 @@ struct SysTables {
   __bf16 *Kp16h = nullptr, *Kp16l = nullptr;   // BF16 hi/lo split, primal layout
   double *lpref_d = nullptr;   // [N+1]
   double *epow_d = nullptr;    // [POW_LEVELS][n][n]
+  // the probe-setup matrices on the device are stored by columns:
+  // element (i, k) of each n x n matrix at [k n + i]
   double *hbin_d = nullptr;    // [n_hbin][n][n]
   double *rdig_d = nullptr;    // [RDIG_LEVELS][15][n][n]
+  double *At_d = nullptr;      // [n][n]   A by columns
   double *U_d = nullptr;       // [n][n] (rotated systems only)
   double *A_d = nullptr;       // [n][n]
   double *BQ_d = nullptr;      // [n][m]   -B Qu
@@ -84,6 +87,8 @@ struct Ctx {
   double t_total = 0.0, t_iter = 0.0, point_rows = 0.0, alg_flops = 0.0;
   double t_tail = 0.0, tail_rows = 0.0;
   long iter_launches = 0, tail_points = 0;
+  double t_wide = 0.0, wide_rows = 0.0;   // the 64-point kernel's share of the iteration launches
+  long wide_launches = 0;
   // point-state buffers of each job (one job per system in a call), grown on demand
   struct Buf { void *p = nullptr; size_t bytes = 0; };
   std::vector<std::vector<Buf>> jbufs;

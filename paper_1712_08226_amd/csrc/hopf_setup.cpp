@@ -192,8 +192,8 @@ bool all_finite(const double *p, size_t k) {
 
 void free_tables(SysTables &t) {
   hipFree(t.K32); hipFree(t.K64); hipFree(t.K32T); hipFree(t.K64T); hipFree(t.lpref_d); hipFree(t.epow_d);
-  hipFree(t.hbin_d); hipFree(t.rdig_d); hipFree(t.U_d);
-  t.hbin_d = t.rdig_d = t.U_d = nullptr;
+  hipFree(t.hbin_d); hipFree(t.rdig_d); hipFree(t.At_d); hipFree(t.U_d);
+  t.hbin_d = t.rdig_d = t.At_d = t.U_d = nullptr;
   hipFree(t.Kd16h); hipFree(t.Kd16l); hipFree(t.Kp16h); hipFree(t.Kp16l);
   t.K32T = nullptr; t.K64T = nullptr;
   t.Kd16h = t.Kd16l = t.Kp16h = t.Kp16l = nullptr;
@@ -445,6 +445,16 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
   for (int i = 0; i < n; ++i) { Wd[i] = t.W[(size_t)i * n + i]; cc[i] = t.c[i]; }
   std::vector<double> mBQ(BQ);
   for (auto &v : mBQ) v = -v;
+  // the probe setup reads its matrices by columns
+  auto by_columns = [n](const std::vector<double> &src) {
+    const size_t nn = (size_t)n * n;
+    std::vector<double> dst(src.size());
+    for (size_t b = 0; b < src.size() / nn; ++b)
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) dst[b * nn + (size_t)k * n + i] = src[b * nn + (size_t)i * n + k];
+    return dst;
+  };
+  const std::vector<double> hbin_c = by_columns(t.hbin), rdig_c = by_columns(t.rdig), A_c = by_columns(t.A);
 
   free_tables(t);
   auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
@@ -461,8 +471,9 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t) {
             up((void **)&t.Kp16l, Kpl.data(), kel * sizeof(__bf16)) &&
             up((void **)&t.lpref_d, t.lpref.data(), t.lpref.size() * sizeof(double)) &&
             up((void **)&t.epow_d, t.epow.data(), t.epow.size() * sizeof(double)) &&
-            up((void **)&t.hbin_d, t.hbin.data(), t.hbin.size() * sizeof(double)) &&
-            up((void **)&t.rdig_d, t.rdig.data(), t.rdig.size() * sizeof(double)) &&
+            up((void **)&t.hbin_d, hbin_c.data(), hbin_c.size() * sizeof(double)) &&
+            up((void **)&t.rdig_d, rdig_c.data(), rdig_c.size() * sizeof(double)) &&
+            up((void **)&t.At_d, A_c.data(), A_c.size() * sizeof(double)) &&
             up((void **)&t.A_d, t.A.data(), t.A.size() * sizeof(double)) &&
             up((void **)&t.BQ_d, mBQ.data(), mBQ.size() * sizeof(double)) &&
             up((void **)&t.Wd_d, Wd.data(), Wd.size() * sizeof(double)) &&
@@ -610,6 +621,9 @@ hopf_status hopf_last_timing(const hopf_ctx *h, hopf_timing *out) {
   out->tail_kernel_s = c->t_tail;
   out->tail_point_rows = c->tail_rows;
   out->tail_points = c->tail_points;
+  out->wide_kernel_s = c->t_wide;
+  out->wide_launches = c->wide_launches;
+  out->wide_point_rows = c->wide_rows;
   return HOPF_OK;
 }
 

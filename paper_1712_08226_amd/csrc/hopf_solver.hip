@@ -57,7 +57,7 @@ __global__ void k_pack(const double *__restrict__ x, double *__restrict__ x0, lo
 // memset, so that the sequence needs no runtime memset nodes)
 __global__ void k_clear(PtState st) {
   if (threadIdx.x < 4) st.counters[threadIdx.x] = 0;
-  if (threadIdx.x < 2) st.rowsum[threadIdx.x] = 0.0;
+  if (threadIdx.x < 3) st.rowsum[threadIdx.x] = 0.0;
 }
 
 // t_in: value-mode horizons; lam0 (rows of stride ls) and tb (pairs a, b):
@@ -156,41 +156,150 @@ __global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__
 
 // ------------------------------------------------------------------ probe setup
 
-// One workgroup per point flagged for setup: nodes and weights for the new
-// horizon, x_f = e^{T A} x0 and (trapezoid, off-grid T) the private node
-// R = -Qu^T B^T e^{T A^T}, all in FP64 from the binary-power table
-// e^{2^b delta A} and a short Taylor series for the remainder, then step
-// sizes and the warm or cold start.
-constexpr int SETUP_COLS = 8;
-// sv[3][256 * SETUP_COLS] | red[256] | network activations (4 x 260 floats)
-constexpr int SETUP_SCRATCH = 3 * 256 * SETUP_COLS + 256 + 520;
+// Probe setup: the horizon split T = M h + r, x_f = e^{T A} x0 and (trapezoid,
+// off-grid T) the extra node's block R = -Qu^T B^T e^{T A^T} = K_M e^{r A^T},
+// all in FP64, then the warm or cold start and the step sizes.
+//   1. x_M = e^{M h A} x0 by the binary node powers e^{2^b h A};
+//   2. e^{r A} applied to [x_M | rows of K_M] (ncols columns, a few at a
+//      time): r = q dr + rho, the base-16 digits of q pick the powers
+//      e^{d 16^b dr A}, then a Taylor series for rho < dr with as many terms
+//      as (rho ||A||)^k / k! needs to fall below 1e-17.
+// A group of GS threads (one wave, GS = 64, or a workgroup, GS = 256) does
+// the linear algebra of one probe.  Thread l of the group owns rows l + GS g
+// of every vector; the CW vectors being transformed sit in LDS as
+// vs[i CW + c] (row i of column c), and the matrices are stored by columns,
+// so one column of a matrix is a single contiguous read of the group.
+struct SetupInfo {
+  int M, rows, part;
+  double r, Rfro;
+};
 
-// a[0..n) . b[0, stride, 2 stride, ...): four partial sums so that the loads
-// of consecutive terms are in flight together
-__device__ __forceinline__ double dot_strided(const double *__restrict__ a, const double *__restrict__ b,
-                                              int stride, int n) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int l = 0;
-#pragma unroll 2
-  for (; l + 3 < n; l += 4) {
-    s0 += a[l] * b[l * stride];
-    s1 += a[l + 1] * b[(l + 1) * stride];
-    s2 += a[l + 2] * b[(l + 2) * stride];
-    s3 += a[l + 3] * b[(l + 3) * stride];
+// columns per pass of step 2: a wave keeps 6 (3 for n > 128) in registers,
+// a workgroup 4
+template <int GS, int RG>
+__host__ __device__ constexpr int setup_cw() { return GS == 64 ? (RG <= 2 ? 6 : 3) : 4; }
+
+// Make the group's LDS writes visible to all of its threads before later reads.
+template <int GS>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (GS == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
   }
-  for (; l < n; ++l) s0 += a[l] * b[l * stride];
-  return (s0 + s1) + (s2 + s3);
 }
 
-// sm: LDS scratch of SETUP_SCRATCH doubles (the caller's; free during the call)
-__device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, double *sm) {
-  double (*sv)[256 * SETUP_COLS] = reinterpret_cast<double (*)[256 * SETUP_COLS]>(sm);
-  double *red = sm + 3 * 256 * SETUP_COLS;
-  __syncthreads();
-  const int tid = threadIdx.x;
+// acc[c][g] = sum_k E(l + GS g, k) vs[k CW + c], c < CC, for an n x n matrix
+// E stored by columns (E(i, k) at Ec[k n + i]).  U columns of E are loaded
+// before their products, so that many loads are in flight together.
+template <int GS, int RG, int CC, int CW>
+__device__ __forceinline__ void group_apply(const double *__restrict__ Ec, const double *vs, int n, int l,
+                                            double (&acc)[CC][RG]) {
+  constexpr int U = CC == 1 ? 8 : 2;
+#pragma unroll
+  for (int c = 0; c < CC; ++c)
+#pragma unroll
+    for (int g = 0; g < RG; ++g) acc[c][g] = 0.0;
+  int k = 0;
+  for (; k + U <= n; k += U) {
+    double e[U][RG];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        const int i = l + GS * g;
+        e[u][g] = (i < n) ? Ec[(size_t)(k + u) * n + i] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        const double v = vs[(k + u) * CW + c];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) acc[c][g] = fma(e[u][g], v, acc[c][g]);
+      }
+  }
+  for (; k < n; ++k) {
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int i = l + GS * g;
+      const double e = (i < n) ? Ec[(size_t)k * n + i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < CC; ++c) acc[c][g] = fma(e, vs[k * CW + c], acc[c][g]);
+    }
+  }
+}
+
+// vs <- E vs on the first CC columns
+template <int GS, int RG, int CC, int CW>
+__device__ __forceinline__ void group_transform(const double *__restrict__ Ec, double *vs, int n, int l) {
+  double acc[CC][RG];
+  group_apply<GS, RG, CC, CW>(Ec, vs, n, l, acc);
+  group_sync<GS>();   // every thread has read vs
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int i = l + GS * g;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) vs[i * CW + c] = acc[c][g];
+  }
+  group_sync<GS>();
+}
+
+// vs <- e^{rho A} vs = sum_{k <= kt} (rho A)^k vs / k! on the first CC columns
+// (the running term stays in vs, the sum in registers)
+template <int GS, int RG, int CC, int CW>
+__device__ __forceinline__ void group_taylor(const double *__restrict__ At, double *vs, int n, int l, double rho,
+                                             int kt) {
+  double sum[CC][RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int i = l + GS * g;
+#pragma unroll
+    for (int c = 0; c < CC; ++c) sum[c][g] = (i < n) ? vs[i * CW + c] : 0.0;
+  }
+  for (int k = 1; k <= kt; ++k) {
+    double acc[CC][RG];
+    group_apply<GS, RG, CC, CW>(At, vs, n, l, acc);
+    group_sync<GS>();
+    const double f = rho / k;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int i = l + GS * g;
+      if (i < n)
+#pragma unroll
+        for (int c = 0; c < CC; ++c) {
+          const double t = acc[c][g] * f;
+          vs[i * CW + c] = t;
+          sum[c][g] += t;
+        }
+    }
+    group_sync<GS>();
+  }
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int i = l + GS * g;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) vs[i * CW + c] = sum[c][g];
+  }
+  group_sync<GS>();
+}
+
+// The linear algebra of the setup of point p by a group of GS threads
+// (l: the thread's index in it, every thread of the group calls this):
+// horizon split, x_f, A x_f and (off-grid trapezoid) the extra node's block
+// and its Frobenius norm.  vs: n_pad setup_cw<GS, RG>() doubles of LDS;
+// red: GS / 64 doubles of LDS for the norm (GS > 64).  Needs RG GS >= n.
+template <int GS, int RG>
+__device__ SetupInfo setup_linear(const SysView &S, const PtState &st, long p, int l, double *vs, double *red) {
+  constexpr int CW = setup_cw<GS, RG>();
   const int n = S.n, m = S.m, np = S.n_pad;
   const double T = st.T[p];
-  // horizon split T = M h + r (snap to the grid within 1e-12 relative)
+  SetupInfo in;
+  // horizon split T = M h + r (snapped to the grid within 1e-12 relative)
   const double q = T / S.h;
   const double qr = rint(q);
   int M;
@@ -208,13 +317,6 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     if (rows > S.N) rows = S.N;
     part = 0;
   }
-  // x_f = e^{T A} x0 and (trapezoid, r > 0) the extra node's block
-  // R = -Qu^T B^T e^{T A^T} = K_M e^{r A^T}, for T = M h + r:
-  //   1. x_M = e^{M h A} x0 by the binary node powers (one column);
-  //   2. e^{r A} applied to [x_M | rows of K_M] (columns of one LDS block):
-  //      r = q dr + rho, the base-16 digits of q pick powers e^{d 16^b dr A},
-  //      then a Taylor series for rho < dr with as many terms as
-  //      (rho ||A||)^k / k! needs to fall below 1e-17.
   const int ncols = 1 + (part ? m : 0);
   const long qd = (r > 0.0) ? (long)floor(r / S.dr) : 0;
   const long qdig = qd > 4095 ? 4095 : (qd < 0 ? 0 : qd);
@@ -229,109 +331,104 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       if (term < 1e-17) break;
     }
   }
-  double Rfro = 0.0;
-  int cur = 0;
-  // 1. x_M into column 0 of sv[cur]
-  for (int i = tid; i < n; i += 256) sv[0][i * SETUP_COLS] = st.x0[p * np + i];
-  __syncthreads();
-  for (int b = 0; b < S.n_hbin; ++b) {
-    if (!((M >> b) & 1)) continue;
-    const double *E = S.hbin + (size_t)b * n * n;
-    const int nxt = cur ^ 1;
-    for (int i = tid; i < n; i += 256) sv[nxt][i * SETUP_COLS] = dot_strided(E + (size_t)i * n, &sv[cur][0], SETUP_COLS, n);
-    __syncthreads();
-    cur = nxt;
-  }
+  // 1. x_M in column 0
+  for (int i = l; i < n; i += GS) vs[i * CW] = st.x0[p * np + i];
+  group_sync<GS>();
+  for (int b = 0; b < S.n_hbin; ++b)
+    if ((M >> b) & 1) group_transform<GS, RG, 1, CW>(S.hbin + (size_t)b * n * n, vs, n, l);
+  // 2. e^{r A} on [x_M | K_M rows], CW columns at a time
   const int kb_M = M / NODE_BLOCK, kk_M = M % NODE_BLOCK;
-  for (int c0 = 0; c0 < ncols; c0 += SETUP_COLS) {
-    const int cc = min(SETUP_COLS, ncols - c0);
-    // columns: x_M (first block, already in place), then rows j of K_M
-    for (int e = tid; e < n * cc; e += 256) {
-      const int i = e / cc, cl = e % cc, col = c0 + cl;
-      if (col > 0)
-        sv[cur][i * SETUP_COLS + cl] = S.K64[(((size_t)kb_M * m + (col - 1)) * NODE_BLOCK + kk_M) * np + i];
+  double Rfro = 0.0;
+  for (int c0 = 0; c0 < ncols; c0 += CW) {
+    const int cc = min(CW, ncols - c0);
+    if (ncols > 1) {
+      // columns c0 + cl: x_M (already in place), then rows j = col - 1 of
+      // K_M; columns past ncols are zero
+      for (int cl = (c0 == 0 ? 1 : 0); cl < CW; ++cl) {
+        const int col = c0 + cl;
+        for (int i = l; i < n; i += GS)
+          vs[i * CW + cl] =
+              col < ncols ? S.K64[(((size_t)kb_M * m + (col - 1)) * NODE_BLOCK + kk_M) * np + i] : 0.0;
+      }
+      group_sync<GS>();
     }
-    __syncthreads();
     for (int lv = 0; lv < RDIG_LEVELS; ++lv) {
       const int d = (int)((qdig >> (4 * lv)) & 15);
       if (!d) continue;
       const double *E = S.rdig + ((size_t)lv * 15 + (d - 1)) * n * n;
-      const int nxt = cur ^ 1;
-      for (int e = tid; e < n * cc; e += 256) {
-        const int i = e / cc, cl = e % cc;
-        sv[nxt][i * SETUP_COLS + cl] = dot_strided(E + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
-      }
-      __syncthreads();
-      cur = nxt;
+      if (ncols == 1) group_transform<GS, RG, 1, CW>(E, vs, n, l);
+      else group_transform<GS, RG, CW, CW>(E, vs, n, l);
     }
-    if (kt > 0) {   // e^{rho A} v = v + sum_k (rho A)^k v / k!
-      const int tv = 2;   // sv[2] holds the running term
-      for (int e = tid; e < n * cc; e += 256) sv[tv][(e / cc) * SETUP_COLS + e % cc] = sv[cur][(e / cc) * SETUP_COLS + e % cc];
-      __syncthreads();
-      const int other = cur ^ 1;
-      for (int k = 1; k <= kt; ++k) {
-        for (int e = tid; e < n * cc; e += 256) {
-          const int i = e / cc, cl = e % cc;
-          const double acc = dot_strided(S.A + (size_t)i * n, &sv[tv][cl], SETUP_COLS, n);
-          sv[other][i * SETUP_COLS + cl] = acc * (rho / k);
+    if (kt > 0) {
+      if (ncols == 1) group_taylor<GS, RG, 1, CW>(S.At, vs, n, l, rho, kt);
+      else group_taylor<GS, RG, CW, CW>(S.At, vs, n, l, rho, kt);
+    }
+    // store: column 0 is x_f (with A x_f), the others rows of R
+    for (int cl = 0; cl < cc; ++cl) {
+      const int col = c0 + cl;
+      for (int i = l; i < np; i += GS) {
+        const double v = i < n ? vs[i * CW + cl] : 0.0;
+        if (col == 0) {
+          st.xf[p * np + i] = v;
+          st.xfc32[p * np + i] = (float)(i < n ? v - S.c[i] : 0.0);
+        } else {
+          const size_t o2 = ((size_t)p * m + (col - 1)) * np + i;
+          st.R64[o2] = v;
+          st.R32[o2] = (float)v;
+          Rfro += v * v;
         }
-        __syncthreads();
-        for (int e = tid; e < n * cc; e += 256) {
-          const int i = e / cc, cl = e % cc;
-          sv[tv][i * SETUP_COLS + cl] = sv[other][i * SETUP_COLS + cl];
-          sv[cur][i * SETUP_COLS + cl] += sv[other][i * SETUP_COLS + cl];
-        }
-        __syncthreads();
       }
     }
-    // store
-    for (int e = tid; e < np * cc; e += 256) {
-      const int i = e / cc, cl = e % cc, col = c0 + cl;
-      const double v = i < n ? sv[cur][i * SETUP_COLS + cl] : 0.0;
-      if (col == 0) {
-        st.xf[p * np + i] = v;
-        st.xfc32[p * np + i] = (float)(i < n ? v - S.c[i] : 0.0);
-        double ax = 0.0;   // (A x_f)_i
-        if (i < n)
-          ax = dot_strided(S.A + (size_t)i * n, &sv[cur][cl], SETUP_COLS, n);
-        st.axf[p * np + i] = ax;
-      } else {
-        const size_t o2 = ((size_t)p * m + (col - 1)) * np + i;
-        st.R64[o2] = v;
-        st.R32[o2] = (float)v;
+    if (c0 == 0) {
+      double ax[1][RG];
+      group_apply<GS, RG, 1, CW>(S.At, vs, n, l, ax);
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        const int i = l + GS * g;
+        if (i < np) st.axf[p * np + i] = i < n ? ax[0][g] : 0.0;
       }
     }
-    // Frobenius norm of R (for the step-size bound)
-    double loc = 0.0;
-    for (int e = tid; e < n * cc; e += 256) {
-      const int i = e / cc, cl = e % cc, col = c0 + cl;
-      if (col > 0) { const double v = sv[cur][i * SETUP_COLS + cl]; loc += v * v; }
-    }
-    red[tid] = loc;
+    group_sync<GS>();   // every thread is done reading vs before the next columns land
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) Rfro += __shfl_xor(Rfro, off, 64);
+  if constexpr (GS > 64) {
+    if ((l & 63) == 0) red[l >> 6] = Rfro;
     __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
-      if (tid < s2) red[tid] += red[tid + s2];
-      __syncthreads();
-    }
-    Rfro += red[0];
+    Rfro = 0.0;
+    for (int w = 0; w < GS / 64; ++w) Rfro += red[w];
     __syncthreads();
   }
-  // cold or warm start
+  in.M = M;
+  in.rows = rows;
+  in.part = part;
+  in.r = r;
+  in.Rfro = Rfro;
+  return in;
+}
+
+// Cold or continued start of point p's new probe by a group of GS threads
+// (l: the thread's index in it): lambda from 0 (or the caller's lam0 at the
+// first probe) or carried over, dual rows carried over where both probes
+// have them, every other row at zero.
+template <int GS>
+__device__ void setup_start(const PtState &st, const Opts &o, long p, int m, int np, int rows, int l) {
   const int old_rows = st.rows[p];
-  const bool cold = (o.warm == HOPF_WARM_COLD) || (st.probes[p] == 0);   // CONT and MLP keep y
+  const bool first = st.probes[p] == 0;
+  const bool cold = (o.warm == HOPF_WARM_COLD) || first;   // CONT and MLP keep y
   // FP64 iterations keep their own FP64 iterate (carried over when it is current)
   const bool f64 = st.s64 != nullptr;
   const bool had64 = f64 && st.s64[p] != 0;
-  if (cold) {   // lam = 0, or the caller's lam0 at the first probe
-    const bool given = st.lam0s != nullptr && st.probes[p] == 0;
-    for (int i = tid; i < np; i += 256) {
+  if (cold) {
+    const bool given = st.lam0s != nullptr && first;
+    for (int i = l; i < np; i += GS) {
       const double l = given ? st.lam0s[p * np + i] : 0.0;
       st.lam[p * np + i] = (float)l;
       st.lamb[p * np + i] = (float)l;
       if (f64) { st.lam64[p * np + i] = l; st.lamb64[p * np + i] = l; }
     }
   } else {
-    for (int i = tid; i < np; i += 256) {
+    for (int i = l; i < np; i += GS) {
       st.lamb[p * np + i] = st.lam[p * np + i];
       if (f64) {
         const double l = had64 ? st.lam64[p * np + i] : (double)st.lam[p * np + i];
@@ -340,27 +437,80 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
       }
     }
   }
-  // The kernels read the node blocks of the tile's longest point, so every
-  // row of the point's dual iterate must hold a finite value: rows this probe
-  // does not carry over from the previous one (all rows for a cold start,
-  // rows beyond either probe's node count otherwise) start at zero.
+  // The iteration kernels read the node blocks of a tile's longest point, so
+  // every row of a point's dual iterate holds a finite value.  Rows at or
+  // past the point's node count are zero after every setup and every
+  // iteration (outside the horizon a node's weight is 0 and its dual projects
+  // to 0), so only rows [keep, old_rows) can hold values to clear; the first
+  // probe clears every row.
   const int keep = cold ? 0 : min(old_rows, rows);
-  for (int e = tid; e < st.ystride; e += 256) {
-    const int kb = e / (m * NODE_BLOCK), kk = e % NODE_BLOCK;
-    const size_t ye = (size_t)p * st.ystride + e;
-    const bool zero = kb * NODE_BLOCK + kk >= keep;
-    if (zero) st.y[ye] = 0.0f;
-    if (f64) st.y64[ye] = zero ? 0.0 : (had64 ? st.y64[ye] : (double)st.y[ye]);
+  const int m16 = m * NODE_BLOCK;
+  if (f64) {
+    for (int e = l; e < st.ystride; e += GS) {
+      const int kb = e / m16, kk = e % NODE_BLOCK;
+      const size_t ye = (size_t)p * st.ystride + e;
+      const bool zero = kb * NODE_BLOCK + kk >= keep;
+      if (zero) st.y[ye] = 0.0f;
+      st.y64[ye] = zero ? 0.0 : (had64 ? st.y64[ye] : (double)st.y[ye]);
+    }
+  } else {
+    const int end = first ? st.ystride / m : max(keep, old_rows);
+    const int e0 = (keep / NODE_BLOCK) * m16, e1 = ((end + NODE_BLOCK - 1) / NODE_BLOCK) * m16;
+    for (int e = e0 + l; e < e1; e += GS) {
+      const int kb = e / m16, kk = e % NODE_BLOCK;
+      if (kb * NODE_BLOCK + kk >= keep) st.y[(size_t)p * st.ystride + e] = 0.0f;
+    }
   }
-  for (int j = tid; j < st.mpad; j += 256) {
+  for (int j = l; j < st.mpad; j += GS) {
     st.yR[(size_t)p * st.mpad + j] = 0.0f;
     if (f64) st.yR64[(size_t)p * st.mpad + j] = 0.0;
   }
+}
+
+// Per-point fields of the new probe and its step sizes (one thread).
+__device__ void setup_finish(const SysView &S, const PtState &st, const Opts &o, long p, const SetupInfo &in) {
+  const double L2 = S.lpref[in.rows] + (in.part ? in.Rfro : 0.0);
+  const double L = sqrt(L2);
+  st.M[p] = in.M;
+  st.r[p] = in.r;
+  st.rows[p] = in.rows;
+  st.partial[p] = in.part;
+  if (L > 0.0) {
+    const double ct = S.c_tau > 0.0 ? S.c_tau : o.c_tau;
+    st.tau[p] = ct / L;
+    st.sig[p] = 0.999 / (ct * L);
+  } else {   // no quadrature nodes: the prox of G alone is exact in one step
+    st.tau[p] = 1e20;
+    st.sig[p] = 0.0;
+  }
+  st.iters_probe[p] = 0;
+  st.probes[p] += 1;
+  st.flags[p] = 0;
+  if (st.s64 != nullptr) st.s64[p] = 1;
+}
+
+// Block scratch of setup_point (doubles): the vectors | norm partial sums |
+// network activations (4 x 260 floats)
+constexpr int SETUP_VS = 256 * setup_cw<256, 1>();
+constexpr int SETUP_SCRATCH = SETUP_VS + 8 + 520;
+
+// The setup of point p by a workgroup of 256 threads (one row per thread),
+// with the learned warm start.  sm: SETUP_SCRATCH doubles of LDS (the
+// caller's; free during the call).
+__device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, double *sm) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int n = S.n, np = S.n_pad;
+  const SetupInfo info = setup_linear<256, 1>(S, st, p, tid, sm, sm + SETUP_VS);
+  setup_start<256>(st, o, p, S.m, np, info.rows, tid);
+  __syncthreads();
+  const double T = st.T[p];
+  const bool f64 = st.s64 != nullptr;
   // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
   const bool net_first = o.warm == HOPF_WARM_MLP_FIRST && st.probes[p] == 0;
   if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM || net_first) && mv.valid && mv.n == n &&
       mv.H == 256) {
-    float *zin = reinterpret_cast<float *>(red + 256), *ha = zin + 260, *hb = ha + 260, *outv = hb + 260;
+    float *zin = reinterpret_cast<float *>(sm + SETUP_VS + 8), *ha = zin + 260, *hb = ha + 260, *outv = hb + 260;
     const int di = n + 1, dout = n + 2, H = 256;
     __syncthreads();
     for (int i = tid; i < di; i += 256)
@@ -425,28 +575,35 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    double L2 = S.lpref[rows] + (part ? Rfro : 0.0);
-    const double L = sqrt(L2);
-    st.M[p] = M;
-    st.r[p] = r;
-    st.rows[p] = rows;
-    st.partial[p] = part;
-    if (L > 0.0) {
-      const double ct = S.c_tau > 0.0 ? S.c_tau : o.c_tau;
-      st.tau[p] = ct / L;
-      st.sig[p] = 0.999 / (ct * L);
-    } else {          // no quadrature nodes: the prox of G alone is exact in one step
-      st.tau[p] = 1e20;
-      st.sig[p] = 0.0;
-    }
-    st.iters_probe[p] = 0;
-    st.probes[p] += 1;
-    st.flags[p] = 0;
-    if (f64) st.s64[p] = 1;
+  if (tid == 0) setup_finish(S, st, o, p, info);
+}
+
+// Probe setups without the network: one wave per point on the setup list,
+// RG 64 >= n.  Dynamic LDS: 4 n_pad setup_cw<64, RG>() doubles.
+template <int RG>
+__global__ __launch_bounds__(256) void k_setup_waves(SysView S, PtState st, Opts o) {
+  extern __shared__ __align__(16) double sw[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *vs = sw + (size_t)wave * S.n_pad * setup_cw<64, RG>();
+  const int nset = st.counters[1];
+  for (int li = blockIdx.x * 4 + wave; li < nset; li += gridDim.x * 4) {
+    const long p = st.setup_list[li];
+    const SetupInfo in = setup_linear<64, RG>(S, st, p, lane, vs, nullptr);
+    setup_start<64>(st, o, p, S.m, S.n_pad, in.rows, lane);
+    if (lane == 0) setup_finish(S, st, o, p, in);
+    group_sync<64>();
   }
 }
 
+typedef void (*SetupWavesFn)(SysView, PtState, Opts);
+SetupWavesFn setup_waves_for(int n) {
+  if (n <= 64) return k_setup_waves<1>;
+  if (n <= 128) return k_setup_waves<2>;
+  if (n <= 192) return k_setup_waves<3>;
+  return k_setup_waves<4>;
+}
+
+// Probe setups with the learned warm start: one workgroup per point.
 __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, MlpView mv) {
   __shared__ double sm[SETUP_SCRATCH];
   const int nset = st.counters[1];
@@ -897,7 +1054,8 @@ __global__ __launch_bounds__(256) void k_tail_multi(const TailJob *__restrict__ 
 // (FP32-escalated first) and by rows (descending) so that a tile's points
 // need similar table prefixes.  reset_setup: the setup list was consumed by
 // the k_setup launch before this one; count_rows: add the active point-rows
-// to the flop accounting (the iteration launch after this sort runs them).
+// to the flop accounting (the iteration launch after this sort runs them:
+// 1 on the 16-point tiles, 2 on the 64-point kernel).
 __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int reset_setup, int count_rows) {
   __shared__ int hist[2 * 4097 + 2];
   __shared__ double rsum[1024];
@@ -930,7 +1088,7 @@ __global__ __launch_bounds__(1024) void k_sort(PtState st, int N, int reset_setu
     }
     st.counters[0] = acc;
     st.counters[3] = nesc;
-    if (count_rows) st.rowsum[0] += rsum[0];
+    if (count_rows) st.rowsum[count_rows == 2 ? 2 : 0] += rsum[0];
   }
   __syncthreads();
   for (long p = tid; p < st.npts; p += 1024) {
@@ -1210,7 +1368,7 @@ bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool 
   st.bT = al.template get<float>(npts);
   st.bD = al.template get<float>(npts);
   st.counters = al.template get<int>(4);
-  st.rowsum = al.template get<double>(2);   // [0] tiled rounds, [1] tail solver
+  st.rowsum = al.template get<double>(3);   // [0] 16-point rounds, [1] tail solver, [2] 64-point rounds
   st.lam0s = nullptr;
   if (with_lam0 && !(st.lam0s = al.template get<double>(npts * np))) return false;
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
@@ -1241,7 +1399,7 @@ SysView view(const SysTables &t) {
   v.Kd16h = t.Kd16h; v.Kd16l = t.Kd16l; v.Kp16h = t.Kp16h; v.Kp16l = t.Kp16l; v.lpref = t.lpref_d; v.epow = t.epow_d;
   v.A = t.A_d; v.BQ = t.BQ_d; v.Wd = t.Wd_d; v.c = t.c_d;
   v.Eh = t.Eh_d; v.Qu = t.Qu_d; v.m_user = t.m_user;
-  v.n_hbin = t.n_hbin; v.dr = t.dr; v.anorm = t.anorm; v.hbin = t.hbin_d; v.rdig = t.rdig_d;
+  v.n_hbin = t.n_hbin; v.dr = t.dr; v.anorm = t.anorm; v.hbin = t.hbin_d; v.rdig = t.rdig_d; v.At = t.At_d;
   v.U = t.rotated ? t.U_d : nullptr;
   return v;
 }
@@ -1263,8 +1421,9 @@ struct Job {
   SysView S{};
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
   pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
+  SetupWavesFn fs = nullptr;     // probe setups without the network
   cert_fn fc = nullptr;
-  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0;
+  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0, lds_setup = 0;
   long last_active = 0;          // active points at the last check read (picks the iteration kernel)
   PtState st{};
   long npts = 0;
@@ -1278,6 +1437,7 @@ struct Job {
   bool done = false;
   MlpView mv{};
   std::vector<hipEvent_t> kev;
+  std::vector<char> kwide;   // per timed round: the 64-point kernel ran it
   bool tail_ok = false;          // FP32 iterations: the tail solver may take over
   bool parked = false;           // waiting for the combined tail launch
   hipEvent_t park_ev = nullptr;
@@ -1339,7 +1499,21 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   }
   HIPCHK(hipFuncSetAttribute((const void *)J.fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_pdhg));
   HIPCHK(hipFuncSetAttribute((const void *)J.fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_cert));
+  J.fs = setup_waves_for(tab.n);
+  J.lds_setup = (size_t)4 * tab.n_pad * (tab.n <= 128 ? setup_cw<64, 1>() : setup_cw<64, 3>()) * sizeof(double);
+  HIPCHK(hipFuncSetAttribute((const void *)J.fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_setup));
   return HOPF_OK;
+}
+
+// Probe setups of the points on the setup list: one wave per point, or one
+// workgroup per point when a network gives the warm start.
+void launch_setup(const Job &J, const Opts &o) {
+  const bool net = J.mv.valid && (o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM ||
+                                  o.warm == HOPF_WARM_MLP_FIRST);
+  if (net)
+    k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, J.s>>>(J.S, J.st, o, J.mv);
+  else
+    J.fs<<<(unsigned)std::min<long>((J.npts + 3) / 4, 4096), 256, J.lds_setup, J.s>>>(J.S, J.st, o);
 }
 
 // Timing events come from a pool the context keeps (created on first use,
@@ -1363,10 +1537,11 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
   const hopf_opts &ho = ctx->opts;
   const hipStream_t s = J.s;
   for (int r = 0; r < GROUP_ROUNDS && J.rounds < J.max_rounds; ++r) {
-    k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
+    launch_setup(J, o);
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
     J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
-    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0, 1);
+    const bool wide = J.fw && J.last_active >= ho.wide_min;
+    k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0, wide ? 2 : 1);
     hipEvent_t a = nullptr, b = nullptr;
     if (J.timed) {
       a = take_event(ctx);
@@ -1375,7 +1550,7 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
       HIPCHK(hipEventRecord(a, s));
     }
     if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
-    if (J.fw && J.last_active >= ho.wide_min) {
+    if (wide) {
       const unsigned wgrid = (unsigned)((J.npts + WIDE_PTS - 1) / WIDE_PTS);
       J.fw<<<wgrid, THREADS, J.lds_wide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
     } else {
@@ -1385,6 +1560,7 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
       HIPCHK(hipEventRecord(b, s));
       J.kev.push_back(a);
       J.kev.push_back(b);
+      J.kwide.push_back(wide ? 1 : 0);
     }
     ctx->iter_launches++;
     ++J.rounds;
@@ -1402,7 +1578,7 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
 // (at most `count`) active points; the combined tail launch picks them up.
 hopf_status park_job(Ctx *ctx, Job &J, const Opts &o, long count) {
   const hipStream_t s = J.s;
-  k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, s>>>(J.S, J.st, o, J.mv);
+  launch_setup(J, o);
   k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
   if (J.timed) {
     J.park_ev = take_event(ctx);
@@ -1642,7 +1818,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     if (hipGetLastError() != hipSuccess) rc = set_err(ctx, HOPF_EDEVICE, "kernel launch failed");
   }
   bool hit_limit = false;
-  double it_s = 0.0, rows_tot = 0.0, flops = 0.0, tail_rows = 0.0;
+  double it_s = 0.0, rows_tot = 0.0, flops = 0.0, tail_rows = 0.0, wide_s = 0.0, wide_rows = 0.0;
+  long wide_n = 0;
   for (int j = 0; j < nj; ++j) {
     Job &J = jobs[j];
     if (rc == HOPF_OK && J.st.x0) {
@@ -1665,15 +1842,20 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       float km = 0.f;
       if (rc == HOPF_OK) hipEventElapsedTime(&km, J.kev[i], J.kev[i + 1]);
       it_s += km * 1e-3;
+      if (J.kwide[i / 2]) {
+        wide_s += km * 1e-3;
+        ++wide_n;
+      }
     }
     if (rc == HOPF_OK && J.st.rowsum) {
-      double rs[2] = {0.0, 0.0};
-      hipMemcpy(rs, J.st.rowsum, 2 * sizeof(double), hipMemcpyDeviceToHost);
+      double rs[3] = {0.0, 0.0, 0.0};
+      hipMemcpy(rs, J.st.rowsum, 3 * sizeof(double), hipMemcpyDeviceToHost);
       // point-rows are summed once per round (per interval in the tail
       // solver); each runs check_every iterations
-      rows_tot += rs[0] * ho.check_every;
+      rows_tot += (rs[0] + rs[2]) * ho.check_every;
+      wide_rows += rs[2] * ho.check_every;
       tail_rows += rs[1] * ho.check_every;
-      flops += 4.0 * J.tab->m_user * J.tab->n * (rs[0] + rs[1]) * ho.check_every;
+      flops += 4.0 * J.tab->m_user * J.tab->n * (rs[0] + rs[1] + rs[2]) * ho.check_every;
     }
     if (rc == HOPF_OK && ctx->log_pt && j == 0) {
       int lc = 0;
@@ -1690,6 +1872,9 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   ctx->t_tail = tail_s;
   ctx->tail_rows = tail_rows;
   ctx->tail_points = tail_pts;
+  ctx->t_wide = wide_s;
+  ctx->wide_rows = wide_rows;
+  ctx->wide_launches = wide_n;
   if (nj > 1)
     for (auto ps : ctx->pool) hipStreamSynchronize(ps);   // nothing of this call may outlive it
   if (rc == HOPF_OK && hit_limit) ctx->err = "round limit reached; unfinished points report NOCONV";
@@ -1801,7 +1986,8 @@ hopf_status solve_noalloc(Ctx *ctx, int sid, long npts, const double *x, const d
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   ctx->t_total = ctx->t_iter = ctx->point_rows = ctx->alg_flops = ctx->t_tail = ctx->tail_rows = 0.0;
-  ctx->tail_points = 0;
+  ctx->t_wide = ctx->wide_rows = 0.0;
+  ctx->tail_points = ctx->wide_launches = 0;
   if (J.rounds >= J.max_rounds) ctx->err = "round limit reached; unfinished points report NOCONV";
   return HOPF_OK;
 }

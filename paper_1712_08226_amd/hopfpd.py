@@ -48,7 +48,8 @@ class HopfOpts(C.Structure):
 class HopfTiming(C.Structure):
     _fields_ = [("total_s", C.c_double), ("iter_kernel_s", C.c_double), ("iter_launches", C.c_long),
                 ("iter_point_rows", C.c_double), ("alg_flops", C.c_double), ("tail_kernel_s", C.c_double),
-                ("tail_point_rows", C.c_double), ("tail_points", C.c_long)]
+                ("tail_point_rows", C.c_double), ("tail_points", C.c_long), ("wide_kernel_s", C.c_double),
+                ("wide_launches", C.c_long), ("wide_point_rows", C.c_double)]
 
 
 class HopfError(RuntimeError):
@@ -397,4 +398,5 @@ class Solver:
         self._check(self.lib.hopf_last_timing(self.h, C.byref(t)), "hopf_last_timing")
         return dict(total_s=t.total_s, iter_kernel_s=t.iter_kernel_s, iter_launches=t.iter_launches,
                     point_rows=t.iter_point_rows, alg_flops=t.alg_flops, tail_kernel_s=t.tail_kernel_s,
-                    tail_point_rows=t.tail_point_rows, tail_points=t.tail_points)
+                    tail_point_rows=t.tail_point_rows, tail_points=t.tail_points, wide_kernel_s=t.wide_kernel_s,
+                    wide_launches=t.wide_launches, wide_point_rows=t.wide_point_rows)

@@ -16,19 +16,22 @@ def test_counter_traffic_matches_only_the_profiled_run(tmp_path, monkeypatch):
     src = tmp_path / "kernel.h"
     src.write_text("// kernel source\n")
     sha = hashlib.sha256(src.read_bytes()).hexdigest()
-    recs = [dict(variant="mlp_first", check_every=75, c_tau=2.0, hbm_bytes_per_launch=10, kernel_source_sha256=sha),
-            dict(variant="cont", check_every=75, c_tau=2.0, hbm_bytes_per_launch=20, kernel_source_sha256="0" * 64)]
+    recs = [dict(kernel="k_pdhg_wide", variant="cont", check_every=75, c_tau=2.0, hbm_bytes_per_launch=10,
+                 kernel_source_sha256=sha),
+            dict(kernel="k_pdhg_wide", variant="mlp", check_every=75, c_tau=2.0, hbm_bytes_per_launch=20,
+                 kernel_source_sha256="0" * 64)]
     prof = tmp_path / "prof.md"
     prof.write_text("# summary\n\n" + "".join("traffic:" + json.dumps(r) + "\n" for r in recs))
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
     monkeypatch.setattr(bench, "COUNTERS", str(prof))
-    assert bench.counter_traffic("mlp_first", 75, 2.0)["hbm_bytes_per_launch"] == 10
-    assert bench.counter_traffic("mlp_first", 50, 2.0) is None       # other launch length
-    assert bench.counter_traffic("mlp_first", 75, 5.0) is None       # other step ratio
-    assert bench.counter_traffic("cont", 75, 2.0) is None            # kernel changed since
-    assert bench.counter_traffic("mlp+newton", 75, 2.0) is None      # not profiled
+    assert bench.counter_traffic("cont", 75, 2.0, "k_pdhg_wide")["hbm_bytes_per_launch"] == 10
+    assert bench.counter_traffic("cont", 75, 2.0, "k_pdhg") is None          # other kernel
+    assert bench.counter_traffic("cont", 50, 2.0, "k_pdhg_wide") is None     # other launch length
+    assert bench.counter_traffic("cont", 75, 5.0, "k_pdhg_wide") is None     # other step ratio
+    assert bench.counter_traffic("mlp", 75, 2.0, "k_pdhg_wide") is None      # kernel changed since
+    assert bench.counter_traffic("cold", 75, 2.0, "k_pdhg_wide") is None     # not profiled
     src.write_text("// edited kernel\n")
-    assert bench.counter_traffic("mlp_first", 75, 2.0) is None
+    assert bench.counter_traffic("cont", 75, 2.0, "k_pdhg_wide") is None
 
 
 def test_committed_traffic_records_are_for_the_headline_settings():
