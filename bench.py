@@ -161,6 +161,8 @@ def main():
                     help="points per system at which the per-point tail solver takes over (0: never)")
     ap.add_argument("--wide-min", type=int, default=None,
                     help="active points from which the 64-point LDS-staged kernel runs the iterations (0: never)")
+    ap.add_argument("--deep-max", type=int, default=None,
+                    help="active points up to which 16-point tiles run on 8 waves (-1: 16 per compute unit, 0: never)")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
                     help="iteration precision (default: the workload's, fp32)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -256,6 +258,8 @@ def bench_c5(args):
         extra = {} if args.tail_max is None else {"tail_max": args.tail_max}
         if args.wide_min is not None:
             extra["wide_min"] = args.wide_min
+        if args.deep_max is not None:
+            extra["deep_max"] = args.deep_max
         solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm=wmode, root=root, check_every=ce_run,
                         **extra)
 
@@ -365,6 +369,7 @@ def bench_c5(args):
                                   f"(value: warm start '{args.warm}'; plain: cold start at every probe)",
                       "npts": npts, "warm": args.warm, "scan": default_opts().scan,
                       "wide_min": args.wide_min if args.wide_min is not None else default_opts().wide_min,
+                      "deep_max": args.deep_max if args.deep_max is not None else default_opts().deep_max,
                       "tail_max": args.tail_max if args.tail_max is not None else default_opts().tail_max,
                       "check_every": ce_run, "c_tau": w.opts["c_tau"], "gap_tol": 1e-6, "certificate": "fp64"},
            "results": head, "plain": plain, "literal": literal, "warm_start_training": train_info,

@@ -146,6 +146,10 @@ typedef struct {
  *   wide_min      FP32 iterations run on 64-point workgroups that share one LDS copy
  *                 of each node block of the table while at least wide_min of a
  *                 system's points are active (then on 16-point tiles); 0: never  [16384]
+ *   deep_max      FP32 16-point tiles: while at most deep_max of a system's points
+ *                 are active, each tile's node blocks are spread over 8 waves
+ *                 instead of 4; -1: 16 points per compute unit of the device,
+ *                 0: never                                                           [-1]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
@@ -167,6 +171,7 @@ typedef struct {
   int tail_max, adapt;
   int scan;
   int wide_min;
+  int deep_max;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);

@@ -192,12 +192,12 @@ __device__ __forceinline__ double node_weight(int k, int M, double r, double h, 
 // The per-wave partial G is summed over the waves through LDS once per
 // iteration; every wave then applies the (cheap) prox redundantly so that
 // all of them hold sigma * lam_bar for the next dual GEMM.
-template <typename Tv, int NT, int MM>
-__global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int iters, int part) {
+template <typename Tv, int NT, int MM, int WV>
+__global__ __launch_bounds__(WV * 64, WV == 4 ? 2 : 1) void k_pdhg(SysView S, PtState st, int iters, int part) {
   typedef typename V4<Tv>::t vec4;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Tv *gred = reinterpret_cast<Tv *>(lds_raw);                       // [2][WAVES][NT][4][64]
-  Tv *pscr = gred + 2 * WAVES * NT * 4 * 64;                        // partial-node scratch
+  Tv *gred = reinterpret_cast<Tv *>(lds_raw);                       // [2][WV][NT][4][64]
+  Tv *pscr = gred + 2 * WV * NT * 4 * 64;                        // partial-node scratch
   const int tile = blockIdx.x;
   int beg, nact;
   launch_range(st, part, beg, nact);
@@ -256,8 +256,68 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
 #pragma unroll
     for (int t = 0; t < NT; ++t) G[t] = vec4{0, 0, 0, 0};
 
-    // ---- private node at tau = T (trapezoid rule, T off the grid): wave 0
-    if (wg_part) {
+    // ---- private node at tau = T (trapezoid rule, T off the grid): wave 0.
+    // FP32: in registers in one pass over R, as in k_pdhg_wide (the four
+    // lanes of a point hold all of its lambda_bar rows, 16 t + 4 g + q); the
+    // term enters wave 0's share of G only.
+    if constexpr (sizeof(Tv) == 4) {
+      if (wave == 0 && wg_part) {
+        const bool ppart = live && st.partial[p] != 0;
+        const float wR = ppart ? 0.5f * (float)rr : 0.f;
+        const float *Rp = ppart ? st.R32 + (size_t)p * m * np : nullptr;
+        float *yRp = ppart ? st.yR + (size_t)p * st.mpad : nullptr;
+        const bool box = S.uset != HOPF_U_L2;
+        float ssq = 0.f;
+        float4 rn[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          rn[t] = ppart ? *reinterpret_cast<const float4 *>(Rp + 16 * t + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 1
+        for (int j = 0; j < m; ++j) {
+          float4 rv[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) rv[t] = rn[t];
+          if (j + 1 < m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              rn[t] = ppart ? *reinterpret_cast<const float4 *>(Rp + (size_t)(j + 1) * np + 16 * t + 4 * g)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+          float acc = 0.f;
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc += rv[t].x * bop[t][0] + rv[t].y * bop[t][1] + rv[t].z * bop[t][2] + rv[t].w * bop[t][3];
+          acc += __shfl_xor(acc, 16);
+          acc += __shfl_xor(acc, 32);
+          float v = ppart ? yRp[j] + acc : 0.f;
+          if (box) v = fminf(fmaxf(v, -wR), wR);
+          ssq += v * v;
+          if (ppart && g == 0) {
+            yRp[j] = v;                              // the l2 ball's scale is applied below
+            if (st.yR64) st.yR64[(size_t)p * st.mpad + j] = (double)v;
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            G[t][0] += rv[t].x * v;
+            G[t][1] += rv[t].y * v;
+            G[t][2] += rv[t].z * v;
+            G[t][3] += rv[t].w * v;
+          }
+        }
+        if (!box) {
+          const float nv = sqrtf(ssq);
+          const float sc = (nv > wR) ? (nv > 0.f ? wR / nv : 0.f) : 1.f;
+          if (ppart && g == 0)
+            for (int j = 0; j < m; ++j) {
+              yRp[j] *= sc;
+              if (st.yR64) st.yR64[(size_t)p * st.mpad + j] = (double)yRp[j];
+            }
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) G[t][q] *= sc;
+        }
+      }
+    } else if (wg_part) {
       Tv *lb_s = pscr;                 // [16][np]
       Tv *gr_s = lb_s + 16 * np;       // [16][np]
       Tv *yr_s = gr_s + 16 * np;       // [16][MM]
@@ -339,7 +399,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
     }
 
     // ---- this wave's share of the node table
-    for (int kb = wave; kb < nkb; kb += WAVES) {
+    for (int kb = wave; kb < nkb; kb += WV) {
       // y is stored node-major within a block: offset kk = node % 16
       vec4 V[MM];
 #pragma unroll
@@ -445,7 +505,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
     }
 
     // ---- sum G over the waves (double-buffered LDS), then prox and extrapolation
-    Tv *gb = gred + (size_t)(it & 1) * WAVES * NT * 4 * 64;
+    Tv *gb = gred + (size_t)(it & 1) * WV * NT * 4 * 64;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -457,7 +517,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg(SysView S, PtState st, int 
       for (int q = 0; q < 4; ++q) {
         Tv gs = 0;
 #pragma unroll
-        for (int w2 = 0; w2 < WAVES; ++w2) gs += gb[((w2 * NT + t) * 4 + q) * 64 + lane];
+        for (int w2 = 0; w2 < WV; ++w2) gs += gb[((w2 * NT + t) * 4 + q) * 64 + lane];
         const int i = 16 * t + acc_row<Tv>(g, q);
         const Tv xfc = (Tv)st.xfc32[pd * np + i];
         const Tv wd = (Tv)S.Wd[i];
@@ -1476,7 +1536,7 @@ typedef void (*pdhg_fn)(SysView, PtState, int, int);
 typedef void (*cert_fn)(SysView, PtState, Opts, int);
 
 // kernel instances, one lookup per NT (hopf_inst_nt*.hip); nullptr if absent
-pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM_out);
+pdhg_fn pdhg_lookup(int NT, int m, int prec, int waves, int *MM_out);
 pdhg_fn wide_lookup(int NT, int m);
 cert_fn cert_lookup(int NT);
 pdhg_fn stream_lookup(int NT, int bf16);

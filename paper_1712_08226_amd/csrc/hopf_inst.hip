@@ -14,9 +14,11 @@ namespace hopf {
 // number of control components held in registers (the system's m is rounded up)
 static const int kMM[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
 
-pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
+// waves: 4, or 8 for the FP32 kernel (the node blocks of a tile over twice
+// as many waves, for launches with few tiles)
+pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int waves, int *MM_out) {
 #if HOPF_NT > 8
-  (void)m; (void)prec;
+  (void)m; (void)prec; (void)waves;
   if (MM_out) *MM_out = 0;
   return nullptr;
 #else
@@ -26,30 +28,36 @@ pdhg_fn HOPF_CAT(pdhg_lookup_nt, HOPF_NT)(int m, int prec, int *MM_out) {
   if (MM_out) *MM_out = MM;
   if (prec == HOPF_FP64) {
 #if HOPF_NT <= 2
+    if (waves != WAVES) return nullptr;
     switch (MM) {
-      case 1: return k_pdhg<double, HOPF_NT, 1>;
-      case 2: return k_pdhg<double, HOPF_NT, 2>;
-      case 3: return k_pdhg<double, HOPF_NT, 3>;
-      case 4: return k_pdhg<double, HOPF_NT, 4>;
+      case 1: return k_pdhg<double, HOPF_NT, 1, WAVES>;
+      case 2: return k_pdhg<double, HOPF_NT, 2, WAVES>;
+      case 3: return k_pdhg<double, HOPF_NT, 3, WAVES>;
+      case 4: return k_pdhg<double, HOPF_NT, 4, WAVES>;
       default: return nullptr;
     }
 #else
     return nullptr;
 #endif
   }
+#define HOPF_F32(MMV)                                                           \
+  case MMV:                                                                     \
+    return waves == 8 ? k_pdhg<float, HOPF_NT, MMV, 8> : k_pdhg<float, HOPF_NT, MMV, WAVES>;
+  if (waves != WAVES && waves != 8) return nullptr;
   switch (MM) {
-    case 1: return k_pdhg<float, HOPF_NT, 1>;
-    case 2: return k_pdhg<float, HOPF_NT, 2>;
-    case 3: return k_pdhg<float, HOPF_NT, 3>;
-    case 4: return k_pdhg<float, HOPF_NT, 4>;
-    case 5: return k_pdhg<float, HOPF_NT, 5>;
-    case 6: return k_pdhg<float, HOPF_NT, 6>;
-    case 8: return k_pdhg<float, HOPF_NT, 8>;
-    case 10: return k_pdhg<float, HOPF_NT, 10>;
-    case 12: return k_pdhg<float, HOPF_NT, 12>;
-    case 16: return k_pdhg<float, HOPF_NT, 16>;
+    HOPF_F32(1)
+    HOPF_F32(2)
+    HOPF_F32(3)
+    HOPF_F32(4)
+    HOPF_F32(5)
+    HOPF_F32(6)
+    HOPF_F32(8)
+    HOPF_F32(10)
+    HOPF_F32(12)
+    HOPF_F32(16)
     default: return nullptr;
   }
+#undef HOPF_F32
 #endif
 }
 

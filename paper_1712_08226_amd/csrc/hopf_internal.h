@@ -73,6 +73,7 @@ void mlp_free(MlpState &w);
 
 struct Ctx {
   int device = 0;
+  int n_cu = 1;                // compute units of the device
   hipStream_t stream = nullptr;
   hopf_opts opts{};
   std::vector<SysTables> sys;

@@ -512,6 +512,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->adapt = 1;
   o->scan = 48;
   o->wide_min = 16384;
+  o->deep_max = -1;
   return HOPF_OK;
 }
 
@@ -536,6 +537,8 @@ hopf_status hopf_create(int device, hopf_ctx **out) {
   Ctx *c = new (std::nothrow) Ctx();
   if (!c) return HOPF_ENOMEM;
   c->device = device;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+    c->n_cu = 1;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return HOPF_EDEVICE;
@@ -581,7 +584,8 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
       o->root < 0 || o->root > 1 || o->newton_after < 0 || !(o->newton_rho > 0.0) ||
-      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0)
+      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0 ||
+      o->deep_max < -1)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;

@@ -1421,9 +1421,10 @@ struct Job {
   SysView S{};
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
   pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
+  pdhg_fn fd = nullptr;          // 16-point FP32 iterations on 8 waves (few tiles)
   SetupWavesFn fs = nullptr;     // probe setups without the network
   cert_fn fc = nullptr;
-  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0, lds_setup = 0;
+  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0, lds_setup = 0, lds_deep = 0;
   long last_active = 0;          // active points at the last check read (picks the iteration kernel)
   PtState st{};
   long npts = 0;
@@ -1456,7 +1457,7 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   // register-resident kernel where an instance exists (FP32/FP64, small m
   // and n), the streaming kernel otherwise and for BF16 hi+lo
   bool streaming = false;
-  if (ho.prec != HOPF_BF16X3) J.fp = pdhg_lookup(NT, tab.m, ho.prec, &MMc);
+  if (ho.prec != HOPF_BF16X3) J.fp = pdhg_lookup(NT, tab.m, ho.prec, WAVES, &MMc);
   if (!J.fp && ho.prec != HOPF_FP64) {
     J.fp = stream_lookup(NT, ho.prec == HOPF_BF16X3 ? 1 : 0);
     streaming = true;
@@ -1489,7 +1490,7 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
   // BF16 hi+lo: points that stall are escalated to an FP32 kernel
   if (ho.prec == HOPF_BF16X3) {
     int mm2 = 0;
-    J.fp32_esc = pdhg_lookup(NT, tab.m, HOPF_FP32, &mm2);
+    J.fp32_esc = pdhg_lookup(NT, tab.m, HOPF_FP32, WAVES, &mm2);
     if (J.fp32_esc) J.lds_esc = (size_t)2 * WAVES * NT * 4 * 64 * 4 + (size_t)(2 * 16 * tab.n_pad + 16 * mm2) * 4;
     else {
       J.fp32_esc = stream_lookup(NT, 0);
@@ -1498,6 +1499,17 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
     HIPCHK(hipFuncSetAttribute((const void *)J.fp32_esc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_esc));
   }
   HIPCHK(hipFuncSetAttribute((const void *)J.fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_pdhg));
+  // launches with at most one tile per compute unit: the tile's node blocks
+  // over 8 waves
+  if (ho.prec == HOPF_FP32 && !streaming) {
+    int mm3 = 0;
+    J.fd = pdhg_lookup(NT, tab.m, HOPF_FP32, 8, &mm3);
+    J.lds_deep = (size_t)2 * 8 * NT * 4 * 64 * 4 + (size_t)(2 * 16 * tab.n_pad + 16 * mm3) * 4;
+    if (J.fd && J.lds_deep <= 150 * 1024)
+      HIPCHK(hipFuncSetAttribute((const void *)J.fd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_deep));
+    else
+      J.fd = nullptr;
+  }
   HIPCHK(hipFuncSetAttribute((const void *)J.fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_cert));
   J.fs = setup_waves_for(tab.n);
   J.lds_setup = (size_t)4 * tab.n_pad * (tab.n <= 128 ? setup_cw<64, 1>() : setup_cw<64, 3>()) * sizeof(double);
@@ -1553,6 +1565,8 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
     if (wide) {
       const unsigned wgrid = (unsigned)((J.npts + WIDE_PTS - 1) / WIDE_PTS);
       J.fw<<<wgrid, THREADS, J.lds_wide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+    } else if (J.fd && J.last_active <= (ho.deep_max < 0 ? (long)PTS_TILE * ctx->n_cu : (long)ho.deep_max)) {
+      J.fd<<<J.ngrid, 8 * 64, J.lds_deep, s>>>(J.S, J.st, ho.check_every, 2);
     } else {
       J.fp<<<J.ngrid, THREADS, J.lds_pdhg, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
     }
@@ -2205,7 +2219,7 @@ hopf_status hopf_trajectory(hopf_ctx *h, int sys_id, const double *x0, double T,
 namespace hopf {
 
 #define HOPF_DECL(k)                                   \
-  pdhg_fn pdhg_lookup_nt##k(int m, int prec, int *MM); \
+  pdhg_fn pdhg_lookup_nt##k(int m, int prec, int waves, int *MM); \
   pdhg_fn wide_lookup_nt##k(int m);                    \
   pdhg_fn stream_lookup_nt##k(int bf16);               \
   cert_fn cert_lookup_nt##k();
@@ -2224,8 +2238,8 @@ HOPF_DECL(9) HOPF_DECL(10) HOPF_DECL(11) HOPF_DECL(12) HOPF_DECL(13) HOPF_DECL(1
   }                                                                                   \
   return nullptr;
 
-pdhg_fn pdhg_lookup(int NT, int m, int prec, int *MM) {
-#define E(k) pdhg_lookup_nt##k(m, prec, MM)
+pdhg_fn pdhg_lookup(int NT, int m, int prec, int waves, int *MM) {
+#define E(k) pdhg_lookup_nt##k(m, prec, waves, MM)
   HOPF_SW(E)
 #undef E
 }

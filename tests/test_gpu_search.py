@@ -166,16 +166,23 @@ def test_caller_lam0_and_hints_vs_oracle(solver, tail):
     _check_sample(r, idx, outs)
 
 
+# the 4-wave 16-point tiles throughout, against the 64-point kernel or the
+# 8-wave tiles throughout
+KERNELS = {"wide": dict(wide_min=1, deep_max=0), "deep": dict(wide_min=0, deep_max=1 << 30)}
+
+
 @pytest.mark.parametrize("mode", ["min_time", "value"])
 @pytest.mark.parametrize("shape", [("c5", 100, 10, 300, "l2"), ("box", 40, 8, 120, "box"), ("c2", 50, 5, 200, "l2")])
-def test_wide_kernel_matches_16_point_tiles(solver, mode, shape):
-    """The 64-point LDS-staged iteration kernel against the 16-point tiles on
-    the same points, every round on one of them (no tail solver): identical
-    statuses and results to the parity bar, and sampled points against the
-    oracle.  Horizons off the table grid exercise the extra node."""
+@pytest.mark.parametrize("kernel", ["wide", "deep"])
+def test_iteration_kernels_match_16_point_tiles(solver, mode, shape, kernel):
+    """The 64-point LDS-staged iteration kernel, and the 16-point tiles on 8
+    waves, against the 16-point tiles on 4 waves on the same points, every
+    round on one of them (no tail solver): identical statuses and results to
+    the parity bar, and sampled points against the oracle.  Horizons off the
+    table grid exercise the extra node."""
     from gen import random_system
     name, n, m, N, uset = shape
-    say("case: wide kernel vs tiles", mode, name)
+    say("case: iteration kernel vs tiles", kernel, mode, name)
     if name == "c5":
         spec = config5(npts=8).systems[0]
     elif name == "c2":
@@ -187,10 +194,10 @@ def test_wide_kernel_matches_16_point_tiles(solver, mode, shape):
     t = np.linspace(0.05, 0.3 * spec.t_max, 700)     # horizons where fixed steps converge within max_iter
     solver.set_systems([spec])
     res = {}
-    for wide in (0, 1):
-        solver.set_opts(prec="fp32", c_tau=c_tau, warm="cont", tail_max=0, wide_min=wide)
-        res[wide] = solver.min_time(x) if mode == "min_time" else solver.value(x, t)
-        say("wide_min", wide, "status", np.bincount(res[wide]["status"], minlength=5))
+    for k, kw in enumerate([dict(wide_min=0, deep_max=0), KERNELS[kernel]]):
+        solver.set_opts(prec="fp32", c_tau=c_tau, warm="cont", tail_max=0, **kw)
+        res[k] = solver.min_time(x) if mode == "min_time" else solver.value(x, t)
+        say(kw, "status", np.bincount(res[k]["status"], minlength=5))
     a, b = res[0], res[1]
     assert np.array_equal(a["status"], b["status"])
     ok = a["status"] == 0
