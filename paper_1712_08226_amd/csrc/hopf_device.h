@@ -686,24 +686,31 @@ __global__ __launch_bounds__(THREADS, 2) void k_pdhg_wide(SysView S, PtState st,
         const float4 f = *reinterpret_cast<const float4 *>(yp + (size_t)(kb * m + j) * NODE_BLOCK + 4 * g);
         V[j] = floatx4{f.x, f.y, f.z, f.w};
       }
-      // operands of step s + 1 are read from LDS before the MFMAs of step s
-      // (s = 4 t + q), so the LDS latency hides behind the matrix core
+      // A = K_j[node cl][16 t + 4 g + q]: one 16-byte LDS read per (j, t)
+      // gives the four steps q of column group t (the row stride puts the 16
+      // rows of a read in distinct banks); the reads of group t + 1 are
+      // issued at the last step of group t, so their latency hides behind
+      // that step's matrix-core work
       {
-        float a[2][MM];
         const float *kd = ks + cl * KS + 4 * g;
+        float4 a4[MM];
 #pragma unroll
-        for (int j = 0; j < MM; ++j) a[0][j] = kd[j * NODE_BLOCK * KS];
+        for (int j = 0; j < MM; ++j) a4[j] = *reinterpret_cast<const float4 *>(kd + j * NODE_BLOCK * KS);
 #pragma unroll
-        for (int sidx = 0; sidx < 4 * NT; ++sidx) {
-          const int t = sidx >> 2, q = sidx & 3;
-          if (sidx + 1 < 4 * NT) {
-            const int t1 = (sidx + 1) >> 2, q1 = (sidx + 1) & 3;
+        for (int t = 0; t < NT; ++t) {
 #pragma unroll
-            for (int j = 0; j < MM; ++j) a[(sidx + 1) & 1][j] = kd[j * NODE_BLOCK * KS + 16 * t1 + q1];
+          for (int q = 0; q < 4; ++q) {
+            float a[MM];
+#pragma unroll
+            for (int j = 0; j < MM; ++j) a[j] = q == 0 ? a4[j].x : q == 1 ? a4[j].y : q == 2 ? a4[j].z : a4[j].w;
+            if (q == 3 && t + 1 < NT)
+#pragma unroll
+              for (int j = 0; j < MM; ++j)
+                a4[j] = *reinterpret_cast<const float4 *>(kd + j * NODE_BLOCK * KS + 16 * (t + 1));
+#pragma unroll
+            for (int j = 0; j < MM; ++j) V[j] = mfma(a[j], bop[t][q], V[j]);
+            __builtin_amdgcn_sched_barrier(0);
           }
-#pragma unroll
-          for (int j = 0; j < MM; ++j) V[j] = mfma(a[sidx & 1][j], bop[t][q], V[j]);
-          __builtin_amdgcn_sched_barrier(0);
         }
       }
       // ---- projection onto w_k C per (node, point), rows 4 g + q
