@@ -84,6 +84,8 @@ struct Ctx {
   float *log_T = nullptr, *log_lam = nullptr;
   long log_cap = 0;
   long log_count = 0;
+  float *net_buf = nullptr;        // first-probe network evaluation (grown on demand)
+  size_t net_cap = 0;
   // timing of the last solve
   double t_total = 0.0, t_iter = 0.0, point_rows = 0.0, alg_flops = 0.0;
   double t_tail = 0.0, tail_rows = 0.0;
@@ -108,6 +110,11 @@ hopf_status build_tables(Ctx *ctx, const hopf_system &s, SysTables &t);
 void free_tables(SysTables &t);
 
 // device solver (hopf_solver.hip)
+// first-probe network evaluation of one job's points (hopf_mlp.hip)
+struct MlpView;
+struct PtState;
+hopf_status mlp_first_probe(Ctx *ctx, const MlpView &mv, int warm, const PtState &st, long npts, int np,
+                            bool caller_lam0, hipStream_t s);
 hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const double *x,
                       const double *t_in, const double *lam0, const double *t_bracket, double *T_out,
                       double *gap_out, double *philo_out, double *phihi_out, double *lam_out,

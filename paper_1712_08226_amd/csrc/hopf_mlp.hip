@@ -35,61 +35,103 @@ constexpr float MLP_ETA = 0.05f;
 
 // ------------------------------------------------------------------ GEMM
 
-// C (M x N) = op(A) (M x K) * op(B) (K x N) [+ bias_j], with A(i,k) at
-// A[i*ars + k*acs] and B(k,j) at B[k*brs + j*bcs] (strides express the
-// transposes of the backward pass).  64x64 tile per workgroup, K in chunks
-// of 16 through LDS, 4x4 outputs per thread, FP32 FMA.
+// C (M x N) = op(A) (M x K) * op(B) (K x N) on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32), with A(i,k) at A[i*ars + k*acs] and B(k,j) at
+// B[k*brs + j*bcs] (strides express the transposes of the backward pass).
+// A workgroup of four waves computes a 64 x 64 tile of C, each wave a
+// 32 x 32 quarter as 2 x 2 MFMA tiles; K runs in chunks of 16 through LDS
+// (row stride 80 floats: the four k rows of an operand read fall in distinct
+// banks).  Options:
+//   ones_row >= 0  row ones_row of op(A) is all ones (row ones_row of C then
+//                  holds the column sums of op(B): a bias gradient computed
+//                  with its weight gradient)
+//   gridDim.z > 1  split K: workgroup z takes K chunks z, z + gridDim.z, ...
+//                  and adds its partial tile to C atomically (C zeroed first)
+//   epi            GEMM_STORE: C = acc + bias_j;  GEMM_GELU: C = acc + bias_j
+//                  and H = gelu(C) (same layout);  GEMM_GELU_BWD:
+//                  C = acc * gelu'(aux) (aux in C's layout);  GEMM_GELU_ONLY:
+//                  C = gelu(acc + bias_j)
+constexpr int GEMM_STORE = 0, GEMM_GELU = 1, GEMM_GELU_BWD = 2, GEMM_GELU_ONLY = 3;
+constexpr int GEMM_LDS = 80;
+
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *__restrict__ A, long ars, long acs,
                                               const float *__restrict__ B, long brs, long bcs, float *__restrict__ C,
-                                              long ldc, const float *__restrict__ bias) {
-  __shared__ float As[16][64 + 1];
-  __shared__ float Bs[16][64 + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+                                              long ldc, const float *__restrict__ bias, int ones_row, int epi,
+                                              float *__restrict__ Hout, const float *__restrict__ aux) {
+  __shared__ __align__(16) float As[16 * GEMM_LDS];   // As[k][row]
+  __shared__ __align__(16) float Bs[16 * GEMM_LDS];   // Bs[k][col]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = (K + 15) / 16;
+  for (int ch = blockIdx.z; ch < nchunk; ch += gridDim.z) {
+    const int k0 = ch * 16;
+    // stage op(A)[i0 .. +64][k0 .. +16] and op(B)[k0 .. +16][j0 .. +64];
+    // consecutive threads take the operand's unit-stride index
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int kk = e / 64, r = e % 64;
+      int kk, r;
+      if (acs == 1) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
       const int ia = i0 + r, ka = k0 + kk;
-      As[kk][r] = (ia < M && ka < K) ? A[(long)ia * ars + (long)ka * acs] : 0.0f;
-      const int jb = j0 + r;
-      Bs[kk][r] = (jb < N && ka < K) ? B[(long)ka * brs + (long)jb * bcs] : 0.0f;
+      float v = 0.0f;
+      if (ia < M && ka < K) v = (ia == ones_row) ? 1.0f : A[(long)ia * ars + (long)ka * acs];
+      As[kk * GEMM_LDS + r] = v;
+      if (bcs == 1) { kk = e >> 6; r = e & 63; } else { r = e >> 4; kk = e & 15; }
+      const int jb = j0 + r, kb = k0 + kk;
+      Bs[kk * GEMM_LDS + r] = (jb < N && kb < K) ? B[(long)kb * brs + (long)jb * bcs] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      float av[2], bv[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty * 4 + u]; b[u] = Bs[kk][tx * 4 + u]; }
+      for (int a = 0; a < 2; ++a) av[a] = As[(k4 + g) * GEMM_LDS + wr + 16 * a + cl];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[(k4 + g) * GEMM_LDS + wc + 16 * b + cl];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
+  // lane (cl, g) holds rows 4 g + q, column cl of each 16 x 16 tile
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < M && j < N) C[(long)i * ldc + j] = acc[u][v] + (bias ? bias[j] : 0.0f);
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wr + 16 * a + 4 * g + q, j = j0 + wc + 16 * b + cl;
+        if (i >= M || j >= N) continue;
+        const long o = (long)i * ldc + j;
+        float v = acc[a][b][q];
+        if (gridDim.z > 1) {
+          atomicAdd(&C[o], v);
+        } else if (epi == GEMM_GELU_BWD) {
+          C[o] = v * gelu_grad_f(aux[o]);
+        } else {
+          v += bias ? bias[j] : 0.0f;
+          C[o] = epi == GEMM_GELU_ONLY ? gelu_f(v) : v;
+          if (epi == GEMM_GELU) Hout[o] = gelu_f(v);
+        }
+      }
 }
 
-__global__ void k_gelu_fwd(const float *__restrict__ a, float *__restrict__ h, long count) {
+__global__ void k_fill(float *__restrict__ p, long count, float v) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) h[i] = gelu_f(a[i]);
+  if (i < count) p[i] = v;
 }
 
-__global__ void k_gelu_bwd(float *__restrict__ g, const float *__restrict__ a, long count) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) g[i] *= gelu_grad_f(a[i]);
-}
-
-// loss and gradient with respect to the output rows
+// loss and gradient with respect to the output rows; loss += the batch
+// mean, esum (if given) += the batch sum
 __global__ void k_loss_grad(const float *__restrict__ out, const float *__restrict__ Y, int Bn, int n,
-                            float *__restrict__ gout, double *__restrict__ loss) {
+                            float *__restrict__ gout, double *__restrict__ loss, double *__restrict__ esum) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= Bn) return;
   const int d = n + 2;
@@ -112,15 +154,11 @@ __global__ void k_loss_grad(const float *__restrict__ out, const float *__restri
   const float sg = 1.0f / (1.0f + expf(-r));
   go[n + 1] = mk * ((miss ? -1.0f : 0.0f) + MLP_ETA) * sg / Bn;
   atomicAdd(loss, ls / Bn);
+  if (esum) atomicAdd(esum, ls);
 }
 
-// column sums (bias gradients): out[j] = sum_i g[i*N + j]
-__global__ void k_colsum(const float *__restrict__ g, int M, int N, float *__restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  float s = 0.0f;
-  for (int i = 0; i < M; ++i) s += g[(long)i * N + j];
-  out[j] = s;
+__global__ void k_zero_d(double *__restrict__ p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
 }
 
 __global__ void k_adam(float *__restrict__ th, const float *__restrict__ g, float *__restrict__ m,
@@ -168,11 +206,12 @@ namespace {
 struct MlpBufs {
   float *Z = nullptr, *Y = nullptr, *a1 = nullptr, *h1 = nullptr, *a2 = nullptr, *h2 = nullptr, *a3 = nullptr,
         *h3 = nullptr, *out = nullptr, *g = nullptr, *g2 = nullptr, *grad = nullptr;
-  double *loss = nullptr;
+  double *loss = nullptr, *esum = nullptr;
   int cap = 0;
+  size_t np = 0;
   void free_all() {
     hipFree(Z); hipFree(Y); hipFree(a1); hipFree(h1); hipFree(a2); hipFree(h2); hipFree(a3); hipFree(h3);
-    hipFree(out); hipFree(g); hipFree(g2); hipFree(grad); hipFree(loss);
+    hipFree(out); hipFree(g); hipFree(g2); hipFree(grad); hipFree(loss); hipFree(esum);
     *this = MlpBufs();
   }
 };
@@ -183,9 +222,21 @@ size_t nparams(int n, int H) {
 }
 
 void gemm(hipStream_t s, int M, int N, int K, const float *A, long ars, long acs, const float *B, long brs,
-          long bcs, float *C, long ldc, const float *bias) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, ars, acs, B, brs, bcs, C, ldc, bias);
+          long bcs, float *C, long ldc, const float *bias, int epi = GEMM_STORE, float *Hout = nullptr,
+          const float *aux = nullptr, int ones_row = -1, int split = 1) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64, split);
+  k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, ars, acs, B, brs, bcs, C, ldc, bias, ones_row, epi, Hout, aux);
+}
+
+// weight and bias gradient of one layer in one GEMM: [gW; gb] = [X^T; 1] G,
+// X (Bn x rows) the layer's input, G (Bn x cols) the gradient at its output;
+// gb follows gW in the parameter vector (row `rows` of a (rows+1) x cols
+// matrix).  K = Bn is split so that about 512 workgroups run; the partial
+// tiles add into gW, which the caller has zeroed.
+void wgrad(hipStream_t s, int rows, int cols, int Bn, const float *X, const float *G, float *gW) {
+  const int tiles = ((cols + 63) / 64) * ((rows + 1 + 63) / 64);
+  const int split = std::max(1, std::min((Bn + 15) / 16, (512 + tiles - 1) / tiles));
+  gemm(s, rows + 1, cols, Bn, X, 1, rows, G, cols, 1, gW, cols, nullptr, GEMM_STORE, nullptr, nullptr, rows, split);
 }
 
 bool alloc_bufs(MlpBufs &b, int Bn, int n, int H, size_t np_) {
@@ -196,51 +247,106 @@ bool alloc_bufs(MlpBufs &b, int Bn, int n, int H, size_t np_) {
             al(&b.h1, (size_t)Bn * H) && al(&b.a2, (size_t)Bn * H) && al(&b.h2, (size_t)Bn * H) &&
             al(&b.a3, (size_t)Bn * H) && al(&b.h3, (size_t)Bn * H) && al(&b.out, (size_t)Bn * (n + 2)) &&
             al(&b.g, (size_t)Bn * std::max(H, n + 2)) && al(&b.g2, (size_t)Bn * std::max(H, n + 2)) &&
-            al(&b.grad, np_) && hipMalloc(&b.loss, sizeof(double)) == hipSuccess;
+            al(&b.grad, np_) && hipMalloc(&b.loss, sizeof(double)) == hipSuccess &&
+            hipMalloc(&b.esum, sizeof(double)) == hipSuccess;
   if (!ok) { b.free_all(); return false; }
   b.cap = Bn;
+  b.np = np_;
   return true;
 }
 
-// forward + loss + backward on rows Z, Y (device); gradient into b.grad, loss into b.loss
-void loss_grad(hipStream_t s, const float *th, MlpBufs &b, int Bn, int n, int H) {
+// forward + loss + backward on rows Z, Y (device); gradient into b.grad, the
+// batch's mean loss into b.loss (and its sum added to esum when given)
+void loss_grad(hipStream_t s, const float *th, MlpBufs &b, int Bn, int n, int H, double *esum = nullptr) {
   const int di = n + 1, dout = n + 2;
   const float *W1 = th, *b1 = W1 + (size_t)di * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *W3 = b2 + H,
               *b3 = W3 + (size_t)H * H, *W4 = b3 + H, *b4 = W4 + (size_t)H * dout;
-  float *gW1 = b.grad, *gb1 = gW1 + (size_t)di * H, *gW2 = gb1 + H, *gb2 = gW2 + (size_t)H * H, *gW3 = gb2 + H,
-        *gb3 = gW3 + (size_t)H * H, *gW4 = gb3 + H, *gb4 = gW4 + (size_t)H * dout;
-  const long BH = (long)Bn * H;
-  const unsigned eb = (unsigned)((BH + 255) / 256);
-  gemm(s, Bn, H, di, b.Z, di, 1, W1, H, 1, b.a1, H, b1);
-  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a1, b.h1, BH);
-  gemm(s, Bn, H, H, b.h1, H, 1, W2, H, 1, b.a2, H, b2);
-  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a2, b.h2, BH);
-  gemm(s, Bn, H, H, b.h2, H, 1, W3, H, 1, b.a3, H, b3);
-  k_gelu_fwd<<<eb, 256, 0, s>>>(b.a3, b.h3, BH);
+  float *gW1 = b.grad, *gW2 = gW1 + (size_t)di * H + H, *gW3 = gW2 + (size_t)H * H + H,
+        *gW4 = gW3 + (size_t)H * H + H;
+  // forward: a_l = h_{l-1} W_l + b_l and h_l = gelu(a_l) in one pass
+  gemm(s, Bn, H, di, b.Z, di, 1, W1, H, 1, b.a1, H, b1, GEMM_GELU, b.h1);
+  gemm(s, Bn, H, H, b.h1, H, 1, W2, H, 1, b.a2, H, b2, GEMM_GELU, b.h2);
+  gemm(s, Bn, H, H, b.h2, H, 1, W3, H, 1, b.a3, H, b3, GEMM_GELU, b.h3);
   gemm(s, Bn, dout, H, b.h3, H, 1, W4, dout, 1, b.out, dout, b4);
-  hipMemsetAsync(b.loss, 0, sizeof(double), s);
-  k_loss_grad<<<(Bn + 127) / 128, 128, 0, s>>>(b.out, b.Y, Bn, n, b.g, b.loss);   // g = dL/dout (Bn x dout)
-  // layer 4
-  gemm(s, H, dout, Bn, b.h3, 1, H, b.g, dout, 1, gW4, dout, nullptr);             // h3^T g
-  k_colsum<<<(dout + 127) / 128, 128, 0, s>>>(b.g, Bn, dout, gb4);
-  gemm(s, Bn, H, dout, b.g, dout, 1, W4, 1, dout, b.g2, H, nullptr);              // g W4^T
-  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g2, b.a3, BH);
-  // layer 3
-  gemm(s, H, H, Bn, b.h2, 1, H, b.g2, H, 1, gW3, H, nullptr);
-  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g2, Bn, H, gb3);
-  gemm(s, Bn, H, H, b.g2, H, 1, W3, 1, H, b.g, H, nullptr);
-  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g, b.a2, BH);
-  // layer 2
-  gemm(s, H, H, Bn, b.h1, 1, H, b.g, H, 1, gW2, H, nullptr);
-  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g, Bn, H, gb2);
-  gemm(s, Bn, H, H, b.g, H, 1, W2, 1, H, b.g2, H, nullptr);
-  k_gelu_bwd<<<eb, 256, 0, s>>>(b.g2, b.a1, BH);
-  // layer 1
-  gemm(s, di, H, Bn, b.Z, 1, di, b.g2, H, 1, gW1, H, nullptr);
-  k_colsum<<<(H + 127) / 128, 128, 0, s>>>(b.g2, Bn, H, gb1);
+  k_zero_d<<<1, 64, 0, s>>>(b.loss);
+  k_loss_grad<<<(Bn + 127) / 128, 128, 0, s>>>(b.out, b.Y, Bn, n, b.g, b.loss, esum);   // g = dL/dout
+  k_fill<<<(unsigned)((b.np + 255) / 256), 256, 0, s>>>(b.grad, (long)b.np, 0.0f);
+  // backward: layer l's weight and bias gradient, then the gradient at the
+  // previous layer's pre-activation, (g W_l^T) * gelu'(a_{l-1}), in one pass
+  wgrad(s, H, dout, Bn, b.h3, b.g, gW4);
+  gemm(s, Bn, H, dout, b.g, dout, 1, W4, 1, dout, b.g2, H, nullptr, GEMM_GELU_BWD, nullptr, b.a3);
+  wgrad(s, H, H, Bn, b.h2, b.g2, gW3);
+  gemm(s, Bn, H, H, b.g2, H, 1, W3, 1, H, b.g, H, nullptr, GEMM_GELU_BWD, nullptr, b.a2);
+  wgrad(s, H, H, Bn, b.h1, b.g, gW2);
+  gemm(s, Bn, H, H, b.g, H, 1, W2, 1, H, b.g2, H, nullptr, GEMM_GELU_BWD, nullptr, b.a1);
+  wgrad(s, di, H, Bn, b.Z, b.g2, gW1);
+}
+
+// network inputs of the first probe: Z = ((x0 - mean)/std, T/t_scale), one
+// workgroup per point
+__global__ void k_net_in(MlpView mv, PtState st, long npts, int np, float *__restrict__ Z) {
+  const long p = blockIdx.x;
+  if (p >= npts) return;
+  const int n = mv.n;
+  for (int i = threadIdx.x; i <= n; i += blockDim.x)
+    Z[p * (n + 1) + i] = i < n ? (float)((st.x0[p * np + i] - mv.xm[i]) / mv.xs[i]) : (float)(st.T[p] / mv.t_scale);
+}
+
+// network outputs of the first probe, one thread per point.  An output that
+// is not finite, or a costate more than 1000 times the training costates'
+// scale, is not used (lambda_0 = 0, no bracket): a damaged network can slow a
+// solve down, not change it.
+__global__ void k_net_out(MlpView mv, PtState st, long npts, int np, const float *__restrict__ out, int warm,
+                          int caller_lam0) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const int n = mv.n, dout = n + 2;
+  const float *o = out + p * dout;
+  bool bad = !(isfinite(mv.lam_scale) && mv.lam_scale > 0.0f);
+  for (int k = 0; k < dout; ++k) bad |= !isfinite(o[k] * (k < n ? mv.lam_scale : 1.0f));
+  for (int k = 0; k < n; ++k) bad |= fabsf(o[k]) > 1e3f;
+  if ((warm == HOPF_WARM_MLP_FIRST || warm == HOPF_WARM_MLP_LAM) && !caller_lam0 && st.lam0s)
+    for (int i = 0; i < np; ++i) st.lam0s[p * np + i] = (!bad && i < n) ? (double)(o[i] * mv.lam_scale) : 0.0;
+  if (bad) return;
+  const float r2 = o[n + 1];
+  st.bT[p] = expf(o[n]);
+  st.bD[p] = log1pf(expf(-fabsf(r2))) + fmaxf(r2, 0.0f) + MLP_DELTA_MIN;
+  // the network's bracket [T e^-d, T e^d] as probe hints inside the first
+  // sign-change cell, unless the caller gave hints
+  if ((warm == HOPF_WARM_MLP || warm == HOPF_WARM_MLP_LAM) && st.stage[p] == 2) {
+    st.ha[p] = (double)st.bT[p] * exp(-(double)st.bD[p]);
+    st.hb[p] = (double)st.bT[p] * exp((double)st.bD[p]);
+    st.stage[p] = 0;
+  }
 }
 
 }  // namespace
+
+hopf_status mlp_first_probe(Ctx *ctx, const MlpView &mv, int warm, const PtState &st, long npts, int np,
+                            bool caller_lam0, hipStream_t s) {
+  if (npts < 1) return HOPF_OK;
+  const int n = mv.n, H = mv.H, di = n + 1, dout = n + 2;
+  const size_t need = (size_t)npts * ((size_t)di + 2 * (size_t)H + (size_t)dout);
+  if (ctx->net_cap < need) {
+    hipFree(ctx->net_buf);
+    ctx->net_buf = nullptr;
+    ctx->net_cap = 0;
+    if (hipMalloc((void **)&ctx->net_buf, need * sizeof(float)) != hipSuccess)
+      return set_err(ctx, HOPF_ENOMEM, "network evaluation buffers");
+    ctx->net_cap = need;
+  }
+  float *Z = ctx->net_buf, *h1 = Z + (size_t)npts * di, *h2 = h1 + (size_t)npts * H, *out = h2 + (size_t)npts * H;
+  const float *W1 = mv.theta, *b1 = W1 + (size_t)di * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *W3 = b2 + H,
+              *b3 = W3 + (size_t)H * H, *W4 = b3 + H, *b4 = W4 + (size_t)H * dout;
+  const int M = (int)npts;
+  k_net_in<<<(unsigned)npts, 128, 0, s>>>(mv, st, npts, np, Z);
+  gemm(s, M, H, di, Z, di, 1, W1, H, 1, h1, H, b1, GEMM_GELU_ONLY);
+  gemm(s, M, H, H, h1, H, 1, W2, H, 1, h2, H, b2, GEMM_GELU_ONLY);
+  gemm(s, M, H, H, h2, H, 1, W3, H, 1, h1, H, b3, GEMM_GELU_ONLY);
+  gemm(s, M, dout, H, h1, H, 1, W4, dout, 1, out, dout, b4);
+  k_net_out<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(mv, st, npts, np, out, warm, caller_lam0 ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? HOPF_OK : set_err(ctx, HOPF_EDEVICE, "network evaluation launch failed");
+}
 
 void mlp_free(MlpState &w) {
   hipFree(w.theta); hipFree(w.m); hipFree(w.v); hipFree(w.xm); hipFree(w.xs);
@@ -540,24 +646,25 @@ hopf_status hopf_warm_train(hopf_ctx *h, int sys_id, long npts, const double *x,
     for (int ep = 0; ep < epochs; ++ep) {
       std::shuffle(order.begin(), order.end(), rng);
       hipMemcpy(didx, order.data(), rows * 4, hipMemcpyHostToDevice);
-      double tot = 0.0;
+      // the epoch's loss is summed on the device and read once at its end
+      // (the stream is idle then, so the next epoch's order can be copied in)
       long seen = 0;
+      hopf::k_zero_d<<<1, 64, 0, c->stream>>>(b.esum);
       for (long s0 = 0; s0 + Bn <= rows || (s0 == 0 && rows < Bn); s0 += Bn) {
         const int nb = (int)std::min<long>(Bn, rows - s0);
         hopf::k_make_rows<<<nb, 128, 0, c->stream>>>(didx + s0, nb, c->log_pt, c->log_T, c->log_lam, np,
                                                      dxf ? dxf : dx, dT, dst,
                                                      n, w.xm, w.xs, w.t_scale, w.lam_scale, b.Z, b.Y);
-        hopf::loss_grad(c->stream, w.theta, b, nb, n, w.H);
+        hopf::loss_grad(c->stream, w.theta, b, nb, n, w.H, b.esum);
         w.step += 1;
         const float c1 = 1.0f - std::pow(0.9f, (float)w.step), c2 = 1.0f - std::pow(0.999f, (float)w.step);
         hopf::k_adam<<<(unsigned)((w.nparam + 255) / 256), 256, 0, c->stream>>>(w.theta, b.grad, w.m, w.v,
                                                                                  (long)w.nparam, lr, c1, c2);
-        double l = 0.0;
-        hipMemcpyAsync(&l, b.loss, 8, hipMemcpyDeviceToHost, c->stream);
-        hipStreamSynchronize(c->stream);
-        tot += l * nb;
         seen += nb;
       }
+      double tot = 0.0;
+      hipMemcpyAsync(&tot, b.esum, 8, hipMemcpyDeviceToHost, c->stream);
+      hipStreamSynchronize(c->stream);
       if (epoch_loss) epoch_loss[ep] = seen ? tot / seen : 0.0;
     }
     hipError_t e = hipGetLastError();

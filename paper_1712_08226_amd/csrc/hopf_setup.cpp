@@ -569,6 +569,7 @@ void hopf_destroy(hopf_ctx *h) {
   }
   for (auto &e : c->evpool) hipEventDestroy(e);
   if (c->hcount) hipHostFree(c->hcount);
+  hipFree(c->net_buf);
   hipStreamDestroy(c->stream);
   delete c;
 }

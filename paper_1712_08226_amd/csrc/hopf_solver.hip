@@ -506,10 +506,9 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
   __syncthreads();
   const double T = st.T[p];
   const bool f64 = st.s64 != nullptr;
-  // learned warm start: lam_0 = network(x, T) (and, at the first probe, its bracket)
-  const bool net_first = o.warm == HOPF_WARM_MLP_FIRST && st.probes[p] == 0;
-  if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM || net_first) && mv.valid && mv.n == n &&
-      mv.H == 256) {
+  // learned warm start at a later probe (mode mlp_lam): lam_0 = network(x, T);
+  // the first probe's network output was evaluated for all points at once
+  if (o.warm == HOPF_WARM_MLP_LAM && st.probes[p] > 0 && mv.valid && mv.n == n && mv.H == 256) {
     float *zin = reinterpret_cast<float *>(sm + SETUP_VS + 8), *ha = zin + 260, *hb = ha + 260, *outv = hb + 260;
     const int di = n + 1, dout = n + 2, H = 256;
     __syncthreads();
@@ -553,24 +552,12 @@ __device__ void setup_point(SysView S, PtState st, Opts o, MlpView mv, long p, d
     }
     __syncthreads();
     const bool net_bad = reinterpret_cast<const int *>(outv)[dout] != 0;
-    if ((o.warm == HOPF_WARM_MLP_LAM || net_first) && !net_bad && !(st.lam0s != nullptr && st.probes[p] == 0)) {
+    if (!net_bad) {
       for (int i = tid; i < np; i += 256) {
         const float l = i < n ? outv[i] * mv.lam_scale : 0.0f;
         st.lam[p * np + i] = l;
         st.lamb[p * np + i] = l;
         if (f64) { st.lam64[p * np + i] = l; st.lamb64[p * np + i] = l; }
-      }
-    }
-    if (tid == 0 && st.probes[p] == 0 && !net_bad) {
-      const float r2 = outv[n + 1];
-      st.bT[p] = expf(outv[n]);
-      st.bD[p] = log1pf(expf(-fabsf(r2))) + fmaxf(r2, 0.0f) + 1e-3f;
-      // the network's bracket [T e^-d, T e^d] as probe hints inside the first
-      // sign-change cell, unless the caller gave hints
-      if ((o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM) && st.stage[p] == 2) {
-        st.ha[p] = (double)st.bT[p] * exp(-(double)st.bD[p]);
-        st.hb[p] = (double)st.bT[p] * exp((double)st.bD[p]);
-        st.stage[p] = 0;
       }
     }
     __syncthreads();
@@ -1520,8 +1507,7 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
 // Probe setups of the points on the setup list: one wave per point, or one
 // workgroup per point when a network gives the warm start.
 void launch_setup(const Job &J, const Opts &o) {
-  const bool net = J.mv.valid && (o.warm == HOPF_WARM_MLP || o.warm == HOPF_WARM_MLP_LAM ||
-                                  o.warm == HOPF_WARM_MLP_FIRST);
+  const bool net = J.mv.valid && o.warm == HOPF_WARM_MLP_LAM;
   if (net)
     k_setup<<<(unsigned)std::min<long>(J.npts, 2048), 256, 0, J.s>>>(J.S, J.st, o, J.mv);
   else
@@ -1703,7 +1689,9 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.hcount = hcount + 4 * j;
     J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
     if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
-    if (!make_state(ctx, j, *J.tab, J.npts, J.st, lam0 != nullptr && mode == MODE_MINTIME)) {
+    const bool net = (ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
+                     J.sid < (int)ctx->mlp.size() && ctx->mlp[J.sid].valid;
+    if (!make_state(ctx, j, *J.tab, J.npts, J.st, (lam0 != nullptr && mode == MODE_MINTIME) || net)) {
       rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
       break;
     }
@@ -1714,9 +1702,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       rc = set_err(ctx, HOPF_EDEVICE, "stream wait");
       break;
     }
-    if ((ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
-        J.sid < (int)ctx->mlp.size() &&
-        ctx->mlp[J.sid].valid) {
+    if (net) {
       const MlpState &w = ctx->mlp[J.sid];
       J.mv = MlpView{w.theta, w.xm, w.xs, w.t_scale, w.lam_scale, w.n, w.H, 1};
     }
@@ -1728,6 +1714,10 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     k_clear<<<1, 64, 0, s>>>(st);
     k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
+    // learned start: the network at every point's first probe, batched on
+    // the matrix cores (later probes of mode mlp_lam evaluate it in the setup)
+    if (net && J.mv.n == J.tab->n && J.mv.H == 256)
+      rc = mlp_first_probe(ctx, J.mv, ho.warm, st, np_, J.tab->n_pad, lam0 != nullptr && mode == MODE_MINTIME, s);
   }
   // ---- interleaved rounds: each job keeps up to two groups in flight until
   // its points are done or at most tail_max remain (then it is parked); the

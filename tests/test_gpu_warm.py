@@ -100,6 +100,9 @@ def test_training_and_warm_min_time(solver, tmp_path):
         "gain of the network's lam_0 over continuation:", round(float(iters["cont"] / iters["mlp_lam"]), 3),
         "of the network's first-probe start:", round(float(iters["cont"] / iters["mlp_first"]), 3))
     assert iters["mlp_lam"] < 0.9 * iters["cold"]
+    # the first-probe start against continuation, the non-learned baseline:
+    # measured and reported above; it must not cost more than a tenth
+    assert iters["mlp_first"] <= 1.1 * iters["cont"]
     # the trained network survives a save and a load into a fresh context
     from paper_1712_08226_amd import Solver
     path = str(tmp_path / "net.npz")
