@@ -73,6 +73,18 @@ def _oracle_query(args):
     return r.status, r.T, time.perf_counter() - t0
 
 
+def _oracle_value(args):
+    """One oracle value solve phi(x, t) (run in a worker process); returns
+    the job's index, the certified interval, lambda, iterations and wall
+    seconds."""
+    k, spec, x, t, opts = args
+    from oracle import hopf_oracle as O
+    S = O.System(spec.A, spec.B, spec.W, spec.c, uset=spec.uset, N=spec.N, t_max=spec.t_max, quad=spec.quad)
+    t0 = time.perf_counter()
+    pr = O.solve_value(S, x, t, O.Options(**opts))
+    return k, -pr.P, -pr.D, pr.lam, pr.iters, time.perf_counter() - t0
+
+
 def host_info():
     """CPU model, logical CPUs, and the NumPy / BLAS build of this host."""
     import platform
@@ -143,6 +155,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=96, help="oracle queries in the CPU baseline sample")
     ap.add_argument("--cpu-workers", type=int, default=16, help="oracle worker processes (one thread each)")
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle wall time (value workloads)")
+    ap.add_argument("--c3-sample", type=int, default=8,
+                    help="c3: points (evenly spaced) solved by the oracle for the CPU rate and the error line")
     ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its BF16 / FP32 difference; c4: 64 uneven systems in one call; "
@@ -603,8 +617,12 @@ def bench_grid(args):
 def bench_c3(args):
     """Precision workload (n=200, m=20, N=400, box): value solves phi(x, t) of
     16384 points in BF16 hi+lo (FP32 accumulate, FP32 escalation of stalled
-    probes) and in FP32, both certified in FP64; the BF16 / FP32 difference,
-    and the one-probe min-time queries."""
+    probes) and in FP32, both certified in FP64, inputs resident on the
+    device; the BF16 / FP32 difference; the one-probe min-time queries; and
+    (CPU leg) the FP64 oracle on an evenly spaced sample of the points at the
+    full N = 400, timed, with each sampled point's error of the BF16 result
+    against it: |dphi| of the interval midpoints, interval overlap, and
+    ||dlam|| / ||lam||."""
     import numpy as np
     import torch
     from gen.configs import config3
@@ -614,57 +632,112 @@ def bench_c3(args):
         w.opts["c_tau"] = args.c_tau
     spec = w.systems[0]
     npts = len(w.x)
-    t = w.meta["t"]
-    # the device intervals of 16 evenly spaced points are reported so that the
-    # FP64 oracle can be run on the same points apart from the benchmark
+    t = np.asarray(w.meta["t"], dtype=np.float64)
+    dev = torch.device("cuda:0")
     solver = Solver(0)
     t0 = time.perf_counter()
     solver.set_systems([spec])
     setup_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream(dev)
+    xd = torch.tensor(w.x, dtype=torch.float64, device=dev)
+    td = torch.tensor(t, dtype=torch.float64, device=dev)
+    lo, hi = torch.empty_like(td), torch.empty_like(td)
+    lam = torch.empty_like(xd)
+    st = torch.empty(npts, dtype=torch.int32, device=dev)
+    it = torch.empty(npts, dtype=torch.int32, device=dev)
     out = {}
+    wmin = args.wide_min if args.wide_min is not None else w.opts.get("wide_min")
+    extra = {} if wmin is None else {"wide_min": wmin}
     for prec in ("bf16x3", "fp32"):
-        solver.set_opts(prec=prec, c_tau=w.opts["c_tau"])
+        solver.set_opts(prec=prec, c_tau=w.opts["c_tau"], **extra)
         for i in range(args.warmup):
             solver.value(w.x[:256], t[:256])
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = solver.value(w.x, t)
+        solver.value_dev(xd, td, lo, hi, st, lam=lam, iters=it, stream=stream)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         tm = solver.last_timing()
-        out[prec] = dict(r=r, dt=dt, tm=tm)
-        print(f"[c3 {prec}] {npts} value solves in {dt:.2f} s", file=sys.stderr, flush=True)
+        out[prec] = dict(r=dict(phi_lo=lo.cpu().numpy(), phi_hi=hi.cpu().numpy(), lam=lam.cpu().numpy(),
+                                status=st.cpu().numpy(), iters=it.cpu().numpy()), dt=dt, tm=tm)
+        log(f"[c3 {prec}] {npts} value solves in {dt:.2f} s")
     solver.set_opts(prec="bf16x3", c_tau=w.opts["c_tau"])
     nmt = min(npts, 2048)
     t0 = time.perf_counter()
     rm = solver.min_time(w.x[:nmt])
     dtm = time.perf_counter() - t0
-    print(f"[c3] {nmt} min-time queries in {dtm:.2f} s", file=sys.stderr, flush=True)
+    log(f"[c3] {nmt} min-time queries in {dtm:.2f} s")
     b, f = out["bf16x3"]["r"], out["fp32"]["r"]
-    rep = np.linspace(0, npts - 1, min(16, npts)).astype(int)
     mid_b = 0.5 * (b["phi_lo"] + b["phi_hi"])
     mid_f = 0.5 * (f["phi_lo"] + f["phi_hi"])
     tmb = out["bf16x3"]["tm"]
-    ach = tmb["alg_flops"] / tmb["iter_kernel_s"] / 1e12 if tmb["iter_kernel_s"] > 0 else 0.0
+
+    def kern(tm):
+        nw = tm["wide_launches"]
+        ks = {"k_pdhg_swide": (tm["wide_kernel_s"], nw, tm["wide_point_rows"]),
+              "k_pdhg_stream": (tm["iter_kernel_s"] - tm["wide_kernel_s"], tm["iter_launches"] - nw,
+                                tm["point_rows"] - tm["wide_point_rows"])}
+        fpr = 4.0 * spec.m * spec.n
+        return {k: {"s": round(v[0], 4), "launches": int(v[1]),
+                    "tflops": round(fpr * v[2] / v[0] / 1e12, 3) if v[0] > 0 else None} for k, v in ks.items()}
+    kb = kern(tmb)
+    dom = max(kb, key=lambda k: kb[k]["s"])
+    ach = kb[dom]["tflops"] or 0.0
     res = {"metric": "value solves/sec at dual gap<=1e-6, BF16 hi+lo (n=200, m=20, N=400, box)",
            "value": round(npts / out["bf16x3"]["dt"], 2), "unit": "solves/s", "n_gpus": 1, "steps": 1,
            "warmup": args.warmup, "ms_per_step": round(1e3 * out["bf16x3"]["dt"], 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
            "config": {"workload": f"value phi(x,t), n=200 m=20 N=400 box control, {npts} points x~N(0,4I), "
-                                  "t~U[0.5,10], K as bf16 hi+lo with fp32 accumulation, fp64 tables and certificate"},
+                                  "t~U[0.5,10], K as bf16 hi+lo with fp32 accumulation, fp64 tables and certificate",
+                      "c_tau": w.opts["c_tau"], "check_every": w.opts.get("check_every"),
+                      "wide_min": wmin if wmin is not None else default_opts().wide_min},
            "fp32_solves_per_s": round(npts / out["fp32"]["dt"], 2),
+           "bf16_over_fp32": round(out["fp32"]["dt"] / out["bf16x3"]["dt"], 3),
            "statuses_bf16": np.bincount(b["status"], minlength=5).tolist(),
            "statuses_fp32": np.bincount(f["status"], minlength=5).tolist(),
            "mean_iters_bf16_fp32": [float(b["iters"].mean()), float(f["iters"].mean())],
            "max_gap_bf16": float(np.max((b["phi_hi"] - b["phi_lo"]) / np.maximum(1, np.abs(b["phi_hi"])))),
            "error": {"max_abs_phi_bf16_vs_fp32_all": float(np.max(np.abs(mid_b - mid_f)))},
-           "sample_intervals_idx_t_bf16lo_bf16hi_fp32lo_fp32hi": [
-               [int(i), float(t[i]), float(b["phi_lo"][i]), float(b["phi_hi"][i]), float(f["phi_lo"][i]),
-                float(f["phi_hi"][i])] for i in rep],
+           "iteration_kernels": {"bf16x3": kb, "fp32": kern(out["fp32"]["tm"])},
            "min_time": {"queries": nmt, "queries_per_s": round(nmt / dtm, 2),
                         "statuses": np.bincount(rm["status"], minlength=5).tolist()},
            "setup_s": round(setup_s, 2),
            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(ach / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
-                        "kernel": "k_pdhg_stream<bf16 hi+lo>; achieved counts algorithmic flops (x3 executed)"}}
+                        "kernel": f"{dom}<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"}}
+    if not args.no_cpu and args.c3_sample > 0:
+        import multiprocessing as mp
+        idx = np.linspace(0, npts - 1, min(args.c3_sample, npts)).astype(int)
+        workers = max(1, min(args.cpu_workers, os.cpu_count() or 1, len(idx)))
+        single_thread_workers()
+        opts = dict(c_tau=w.opts["c_tau"], max_iter=2_000_000)
+        log(f"[c3 cpu] oracle on {len(idx)} points at N={spec.N}, {workers} workers")
+        t0 = time.perf_counter()
+        orc = [None] * len(idx)
+        with mp.get_context("spawn").Pool(workers) as pool:
+            jobs = [(k, spec, w.x[i], float(t[i]), opts) for k, i in enumerate(idx)]
+            for done, r in enumerate(pool.imap_unordered(_oracle_value, jobs, chunksize=1)):
+                orc[r[0]] = r[1:]
+                log(f"[c3 cpu] oracle point {done + 1}/{len(idx)} (sample {r[0]}): {r[4]} iterations, {r[5]:.1f} s")
+        wall = time.perf_counter() - t0
+        per = []
+        for k, i in enumerate(idx):
+            olo, ohi, olam, oit, osec = orc[k]
+            mo = 0.5 * (olo + ohi)
+            dl = float(np.linalg.norm(b["lam"][i] - olam) / max(np.linalg.norm(olam), 1e-300))
+            per.append({"idx": int(i), "t": round(float(t[i]), 4), "phi_oracle": mo,
+                        "abs_dphi": abs(float(mid_b[i]) - mo),
+                        "rel_dphi": abs(float(mid_b[i]) - mo) / max(1.0, abs(mo)),
+                        "intervals_overlap": bool(max(b["phi_lo"][i], olo) <= min(b["phi_hi"][i], ohi) +
+                                                  1e-9 * max(1.0, abs(mo))),
+                        "rel_dlam": dl, "oracle_iters": int(oit), "oracle_s": round(osec, 2)})
+        res["error"]["bf16_vs_fp64_oracle_sample"] = per
+        res["error"]["max_rel_dphi_sample"] = max(e["rel_dphi"] for e in per)
+        res["error"]["max_rel_dlam_sample"] = max(e["rel_dlam"] for e in per)
+        res["cpu_baseline"] = {"value": round(len(idx) / wall, 4), "unit": "solves/s", "cores": workers,
+                               "kind": "oracle", "sample": f"{len(idx)} evenly spaced points of the batch, "
+                                                           f"value solves at N={spec.N} run to completion",
+                               "host": host_info()}
     print(json.dumps(res), flush=True)
 
 

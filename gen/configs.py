@@ -72,7 +72,7 @@ def config3(npts=16384, seed=3, N=400):
     spec = random_system(200, 20, N, "box", seed=1003)
     x = gaussian_points(npts, 200, 2.0, seed)
     t = np.random.default_rng(seed + 1).uniform(0.5, 10.0, npts)
-    return Workload("c3_n200_m20_N400_box", [spec], x, None, dict(prec="bf16x3", c_tau=5.0),
+    return Workload("c3_n200_m20_N400_box", [spec], x, None, dict(prec="bf16x3", c_tau=5.0, wide_min=4096),
                     dict(points="literal N(0,4I)", t=t))
 
 

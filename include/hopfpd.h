@@ -143,8 +143,9 @@ typedef struct {
  *   newton_rho    hybrid only: cell probes from newton_after on also run until
  *                 P - D <= newton_rho |P + D| / 2 so the Newton step sees an accurate
  *                 value                                                              [0.5]
- *   wide_min      FP32 iterations run on 64-point workgroups that share one LDS copy
- *                 of each node block of the table while at least wide_min of a
+ *   wide_min      FP32 and BF16 iterations run on 64-point workgroups that share one
+ *                 LDS copy of the table's rows (each node block; for large m or n
+ *                 each component pair of a block) while at least wide_min of a
  *                 system's points are active (then on 16-point tiles); 0: never  [16384]
  *   deep_max      FP32 16-point tiles: while at most deep_max of a system's points
  *                 are active, each tile's node blocks are spread over 8 waves

@@ -1539,6 +1539,383 @@ __global__ __launch_bounds__(THREADS, 1) void k_pdhg_stream(SysView S, PtState s
   }
 }
 
+// ------------------------------------------------------------------ 64-point streaming variant (any m, BF16 hi+lo)
+
+// The streaming iteration for a workgroup of 64 points (wave w owns points
+// 16 w .. 16 w + 15 and runs every node block for them, as in k_pdhg_wide):
+// for each node block and component pair (j, j+1) the table rows are copied
+// once into LDS and read by all four waves.  FP32: one copy in the dual
+// layout, rows (component, node) of n_pad floats at stride n_pad + 4 (dual
+// operand: one 16-byte read per column group; primal operand: 4-byte reads
+// at node 4 g + q).  BF16 hi+lo: the dual-layout hi and lo rows at stride
+// n_pad + 4 bf16 (an odd multiple of 8 bytes: the 16 rows of an 8-byte read
+// fall in distinct banks) and the primal-layout hi and lo copies
+// [component][n_pad][16 nodes] (two 8-byte reads give a lane its 8 values of
+// the 16x16x32 operand).  The extra node is applied per point in registers.
+__host__ __device__ constexpr int swide_bf_stride(int NT) { return 16 * NT + 4; }
+__host__ __device__ inline size_t swide_lds_bytes(int NT, bool bf) {
+  return bf ? (size_t)2 * (2 * 16 * swide_bf_stride(NT)) * 2 + (size_t)2 * (2 * 16 * NT * 16) * 2
+            : (size_t)2 * 16 * wide_row_stride(NT) * 4;
+}
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+template <int NT, bool BF>
+__global__ __launch_bounds__(THREADS, NT <= 12 ? 2 : 1) void k_pdhg_swide(SysView S, PtState st, int iters, int part) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  constexpr int np = 16 * NT;
+  constexpr int KS = wide_row_stride(NT);
+  constexpr int KB = swide_bf_stride(NT);
+  float *ks = reinterpret_cast<float *>(lds_raw);                 // FP32: [2][16][KS]
+  __bf16 *kdh = reinterpret_cast<__bf16 *>(lds_raw);             // BF16: [2][16][KB] hi, lo
+  __bf16 *kdl = kdh + 2 * 16 * KB;
+  __bf16 *kph = kdl + 2 * 16 * KB;                                // [2][np][16] hi, lo
+  __bf16 *kpl = kph + 2 * np * 16;
+  int beg, nact;
+  launch_range(st, part, beg, nact);
+  const int wg0 = beg + blockIdx.x * WIDE_PTS;
+  if (wg0 >= nact) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, g = lane >> 4;
+  const int m = S.m;
+  const int slot = wg0 + wave * PTS_WAVE + cl;
+  const bool live = slot < nact;
+  const long p = live ? st.perm[slot] : -1;
+  const long pd = live ? p : st.npts;
+  const int rows_max = st.rows[st.perm[wg0]];     // slots are sorted by rows, descending
+  const int nkb = (rows_max + NODE_BLOCK - 1) / NODE_BLOCK;
+
+  float tau = 0.f, sig = 0.f, rr = 0.f;
+  int M = -1, rowsp = 0;
+  bool ppart = false;
+  if (live) {
+    tau = (float)st.tau[p];
+    sig = (float)st.sig[p];
+    rr = (float)st.r[p];
+    M = st.M[p];
+    rowsp = st.rows[p];
+    ppart = st.partial[p] != 0;
+  }
+  const bool wave_part = __any(ppart);
+  const float wR = ppart ? 0.5f * rr : 0.f;
+  const float hw = (float)S.h;
+  const bool l2 = S.uset == HOPF_U_L2;
+  float bop[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bop[t][q] = sig * st.lamb[pd * np + 16 * t + 4 * g + q];
+  float *lamp = st.lam + pd * np;
+  float *yp = st.y + (size_t)pd * st.ystride;
+  const float *Rp = ppart ? st.R32 + (size_t)p * m * np : nullptr;
+
+  for (int it = 0; it < iters; ++it) {
+    floatx4 G[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) G[t] = floatx4{0, 0, 0, 0};
+
+    // ---- extra node at tau = T, in registers (see k_pdhg_wide)
+    if (wave_part) {
+      float ssq = 0.f;
+      float *yRp = ppart ? st.yR + (size_t)p * st.mpad : nullptr;
+#pragma unroll 1
+      for (int j = 0; j < m; ++j) {
+        float4 rv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          rv[t] = ppart ? *reinterpret_cast<const float4 *>(Rp + (size_t)j * np + 16 * t + 4 * g)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc += rv[t].x * bop[t][0] + rv[t].y * bop[t][1] + rv[t].z * bop[t][2] + rv[t].w * bop[t][3];
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        float v = ppart ? yRp[j] + acc : 0.f;
+        if (!l2) v = fminf(fmaxf(v, -wR), wR);
+        ssq += v * v;
+        if (ppart && g == 0) yRp[j] = v;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          G[t][0] += rv[t].x * v;
+          G[t][1] += rv[t].y * v;
+          G[t][2] += rv[t].z * v;
+          G[t][3] += rv[t].w * v;
+        }
+      }
+      if (l2) {
+        const float nv = sqrtf(ssq);
+        const float sc = (nv > wR) ? (nv > 0.f ? wR / nv : 0.f) : 1.f;
+        if (ppart && g == 0)
+          for (int j = 0; j < m; ++j) yRp[j] *= sc;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) G[t][q] *= sc;
+      }
+    }
+
+    // B operand of the dual GEMM as hi + lo, split once per iteration
+    bf16x8 bdh[(NT + 1) / 2], bdl[(NT + 1) / 2];
+    if constexpr (BF) {
+#pragma unroll
+      for (int c = 0; c < (NT + 1) / 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int t = 2 * c + (e >> 2);
+          const float v = (t < NT) ? bop[t < NT ? t : 0][e & 3] : 0.f;
+          __bf16 hi, lo;
+          split_bf16(v, hi, lo);
+          bdh[c][e] = hi;
+          bdl[c][e] = lo;
+        }
+    }
+
+    // staging of the rows of one (node block, pass, component pair) through
+    // registers: PF / PD / PP chunks per thread
+    const int npass = l2 ? 2 : 1;
+    struct Stage { int kb, pass, j; };
+    constexpr int FCH = 2 * 16 * (np / 4);              // FP32 float4 chunks
+    constexpr int DCH = 2 * 16 * (np / 4);              // BF16 dual 8-byte chunks (per table)
+    constexpr int PCH = 2 * np * NODE_BLOCK / 8;        // BF16 primal 16-byte chunks (per table)
+    constexpr int PF = BF ? 1 : (FCH + THREADS - 1) / THREADS;
+    constexpr int PD = BF ? (DCH + THREADS - 1) / THREADS : 1;
+    constexpr int PP = BF ? (PCH + THREADS - 1) / THREADS : 1;
+    float4 rf[PF];
+    uint2 rdh[PD], rdl[PD];
+    uint4 rph[PP], rpl[PP];
+    auto stage_load = [&](const Stage &q) {
+      const bool h2 = q.j + 1 < m;
+      if constexpr (BF) {
+        if (!l2 || q.pass == 0) {
+          const uint2 *sh = reinterpret_cast<const uint2 *>(S.Kd16h + ((size_t)q.kb * m + q.j) * NODE_BLOCK * np);
+          const uint2 *sl = reinterpret_cast<const uint2 *>(S.Kd16l + ((size_t)q.kb * m + q.j) * NODE_BLOCK * np);
+#pragma unroll
+          for (int r = 0; r < PD; ++r) {
+            const int e = threadIdx.x + r * THREADS;
+            const bool ok = e < DCH && (e < DCH / 2 || h2);
+            rdh[r] = ok ? sh[e] : make_uint2(0u, 0u);
+            rdl[r] = ok ? sl[e] : make_uint2(0u, 0u);
+          }
+        }
+        if (!l2 || q.pass == 1) {
+          const uint4 *sh = reinterpret_cast<const uint4 *>(S.Kp16h + ((size_t)q.kb * m + q.j) * np * NODE_BLOCK);
+          const uint4 *sl = reinterpret_cast<const uint4 *>(S.Kp16l + ((size_t)q.kb * m + q.j) * np * NODE_BLOCK);
+#pragma unroll
+          for (int r = 0; r < PP; ++r) {
+            const int e = threadIdx.x + r * THREADS;
+            const bool ok = e < PCH && (e < PCH / 2 || h2);
+            rph[r] = ok ? sh[e] : make_uint4(0u, 0u, 0u, 0u);
+            rpl[r] = ok ? sl[e] : make_uint4(0u, 0u, 0u, 0u);
+          }
+        }
+      } else {
+        const float4 *src = reinterpret_cast<const float4 *>(S.K32 + ((size_t)q.kb * m + q.j) * NODE_BLOCK * np);
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+          const int e = threadIdx.x + r * THREADS;
+          const bool ok = e < FCH && (e < FCH / 2 || h2);
+          rf[r] = ok ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+    };
+    auto stage_store = [&](const Stage &q) {
+      if constexpr (BF) {
+        if (!l2 || q.pass == 0) {
+          constexpr int C2 = np / 4;
+#pragma unroll
+          for (int r = 0; r < PD; ++r) {
+            const int e = threadIdx.x + r * THREADS;
+            if (e < DCH) {
+              const int row = e / C2, c2 = e - row * C2;
+              *reinterpret_cast<uint2 *>(kdh + row * KB + 4 * c2) = rdh[r];
+              *reinterpret_cast<uint2 *>(kdl + row * KB + 4 * c2) = rdl[r];
+            }
+          }
+        }
+        if (!l2 || q.pass == 1) {
+#pragma unroll
+          for (int r = 0; r < PP; ++r) {
+            const int e = threadIdx.x + r * THREADS;
+            if (e < PCH) {
+              reinterpret_cast<uint4 *>(kph)[e] = rph[r];
+              reinterpret_cast<uint4 *>(kpl)[e] = rpl[r];
+            }
+          }
+        }
+      } else {
+        constexpr int C4 = np / 4;
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+          const int e = threadIdx.x + r * THREADS;
+          if (e < FCH) {
+            const int row = e / C4, c4 = e - row * C4;
+            *reinterpret_cast<float4 *>(ks + row * KS + 4 * c4) = rf[r];
+          }
+        }
+      }
+    };
+    Stage cur{0, 0, 0};
+    if (nkb > 0) stage_load(cur);
+
+    for (int kb = 0; kb < nkb; ++kb) {
+      float w4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb * NODE_BLOCK + 4 * g + q;
+        w4[q] = (k < rowsp) ? (float)node_weight(k, M, (double)rr, (double)hw, S.quad) : 0.f;
+      }
+      float s4[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int pass = 0; pass < (l2 ? 2 : 1); ++pass) {
+        const bool dual = !l2 || pass == 0, primal = !l2 || pass == 1;
+        float sc4[4] = {1.f, 1.f, 1.f, 1.f};
+        if (l2 && pass == 1) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float nv = sqrtf(s4[q]);
+            sc4[q] = (nv > w4[q]) ? (nv > 0 ? w4[q] / nv : 0.f) : 1.f;
+          }
+        }
+        for (int j = 0; j < m; j += 2) {
+          const bool has2 = j + 1 < m;
+          // ---- the prefetched rows of components j, j+1 into LDS, then the
+          // next pair's rows from memory into registers (in flight during
+          // this pair's matrix-core work)
+          __syncthreads();                     // every wave is done with the previous pair
+          stage_store(cur);
+          __syncthreads();
+          {
+            int nkb2 = kb, np2 = pass, nj = j + 2;
+            if (nj >= m) { nj = 0; if (++np2 >= npass) { np2 = 0; ++nkb2; } }
+            cur = Stage{nkb2, np2, nj};
+            if (nkb2 < nkb) stage_load(cur);
+          }
+          // ---- y of the pair (node-major within the block)
+          floatx4 V[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            V[u] = floatx4{0, 0, 0, 0};
+            if (u == 0 || has2) {
+              const float4 f = *reinterpret_cast<const float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g);
+              V[u] = floatx4{f.x, f.y, f.z, f.w};
+            }
+          }
+          if (dual) {
+            // ---- dual GEMM V_u += K_{j+u} (sigma lam_bar)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if constexpr (BF) {
+                const __bf16 *rh = kdh + (u * 16 + cl) * KB + 4 * g;
+                const __bf16 *rl = kdl + (u * 16 + cl) * KB + 4 * g;
+#pragma unroll
+                for (int c = 0; c < (NT + 1) / 2; ++c) {
+                  const bf16x4 h0 = *reinterpret_cast<const bf16x4 *>(rh + 32 * c);
+                  const bf16x4 l0 = *reinterpret_cast<const bf16x4 *>(rl + 32 * c);
+                  bf16x4 h1 = {}, l1 = {};
+                  if (2 * c + 1 < NT) {
+                    h1 = *reinterpret_cast<const bf16x4 *>(rh + 32 * c + 16);
+                    l1 = *reinterpret_cast<const bf16x4 *>(rl + 32 * c + 16);
+                  }
+                  const bf16x8 ah = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+                  const bf16x8 al = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+                  V[u] = mfma_bf16(ah, bdh[c], V[u]);
+                  V[u] = mfma_bf16(ah, bdl[c], V[u]);
+                  V[u] = mfma_bf16(al, bdh[c], V[u]);
+                }
+              } else {
+                const float *kd = ks + (u * 16 + cl) * KS + 4 * g;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                  const float4 f = *reinterpret_cast<const float4 *>(kd + 16 * t);
+                  V[u] = mfma(f.x, bop[t][0], V[u]);
+                  V[u] = mfma(f.y, bop[t][1], V[u]);
+                  V[u] = mfma(f.z, bop[t][2], V[u]);
+                  V[u] = mfma(f.w, bop[t][3], V[u]);
+                }
+              }
+            }
+          }
+          if (l2 && pass == 0) {       // store unprojected, accumulate node norms
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              if (u == 1 && !has2) break;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) s4[q] += V[u][q] * V[u][q];
+              *reinterpret_cast<float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g) =
+                  make_float4(V[u][0], V[u][1], V[u][2], V[u][3]);
+            }
+            continue;
+          }
+          // ---- project, store, primal GEMM G_t += K_{j+u}^T V_u
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) V[u][q] = l2 ? V[u][q] * sc4[q] : fminf(fmaxf(V[u][q], -w4[q]), w4[q]);
+            if (u == 0 || has2)
+              *reinterpret_cast<float4 *>(yp + (size_t)(kb * m + j + u) * NODE_BLOCK + 4 * g) =
+                  make_float4(V[u][0], V[u][1], V[u][2], V[u][3]);
+          }
+          if constexpr (BF) {
+            bf16x8 byh, byl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              __bf16 hi, lo;
+              split_bf16(V[e >> 2][e & 3], hi, lo);
+              byh[e] = hi;
+              byl[e] = lo;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const int o = (16 * t + cl) * NODE_BLOCK + 4 * g;
+              const bf16x4 h0 = *reinterpret_cast<const bf16x4 *>(kph + o);
+              const bf16x4 h1 = *reinterpret_cast<const bf16x4 *>(kph + np * NODE_BLOCK + o);
+              const bf16x4 l0 = *reinterpret_cast<const bf16x4 *>(kpl + o);
+              const bf16x4 l1 = *reinterpret_cast<const bf16x4 *>(kpl + np * NODE_BLOCK + o);
+              const bf16x8 ah = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+              const bf16x8 al = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+              G[t] = mfma_bf16(ah, byh, G[t]);
+              G[t] = mfma_bf16(ah, byl, G[t]);
+              G[t] = mfma_bf16(al, byh, G[t]);
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const float *row = ks + (u * 16 + 4 * g + q) * KS + cl;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) G[t] = mfma(row[16 * t], V[u][q], G[t]);
+              }
+          }
+        }
+      }
+    }
+    // ---- prox of G and extrapolation (theta = 1), rows 16 t + 4 g + q
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float4 l4 = *reinterpret_cast<const float4 *>(lamp + 16 * t + 4 * g);
+      const float4 x4 = *reinterpret_cast<const float4 *>(st.xfc32 + pd * np + 16 * t + 4 * g);
+      const float l0[4] = {l4.x, l4.y, l4.z, l4.w}, xc[4] = {x4.x, x4.y, x4.z, x4.w};
+      float ln[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float wd = (float)S.Wd[16 * t + 4 * g + q];
+        ln[q] = (l0[q] - tau * (G[t][q] - xc[q])) / (1.0f + tau * wd);
+        bop[t][q] = sig * (2.0f * ln[q] - l0[q]);
+      }
+      *reinterpret_cast<float4 *>(lamp + 16 * t + 4 * g) = make_float4(ln[0], ln[1], ln[2], ln[3]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st.lamb[pd * np + 16 * t + 4 * g + q] = sig > 0.f ? bop[t][q] / sig : 0.f;
+  if (live && g == 0) {
+    st.iters_probe[p] += iters;
+    st.iters_tot[p] += iters;
+  }
+}
+
 typedef void (*pdhg_fn)(SysView, PtState, int, int);
 typedef void (*cert_fn)(SysView, PtState, Opts, int);
 
@@ -1547,5 +1924,6 @@ pdhg_fn pdhg_lookup(int NT, int m, int prec, int waves, int *MM_out);
 pdhg_fn wide_lookup(int NT, int m);
 cert_fn cert_lookup(int NT);
 pdhg_fn stream_lookup(int NT, int bf16);
+pdhg_fn swide_lookup(int NT, int bf16);
 
 }  // namespace hopf

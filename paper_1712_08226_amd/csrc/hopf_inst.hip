@@ -91,6 +91,10 @@ pdhg_fn HOPF_CAT(stream_lookup_nt, HOPF_NT)(int bf16) {
   return bf16 ? k_pdhg_stream<HOPF_NT, true> : k_pdhg_stream<HOPF_NT, false>;
 }
 
+pdhg_fn HOPF_CAT(swide_lookup_nt, HOPF_NT)(int bf16) {
+  return bf16 ? k_pdhg_swide<HOPF_NT, true> : k_pdhg_swide<HOPF_NT, false>;
+}
+
 cert_fn HOPF_CAT(cert_lookup_nt, HOPF_NT)() { return k_certify<HOPF_NT>; }
 
 }  // namespace hopf

@@ -1409,9 +1409,12 @@ struct Job {
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
   pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
   pdhg_fn fd = nullptr;          // 16-point FP32 iterations on 8 waves (few tiles)
+  pdhg_fn fsw = nullptr;         // 64-point streaming iterations (FP32 or BF16 hi+lo)
+  pdhg_fn fsw32 = nullptr;       // 64-point FP32 streaming iterations of escalated BF16 points
   SetupWavesFn fs = nullptr;     // probe setups without the network
   cert_fn fc = nullptr;
-  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0, lds_setup = 0, lds_deep = 0;
+  size_t lds_pdhg = 0, lds_esc = 0, lds_cert = 0, lds_wide = 0, lds_setup = 0, lds_deep = 0, lds_swide = 0,
+         lds_swide32 = 0;
   long last_active = 0;          // active points at the last check read (picks the iteration kernel)
   PtState st{};
   long npts = 0;
@@ -1472,6 +1475,22 @@ hopf_status plan_job(Ctx *ctx, Job &J) {
     if (J.fw) {
       J.lds_wide = (size_t)NODE_BLOCK * MMc * wide_row_stride(NT) * sizeof(float);
       HIPCHK(hipFuncSetAttribute((const void *)J.fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_wide));
+    }
+  }
+  // large m or n: the streaming iteration on 64-point workgroups
+  if (streaming && ho.wide_min > 0) {
+    J.fsw = swide_lookup(NT, ho.prec == HOPF_BF16X3 ? 1 : 0);
+    J.lds_swide = swide_lds_bytes(NT, ho.prec == HOPF_BF16X3);
+    if (J.fsw && J.lds_swide <= 150 * 1024)
+      HIPCHK(hipFuncSetAttribute((const void *)J.fsw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)J.lds_swide));
+    else
+      J.fsw = nullptr;
+    if (J.fsw && ho.prec == HOPF_BF16X3) {
+      J.fsw32 = swide_lookup(NT, 0);
+      J.lds_swide32 = swide_lds_bytes(NT, false);
+      if (J.fsw32)
+        HIPCHK(hipFuncSetAttribute((const void *)J.fsw32, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)J.lds_swide32));
     }
   }
   // BF16 hi+lo: points that stall are escalated to an FP32 kernel
@@ -1538,7 +1557,7 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
     launch_setup(J, o);
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
     J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
-    const bool wide = J.fw && J.last_active >= ho.wide_min;
+    const bool wide = (J.fw || J.fsw) && J.last_active >= ho.wide_min;
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 0, wide ? 2 : 1);
     hipEvent_t a = nullptr, b = nullptr;
     if (J.timed) {
@@ -1547,10 +1566,17 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
       if (!a || !b) return set_err(ctx, HOPF_EDEVICE, "hipEventCreate failed");
       HIPCHK(hipEventRecord(a, s));
     }
-    if (J.fp32_esc) J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
+    if (J.fp32_esc) {   // escalated BF16 points (sorted first) in FP32
+      if (wide && J.fsw32)
+        J.fsw32<<<(unsigned)((J.npts + WIDE_PTS - 1) / WIDE_PTS), THREADS, J.lds_swide32, s>>>(J.S, J.st,
+                                                                                               ho.check_every, 0);
+      else
+        J.fp32_esc<<<J.ngrid, THREADS, J.lds_esc, s>>>(J.S, J.st, ho.check_every, 0);
+    }
     if (wide) {
       const unsigned wgrid = (unsigned)((J.npts + WIDE_PTS - 1) / WIDE_PTS);
-      J.fw<<<wgrid, THREADS, J.lds_wide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+      if (J.fw) J.fw<<<wgrid, THREADS, J.lds_wide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
+      else J.fsw<<<wgrid, THREADS, J.lds_swide, s>>>(J.S, J.st, ho.check_every, J.fp32_esc ? 1 : 2);
     } else if (J.fd && J.last_active <= (ho.deep_max < 0 ? (long)PTS_TILE * ctx->n_cu : (long)ho.deep_max)) {
       J.fd<<<J.ngrid, 8 * 64, J.lds_deep, s>>>(J.S, J.st, ho.check_every, 2);
     } else {
@@ -2212,6 +2238,7 @@ namespace hopf {
   pdhg_fn pdhg_lookup_nt##k(int m, int prec, int waves, int *MM); \
   pdhg_fn wide_lookup_nt##k(int m);                    \
   pdhg_fn stream_lookup_nt##k(int bf16);               \
+  pdhg_fn swide_lookup_nt##k(int bf16);                \
   cert_fn cert_lookup_nt##k();
 HOPF_DECL(1) HOPF_DECL(2) HOPF_DECL(3) HOPF_DECL(4) HOPF_DECL(5) HOPF_DECL(6) HOPF_DECL(7) HOPF_DECL(8)
 HOPF_DECL(9) HOPF_DECL(10) HOPF_DECL(11) HOPF_DECL(12) HOPF_DECL(13) HOPF_DECL(14) HOPF_DECL(15) HOPF_DECL(16)
@@ -2242,6 +2269,12 @@ pdhg_fn wide_lookup(int NT, int m) {
 
 pdhg_fn stream_lookup(int NT, int bf16) {
 #define E(k) stream_lookup_nt##k(bf16)
+  HOPF_SW(E)
+#undef E
+}
+
+pdhg_fn swide_lookup(int NT, int bf16) {
+#define E(k) swide_lookup_nt##k(bf16)
   HOPF_SW(E)
 #undef E
 }
