@@ -73,7 +73,7 @@ def _oracle_query(args):
     return r.status, r.T, time.perf_counter() - t0
 
 
-def _oracle_value(args):
+def _oracle_value_full(args):
     """One oracle value solve phi(x, t) (run in a worker process); returns
     the job's index, the certified interval, lambda, iterations and wall
     seconds."""
@@ -716,7 +716,7 @@ def bench_c3(args):
         orc = [None] * len(idx)
         with mp.get_context("spawn").Pool(workers) as pool:
             jobs = [(k, spec, w.x[i], float(t[i]), opts) for k, i in enumerate(idx)]
-            for done, r in enumerate(pool.imap_unordered(_oracle_value, jobs, chunksize=1)):
+            for done, r in enumerate(pool.imap_unordered(_oracle_value_full, jobs, chunksize=1)):
                 orc[r[0]] = r[1:]
                 log(f"[c3 cpu] oracle point {done + 1}/{len(idx)} (sample {r[0]}): {r[4]} iterations, {r[5]:.1f} s")
         wall = time.perf_counter() - t0
