@@ -157,7 +157,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle wall time (value workloads)")
     ap.add_argument("--c3-sample", type=int, default=8,
                     help="c3: points (evenly spaced) solved by the oracle for the CPU rate and the error line")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid"],
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid", "tune"],
                     help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
                          "workload with its BF16 / FP32 difference; c4: 64 uneven systems in one call; "
                          "tychastic: the paper's dimensional-scaling value solves, d = 2k sampled copies; "
@@ -198,6 +198,8 @@ def main():
         return bench_grid(args)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload == "tune":
+        return bench_tune(args)
     return bench_c5(args)
 
 
@@ -739,6 +741,24 @@ def bench_c3(args):
                                                            f"value solves at N={spec.N} run to completion",
                                "host": host_info()}
     print(json.dumps(res), flush=True)
+
+
+def bench_tune(args):
+    """The launch-parameter tuner (paper_1712_08226_amd.tune) on the headline
+    system: the drift-planted queries (--npts of them), continuation start,
+    the workload's step ratio; prints the table and the chosen setting."""
+    from gen.configs import config5
+    from paper_1712_08226_amd import Solver
+    from paper_1712_08226_amd.tune import tune
+    w = config5(npts=args.npts)
+    solver = Solver(0)
+    solver.set_systems(w.systems)
+    base = dict(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont", check_every=w.opts["check_every"])
+    solver.set_opts(**base)
+    solver.min_time(w.x[:1024])                      # first-call costs out of the table
+    res = tune(solver, w.x, mode="min_time", base=base, log=log)
+    print(json.dumps({"workload": f"min-time n=100 m=10 N=300, {len(w.x)} drift-planted queries, warm cont",
+                      **res}), flush=True)
 
 
 def bench_c4(args):

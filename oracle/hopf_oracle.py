@@ -111,6 +111,9 @@ class Options:
     newton_rho: float = 0.5     # hybrid: a probe also runs until gap <= rho |phi| (Newton accuracy)
     newton_after: int = 1       # hybrid: midpoint probes inside the cell before Newton steps start
     scan: int = 48              # scan horizons: table nodes nearest t_max (j/scan)^2, j = 1..scan
+    steps: str = "fixed"        # "fixed": tau, sigma as above; "accel": Sec. III's accelerated
+                                # variant for a strongly convex G; "precond": diagonal
+                                # preconditioning (Sec. III-A); see pdhg_iteration
 
 
 # ---------------------------------------------------------------- terminal data
@@ -279,6 +282,10 @@ class Probe:
     D: float = -math.inf
     tight: bool = False          # run to the hybrid's relative accuracy as well as the sign
     history: list = field(default_factory=list)
+    steps: str = "fixed"         # step rule (Options.steps)
+    gamma: float = 0.0           # "accel": strong-convexity modulus of G, lambda_min(W)
+    tau_vec: np.ndarray | None = None    # "precond": per-component primal steps
+    sig_node: np.ndarray | None = None   # "precond": per-node dual steps
 
     @property
     def phi_lo(self):
@@ -306,13 +313,27 @@ def make_probe(sys: System, x0, T, opt: Options, lam0=None, y0=None):
         tau_p, sigma_d = 1.0, 0.0
     lam = np.zeros(sys.n) if lam0 is None else np.array(lam0, dtype=np.float64)
     y = np.zeros((len(tau), sys.m))
+    gamma, tau_vec, sig_node = 0.0, None, None
+    if opt.steps == "accel":
+        gamma = float(eigvalsh(sys.W)[0])
+    elif opt.steps == "precond" and len(tau):
+        # Pock-Chambolle diagonal steps with alpha = 1, the ratio c_tau moved
+        # between the two sides: tau_i = c_tau / sum_r |K_ri|, and for node k
+        # the smallest 1 / (c_tau sum_i |K_ri|) over its rows r, so that the
+        # projection onto w_k C stays Euclidean (a smaller step per row keeps
+        # the convergence condition)
+        Kall = np.vstack(Ks)
+        col = np.abs(Kall).sum(axis=0)
+        tau_vec = np.where(col > 0.0, opt.c_tau / np.where(col > 0.0, col, 1.0), opt.c_tau)
+        sig_node = np.array([0.999 / (opt.c_tau * max(np.abs(Kk).sum(axis=1).max(), 1e-300)) for Kk in Ks])
     if y0 is not None:
         # table nodes keep their rows, re-projected onto the new weights; the
         # extra node at tau = T starts from zero
         ntab = len(tau) - (1 if partial else 0)
         for k in range(min(ntab, y0.shape[0])):
             y[k] = project(y0[k], w[k], sys.uset)
-    return Probe(T, tau, w, partial, Ks, xf, L, tau_p, sigma_d, lam, lam.copy(), y)
+    return Probe(T, tau, w, partial, Ks, xf, L, tau_p, sigma_d, lam, lam.copy(), y, steps=opt.steps,
+                 gamma=gamma, tau_vec=tau_vec, sig_node=sig_node)
 
 
 def pdhg_iteration(sys: System, pr: Probe):
@@ -321,7 +342,30 @@ def pdhg_iteration(sys: System, pr: Probe):
       lam+ <- prox_{tau G}(lam - tau K^T y)           (G = J* - <x_f,.>)
       lam_bar <- lam+ + (lam+ - lam).
     The prox of G solves (I + tau W) lam+ = lam - tau K^T y + tau (x_f - c),
-    the terminal-costate form of eq. (37)."""
+    the terminal-costate form of eq. (37).
+
+    The variants Sec. III names (Options.steps): "accel", the accelerated
+    step for a G that is strongly convex with modulus gamma (here
+    lambda_min(W)): theta = 1 / sqrt(1 + 2 gamma tau), then tau <- theta tau,
+    sigma <- sigma / theta and lam_bar <- lam+ + theta (lam+ - lam);
+    "precond", diagonal steps T (per component) and Sigma (per node): the
+    dual step uses sigma_k on node k, the prox of G becomes
+    (I + T W) lam+ = lam - T K^T y + T (x_f - c)."""
+    if pr.steps == "precond":
+        Kl = apply_K(pr.Ks, pr.lam_bar)
+        v = pr.y + pr.sig_node[:, None] * Kl
+        y_new = np.zeros_like(v)
+        for k in range(len(pr.w)):
+            y_new[k] = project(v[k], pr.w[k], sys.uset)
+        g = apply_KT(pr.Ks, y_new)
+        Tv = pr.tau_vec
+        rhs = pr.lam - Tv * g + Tv * (pr.xf - sys.c)
+        lam_new = np.linalg.solve(np.eye(sys.n) + Tv[:, None] * sys.W, rhs)
+        pr.lam_bar = 2.0 * lam_new - pr.lam
+        pr.lam = lam_new
+        pr.y = y_new
+        pr.iters += 1
+        return
     v = pr.y + pr.sigma_d * apply_K(pr.Ks, pr.lam_bar)
     y_new = np.zeros_like(v)
     for k in range(len(pr.w)):
@@ -329,7 +373,13 @@ def pdhg_iteration(sys: System, pr: Probe):
     g = apply_KT(pr.Ks, y_new)
     rhs = pr.lam - pr.tau_p * g + pr.tau_p * (pr.xf - sys.c)
     lam_new = np.linalg.solve(np.eye(sys.n) + pr.tau_p * sys.W, rhs)
-    pr.lam_bar = 2.0 * lam_new - pr.lam
+    if pr.steps == "accel":
+        theta = 1.0 / math.sqrt(1.0 + 2.0 * pr.gamma * pr.tau_p)
+        pr.lam_bar = lam_new + theta * (lam_new - pr.lam)
+        pr.tau_p *= theta
+        pr.sigma_d /= theta
+    else:
+        pr.lam_bar = 2.0 * lam_new - pr.lam
     pr.lam = lam_new
     pr.y = y_new
     pr.iters += 1

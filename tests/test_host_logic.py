@@ -77,3 +77,18 @@ def test_grid_generator():
     S = w.systems[0]
     np.testing.assert_allclose(S.W, 0.04 * np.eye(2))
     assert S.quad == "left" and S.N == 100
+
+
+def test_tuner_accepts_only_the_reference_results():
+    """A tuning candidate is eligible only with the reference setting's
+    statuses, T within the search tolerance and gaps within the tolerance
+    (min time), or overlapping certified intervals (value)."""
+    from paper_1712_08226_amd.tune import _same
+    ref = dict(status=np.array([0, 0, 2]), T=np.array([1.0, 2.0, np.inf]), gap=np.array([1e-7, 1e-7, np.nan]))
+    assert _same(ref, dict(ref, T=np.array([1.00005, 2.0, np.inf])), "min_time")
+    assert not _same(ref, dict(ref, T=np.array([1.001, 2.0, np.inf])), "min_time")
+    assert not _same(ref, dict(ref, status=np.array([0, 3, 2])), "min_time")
+    assert not _same(ref, dict(ref, gap=np.array([2e-6, 1e-7, np.nan])), "min_time")
+    v = dict(status=np.array([0, 0]), phi_lo=np.array([1.0, -2.0]), phi_hi=np.array([1.1, -1.9]))
+    assert _same(v, dict(v, phi_lo=np.array([1.05, -1.95]), phi_hi=np.array([1.2, -1.8])), "value")
+    assert not _same(v, dict(v, phi_lo=np.array([1.2, -2.0]), phi_hi=np.array([1.3, -1.9])), "value")

@@ -216,6 +216,40 @@ def test_strong_duality_against_independent_primal_solve(uset, quad, T, shift):
     assert abs(fval - pr.phi_hi) <= 1e-7 * max(1.0, abs(fval))
 
 
+@pytest.mark.parametrize("steps", ["accel", "precond"])
+@pytest.mark.parametrize("uset,quad,T,shift", [("l2", O.TRAP, 1.37, 0.0), ("box", O.TRAP, 0.9, 0.2),
+                                               ("l2", O.LEFT, 2.2, -0.15)])
+def test_step_variants_reach_the_primal_optimum(steps, uset, quad, T, shift):
+    """The accelerated and the diagonally preconditioned iterations (Sec. III,
+    Sec. III-A) converge to the same phi_N: the independent projected-gradient
+    solve of the primal control problem lies in their certified interval,
+    which is as tight as the fixed-step one."""
+    spec = random_system(4, 2, 16, uset, seed=11, t_max=3.0, quad=quad)
+    c = shift * np.array([1.0, -2.0, 0.5, 1.0])
+    S = O.System(spec.A, spec.B, spec.W, c, None, uset, spec.N, spec.t_max, quad)
+    x = np.random.default_rng(0).normal(0, 0.6, 4)
+    pr = O.solve_value(S, x, T, O.Options(c_tau=1.0, gap_tol=1e-9, max_iter=2_000_000, steps=steps))
+    assert pr.gap_n() <= 1e-9
+    fval, _ = PH.primal_fista(spec.A, spec.B, spec.W, c, np.eye(2), uset, x, T, pr.tau, pr.w, iters=40000)
+    assert pr.phi_lo - 1e-8 <= fval <= pr.phi_hi + 1e-8 * max(1.0, abs(fval))
+
+
+def test_accelerated_steps_follow_the_schedule():
+    """One accelerated step from (tau, sigma): theta = 1/sqrt(1 + 2 gamma tau),
+    tau' = theta tau, sigma' = sigma / theta (tau sigma is kept), and the
+    extrapolation is lam+ + theta (lam+ - lam); gamma = lambda_min(W)."""
+    spec = random_system(5, 2, 12, "l2", seed=5, t_max=2.0)
+    S = sysobj(spec)
+    x = np.linspace(-0.5, 0.5, 5)
+    pr = O.make_probe(S, x, 1.1, O.Options(c_tau=1.0, steps="accel"))
+    assert abs(pr.gamma - np.min(np.linalg.eigvalsh(spec.W))) <= 1e-15
+    t0, s0, lam0 = pr.tau_p, pr.sigma_d, pr.lam.copy()
+    O.pdhg_iteration(S, pr)
+    th = 1.0 / math.sqrt(1.0 + 2.0 * pr.gamma * t0)
+    assert abs(pr.tau_p - th * t0) <= 1e-15 * t0 and abs(pr.sigma_d - s0 / th) <= 1e-12 * s0
+    np.testing.assert_allclose(pr.lam_bar, pr.lam + th * (pr.lam - lam0), rtol=0, atol=1e-15)
+
+
 def test_terminal_state_matches_costate():
     """At the optimum x_T = grad J*(lam*) = W lam* + c (Sec. V, eq. (29)), and
     the read-out trajectory ends at x_T; p* = e^{T A^T} lam*."""
