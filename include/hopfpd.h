@@ -151,6 +151,14 @@ typedef struct {
  *                 are active, each tile's node blocks are spread over 8 waves
  *                 instead of 4; -1: 16 points per compute unit of the device,
  *                 0: never                                                           [-1]
+ *   structure     value solves of a system made of k > 1 copies of one b-dimensional
+ *                 system that share the control (A = I_k (x) A_b, B = 1_k (x) B_b,
+ *                 W = I_k (x) W_b with W_b diagonal, c = 1_k (x) c_b: the sampled-copy
+ *                 systems of Sec. VI-B/C) run on the b-dimensional system of the
+ *                 copies' mean with target matrix W_b / k; the value adds the
+ *                 copies' spread (1/2) sum_c |e^{tA_b}(x_c - mean)|^2_{W_b^-1} in
+ *                 FP64 and lambda is rebuilt per copy.  Exact (the copies share z(u)
+ *                 in x_c(t) = e^{tA_b} x_c + z(u)); 0: solve the full system       [1]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
@@ -173,6 +181,7 @@ typedef struct {
   int scan;
   int wide_min;
   int deep_max;
+  int structure;
 } hopf_opts;
 
 hopf_status hopf_default_opts(hopf_opts *out);

@@ -16,6 +16,8 @@ constexpr int POW_BITS = 20;
 constexpr int RDIG_LEVELS = 3;     // base-16 digits of r / dr below one node step
 
 // Host copy of one system plus its device tables.
+constexpr int KRON_BMAX = 8;       // largest block of a Kronecker-structured system
+
 struct SysTables {
   hopf_system desc{};
   std::vector<double> A, B, Qu, W, c;   // host copies (row-major), in the solver's coordinates
@@ -23,6 +25,12 @@ struct SysTables {
   std::vector<double> U;                // [n][n] orthogonal, W = U diag(d) U^T (rotated only)
   int n = 0, m = 0, N = 0, n_pad = 0, nkb = 0;
   int m_user = 0;                      // the caller's m; m >= m_user is the padded kernel size
+  // k > 1 copies of a b-dimensional system that share the control: A =
+  // I_k (x) A_b, B = 1_k (x) B_b, W = I_k (x) W_b (diagonal), c = 1_k (x) c_b;
+  // value solves then run on the reduced system (ctx->ksys[kron_red])
+  int kron_k = 0, kron_b = 0, kron_red = -1;
+  std::vector<double> kron_winv;       // [b] 1 / diag(W_b)
+  double *kron_winv_d = nullptr;
   double h = 0.0, delta = 0.0;
   // host tables
   std::vector<double> phi;     // [N][m][n] node blocks Phi_k = -Qu^T B^T e^{k h A^T}
@@ -77,6 +85,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   hopf_opts opts{};
   std::vector<SysTables> sys;
+  std::vector<SysTables> ksys;     // reduced systems of the Kronecker-structured ones
   std::vector<MlpState> mlp;       // one per system (optional)
   std::string err;
   // optional probe log of the next solve (filled by the warm-start trainer)

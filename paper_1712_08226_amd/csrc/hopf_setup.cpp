@@ -198,6 +198,8 @@ void free_tables(SysTables &t) {
   t.K32T = nullptr; t.K64T = nullptr;
   t.Kd16h = t.Kd16l = t.Kp16h = t.Kp16l = nullptr;
   hipFree(t.A_d); hipFree(t.BQ_d); hipFree(t.Wd_d); hipFree(t.c_d); hipFree(t.Eh_d); hipFree(t.Qu_d);
+  hipFree(t.kron_winv_d);
+  t.kron_winv_d = nullptr;
   t.Eh_d = nullptr; t.Qu_d = nullptr;
   t.K32 = nullptr; t.K64 = nullptr; t.lpref_d = nullptr; t.epow_d = nullptr;
   t.A_d = nullptr; t.BQ_d = nullptr; t.Wd_d = nullptr; t.c_d = nullptr;
@@ -513,6 +515,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->scan = 48;
   o->wide_min = 16384;
   o->deep_max = -1;
+  o->structure = 1;
   return HOPF_OK;
 }
 
@@ -560,6 +563,7 @@ void hopf_destroy(hopf_ctx *h) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (auto &t : c->sys) hopf::free_tables(t);
+  for (auto &t : c->ksys) hopf::free_tables(t);
   for (auto &w : c->mlp) hopf::mlp_free(w);
   for (auto &v : c->jbufs)
     for (auto &b : v) hipFree(b.p);
@@ -586,11 +590,46 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
       o->root < 0 || o->root > 1 || o->newton_after < 0 || !(o->newton_rho > 0.0) ||
       o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0 ||
-      o->deep_max < -1)
+      o->deep_max < -1 || o->structure < 0 || o->structure > 1)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;
   return HOPF_OK;
 }
+
+namespace hopf {
+
+// The smallest block size b (n = k b, k > 1) for which the system is k copies
+// of one b-dimensional system sharing the control (A = I_k (x) A_b, B = 1_k (x)
+// B_b, W = I_k (x) W_b with W_b diagonal, c = 1_k (x) c_b), or 0.  Blocks must
+// match to 1e-14 relative; the system's own coordinates (not rotated).
+int kron_block(const SysTables &t) {
+  const int n = t.n, m = t.m_user;
+  if (t.rotated) return 0;
+  double amax = 0.0, bmax = 0.0;
+  for (double v : t.A) amax = std::max(amax, std::fabs(v));
+  for (double v : t.B) bmax = std::max(bmax, std::fabs(v));
+  auto close = [](double a, double b, double scale) { return std::fabs(a - b) <= 1e-14 * std::max(scale, 1e-300); };
+  for (int b = 1; 2 * b <= n && b <= KRON_BMAX; ++b) {
+    if (n % b) continue;
+    const int k = n / b;
+    bool ok = true;
+    for (int i = 0; i < n && ok; ++i)
+      for (int j = 0; j < n && ok; ++j) {
+        const int ci = i / b, cj = j / b;
+        const double v = t.A[(size_t)i * n + j];
+        if (ci != cj) ok = v == 0.0;
+        else ok = close(v, t.A[(size_t)(i % b) * n + (j % b)], amax);
+      }
+    for (int i = b; i < n && ok; ++i)
+      for (int j = 0; j < m && ok; ++j) ok = close(t.B[(size_t)i * m + j], t.B[(size_t)(i % b) * m + j], bmax);
+    for (int i = b; i < n && ok; ++i)
+      ok = t.W[(size_t)i * n + i] == t.W[(size_t)(i % b) * n + (i % b)] && t.c[i] == t.c[i % b];
+    if (ok && k > 1) return b;
+  }
+  return 0;
+}
+
+}  // namespace hopf
 
 hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
   Ctx *c = reinterpret_cast<Ctx *>(h);
@@ -599,19 +638,56 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
   if (hipSetDevice(c->device) != hipSuccess) return set_err(c, HOPF_EDEVICE, "hipSetDevice failed");
   hipStreamSynchronize(c->stream);
   for (auto &t : c->sys) hopf::free_tables(t);
+  for (auto &t : c->ksys) hopf::free_tables(t);
   for (auto &w : c->mlp) hopf::mlp_free(w);
   c->mlp.clear();
   c->sys.clear();
-  std::vector<hopf::SysTables> tabs(nsys);
+  c->ksys.clear();
+  std::vector<hopf::SysTables> tabs(nsys), ktabs;
+  auto fail = [&](int i, hopf_status st) {
+    for (auto &t : tabs) hopf::free_tables(t);
+    for (auto &t : ktabs) hopf::free_tables(t);
+    c->err = "system " + std::to_string(i) + ": " + c->err;
+    return st;
+  };
   for (int i = 0; i < nsys; ++i) {
     hopf_status st = hopf::build_tables(c, sys[i], tabs[i]);
-    if (st != HOPF_OK) {
-      for (auto &t : tabs) hopf::free_tables(t);
-      c->err = "system " + std::to_string(i) + ": " + c->err;
-      return st;
+    if (st != HOPF_OK) return fail(i, st);
+    // Kronecker structure: the reduced system of the copies' mean, target
+    // matrix W_b / k (k (z^T W_b^-1 z) = z^T (W_b / k)^-1 z)
+    hopf::SysTables &t = tabs[i];
+    const int b = hopf::kron_block(t);
+    if (b > 0) {
+      const int k = t.n / b, m = t.m_user;
+      std::vector<double> Ab((size_t)b * b), Bb((size_t)b * m), Wb((size_t)b * b, 0.0), cb(b);
+      for (int r = 0; r < b; ++r) {
+        for (int j = 0; j < b; ++j) Ab[(size_t)r * b + j] = t.A[(size_t)r * t.n + j];
+        for (int j = 0; j < m; ++j) Bb[(size_t)r * m + j] = t.B[(size_t)r * m + j];
+        Wb[(size_t)r * b + r] = t.W[(size_t)r * t.n + r] / k;
+        cb[r] = t.c[r];
+      }
+      hopf_system rs = sys[i];
+      rs.n = b;
+      rs.A = Ab.data();
+      rs.B = Bb.data();
+      rs.W = Wb.data();
+      rs.c = cb.data();
+      rs.Qu = t.Qu.data();
+      ktabs.emplace_back();
+      st = hopf::build_tables(c, rs, ktabs.back());
+      if (st != HOPF_OK) return fail(i, st);
+      t.kron_k = k;
+      t.kron_b = b;
+      t.kron_red = (int)ktabs.size() - 1;
+      t.kron_winv.resize(b);
+      for (int r = 0; r < b; ++r) t.kron_winv[r] = 1.0 / t.W[(size_t)r * t.n + r];
+      if (hipMalloc((void **)&t.kron_winv_d, b * sizeof(double)) != hipSuccess ||
+          hipMemcpy(t.kron_winv_d, t.kron_winv.data(), b * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(i, set_err(c, HOPF_ENOMEM, "device copy of the copies' target weights failed"));
     }
   }
   c->sys.swap(tabs);
+  c->ksys.swap(ktabs);
   return HOPF_OK;
 }
 

@@ -1255,6 +1255,114 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
   status_out[q] = stt;
 }
 
+// ------------------------------------------------------------------ Kronecker-structured systems
+
+// A system of k copies of one b-dimensional system that share the control
+// (A = I_k (x) A_b, B = 1_k (x) B_b, W = I_k (x) W_b, c = 1_k (x) c_b) has
+// x_c(t) = e^{t A_b} x_c + z(u) for every copy c, so with m_c = e^{t A_b} x_c - c_b
+//   sum_c |m_c + z|^2_{W_b^-1} = k |mean + z|^2_{W_b^-1} + sum_c |m_c - mean|^2_{W_b^-1}
+// and phi(x, t) = phi_red(mean of the copies, t) + spread: phi_red the value of
+// the b-dimensional system with target matrix W_b / k, spread =
+// (1/2) sum_c |e^{t A_b}(x_c - mean)|^2_{W_b^-1}.  The minimiser per copy is
+// lambda_c = W_b^-1 e^{t A_b}(x_c - mean) + lambda_red / k.
+
+// x0 of the reduced solve: the mean of point q's k blocks
+__global__ void k_kron_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int k, int b,
+                            int n_pad, int xs, const int *__restrict__ idx) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts * n_pad) return;
+  const long p = i / n_pad;
+  const int r = (int)(i % n_pad);
+  if (r >= b) { x0[i] = 0.0; return; }
+  const long q = idx ? idx[p] : p;
+  double s = 0.0;
+  for (int c = 0; c < k; ++c) s += x[q * xs + (long)c * b + r];
+  x0[i] = s / k;
+}
+
+// v <- e^{T A} v for a system of at most KRON_BMAX states, from its probe-setup
+// tables (the horizon split, binary node powers, base-16 remainder digits and
+// the Taylor series of the probe setup)
+__device__ void small_expm_apply(const SysView &S, double T, double *v) {
+  const int n = S.n;
+  const double q = T / S.h;
+  const double qr = rint(q);
+  int M;
+  double r;
+  if (fabs(q - qr) <= 1e-12 * fmax(1.0, q)) { M = (int)qr; r = 0.0; }
+  else { M = (int)floor(q); r = T - M * S.h; }
+  const int Mmax = S.quad == HOPF_Q_TRAP ? S.N - 1 : S.N;
+  if (M > Mmax) { M = Mmax; r = 0.0; }
+  double w[KRON_BMAX];
+  auto apply = [&](const double *Ec) {   // v <- E v, E stored by columns
+    for (int i = 0; i < n; ++i) {
+      double a = 0.0;
+      for (int k2 = 0; k2 < n; ++k2) a += Ec[(size_t)k2 * n + i] * v[k2];
+      w[i] = a;
+    }
+    for (int i = 0; i < n; ++i) v[i] = w[i];
+  };
+  for (int bb = 0; bb < S.n_hbin; ++bb)
+    if ((M >> bb) & 1) apply(S.hbin + (size_t)bb * n * n);
+  if (r > 0.0) {
+    const long qd = (long)floor(r / S.dr);
+    const long qdig = qd > 4095 ? 4095 : (qd < 0 ? 0 : qd);
+    for (int lv = 0; lv < RDIG_LEVELS; ++lv) {
+      const int d = (int)((qdig >> (4 * lv)) & 15);
+      if (d) apply(S.rdig + ((size_t)lv * 15 + (d - 1)) * n * n);
+    }
+    const double rho = r - (double)qdig * S.dr;
+    if (rho > 0.0) {   // e^{rho A} v = sum_k (rho A)^k v / k!
+      double term[KRON_BMAX], sum[KRON_BMAX];
+      for (int i = 0; i < n; ++i) term[i] = sum[i] = v[i];
+      const double a = rho * S.anorm;
+      double bound = 1.0;
+      for (int kk = 1; kk <= 30; ++kk) {
+        for (int i = 0; i < n; ++i) {
+          double acc = 0.0;
+          for (int k2 = 0; k2 < n; ++k2) acc += S.At[(size_t)k2 * n + i] * term[k2];
+          w[i] = acc * (rho / kk);
+        }
+        for (int i = 0; i < n; ++i) { term[i] = w[i]; sum[i] += w[i]; }
+        bound *= a / kk;
+        if (bound < 1e-17) break;
+      }
+      for (int i = 0; i < n; ++i) v[i] = sum[i];
+    }
+  }
+}
+
+// outputs of a reduced solve in the full system's terms (one thread per point)
+__global__ void k_kron_outputs(SysView S, PtState st, const double *__restrict__ x, int k,
+                               const double *__restrict__ winv, double *philo, double *phihi, double *lam_out,
+                               int *iters_out, int *status_out, const int *__restrict__ idx, int xs) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= st.npts) return;
+  const long q = idx ? idx[p] : p;
+  const int b = S.n, np = S.n_pad;
+  const double T = st.T[p];
+  const bool f64 = st.s64 != nullptr && st.s64[p] != 0;
+  double mean[KRON_BMAX], lred[KRON_BMAX];
+  for (int r = 0; r < b; ++r) {
+    mean[r] = st.x0[p * np + r];
+    lred[r] = f64 ? st.lam64[p * np + r] : (double)st.lam[p * np + r];
+  }
+  double spread = 0.0;
+  for (int c = 0; c < k; ++c) {
+    double d[KRON_BMAX];
+    for (int r = 0; r < b; ++r) d[r] = x[q * xs + (long)c * b + r] - mean[r];
+    small_expm_apply(S, T, d);
+    for (int r = 0; r < b; ++r) {
+      spread += 0.5 * winv[r] * d[r] * d[r];
+      if (lam_out) lam_out[q * xs + (long)c * b + r] = winv[r] * d[r] + lred[r] / k;
+    }
+  }
+  if (philo) philo[q] = -st.P[p] + spread;
+  if (phihi) phihi[q] = -st.D[p] + spread;
+  if (iters_out) iters_out[q] = st.iters_tot[p];
+  status_out[q] = st.status[p];
+}
+
 // ------------------------------------------------------------------ host orchestration
 
 namespace {
@@ -1405,6 +1513,8 @@ namespace {
 struct Job {
   int sid = 0;
   const SysTables *tab = nullptr;
+  const SysTables *kron = nullptr;   // value solve of a Kronecker-structured system: its full tables
+                                     // (tab is then the reduced system's)
   SysView S{};
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
   pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
@@ -1706,6 +1816,16 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.sid = used[j];
     J.tab = &ctx->sys[J.sid];
     J.S = view(*J.tab);
+    if (mode == MODE_VALUE && ho.structure && J.tab->kron_red >= 0) {
+      // the reduced system of the copies' mean; its step ratio sqrt(k) c_tau
+      // makes its iterates those of the full system (||K||^2 is k times the
+      // reduced one's, and the reduced costate is the sum of the copies')
+      J.kron = J.tab;
+      J.tab = &ctx->ksys[J.kron->kron_red];
+      J.S = view(*J.tab);
+      const double ct = J.kron->desc.c_tau > 0.0 ? J.kron->desc.c_tau : ho.c_tau;
+      J.S.c_tau = std::sqrt((double)J.kron->kron_k) * ct;
+    }
     J.npts = cnt[J.sid];
     J.idx = nj > 1 ? d_idx + off[J.sid] : nullptr;
     J.s = nj > 1 ? ctx->pool[j % NPOOL] : base;
@@ -1716,7 +1836,7 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
     if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
     const bool net = (ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
-                     J.sid < (int)ctx->mlp.size() && ctx->mlp[J.sid].valid;
+                     J.sid < (int)ctx->mlp.size() && ctx->mlp[J.sid].valid && !J.kron;
     if (!make_state(ctx, j, *J.tab, J.npts, J.st, (lam0 != nullptr && mode == MODE_MINTIME) || net)) {
       rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
       break;
@@ -1736,9 +1856,13 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     const long np_ = J.npts;
     const hipStream_t s = J.s;
     const long tot = np_ * J.tab->n_pad;
-    const int ls = nj > 1 ? xs : J.tab->n;     // row stride of x, lam0 and lam
+    const int ls = nj > 1 ? xs : (J.kron ? J.kron->n : J.tab->n);     // row stride of x, lam0 and lam
     k_clear<<<1, 64, 0, s>>>(st);
-    k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
+    if (J.kron)
+      k_kron_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.kron->kron_k, J.kron->kron_b,
+                                                                 J.tab->n_pad, ls, J.idx);
+    else
+      k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
     // learned start: the network at every point's first probe, batched on
     // the matrix cores (later probes of mode mlp_lam evaluate it in the setup)
@@ -1853,9 +1977,14 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   for (int j = 0; j < nj; ++j) {
     Job &J = jobs[j];
     if (rc == HOPF_OK && J.st.x0) {
-      k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
-          J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,
-          J.idx, nj > 1 ? xs : J.tab->n);
+      if (J.kron)
+        k_kron_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
+            J.S, J.st, x, J.kron->kron_k, J.kron->kron_winv_d, philo_out, phihi_out, lam_out, iters_out,
+            status_out, J.idx, nj > 1 ? xs : J.kron->n);
+      else
+        k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
+            J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,
+            J.idx, nj > 1 ? xs : J.tab->n);
       hipEvent_t fin = J.s != base ? take_event(ctx) : nullptr;
       if (fin) {
         hipEventRecord(fin, J.s);

@@ -42,7 +42,7 @@ class HopfOpts(C.Structure):
                 ("t_abs_frac", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("warm", C.c_int), ("prec", C.c_int), ("root", C.c_int), ("newton_after", C.c_int),
                 ("newton_rho", C.c_double), ("tail_max", C.c_int), ("adapt", C.c_int), ("scan", C.c_int),
-                ("wide_min", C.c_int), ("deep_max", C.c_int)]
+                ("wide_min", C.c_int), ("deep_max", C.c_int), ("structure", C.c_int)]
 
 
 class HopfTiming(C.Structure):
