@@ -11,7 +11,9 @@ Workload shapes follow the paper's examples and the configurations the
 library is benchmarked on:
   * the double integrator of Sec. VI-A (n=2, m=1, |u| <= 1, ball target);
   * its tychastic (sampled initial state) extension of Sec. VI-B/C: k copies
-    sharing one control, d = 2k, a mean-squared-error target;
+    sharing one control, d = 2k, a mean-squared-error target, with either
+    random samples (equal weights) or the 5 sigma points of the unscented
+    transform (d = 10, weighted target);
   * random stable-ish linear systems: A = S diag(eig) S^{-1} with
     eig ~ U[-1, 0.2] and S_ij ~ N(0, 1/n), B_ij ~ N(0,1)/sqrt(n), an
     axis-aligned ellipsoid target W = diag(q), q ~ U[0.05, 0.2], and either
@@ -84,6 +86,47 @@ def tychastic_points(k, npts, mu, std, seed):
     rng = np.random.default_rng(seed)
     return (np.asarray(mu, dtype=np.float64)[None, None, :]
             + std * rng.normal(size=(npts, k, 2))).reshape(npts, 2 * k)
+
+
+def unscented_weights(n, alpha=1.0, kappa=None):
+    """Mean weights of the 2n+1 sigma points of the scaled unscented transform
+    (Julier 2002; Thrun et al. 2005, Sec. 3.4): lam = alpha^2 (n + kappa) - n,
+    w_0 = lam / (n + lam), w_i = 1 / (2 (n + lam)).  kappa defaults to 3 - n,
+    which with alpha = 1 keeps every weight positive for n = 2 (1/3 and 1/6)."""
+    if kappa is None:
+        kappa = 3.0 - n
+    lam = alpha * alpha * (n + kappa) - n
+    w = np.full(2 * n + 1, 1.0 / (2.0 * (n + lam)))
+    w[0] = lam / (n + lam)
+    return w, lam
+
+
+def unscented_double_integrator(ell=0.04, N=100, t_max=2.0, quad="left"):
+    """Sec. VI-B: the double integrator augmented by its 2n+1 = 5 sigma points
+    (d = 10), one shared scalar control in [-1, 1], and the target that bounds
+    the weighted mean squared distance sum_i w_i |chi_i(T)|^2 of the terminal
+    sigma points from the origin by ell.  In the ellipsoid form {z : z^T W^-1 z
+    <= 1} that is W = blockdiag((ell / w_i) I_2), the paper's blocks
+    w_i^-1 I_2 scaled by the threshold."""
+    A2 = np.array([[0.0, 1.0], [0.0, 0.0]])
+    B2 = np.array([[0.0], [1.0]])
+    w, _ = unscented_weights(2)
+    k = len(w)
+    W = np.kron(np.diag(ell / w), np.eye(2))
+    return SystemSpec(np.kron(np.eye(k), A2), np.kron(np.ones((k, 1)), B2), W, np.zeros(2 * k), "box", N,
+                      t_max, quad, "unscented_double_integrator")
+
+
+def unscented_points(npts, mu_lo, mu_hi, std, seed):
+    """Each query point stacks the 2n+1 sigma points (mu; mu + s e_i; mu - s e_i,
+    s = std sqrt(n + lam)) of x0 ~ N(mu, std^2 I_2), mu uniform in the box
+    [mu_lo, mu_hi]; the weighted sigma points reproduce mu and std^2 I_2."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(np.asarray(mu_lo, dtype=np.float64), np.asarray(mu_hi, dtype=np.float64), size=(npts, 2))
+    _, lam = unscented_weights(2)
+    s = std * np.sqrt(2.0 + lam)
+    off = np.concatenate([np.zeros((1, 2)), s * np.eye(2), -s * np.eye(2)])
+    return (mu[:, None, :] + off[None, :, :]).reshape(npts, 10)
 
 
 def random_system(n, m, N, uset, seed, t_max=10.0, quad="trap",

@@ -26,10 +26,12 @@ struct SysTables {
   int n = 0, m = 0, N = 0, n_pad = 0, nkb = 0;
   int m_user = 0;                      // the caller's m; m >= m_user is the padded kernel size
   // k > 1 copies of a b-dimensional system that share the control: A =
-  // I_k (x) A_b, B = 1_k (x) B_b, W = I_k (x) W_b (diagonal), c = 1_k (x) c_b;
-  // value solves then run on the reduced system (ctx->ksys[kron_red])
+  // I_k (x) A_b, B = 1_k (x) B_b, c = 1_k (x) c_b, W = blockdiag(W_b / alpha_c)
+  // (W_b diagonal, alpha_0 = 1); value solves then run on the reduced system
+  // (ctx->ksys[kron_red], target W_b / sum alpha)
   int kron_k = 0, kron_b = 0, kron_red = -1;
-  std::vector<double> kron_winv;       // [b] 1 / diag(W_b)
+  double kron_atot = 0.0;              // sum of the copies' weights alpha_c
+  std::vector<double> kron_winv;       // [b] 1 / diag(W_b), then [k] alpha_c
   double *kron_winv_d = nullptr;
   double h = 0.0, delta = 0.0;
   // host tables

@@ -600,9 +600,10 @@ namespace hopf {
 
 // The smallest block size b (n = k b, k > 1) for which the system is k copies
 // of one b-dimensional system sharing the control (A = I_k (x) A_b, B = 1_k (x)
-// B_b, W = I_k (x) W_b with W_b diagonal, c = 1_k (x) c_b), or 0.  Blocks must
-// match to 1e-14 relative; the system's own coordinates (not rotated).
-int kron_block(const SysTables &t) {
+// B_b, c = 1_k (x) c_b, W block-diagonal with blocks W_b / alpha_c, W_b
+// diagonal, alpha_0 = 1, alpha_c > 0), or 0; alpha receives the k weights.
+// Blocks must match to 1e-14 relative; the system's own coordinates.
+int kron_block(const SysTables &t, std::vector<double> &alpha) {
   const int n = t.n, m = t.m_user;
   if (t.rotated) return 0;
   double amax = 0.0, bmax = 0.0;
@@ -622,8 +623,16 @@ int kron_block(const SysTables &t) {
       }
     for (int i = b; i < n && ok; ++i)
       for (int j = 0; j < m && ok; ++j) ok = close(t.B[(size_t)i * m + j], t.B[(size_t)(i % b) * m + j], bmax);
-    for (int i = b; i < n && ok; ++i)
-      ok = t.W[(size_t)i * n + i] == t.W[(size_t)(i % b) * n + (i % b)] && t.c[i] == t.c[i % b];
+    alpha.assign(k, 1.0);
+    for (int cc = 1; cc < k && ok; ++cc) {
+      const double a = t.W[0] / t.W[(size_t)(cc * b) * n + cc * b];
+      ok = a > 0.0 && std::isfinite(a);
+      for (int r = 0; r < b && ok; ++r) {
+        const int i = cc * b + r;
+        ok = close(t.W[(size_t)r * n + r] / t.W[(size_t)i * n + i], a, a) && t.c[i] == t.c[r];
+      }
+      alpha[cc] = a;
+    }
     if (ok && k > 1) return b;
   }
   return 0;
@@ -653,17 +662,20 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
   for (int i = 0; i < nsys; ++i) {
     hopf_status st = hopf::build_tables(c, sys[i], tabs[i]);
     if (st != HOPF_OK) return fail(i, st);
-    // Kronecker structure: the reduced system of the copies' mean, target
-    // matrix W_b / k (k (z^T W_b^-1 z) = z^T (W_b / k)^-1 z)
+    // Kronecker structure: the reduced system of the copies' weighted mean,
+    // target matrix W_b / a with a = sum_c a_c (a z^T W_b^-1 z = z^T (W_b / a)^-1 z)
     hopf::SysTables &t = tabs[i];
-    const int b = hopf::kron_block(t);
+    std::vector<double> alpha;
+    const int b = hopf::kron_block(t, alpha);
     if (b > 0) {
       const int k = t.n / b, m = t.m_user;
+      double atot = 0.0;
+      for (double a : alpha) atot += a;
       std::vector<double> Ab((size_t)b * b), Bb((size_t)b * m), Wb((size_t)b * b, 0.0), cb(b);
       for (int r = 0; r < b; ++r) {
         for (int j = 0; j < b; ++j) Ab[(size_t)r * b + j] = t.A[(size_t)r * t.n + j];
         for (int j = 0; j < m; ++j) Bb[(size_t)r * m + j] = t.B[(size_t)r * m + j];
-        Wb[(size_t)r * b + r] = t.W[(size_t)r * t.n + r] / k;
+        Wb[(size_t)r * b + r] = t.W[(size_t)r * t.n + r] / atot;
         cb[r] = t.c[r];
       }
       hopf_system rs = sys[i];
@@ -679,10 +691,13 @@ hopf_status hopf_set_systems(hopf_ctx *h, int nsys, const hopf_system *sys) {
       t.kron_k = k;
       t.kron_b = b;
       t.kron_red = (int)ktabs.size() - 1;
-      t.kron_winv.resize(b);
+      // [winv (b) | alpha (k)]: 1 / diag(W_b) and the copies' weights
+      t.kron_winv.resize(b + k);
       for (int r = 0; r < b; ++r) t.kron_winv[r] = 1.0 / t.W[(size_t)r * t.n + r];
-      if (hipMalloc((void **)&t.kron_winv_d, b * sizeof(double)) != hipSuccess ||
-          hipMemcpy(t.kron_winv_d, t.kron_winv.data(), b * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      for (int cc = 0; cc < k; ++cc) t.kron_winv[b + cc] = alpha[cc];
+      t.kron_atot = atot;
+      if (hipMalloc((void **)&t.kron_winv_d, (b + k) * sizeof(double)) != hipSuccess ||
+          hipMemcpy(t.kron_winv_d, t.kron_winv.data(), (b + k) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return fail(i, set_err(c, HOPF_ENOMEM, "device copy of the copies' target weights failed"));
     }
   }

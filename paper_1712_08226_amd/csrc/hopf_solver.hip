@@ -1258,17 +1258,20 @@ __global__ void k_outputs(SysView S, PtState st, int mode, double *T_out, double
 // ------------------------------------------------------------------ Kronecker-structured systems
 
 // A system of k copies of one b-dimensional system that share the control
-// (A = I_k (x) A_b, B = 1_k (x) B_b, W = I_k (x) W_b, c = 1_k (x) c_b) has
-// x_c(t) = e^{t A_b} x_c + z(u) for every copy c, so with m_c = e^{t A_b} x_c - c_b
-//   sum_c |m_c + z|^2_{W_b^-1} = k |mean + z|^2_{W_b^-1} + sum_c |m_c - mean|^2_{W_b^-1}
-// and phi(x, t) = phi_red(mean of the copies, t) + spread: phi_red the value of
-// the b-dimensional system with target matrix W_b / k, spread =
-// (1/2) sum_c |e^{t A_b}(x_c - mean)|^2_{W_b^-1}.  The minimiser per copy is
-// lambda_c = W_b^-1 e^{t A_b}(x_c - mean) + lambda_red / k.
+// (A = I_k (x) A_b, B = 1_k (x) B_b, c = 1_k (x) c_b, target blocks W_b / a_c)
+// has x_c(t) = e^{t A_b} x_c + z(u) for every copy c, so with m_c =
+// e^{t A_b} x_c - c_b, a = sum_c a_c and the weighted mean mean = sum_c a_c m_c / a
+//   sum_c a_c |m_c + z|^2_{W_b^-1} = a |mean + z|^2_{W_b^-1} + sum_c a_c |m_c - mean|^2_{W_b^-1}
+// and phi(x, t) = phi_red(weighted mean of the copies, t) + spread: phi_red the
+// value of the b-dimensional system with target matrix W_b / a, spread =
+// (1/2) sum_c a_c |e^{t A_b}(x_c - mean)|^2_{W_b^-1}.  The minimiser per copy is
+// lambda_c = a_c (W_b^-1 e^{t A_b}(x_c - mean) + lambda_red / a).
+// wts = [1 / diag(W_b) (b) | a_c (k)].
 
-// x0 of the reduced solve: the mean of point q's k blocks
+// x0 of the reduced solve: the weighted mean of point q's k blocks
 __global__ void k_kron_pack(const double *__restrict__ x, double *__restrict__ x0, long npts, int k, int b,
-                            int n_pad, int xs, const int *__restrict__ idx) {
+                            int n_pad, int xs, const int *__restrict__ idx, const double *__restrict__ wts,
+                            double atot) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npts * n_pad) return;
   const long p = i / n_pad;
@@ -1276,8 +1279,8 @@ __global__ void k_kron_pack(const double *__restrict__ x, double *__restrict__ x
   if (r >= b) { x0[i] = 0.0; return; }
   const long q = idx ? idx[p] : p;
   double s = 0.0;
-  for (int c = 0; c < k; ++c) s += x[q * xs + (long)c * b + r];
-  x0[i] = s / k;
+  for (int c = 0; c < k; ++c) s += wts[b + c] * x[q * xs + (long)c * b + r];
+  x0[i] = s / atot;
 }
 
 // v <- e^{T A} v for a system of at most KRON_BMAX states, from its probe-setup
@@ -1334,8 +1337,9 @@ __device__ void small_expm_apply(const SysView &S, double T, double *v) {
 
 // outputs of a reduced solve in the full system's terms (one thread per point)
 __global__ void k_kron_outputs(SysView S, PtState st, const double *__restrict__ x, int k,
-                               const double *__restrict__ winv, double *philo, double *phihi, double *lam_out,
-                               int *iters_out, int *status_out, const int *__restrict__ idx, int xs) {
+                               const double *__restrict__ wts, double atot, double *philo, double *phihi,
+                               double *lam_out, int *iters_out, int *status_out, const int *__restrict__ idx,
+                               int xs) {
   const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= st.npts) return;
   const long q = idx ? idx[p] : p;
@@ -1349,12 +1353,13 @@ __global__ void k_kron_outputs(SysView S, PtState st, const double *__restrict__
   }
   double spread = 0.0;
   for (int c = 0; c < k; ++c) {
+    const double ac = wts[b + c];
     double d[KRON_BMAX];
     for (int r = 0; r < b; ++r) d[r] = x[q * xs + (long)c * b + r] - mean[r];
     small_expm_apply(S, T, d);
     for (int r = 0; r < b; ++r) {
-      spread += 0.5 * winv[r] * d[r] * d[r];
-      if (lam_out) lam_out[q * xs + (long)c * b + r] = winv[r] * d[r] + lred[r] / k;
+      spread += 0.5 * ac * wts[r] * d[r] * d[r];
+      if (lam_out) lam_out[q * xs + (long)c * b + r] = ac * (wts[r] * d[r] + lred[r] / atot);
     }
   }
   if (philo) philo[q] = -st.P[p] + spread;
@@ -1860,7 +1865,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     k_clear<<<1, 64, 0, s>>>(st);
     if (J.kron)
       k_kron_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.kron->kron_k, J.kron->kron_b,
-                                                                 J.tab->n_pad, ls, J.idx);
+                                                                 J.tab->n_pad, ls, J.idx, J.kron->kron_winv_d,
+                                                                 J.kron->kron_atot);
     else
       k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
@@ -1979,8 +1985,8 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     if (rc == HOPF_OK && J.st.x0) {
       if (J.kron)
         k_kron_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
-            J.S, J.st, x, J.kron->kron_k, J.kron->kron_winv_d, philo_out, phihi_out, lam_out, iters_out,
-            status_out, J.idx, nj > 1 ? xs : J.kron->n);
+            J.S, J.st, x, J.kron->kron_k, J.kron->kron_winv_d, J.kron->kron_atot, philo_out, phihi_out, lam_out,
+            iters_out, status_out, J.idx, nj > 1 ? xs : J.kron->n);
       else
         k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
             J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,

@@ -14,7 +14,8 @@ import sys
 import numpy as np
 import pytest
 
-from gen import double_integrator, tychastic_double_integrator, tychastic_points
+from gen import (double_integrator, tychastic_double_integrator, tychastic_points, unscented_double_integrator,
+                 unscented_points)
 from gen.configs import config_tychastic
 from oracle import hopf_oracle as O
 
@@ -122,7 +123,7 @@ def kron_system(k, b, m, uset, seed, N=60, t_max=3.0):
                       uset, N, t_max, "trap", f"kron_k{k}_b{b}")
 
 
-@pytest.mark.parametrize("case", ["tychastic30", "kron_l2", "kron_box"])
+@pytest.mark.parametrize("case", ["tychastic30", "unscented10", "kron_l2", "kron_box"])
 def test_structured_value_matches_full_system(solver, case):
     """Value solves of a system of copies sharing the control run on the
     reduced system of the copies' mean (hopf_opts.structure): the certified
@@ -134,18 +135,30 @@ def test_structured_value_matches_full_system(solver, case):
         x = tychastic_points(15, 70, (1.0, 0.0), 0.0667, 41)
         t = np.linspace(0.4, 2.0, 70)
         c_tau = 0.5
+    elif case == "unscented10":
+        # sigma points (weights 1/3, 1/6 in the target); half of them moved
+        # off the sigma pattern so that the weighted mean differs from chi_0
+        spec = unscented_double_integrator(ELL)
+        x = unscented_points(70, (0.6, -0.3), (1.4, 0.3), 0.0667, 43)
+        x[35:] += 0.05 * np.random.default_rng(44).normal(size=(35, 10))
+        t = np.linspace(0.4, 2.0, 70)
+        c_tau = 0.5
     else:
         spec = kron_system(5, 3, 2, "l2" if case == "kron_l2" else "box", seed=7)
         x = np.random.default_rng(8).normal(0, 0.5, (70, spec.A.shape[0]))
         t = np.linspace(0.2, 0.5 * spec.t_max, 70)     # on and off the table grid
         c_tau = 1.0
     solver.set_systems([spec])
-    res = {}
+    res, width = {}, {}
     for st in (1, 0):
         solver.set_opts(prec="fp32", c_tau=c_tau, structure=st, max_iter=400000)
         res[st] = solver.value(x, t)
         tm = solver.last_timing()
-        say("structure", st, "iterations mean", res[st]["iters"].mean(), "device s", tm["total_s"])
+        # algorithmic flops per point-row are 4 m n: n of the system the iterations ran on
+        width[st] = tm["alg_flops"] / (4 * spec.B.shape[1] * (tm["point_rows"] + tm["tail_point_rows"]))
+        say("structure", st, "iterations mean", res[st]["iters"].mean(), "device s", tm["total_s"],
+            "iterated dimension", width[st])
+    assert round(width[1]) == (3 if case.startswith("kron") else 2) and round(width[0]) == spec.A.shape[0]
     a, b = res[1], res[0]
     assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
     ga = (a["phi_hi"] - a["phi_lo"]) / np.maximum(1.0, np.abs(a["phi_hi"]))

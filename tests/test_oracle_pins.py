@@ -8,7 +8,8 @@ import pytest
 from scipy.linalg import expm
 
 from oracle import hopf_oracle as O
-from gen import double_integrator, random_system, tychastic_double_integrator, tychastic_points
+from gen import (double_integrator, random_system, tychastic_double_integrator, tychastic_points,
+                 unscented_weights, unscented_double_integrator, unscented_points)
 from tests import pin_helpers as PH
 
 
@@ -515,6 +516,53 @@ def test_tychastic_value_splits_into_mean_and_spread():
             lo, hi = b.phi_lo + s / (2 * ell), b.phi_hi + s / (2 * ell)
             assert max(a.phi_lo, lo) <= min(a.phi_hi, hi) + 1e-9, (T, a.phi_lo, a.phi_hi, lo, hi)
             assert abs(s / (2 * ell)) > 1e-3     # the spread term is not negligible
+
+
+def test_sigma_points_reproduce_the_moments():
+    """The 2n+1 sigma points with their mean weights reproduce the mean and
+    covariance of N(mu, std^2 I_2) exactly; the weights sum to one and, with
+    kappa = 3 - n, are all positive (so the weighted target is an ellipsoid)."""
+    w, lam = unscented_weights(2)
+    assert abs(w.sum() - 1.0) <= 1e-15 and np.all(w > 0) and lam == 1.0
+    X = unscented_points(4, (0.5, -0.3), (1.5, 0.3), 0.0667, 3).reshape(4, 5, 2)
+    mu = np.einsum("i,qia->qa", w, X)
+    assert np.allclose(mu, X[:, 0, :], atol=1e-15)
+    D = X - mu[:, None, :]
+    C = np.einsum("i,qia,qib->qab", w, D, D)
+    assert np.allclose(C, 0.0667 ** 2 * np.eye(2)[None], atol=1e-15)
+
+
+def test_unscented_value_splits_into_weighted_mean_and_spread():
+    """Sigma points weighted by w_i in the target (W blocks ell / w_i): as for
+    equal samples the copies share the control, so the value of the 10-dim
+    system splits exactly into the double integrator's value at the weighted
+    mean with the disk of radius sqrt(ell) (sum_i w_i = 1) plus
+    sum_i w_i |e^{TA}(chi_i - mean)|^2 / (2 ell).  Points with their sigma
+    points off-centre (mean != chi_0) make the weighting matter."""
+    ell = 0.04
+    w, _ = unscented_weights(2)
+    S = sysobj(unscented_double_integrator(ell, N=100, t_max=2.0, quad="left"))
+    S2 = sysobj(double_integrator(math.sqrt(ell), 100, t_max=2.0, quad="left"))
+    opt = O.Options(c_tau=0.5, gap_tol=1e-10, max_iter=400000)
+    rng = np.random.default_rng(5)
+    X = unscented_points(2, (0.8, -0.2), (1.2, 0.2), 0.0667, 22)
+    X = X + 0.05 * rng.normal(size=X.shape)          # a general stack of 5 states
+    for x in X:
+        chi = x.reshape(5, 2)
+        mean = w @ chi
+        for T in (0.7, 2.0):
+            E = np.array([[1.0, T], [0.0, 1.0]])
+            s = float(w @ np.sum(((chi - mean) @ E.T) ** 2, axis=1))
+            a = O.solve_value(S, x, T, opt)
+            b = O.solve_value(S2, mean, T, opt)
+            assert a.gap_n() <= 1e-10 and b.gap_n() <= 1e-10
+            lo, hi = b.phi_lo + s / (2 * ell), b.phi_hi + s / (2 * ell)
+            assert max(a.phi_lo, lo) <= min(a.phi_hi, hi) + 1e-9, (T, a.phi_lo, a.phi_hi, lo, hi)
+            # the plain (unweighted) mean and spread do not give the value
+            um = chi.mean(axis=0)
+            us = float(np.mean(np.sum(((chi - um) @ E.T) ** 2, axis=1)))
+            c = O.solve_value(S2, um, T, opt)
+            assert abs(c.phi_hi + us / (2 * ell) - a.phi_hi) > 1e-4
 
 
 @pytest.mark.parametrize("T", [3.0, 1.37])
