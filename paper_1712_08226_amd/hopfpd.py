@@ -184,7 +184,10 @@ class Solver:
 
     def set_opts(self, **kw):
         o = default_opts()
+        names = {f[0] for f in HopfOpts._fields_}
         for k, v in kw.items():
+            if k not in names:
+                raise TypeError(f"unknown solver option {k!r}")
             if k == "prec":
                 v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(v, v)
             if k == "warm":

@@ -74,3 +74,12 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_set_opts_rejects_unknown_option_names():
+    """A misspelt option must not be dropped silently (ctypes structures
+    accept any attribute); the check runs before the library is called."""
+    class NoCtx:
+        pass
+    with pytest.raises(TypeError, match="unknown solver option"):
+        H.Solver.set_opts(NoCtx(), wide_minn=1)
