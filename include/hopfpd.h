@@ -164,7 +164,8 @@ typedef struct {
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
  *                 launch) finishes them; 0 keeps every point on the 16-point tiles
- *                 (at most 512: two workgroups per compute unit)                     [512]
+ *                 (at most 8192; workgroups beyond two per compute unit wait
+ *                 for a free slot)                                                  [2048]
  *   adapt         tail solver: adapt each point's step ratio at restarts (not in the
  *                 paper): when the certified gap has fallen to 0.2 of its value at the
  *                 last restart (or to 0.8 and rises again), the primal weight
@@ -318,9 +319,9 @@ hopf_status hopf_warm_train(hopf_ctx *ctx, int sys_id, long npts, const double *
 
 /* Device time and work of the last solve call, for throughput and roofline
  * reporting.  A call runs rounds of tiled kernels (16 points per tile: probe
- * setup, fused iteration kernel, FP64 certificate) and, once at most 512 of
- * a system's points remain (FP32 iterations), a per-point tail solver that
- * finishes them in one launch.
+ * setup, fused iteration kernel, FP64 certificate) and, once at most
+ * hopf_opts.tail_max of a system's points remain (FP32 iterations), a
+ * per-point tail solver that finishes them in one launch.
  *   total_s          HIP events around the whole call
  *   iter_kernel_s    the tiled iteration kernels alone, summed over launches
  *                    (the launches of a multi-system call can overlap)

@@ -510,7 +510,7 @@ hopf_status hopf_default_opts(hopf_opts *o) {
   o->root = HOPF_ROOT_BISECT;
   o->newton_after = 1;
   o->newton_rho = 0.5;
-  o->tail_max = 512;
+  o->tail_max = 2048;
   o->adapt = 1;
   o->scan = 48;
   o->wide_min = 16384;
@@ -589,7 +589,7 @@ hopf_status hopf_set_opts(hopf_ctx *h, const hopf_opts *o) {
   if (!(o->c_tau > 0.0) || !(o->gap_tol > 0.0) || !(o->t_rel_tol >= 0.0) || !(o->t_abs_frac >= 0.0) ||
       o->max_iter < 1 || o->check_every < 1 || o->warm < 0 || o->warm > 4 || o->prec < 0 || o->prec > 2 ||
       o->root < 0 || o->root > 1 || o->newton_after < 0 || !(o->newton_rho > 0.0) ||
-      o->tail_max < 0 || o->tail_max > 512 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0 ||
+      o->tail_max < 0 || o->tail_max > 8192 || o->adapt < 0 || o->adapt > 1 || o->scan < 1 || o->scan > 4096 || o->wide_min < 0 ||
       o->deep_max < -1 || o->structure < 0 || o->structure > 1)
     return set_err(c, HOPF_EINVAL, "invalid solver options");
   c->opts = *o;

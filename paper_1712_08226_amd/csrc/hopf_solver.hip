@@ -612,7 +612,7 @@ __global__ __launch_bounds__(256) void k_setup(SysView S, PtState st, Opts o, Ml
 // step (decide) every check_every iterations, and the next probe's setup in
 // place.  The arithmetic is the same as the tiled path's (same tables, same
 // projections, same certificate); only the summation order differs.
-constexpr int TAIL_MAX_POINTS = 512;
+constexpr int TAIL_MAX_POINTS = 8192;
 
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll

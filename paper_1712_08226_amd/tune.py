@@ -15,7 +15,7 @@ import itertools
 
 import numpy as np
 
-DEFAULT_GRID = {"check_every": (50, 75, 100), "wide_min": (16384, 32768), "tail_max": (256, 512)}
+DEFAULT_GRID = {"check_every": (50, 75, 100), "wide_min": (16384, 32768), "tail_max": (512, 2048)}
 
 
 def _same(ref, r, mode, rel=1e-4):

@@ -303,6 +303,41 @@ def test_min_time_newton_vs_oracle(solver, prec, case, tail):
 
 # ------------------------------------------------------------------ per-point tail solver
 
+def test_tail_solver_beyond_resident_workgroups(solver):
+    """More tail points than workgroups resident at once (two per compute
+    unit): the later workgroups queue behind the first and every point is
+    still solved as on the tiles."""
+    say("case: tail beyond residency")
+    spec = random_system(24, 4, 60, "l2", seed=78, t_max=4.0)
+    solver.set_systems([spec])
+    from gen.workloads import planted_drift_points
+    x, _ = planted_drift_points(spec, 1500, 0.2, 3.0, seed=14)
+    res = {}
+    for tail in (0, 2048):
+        solver.set_opts(prec="fp32", c_tau=1.0, warm="cont", tail_max=tail, adapt=0)
+        res[tail] = solver.min_time(x)
+        tm = solver.last_timing()
+        say("tail", tail, "points", tm["tail_points"], "s", tm["tail_kernel_s"])
+        assert tm["tail_points"] == (len(x) if tail else 0)
+    a, b = res[0], res[2048]
+    assert np.array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    assert ok.mean() > 0.9
+    assert np.all(b["gap"][ok] <= GAP)
+    # a horizon where |phi| is within the gap tolerance counts as reached, so
+    # inside a cell where phi changes sign more than once the two summation
+    # orders may close on different crossings; each T must still be one
+    diff = np.flatnonzero(ok & (np.abs(a["T"] - b["T"]) > 1e-4 * a["T"]))
+    say("points with different T:", len(diff))
+    assert len(diff) <= 0.01 * len(x)
+    if len(diff):
+        solver.set_opts(prec="fp32", c_tau=1.0, max_iter=400000)
+        for r in (a, b):
+            v = solver.value(x[diff], r["T"][diff])
+            assert np.all(v["status"] == 0)
+            assert np.all(v["phi_lo"] <= 2e-6 * np.maximum(1.0, np.abs(v["phi_hi"]))), (diff, v["phi_lo"])
+
+
 @pytest.mark.parametrize("mode,uset,quad", [("min_time", "l2", "trap"), ("min_time", "box", "trap"),
                                             ("min_time", "l2", "left"), ("value", "l2", "trap"),
                                             ("value", "box", "left")])
