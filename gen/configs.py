@@ -16,7 +16,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .workloads import (double_integrator, random_system, uniform_box_points, gaussian_points,
-                        planted_drift_points, tychastic_double_integrator, tychastic_points)
+                        planted_drift_points, tychastic_double_integrator, tychastic_points,
+                        unscented_double_integrator, unscented_points)
 
 
 @dataclass
@@ -129,6 +130,18 @@ def config_tychastic(d=30, npts=65536, seed=6):
     x = tychastic_points(k, npts, (1.0, 0.0), 0.0667, seed + d)
     return Workload(f"tychastic_d{d}", [spec], x, None, dict(prec="fp32", c_tau=0.5, t=2.0),
                     dict(points="k samples of N((1,0), 0.0667^2 I) per point"))
+
+
+def config_unscented(npts=65536, seed=7):
+    """The unscented control problem of Sec. VI-B: the double integrator's
+    five sigma points of N(mu, 0.0667^2 I) (d = 10) sharing one control in
+    [-1, 1], target: the weighted mean squared terminal distance from the
+    origin <= 0.04; mu uniform in [0.8, 1.2] x [-0.2, 0.2] around the start
+    point of Sec. VI-A.  Value solves at t = t_max = 2, left rule, N = 100."""
+    spec = unscented_double_integrator(ell=0.04, N=100, t_max=2.0, quad="left")
+    x = unscented_points(npts, (0.8, -0.2), (1.2, 0.2), 0.0667, seed)
+    return Workload("unscented_d10", [spec], x, None, dict(prec="fp32", c_tau=0.5, t=2.0),
+                    dict(points="the 5 sigma points of N(mu, 0.0667^2 I), mu ~ U([0.8,1.2] x [-0.2,0.2])"))
 
 
 def config_grid(per_axis=50):
