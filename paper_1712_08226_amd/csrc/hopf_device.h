@@ -925,9 +925,11 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
 // 1e-5 of it; any point of w_k C gives a valid bound).  Then the sign / gap
 // decision and the bisection update (paper Sec. IV).  Same tiling as the
 // iteration kernel: 16 points per workgroup, node blocks split over waves,
-// operands from the FP64 copies of the two table layouts.
+// operands from the FP64 copies of the two table layouts.  Two workgroups
+// per CU up to NT = 7 (n_pad <= 112): the register cap spills a few values
+// there but cuts the launch time by a third; wider tiles would spill hundreds.
 template <int NT>
-__global__ __launch_bounds__(THREADS) void k_certify(SysView S, PtState st, Opts o, int mode) {
+__global__ __launch_bounds__(THREADS, NT <= 7 ? 2 : 1) void k_certify(SysView S, PtState st, Opts o, int mode) {
   const int part = 2;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tile = blockIdx.x;

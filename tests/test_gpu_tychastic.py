@@ -83,6 +83,27 @@ def test_tychastic_min_time_vs_oracle(solver):
         assert abs(r["T"][i] - o.T) <= 1e-4 * o.T + 1e-6 * spec.t_max, (i, r["T"][i], o.T)
 
 
+def test_unscented_min_time_vs_oracle(solver):
+    """The unscented problem of Sec. VI-B is a minimum-time one: the first
+    time the weighted mean squared distance of the five terminal sigma points
+    from the origin falls to the threshold (the full 10-state system)."""
+    say("case: unscented min time d 10")
+    spec = unscented_double_integrator(ELL)
+    solver.set_systems([spec])
+    solver.set_opts(prec="fp32", c_tau=0.5)
+    x = unscented_points(40, (0.8, -0.2), (1.2, 0.2), 0.0667, 79)
+    r = solver.min_time(x)
+    assert np.all(np.isin(r["status"], (0, 2))), np.unique(r["status"], return_counts=True)
+    assert np.mean(r["status"] == 0) > 0.5
+    S = osys(spec)
+    for i in (0, 7, 19, 33, 39):
+        o = O.min_time(S, x[i], O.Options(c_tau=0.5))
+        assert r["status"][i] == o.status, (i, r["status"][i], o.status)
+        if o.status == O.PT_OK:
+            assert abs(r["T"][i] - o.T) <= 1e-4 * o.T + 1e-6 * spec.t_max, (i, r["T"][i], o.T)
+            assert r["gap"][i] <= GAP
+
+
 def test_tychastic_full_size_sampled(solver):
     """The benchmark's d = 120 launch (65,536 value solves at t = t_max):
     every solve certified, and sampled points equal the oracle's 2-D value at
