@@ -518,6 +518,20 @@ def test_tychastic_value_splits_into_mean_and_spread():
             assert abs(s / (2 * ell)) > 1e-3     # the spread term is not negligible
 
 
+@pytest.mark.slow
+def test_unscented_with_no_spread_is_the_double_integrator():
+    """Five equal sigma points (zero covariance): the weights sum to one, so
+    the weighted target is the disk of radius sqrt(ell) and the 10-state
+    problem's minimum time is the double integrator's, against one-switch
+    bang-bang brute force within the single system's quadrature bound."""
+    r = 0.1
+    S = sysobj(unscented_double_integrator(ell=r * r, N=100, t_max=10.0, quad="trap"))
+    res = O.min_time(S, np.tile([1.0, 0.0], 5), O.Options(c_tau=30.0))
+    Tc = PH.di_min_time_ball(1.0, 0.0, r)
+    assert res.status == O.PT_OK
+    assert abs(res.T - Tc) <= 3e-4 * Tc + 0.02 * O.grid_step(S) ** 2, (res.T, Tc)
+
+
 def test_sigma_points_reproduce_the_moments():
     """The 2n+1 sigma points with their mean weights reproduce the mean and
     covariance of N(mu, std^2 I_2) exactly; the weights sum to one and, with
