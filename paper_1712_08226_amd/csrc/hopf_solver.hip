@@ -1822,9 +1822,11 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.tab = &ctx->sys[J.sid];
     J.S = view(*J.tab);
     if (mode == MODE_VALUE && ho.structure && J.tab->kron_red >= 0) {
-      // the reduced system of the copies' mean; its step ratio sqrt(k) c_tau
-      // makes its iterates those of the full system (||K||^2 is k times the
-      // reduced one's, and the reduced costate is the sum of the copies')
+      // the reduced system of the copies' weighted mean; with equal weights
+      // its step ratio sqrt(k) c_tau makes its iterates those of the full
+      // system (||K||^2 is k times the reduced one's, and the reduced costate
+      // is the sum of the copies'); with unequal weights the same ratio is a
+      // choice of step only (the certified result does not depend on it)
       J.kron = J.tab;
       J.tab = &ctx->ksys[J.kron->kron_red];
       J.S = view(*J.tab);
