@@ -151,15 +151,18 @@ typedef struct {
  *                 are active, each tile's node blocks are spread over 8 waves
  *                 instead of 4; -1: 16 points per compute unit of the device,
  *                 0: never                                                           [-1]
- *   structure     value solves of a system made of k > 1 copies of one b-dimensional
+ *   structure     value solves and minimum-time searches (those without a caller's
+ *                 lam0) of a system made of k > 1 copies of one b-dimensional
  *                 system that share the control (A = I_k (x) A_b, B = 1_k (x) B_b,
  *                 W block-diagonal with blocks W_b / a_c, W_b diagonal, a_c > 0,
  *                 c = 1_k (x) c_b: the sampled-copy systems of Sec. VI-B/C, equal
  *                 or sigma-point weights) run on the b-dimensional system of the
  *                 copies' a-weighted mean with target matrix W_b / sum_c a_c; the
  *                 value adds the spread (1/2) sum_c a_c |e^{tA_b}(x_c - mean)|^2_{W_b^-1}
- *                 in FP64 and lambda is rebuilt per copy.  Exact (the copies share
- *                 z(u) in x_c(t) = e^{tA_b} x_c + z(u)); 0: solve the full system  [1]
+ *                 in FP64 (a search adds it to the certified bounds at every probe
+ *                 horizon, and its points skip the tail solver) and lambda is
+ *                 rebuilt per copy.  Exact (the copies share z(u) in
+ *                 x_c(t) = e^{tA_b} x_c + z(u)); 0: solve the full system            [1]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one

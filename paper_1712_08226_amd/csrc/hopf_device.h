@@ -77,6 +77,10 @@ struct PtState {
   double *wbef;              // bracket width when the running probe was placed
   double *ha, *hb;           // probe hints inside the cell (caller's t_bracket or the network's)
   double *lam0s;             // [npts][n_pad] caller's starting costate of the first probe, or null
+  // minimum time on the reduced system of k copies (else null): the copies'
+  // spread s(T) at the point's probe horizon and ds/dT, which turn the
+  // reduced problem's bounds into the full system's (phi = phi_red + s)
+  double *kspread, *kdspread;
   double *T, *lo, *hi, *r, *tau, *sig, *P, *D;
   double *xf;                // [npts][n_pad]
   double *axf;               // [npts][n_pad]  A x_f (time derivative of x_f, for the Newton slope)
@@ -805,9 +809,11 @@ __device__ __forceinline__ double search_tol(const Opts &o, double t_max, double
 
 __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long p, int np, double sP,
                        double wsig, double sJ, double sAx, double slast) {
-  // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J)
-  const double Pv = fmin(sP + 0.5 + wsig, 0.5);
-  const double Dv = -0.5 * (sJ - 1.0);
+  // primal bound: the better of the iterate and lam = 0 (P(0) = 1/2 = -min J);
+  // a reduced system of copies shifts both bounds by the copies' spread
+  const double spread = st.kspread ? st.kspread[p] : 0.0;
+  const double Pv = fmin(sP + 0.5 + wsig, 0.5) - spread;
+  const double Dv = -0.5 * (sJ - 1.0) - spread;
   st.P[p] = Pv;
   st.D[p] = Dv;
   const double gap = (Pv - Dv) / fmax(1.0, fabs(Dv));
@@ -903,7 +909,7 @@ __device__ bool decide(const SysView &S, const PtState &st, const Opts &o, long 
       Tn = node_horizon(S.t_max, S.h, K, (ka + kb) / 2);
       cont = false;
     } else if (tight && !(st.newt[p] & 2)) {
-      const double slope = sAx - slast;            // d phi / dT = -H_x(p*, x0)
+      const double slope = sAx - slast + (st.kdspread ? st.kdspread[p] : 0.0);   // d phi / dT = -H_x(p*, x0)
       if (slope < 0.0 && isfinite(slope)) {
         const double r = T - (-0.5 * (Pv + Dv)) / slope;
         const double shift = 0.4 * search_tol(o, S.t_max, hi) + 0.5 * (Pv - Dv) / fabs(slope);

@@ -78,6 +78,8 @@ __global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__
     Jx += d * d / S.Wd[i];
   }
   Jx = 0.5 * (Jx - 1.0);
+  const double s0 = st.kspread ? st.kspread[p] : 0.0;   // reduced copies: J = J_red(mean) + s(0)
+  Jx += s0;
   const long q = idx ? idx[p] : p;
   st.rows[p] = 0;
   st.partial[p] = 0;
@@ -127,7 +129,7 @@ __global__ void k_init(SysView S, PtState st, Opts o, int mode, const double *__
         st.lam[p * S.n_pad + i] = (float)l;
         if (i < S.n) Pv += 0.5 * S.Wd[i] * l * l - (x[i] - S.c[i]) * l;
       }
-      st.P[p] = Pv;
+      st.P[p] = Pv - s0;
       st.D[p] = -Jx;
       return;
     }
@@ -1335,16 +1337,53 @@ __device__ void small_expm_apply(const SysView &S, double T, double *v) {
   }
 }
 
-// outputs of a reduced solve in the full system's terms (one thread per point)
+// The copies' spread s(T) = (1/2) sum_c a_c |e^{T A_b}(x_c - mean)|^2_{W_b^-1}
+// and ds/dT = sum_c a_c (e^{T A_b} d_c)^T W_b^-1 A_b e^{T A_b} d_c of the
+// minimum-time search on a reduced system, at the horizon of every point on
+// the setup list (from_list), or at T = 0 for every point (before k_init).
+__global__ void k_kron_spread(SysView S, PtState st, const double *__restrict__ x, int k,
+                              const double *__restrict__ wts, const int *__restrict__ idx, int xs, int from_list) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (from_list ? (long)st.counters[1] : st.npts)) return;
+  const long p = from_list ? (long)st.setup_list[i] : i;
+  const long q = idx ? idx[p] : p;
+  const int b = S.n, np = S.n_pad;
+  const double T = from_list ? st.T[p] : 0.0;
+  double s = 0.0, ds = 0.0;
+  if (isfinite(T))
+    for (int c = 0; c < k; ++c) {
+      const double ac = wts[b + c];
+      double d[KRON_BMAX];
+      for (int r = 0; r < b; ++r) d[r] = x[q * xs + (long)c * b + r] - st.x0[p * np + r];
+      if (T > 0.0) small_expm_apply(S, T, d);
+      for (int r = 0; r < b; ++r) {
+        double ad = 0.0;   // (A_b e^{T A_b} d_c)_r, A_b stored by columns
+        for (int j = 0; j < b; ++j) ad += S.At[(size_t)j * b + r] * d[j];
+        s += 0.5 * ac * wts[r] * d[r] * d[r];
+        ds += ac * wts[r] * d[r] * ad;
+      }
+    }
+  st.kspread[p] = s;
+  st.kdspread[p] = ds;
+}
+
+// outputs of a reduced solve in the full system's terms (one thread per
+// point): value bounds with the spread added and the copies' costates; a
+// minimum-time call takes the costates at the final horizon (the last scan
+// horizon for unreachable points) and its other outputs from k_outputs
 __global__ void k_kron_outputs(SysView S, PtState st, const double *__restrict__ x, int k,
                                const double *__restrict__ wts, double atot, double *philo, double *phihi,
                                double *lam_out, int *iters_out, int *status_out, const int *__restrict__ idx,
-                               int xs) {
+                               int xs, int min_time) {
   const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= st.npts) return;
   const long q = idx ? idx[p] : p;
   const int b = S.n, np = S.n_pad;
-  const double T = st.T[p];
+  double T = st.T[p];
+  if (min_time) {
+    if (!isfinite(T)) T = st.status[p] == HOPF_PT_UNREACH ? S.t_max : 0.0;
+    if (!lam_out) return;
+  }
   const bool f64 = st.s64 != nullptr && st.s64[p] != 0;
   double mean[KRON_BMAX], lred[KRON_BMAX];
   for (int r = 0; r < b; ++r) {
@@ -1362,6 +1401,7 @@ __global__ void k_kron_outputs(SysView S, PtState st, const double *__restrict__
       if (lam_out) lam_out[q * xs + (long)c * b + r] = ac * (wts[r] * d[r] + lred[r] / atot);
     }
   }
+  if (min_time) return;
   if (philo) philo[q] = -st.P[p] + spread;
   if (phihi) phihi[q] = -st.D[p] + spread;
   if (iters_out) iters_out[q] = st.iters_tot[p];
@@ -1411,7 +1451,8 @@ struct ArenaAlloc {
 };
 
 template <class Alloc>
-bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool with_lam0, bool fp64) {
+bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool with_lam0, bool fp64,
+                  bool kron_spread = false) {
   const int np = tab.n_pad, m = tab.m;
   st = PtState{};
   st.npts = npts;
@@ -1471,6 +1512,9 @@ bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool 
   st.rowsum = al.template get<double>(3);   // [0] 16-point rounds, [1] tail solver, [2] 64-point rounds
   st.lam0s = nullptr;
   if (with_lam0 && !(st.lam0s = al.template get<double>(npts * np))) return false;
+  if (kron_spread &&
+      (!(st.kspread = al.template get<double>(npts)) || !(st.kdspread = al.template get<double>(npts))))
+    return false;
   return st.x0 && st.status && st.phase && st.flags && st.probes && st.iters_tot && st.iters_probe &&
          st.rows && st.M && st.partial && st.nscan && st.ncell && st.newt && st.wbef && st.ha && st.hb && st.T &&
          st.lo && st.hi && st.r && st.tau && st.sig && st.P && st.D && st.xf && st.axf && st.xfc32 && st.R64 &&
@@ -1479,10 +1523,11 @@ bool layout_state(Alloc &al, const SysTables &tab, long npts, PtState &st, bool 
 }
 
 // Point state of job `job` in the context's reusable buffers.
-bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st, bool with_lam0) {
+bool make_state(Ctx *ctx, int job, const SysTables &tab, long npts, PtState &st, bool with_lam0,
+                bool kron_spread = false) {
   if ((int)ctx->jbufs.size() <= job) ctx->jbufs.resize(job + 1);
   GrowAlloc al{ctx->jbufs[job]};
-  if (!layout_state(al, tab, npts, st, with_lam0, ctx->opts.prec == HOPF_FP64)) return false;
+  if (!layout_state(al, tab, npts, st, with_lam0, ctx->opts.prec == HOPF_FP64, kron_spread)) return false;
   st.log_pt = ctx->log_pt;
   st.log_T = ctx->log_T;
   st.log_lam = ctx->log_lam;
@@ -1518,8 +1563,10 @@ namespace {
 struct Job {
   int sid = 0;
   const SysTables *tab = nullptr;
-  const SysTables *kron = nullptr;   // value solve of a Kronecker-structured system: its full tables
+  const SysTables *kron = nullptr;   // solve of a Kronecker-structured system: its full tables
                                      // (tab is then the reduced system's)
+  const double *kx = nullptr;        // the call's x (the copies), for the spread of a minimum-time search
+  int kxs = 0;
   SysView S{};
   pdhg_fn fp = nullptr, fp32_esc = nullptr;
   pdhg_fn fw = nullptr;          // 64-point LDS-staged FP32 iterations (nullptr: none for this shape)
@@ -1670,6 +1717,9 @@ hopf_status issue_group(Ctx *ctx, Job &J, const Opts &o, int mode) {
   const hipStream_t s = J.s;
   for (int r = 0; r < GROUP_ROUNDS && J.rounds < J.max_rounds; ++r) {
     launch_setup(J, o);
+    if (J.kx)   // the copies' spread at the new horizons (the setup list is still set)
+      k_kron_spread<<<(unsigned)((J.npts + 255) / 256), 256, 0, s>>>(J.S, J.st, J.kx, J.kron->kron_k,
+                                                                      J.kron->kron_winv_d, J.idx, J.kxs, 1);
     k_sort<<<1, 1024, 0, s>>>(J.st, J.tab->N, 1, 0);
     J.fc<<<J.ngrid, THREADS, J.lds_cert, s>>>(J.S, J.st, o, mode);
     const bool wide = (J.fw || J.fsw) && J.last_active >= ho.wide_min;
@@ -1821,7 +1871,9 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.sid = used[j];
     J.tab = &ctx->sys[J.sid];
     J.S = view(*J.tab);
-    if (mode == MODE_VALUE && ho.structure && J.tab->kron_red >= 0) {
+    // value solves, and minimum-time searches without a caller's lam0 (whose
+    // rows are the copies'), of a Kronecker-structured system
+    if (ho.structure && J.tab->kron_red >= 0 && (mode == MODE_VALUE || (mode == MODE_MINTIME && !lam0))) {
       // the reduced system of the copies' weighted mean; with equal weights
       // its step ratio sqrt(k) c_tau makes its iterates those of the full
       // system (||K||^2 is k times the reduced one's, and the reduced costate
@@ -1832,6 +1884,10 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
       J.S = view(*J.tab);
       const double ct = J.kron->desc.c_tau > 0.0 ? J.kron->desc.c_tau : ho.c_tau;
       J.S.c_tau = std::sqrt((double)J.kron->kron_k) * ct;
+      if (mode == MODE_MINTIME) {
+        J.kx = x;
+        J.kxs = nj > 1 ? xs : J.kron->n;
+      }
     }
     J.npts = cnt[J.sid];
     J.idx = nj > 1 ? d_idx + off[J.sid] : nullptr;
@@ -1840,11 +1896,12 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     J.last_active = J.npts;
     J.max_rounds = (long)(ho.max_iter / ho.check_every + 3) * (max_probes + 2);
     J.hcount = hcount + 4 * j;
-    J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64;
+    // (the tail solver's in-kernel probe setup has no spread term)
+    J.tail_ok = ho.prec == HOPF_FP32 && J.tab->n_pad <= 256 && J.tab->m <= 64 && !J.kx;
     if ((rc = plan_job(ctx, J)) != HOPF_OK) break;
     const bool net = (ho.warm == HOPF_WARM_MLP || ho.warm == HOPF_WARM_MLP_LAM || ho.warm == HOPF_WARM_MLP_FIRST) &&
                      J.sid < (int)ctx->mlp.size() && ctx->mlp[J.sid].valid && !J.kron;
-    if (!make_state(ctx, j, *J.tab, J.npts, J.st, (lam0 != nullptr && mode == MODE_MINTIME) || net)) {
+    if (!make_state(ctx, j, *J.tab, J.npts, J.st, (lam0 != nullptr && mode == MODE_MINTIME) || net, J.kx != nullptr)) {
       rc = set_err(ctx, HOPF_ENOMEM, "device allocation of the point state failed");
       break;
     }
@@ -1865,12 +1922,16 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
     const long tot = np_ * J.tab->n_pad;
     const int ls = nj > 1 ? xs : (J.kron ? J.kron->n : J.tab->n);     // row stride of x, lam0 and lam
     k_clear<<<1, 64, 0, s>>>(st);
-    if (J.kron)
+    if (J.kron) {
       k_kron_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.kron->kron_k, J.kron->kron_b,
                                                                  J.tab->n_pad, ls, J.idx, J.kron->kron_winv_d,
                                                                  J.kron->kron_atot);
-    else
+      if (J.kx)   // the spread at T = 0 decides which points start inside the target
+        k_kron_spread<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, J.kx, J.kron->kron_k,
+                                                                     J.kron->kron_winv_d, J.idx, J.kxs, 0);
+    } else {
       k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(x, st.x0, np_, J.tab->n, J.tab->n_pad, ls, J.idx, J.S.U);
+    }
     k_init<<<(unsigned)((np_ + 255) / 256), 256, 0, s>>>(J.S, st, o, mode, t_in, J.idx, lam0, t_bracket, ls);
     // learned start: the network at every point's first probe, batched on
     // the matrix cores (later probes of mode mlp_lam evaluate it in the setup)
@@ -1985,14 +2046,21 @@ hopf_status solve_dev(Ctx *ctx, int mode, long npts, const int *sys_id, const do
   for (int j = 0; j < nj; ++j) {
     Job &J = jobs[j];
     if (rc == HOPF_OK && J.st.x0) {
-      if (J.kron)
+      if (J.kron && mode == MODE_VALUE) {
         k_kron_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
             J.S, J.st, x, J.kron->kron_k, J.kron->kron_winv_d, J.kron->kron_atot, philo_out, phihi_out, lam_out,
-            iters_out, status_out, J.idx, nj > 1 ? xs : J.kron->n);
-      else
+            iters_out, status_out, J.idx, nj > 1 ? xs : J.kron->n, 0);
+      } else {
+        // (a minimum-time search on a reduced system: its bounds are already
+        // the full system's; the copies' costates follow)
         k_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
-            J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, lam_out, probes_out, iters_out, status_out,
-            J.idx, nj > 1 ? xs : J.tab->n);
+            J.S, J.st, mode, T_out, gap_out, philo_out, phihi_out, J.kron ? nullptr : lam_out, probes_out,
+            iters_out, status_out, J.idx, nj > 1 ? xs : J.tab->n);
+        if (J.kron && lam_out)
+          k_kron_outputs<<<(unsigned)((J.npts + 255) / 256), 256, 0, J.s>>>(
+              J.S, J.st, x, J.kron->kron_k, J.kron->kron_winv_d, J.kron->kron_atot, nullptr, nullptr, lam_out,
+              nullptr, nullptr, J.idx, nj > 1 ? xs : J.kron->n, 1);
+      }
       hipEvent_t fin = J.s != base ? take_event(ctx) : nullptr;
       if (fin) {
         hipEventRecord(fin, J.s);

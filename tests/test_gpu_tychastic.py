@@ -104,6 +104,61 @@ def test_unscented_min_time_vs_oracle(solver):
             assert r["gap"][i] <= GAP
 
 
+@pytest.mark.parametrize("case", ["tychastic30", "unscented10", "kron_l2"])
+def test_structured_min_time_matches_full_system(solver, case):
+    """Minimum-time searches of a system of copies sharing the control run on
+    the reduced system, each probe's certified bounds shifted by the copies'
+    spread at its horizon: the same statuses and first crossings as the full
+    system's search, the gap bar, the per-copy costates, and the reduced
+    dimension is the one iterated."""
+    say("case: structured min time", case)
+    if case == "tychastic30":
+        spec = tychastic_double_integrator(15, ell=ELL)
+        x = tychastic_points(15, 60, (1.0, 0.0), 0.0667, 45)
+        c_tau = 0.5
+    elif case == "unscented10":
+        spec = unscented_double_integrator(ELL)
+        x = unscented_points(60, (0.6, -0.3), (1.4, 0.3), 0.0667, 46)
+        x[30:] += 0.05 * np.random.default_rng(47).normal(size=(30, 10))
+        c_tau = 0.5
+    else:
+        spec = kron_system(5, 3, 2, "l2", seed=7)
+        x = np.random.default_rng(48).normal(0, 0.3, (60, spec.A.shape[0]))
+        c_tau = 1.0
+    solver.set_systems([spec])
+    res, width = {}, {}
+    for st in (1, 0):
+        solver.set_opts(prec="fp32", c_tau=c_tau, structure=st, max_iter=400000)
+        res[st] = solver.min_time(x)
+        tm = solver.last_timing()
+        rows = tm["point_rows"] + tm["tail_point_rows"]
+        width[st] = tm["alg_flops"] / (4 * spec.B.shape[1] * rows) if rows else 0.0
+        say("structure", st, "status", np.bincount(res[st]["status"], minlength=5), "iterated dimension", width[st])
+    assert round(width[1]) == (3 if case == "kron_l2" else 2) and round(width[0]) == spec.A.shape[0]
+    a, b = res[1], res[0]
+    assert np.array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    assert ok.sum() >= 10
+    assert np.all(a["gap"][ok] <= GAP)
+    # a horizon where |phi| is within the gap tolerance counts as reached, so
+    # where phi changes sign more than once inside the refined cell the two
+    # iteration orders may close on different crossings; each must be one
+    dT = np.abs(np.where(ok, a["T"], 0.0) - np.where(ok, b["T"], 0.0))   # unreachable points hold T = inf
+    diff = np.flatnonzero(ok & (dT > 1e-4 * np.where(ok, b["T"], 0.0)))
+    say("points with different T:", len(diff))
+    assert len(diff) <= 0.05 * len(x)
+    if len(diff):
+        solver.set_opts(prec="fp32", c_tau=c_tau, structure=0, max_iter=400000)
+        for r in (a, b):
+            v = solver.value(x[diff], r["T"][diff])
+            assert np.all(v["status"] == 0)
+            assert np.all(v["phi_lo"] <= 2e-6 * np.maximum(1.0, np.abs(v["phi_hi"]))), (diff, v["phi_lo"])
+    same = np.flatnonzero(ok & (dT <= 1e-4 * np.where(ok, b["T"], 0.0)))
+    dl = np.linalg.norm(a["lam"][same] - b["lam"][same], axis=1) / np.maximum(np.linalg.norm(b["lam"][same], axis=1),
+                                                                             1e-3)
+    assert dl.max() <= 2e-2, dl.max()
+
+
 def test_tychastic_full_size_sampled(solver):
     """The benchmark's d = 120 launch (65,536 value solves at t = t_max):
     every solve certified, and sampled points equal the oracle's 2-D value at
