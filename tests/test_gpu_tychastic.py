@@ -104,14 +104,16 @@ def test_unscented_min_time_vs_oracle(solver):
             assert r["gap"][i] <= GAP
 
 
-@pytest.mark.parametrize("case", ["tychastic30", "unscented10", "kron_l2"])
-def test_structured_min_time_matches_full_system(solver, case):
+@pytest.mark.parametrize("case,root", [("tychastic30", "bisect"), ("unscented10", "bisect"), ("kron_l2", "bisect"),
+                                       ("unscented10", "newton")])
+def test_structured_min_time_matches_full_system(solver, case, root):
     """Minimum-time searches of a system of copies sharing the control run on
     the reduced system, each probe's certified bounds shifted by the copies'
     spread at its horizon: the same statuses and first crossings as the full
     system's search, the gap bar, the per-copy costates, and the reduced
-    dimension is the one iterated."""
-    say("case: structured min time", case)
+    dimension is the one iterated.  With the Newton hybrid the reduced
+    slope adds the spread's derivative."""
+    say("case: structured min time", case, root)
     if case == "tychastic30":
         spec = tychastic_double_integrator(15, ell=ELL)
         x = tychastic_points(15, 60, (1.0, 0.0), 0.0667, 45)
@@ -128,7 +130,7 @@ def test_structured_min_time_matches_full_system(solver, case):
     solver.set_systems([spec])
     res, width = {}, {}
     for st in (1, 0):
-        solver.set_opts(prec="fp32", c_tau=c_tau, structure=st, max_iter=400000)
+        solver.set_opts(prec="fp32", c_tau=c_tau, structure=st, max_iter=400000, root=root)
         res[st] = solver.min_time(x)
         tm = solver.last_timing()
         rows = tm["point_rows"] + tm["tail_point_rows"]
