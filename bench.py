@@ -521,6 +521,37 @@ def bench_tychastic(args):
                "paper_ms_per_solve": round(pms, 3), "paper_solves_per_s": round(1e3 / pms, 1)}
         sweep.append(row)
 
+    # the unscented problem as Sec. VI-B poses it: minimum time to the
+    # weighted target, reduced system (structure 1) and full system
+    w = config_unscented(npts=args.npts)
+    solver.set_systems(w.systems)
+    xd = torch.tensor(w.x, dtype=torch.float64, device=dev)
+    npts = len(w.x)
+    Td, gd = (torch.empty(npts, dtype=torch.float64, device=dev) for _ in range(2))
+    std, prd = (torch.empty(npts, dtype=torch.int32, device=dev) for _ in range(2))
+    mt = {}
+    for structure in (1, 0):
+        solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], structure=structure, warm="cont")
+        nw = min(npts, 4096)
+        solver.min_time_dev(xd[:nw], Td[:nw], gd[:nw], std[:nw], probes=prd[:nw], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.min_time_dev(xd, Td, gd, std, probes=prd, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mt[structure] = (dt, Td.cpu().numpy(), std.cpu().numpy(), prd.cpu().numpy())
+        log(f"[unscented min time structure={structure}] {npts} queries: {dt:.3f} s")
+    (dt, T1, s1, p1), (dtf, T0, s0, _) = mt[1], mt[0]
+    ok = (s1 == 0) & (s0 == 0)
+    n_status = int(np.sum(s1 != s0))
+    n_T = int(np.sum(np.abs(T1[ok] - T0[ok]) > 1e-4 * T0[ok] + 1e-6 * w.systems[0].t_max))
+    unscented_mt = {"points": npts, "queries_per_s": round(npts / dt, 1), "device_s": round(dt, 4),
+                    "statuses": np.bincount(s1, minlength=5).tolist(), "mean_probes": round(float(p1.mean()), 2),
+                    "T_p50": round(float(np.median(T1[s1 == 0])), 4) if (s1 == 0).any() else None,
+                    "full_system": {"queries_per_s": round(npts / dtf, 1), "device_s": round(dtf, 4),
+                                    "points_with_other_status": n_status, "points_with_other_T": n_T},
+                    "paper_ms_per_point": 4.0, "paper_points_per_s": 250.0}
+
     top = sweep[-1]
     cpu = None
     if not args.no_cpu:
@@ -543,6 +574,7 @@ def bench_tychastic(args):
                       "c_tau": args.c_tau if args.c_tau is not None else config_tychastic(dims[-1], npts=1).opts["c_tau"],
                       "certificate": "fp64"},
            "sweep": sweep,
+           "unscented_min_time": unscented_mt,
            "paper_context": "Sec. VI-C fit of MATLAB time per value solve on a laptop CPU (FP64, residual stop "
                             "1e-4): paper_ms_per_solve; for the unscented row the Sec. VI-B average of 4.0 ms per "
                             "point (HJ solutions along trajectories); other hardware and a looser stop, not a target",
