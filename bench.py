@@ -157,8 +157,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="seconds of oracle wall time (value workloads)")
     ap.add_argument("--c3-sample", type=int, default=8,
                     help="c3: points (evenly spaced) solved by the oracle for the CPU rate and the error line")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c4", "tychastic", "grid", "tune"],
-                    help="c5: the headline min-time workload (default); c3: BF16 hi+lo precision "
+    ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c1", "c3", "c4", "tychastic", "grid", "tune"],
+                    help="c5: the headline min-time workload (default); c2 (n=50, m=5, N=200) and c1 (the "
+                         "double integrator, FP64, points uniform in [-2,2]^2): the same legs on those "
+                         "systems; c3: BF16 hi+lo precision "
                          "workload with its BF16 / FP32 difference; c4: 64 uneven systems in one call; "
                          "tychastic: the paper's dimensional-scaling value solves, d = 2k sampled copies; "
                          "grid: the paper's double-integrator level-set grid at ten horizons")
@@ -212,16 +214,22 @@ def bench_c5(args):
     the drift-planted start points, inputs resident in device memory.  Times
     the declared warm-start form (value) for K steps after W warmup steps,
     then the plain form (cold start at every probe) and the literal start
-    points within wall budgets, then the oracle on a stratified sample."""
+    points within wall budgets, then the oracle on a stratified sample.
+    --workload c2 / c1 run the same legs on C2 (n=50, m=5, N=200, drift-
+    planted and literal points) and C1 (the double integrator in FP64 on
+    points uniform in [-2, 2]^2, --npts of them; no literal leg, and the
+    oracle sample spread evenly over the batch)."""
     import numpy as np
     import torch
-    from gen.configs import config5
+    from gen.configs import config1, config2, config5
     from gen.workloads import planted_drift_points
     from paper_1712_08226_amd import Solver
     from paper_1712_08226_amd.hopfpd import default_opts
 
     t_start = time.perf_counter()
-    w = config5(npts=args.npts)
+    make, seed = {"c5": (config5, 5), "c2": (config2, 2), "c1": (config1, 1)}[args.workload]
+    w = make(npts=args.npts)
+    planted = args.workload != "c1"
     if args.prec:
         w.opts["prec"] = args.prec
     if args.c_tau is not None:
@@ -229,7 +237,8 @@ def bench_c5(args):
     ce_run = args.check_every if args.check_every is not None else w.opts.get("check_every",
                                                                               default_opts().check_every)
     spec = w.systems[0]
-    _, T0 = planted_drift_points(spec, args.npts, 0.2, 3.0, 5)     # the planted times of the batch's points
+    # the planted times of the batch's points (C1's points are not planted)
+    T0 = planted_drift_points(spec, args.npts, 0.2, 3.0, seed)[1] if planted else None
     dev = torch.device("cuda:0")
     solver = Solver(0)
     solver.set_systems([spec])
@@ -259,7 +268,7 @@ def bench_c5(args):
     train_info = None
     if warm.startswith("mlp"):
         # learned warm start: trained on separate drift-planted queries (not timed)
-        wt = config5(npts=args.train_npts, seed=105)
+        wt = make(npts=args.train_npts, seed=seed + 100)
         solver.set_opts(prec=w.opts["prec"], c_tau=w.opts["c_tau"], warm="cont", check_every=ce_run)
         t0 = time.perf_counter()
         tr = solver.warm_train(wt.x, epochs=args.epochs, batch=4096, lr=1e-3, seed=7)
@@ -331,7 +340,8 @@ def bench_c5(args):
     R = run_leg(args.warm, warm, main_buf, args.warmup, args.steps)
     head = summary(R)
     ok = R["status"] == 0
-    head["T_le_T0_frac"] = round(float(np.mean(R["T"][ok] <= T0[ok] * (1 + 1e-4))), 6) if ok.any() else None
+    head["T_le_T0_frac"] = (round(float(np.mean(R["T"][ok] <= T0[ok] * (1 + 1e-4))), 6)
+                            if ok.any() and planted else None)
 
     plain = None
     if not args.no_plain and warm != "cold":
@@ -342,8 +352,8 @@ def bench_c5(args):
             np.abs(P["T"][okb] - R["T"][okb]) <= 1e-4 * R["T"][okb]))
         plain["value_over_plain"] = round(R["qps"] / P["qps"], 3)
     literal = None
-    if not args.no_literal:
-        wl = config5(npts=args.npts, literal=True)
+    if not args.no_literal and planted:
+        wl = make(npts=args.npts, literal=True)
         lb = buffers(wl.x)
         L = run_leg("literal", warm, lb, 0, args.steps, args.literal_budget)
         literal = summary(L)
@@ -353,7 +363,7 @@ def bench_c5(args):
     # algorithmic flops: K lam and K^T y per point-row, 4 m n
     fpr = 4.0 * spec.m * spec.n
     bf = w.opts["prec"] == "bf16x3"
-    peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP32_MFMA_TFLOPS
+    peak = PEAK_BF16_MFMA_TFLOPS if bf else PEAK_FP64_TFLOPS if w.opts["prec"] == "fp64" else PEAK_FP32_MFMA_TFLOPS
     kern = {"k_pdhg_wide": (R["tw"], R["nw"], R["rw"]),
             "k_pdhg": (R["tk"] - R["tw"], R["launches"] - R["nw"], R["rows"] - R["rw"])}
     if bf:
@@ -365,7 +375,7 @@ def bench_c5(args):
     ct = None if bf else counter_traffic(args.warm, ce_run, w.opts["c_tau"], dom)
     traffic = None if ct is None else ct["hbm_bytes_per_launch"]
     desc = {"k_pdhg_wide": "k_pdhg_wide (fused FP32 PDHG iterations, 64 points per workgroup)",
-            "k_pdhg": "k_pdhg (fused FP32 PDHG iterations, 16-point tiles)",
+            "k_pdhg": f"k_pdhg (fused {w.opts['prec'].upper()} PDHG iterations, 16-point tiles)",
             "k_pdhg_stream": "k_pdhg_stream<bf16 hi+lo> (3 bf16 MFMAs per product; achieved counts algorithmic flops)"}
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
@@ -377,11 +387,14 @@ def bench_c5(args):
                                           "avg_launch_ms": round(1e3 * v[0] / max(1, v[1]), 4),
                                           "tflops": round(fpr * v[2] / v[0] / 1e12, 3) if v[0] > 0 else None}
                                       for k, v in kern.items()}}
-    out = {"metric": METRIC, "value": round(R["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": R["steps"],
+    metric = METRIC if args.workload == "c5" else \
+        f"min-time queries/sec at dual gap≤1e-6 (n={spec.n},N={spec.N}): plain vs warm-start"
+    out = {"metric": metric, "value": round(R["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": R["steps"],
            "warmup": args.warmup, "ms_per_step": round(R["ms"], 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": w.opts["prec"], "data": "synthetic",
-           "config": {"workload": f"min-time T(x), n={spec.n} m={spec.m} N={spec.N}, l2 control, ellipsoid target, "
-                                  f"t_max={spec.t_max}, trapezoid, {npts} {w.meta.get('points')} points "
+           "config": {"workload": f"min-time T(x), n={spec.n} m={spec.m} N={spec.N}, {spec.uset} control, "
+                                  f"ellipsoid target, t_max={spec.t_max}, {spec.quad}, {npts} "
+                                  f"{w.meta.get('points') or 'uniform in [-2,2]^2'} points "
                                   f"(value: warm start '{args.warm}'; plain: cold start at every probe)",
                       "npts": npts, "warm": args.warm, "scan": default_opts().scan,
                       "wide_min": args.wide_min if args.wide_min is not None else default_opts().wide_min,
@@ -392,13 +405,15 @@ def bench_c5(args):
            "roofline": roofline}
     if not args.no_cpu:
         workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
-        idx = stratified_sample(T0, args.cpu_sample)
+        idx = (stratified_sample(T0, args.cpu_sample) if planted
+               else np.unique(np.linspace(0, npts - 1, min(args.cpu_sample, npts)).astype(int)))
         copts = dict(c_tau=w.opts["c_tau"], warm=warm if warm in ("cold", "cont") else "cont", root=root)
         log(f"[cpu] oracle on {len(idx)} stratified queries, {workers} workers")
         rate, wall, per, cst = cpu_baseline(spec, w.x[idx], copts, workers)
         out["cpu_baseline"] = {"value": round(rate, 4), "unit": "queries/s", "cores": workers, "kind": "oracle",
-                               "sample": f"{len(idx)} of the batch's queries spread evenly over the planted times "
-                                         f"T0, each run to completion on {workers} single-thread processes "
+                               "sample": f"{len(idx)} of the batch's queries spread evenly over "
+                                         f"{'the planted times T0' if planted else 'the batch'}, each run to "
+                                         f"completion on {workers} single-thread processes "
                                          f"({wall:.1f} s wall; per query mean {per.mean():.2f} s, max "
                                          f"{per.max():.2f} s)",
                                "options": copts, "statuses": cst, **host_info()}
