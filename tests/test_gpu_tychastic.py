@@ -161,6 +161,38 @@ def test_structured_min_time_matches_full_system(solver, case, root):
     assert dl.max() <= 2e-2, dl.max()
 
 
+@pytest.mark.parametrize("mode", ["value", "min_time"])
+def test_structured_system_in_a_batched_call(solver, mode):
+    """A system of copies next to an ordinary one in one call: each job is
+    solved as in a call of its own (the copies on their reduced system),
+    bit for bit, costates included."""
+    from gen import random_system
+    say("case: structured system batched", mode)
+    specs = [tychastic_double_integrator(5, ell=ELL), random_system(8, 2, 60, "l2", seed=5, t_max=4.0)]
+    xa = tychastic_points(5, 40, (1.0, 0.0), 0.0667, 50)
+    xb = np.zeros((40, 10))
+    xb[:, :8] = np.random.default_rng(51).normal(0, 0.4, (40, 8))
+    x = np.concatenate([xa, xb])
+    sid = np.repeat([0, 1], 40).astype(np.int32)
+    perm = np.random.default_rng(52).permutation(len(sid))
+    x, sid = x[perm], sid[perm]
+    t = np.linspace(0.3, 1.9, len(sid))
+    solver.set_systems(specs)
+    solver.set_opts(prec="fp32", c_tau=0.5, warm="cont")
+    rb = solver.min_time(x, sys_id=sid) if mode == "min_time" else solver.value(x, t, sys_id=sid)
+    keys = ["T", "gap", "status", "probes", "iters"] if mode == "min_time" else ["phi_lo", "phi_hi", "status", "iters"]
+    for k, spec in enumerate(specs):
+        sel = np.flatnonzero(sid == k)
+        n = spec.A.shape[0]
+        solver.set_systems([spec])
+        r1 = solver.min_time(x[sel, :n]) if mode == "min_time" else solver.value(x[sel, :n], t[sel])
+        for key in keys:
+            assert np.array_equal(rb[key][sel], r1[key], equal_nan=True), (k, key)
+        assert np.array_equal(rb["lam"][sel, :n], r1["lam"]), k
+        say("system", k, "statuses", np.bincount(r1["status"], minlength=5))
+        solver.set_systems(specs)
+
+
 def test_tychastic_full_size_sampled(solver):
     """The benchmark's d = 120 launch (65,536 value solves at t = t_max):
     every solve certified, and sampled points equal the oracle's 2-D value at
