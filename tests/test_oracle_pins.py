@@ -532,6 +532,37 @@ def test_unscented_with_no_spread_is_the_double_integrator():
     assert abs(res.T - Tc) <= 3e-4 * Tc + 0.02 * O.grid_step(S) ** 2, (res.T, Tc)
 
 
+@pytest.mark.slow
+def test_unscented_min_time_is_the_crossing_of_reduced_value_plus_spread():
+    """The reduced minimum-time search rests on phi(x, T) = phi_red(mean, T) +
+    s(T) at every horizon: at the full 10-state system's first crossing T*
+    the reduced value plus the weighted spread is reached (<= 0), and one
+    stopping tolerance earlier it is not, with s(T) of the size that makes
+    the difference."""
+    ell = 0.04
+    w, _ = unscented_weights(2)
+    S = sysobj(unscented_double_integrator(ell, N=100, t_max=2.0, quad="left"))
+    S2 = sysobj(double_integrator(math.sqrt(ell), 100, t_max=2.0, quad="left"))
+    opt = O.Options(c_tau=0.5, gap_tol=1e-10, max_iter=400000)
+    X = unscented_points(2, (0.7, -0.2), (1.0, 0.1), 0.0667, 24)
+    X = X + 0.03 * np.random.default_rng(6).normal(size=X.shape)
+    for x in X:
+        r = O.min_time(S, x, O.Options(c_tau=0.5))
+        assert r.status == O.PT_OK
+        chi = x.reshape(5, 2)
+        mean = w @ chi
+
+        def reduced(T):
+            E = np.array([[1.0, T], [0.0, 1.0]])
+            s = float(w @ np.sum(((chi - mean) @ E.T) ** 2, axis=1)) / (2 * ell)
+            b = O.solve_value(S2, mean, T, opt)
+            return b.phi_hi + s, s
+        at, s_at = reduced(r.T)
+        before, _ = reduced(r.T - 2e-4 * r.T - 2e-6)
+        assert at <= 1e-6 and before > 0.0, (r.T, at, before)
+        assert s_at > 1e-2
+
+
 def test_sigma_points_reproduce_the_moments():
     """The 2n+1 sigma points with their mean weights reproduce the mean and
     covariance of N(mu, std^2 I_2) exactly; the weights sum to one and, with
