@@ -83,3 +83,31 @@ def test_set_opts_rejects_unknown_option_names():
         pass
     with pytest.raises(TypeError, match="unknown solver option"):
         H.Solver.set_opts(NoCtx(), wide_minn=1)
+
+
+def test_documented_option_defaults_match_the_library():
+    """Every numeric default the header documents in brackets after an option
+    is the value hopf_default_opts fills in."""
+    txt = open(os.path.join(ROOT, "include", "hopfpd.h")).read()
+    block = txt[txt.index("/* Solver options"):txt.index("} hopf_opts;")]
+    names = [f[0] for f in H.HopfOpts._fields_]
+    o = H.default_opts()
+    # option name at the start of a doc line, then the text up to the next option
+    starts = [(m.start(), m.group(1)) for m in re.finditer(r"\n \*   ([a-z_0-9]+) ", block) if m.group(1) in names]
+    checked = 0
+    for (pos, name), nxt in zip(starts, starts[1:] + [(len(block), None)]):
+        brackets = re.findall(r"\[([^\]]*)\]\s*(?:\n|\*/|$)", block[pos:nxt[0]])
+        if not brackets:
+            continue
+        vals = [v.strip() for v in brackets[-1].split(",")]
+        try:
+            nums = [float(v) for v in vals]
+        except ValueError:
+            continue                      # symbolic default (an enum name)
+        if len(nums) == 1:
+            assert getattr(o, name) == nums[0], (name, getattr(o, name), nums[0])
+            checked += 1
+        elif name == "t_abs_frac":      # the pair t_rel_tol, t_abs_frac is documented on its line
+            assert (o.t_rel_tol, o.t_abs_frac) == tuple(nums), (o.t_rel_tol, o.t_abs_frac, nums)
+            checked += 2
+    assert checked >= 12, checked
