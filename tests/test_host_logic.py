@@ -3,6 +3,7 @@ traffic, the binding's checks of device tensors, and the workload generators
 of the paper's scaling and level-set experiments."""
 import hashlib
 import json
+import os
 import sys
 
 import numpy as np
@@ -92,3 +93,26 @@ def test_tuner_accepts_only_the_reference_results():
     v = dict(status=np.array([0, 0]), phi_lo=np.array([1.0, -2.0]), phi_hi=np.array([1.1, -1.9]))
     assert _same(v, dict(v, phi_lo=np.array([1.05, -1.95]), phi_hi=np.array([1.2, -1.8])), "value")
     assert not _same(v, dict(v, phi_lo=np.array([1.2, -2.0]), phi_hi=np.array([1.3, -1.9])), "value")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more exits with status 2 and
+    says why, before touching a device."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_unscented_config_and_weights():
+    """The unscented workload: five sigma points per query around means in
+    the stated box, target blocks ell / w_i with the 1/3, 1/6 weights."""
+    from gen.configs import config_unscented
+    w = config_unscented(npts=16)
+    spec = w.systems[0]
+    assert w.x.shape == (16, 10) and spec.A.shape == (10, 10) and spec.B.shape == (10, 1)
+    assert np.allclose(np.diag(spec.W), 0.04 / np.repeat([1 / 3, 1 / 6, 1 / 6, 1 / 6, 1 / 6], 2))
+    mu = w.x[:, :2]
+    assert np.all((mu[:, 0] >= 0.8) & (mu[:, 0] <= 1.2) & (mu[:, 1] >= -0.2) & (mu[:, 1] <= 0.2))
