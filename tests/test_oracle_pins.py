@@ -563,6 +563,29 @@ def test_unscented_min_time_is_the_crossing_of_reduced_value_plus_spread():
         assert s_at > 1e-2
 
 
+def test_unscented_costates_from_the_reduced_solve():
+    """The full system's optimal costate per sigma point is rebuilt from the
+    reduced solve at the weighted mean: lam_c = a_c (W_b^-1 e^{TA}(chi_c -
+    mean) + lam_red / a), a_c = w_c / w_0, a = sum_c a_c (W_b = ell/w_0 I, the
+    first block).  Dropping a_c or the 1/a share fails by a factor of two or
+    more on the four outer points."""
+    ell, T = 0.04, 1.3
+    w, _ = unscented_weights(2)
+    S = sysobj(unscented_double_integrator(ell, N=100, t_max=2.0, quad="left"))
+    S2 = sysobj(double_integrator(math.sqrt(ell), 100, t_max=2.0, quad="left"))
+    opt = O.Options(c_tau=0.5, gap_tol=1e-12, max_iter=800000)
+    x = unscented_points(1, (0.8, -0.2), (1.2, 0.2), 0.0667, 25)[0] + 0.05 * np.random.default_rng(9).normal(size=10)
+    full = O.solve_value(S, x, T, opt)
+    chi = x.reshape(5, 2)
+    mean = w @ chi
+    red = O.solve_value(S2, mean, T, opt)
+    E = np.array([[1.0, T], [0.0, 1.0]])
+    a = w / w[0]
+    wb_inv = w[0] / ell
+    lam = np.concatenate([a[c] * (wb_inv * (E @ (chi[c] - mean)) + red.lam / a.sum()) for c in range(5)])
+    assert np.max(np.abs(full.lam - lam)) <= 1e-4 * np.max(np.abs(full.lam)), np.max(np.abs(full.lam - lam))
+
+
 def test_sigma_points_reproduce_the_moments():
     """The 2n+1 sigma points with their mean weights reproduce the mean and
     covariance of N(mu, std^2 I_2) exactly; the weights sum to one and, with
