@@ -161,8 +161,9 @@ typedef struct {
  *                 value adds the spread (1/2) sum_c a_c |e^{tA_b}(x_c - mean)|^2_{W_b^-1}
  *                 in FP64 (a search adds it to the certified bounds at every probe
  *                 horizon, and its points skip the tail solver) and lambda is
- *                 rebuilt per copy.  Exact (the copies share z(u) in
- *                 x_c(t) = e^{tA_b} x_c + z(u)); 0: solve the full system            [1]
+ *                 rebuilt per copy; iters and probes count the reduced solve's.
+ *                 Exact (the copies share z(u) in x_c(t) = e^{tA_b} x_c + z(u));
+ *                 0: solve the full system                                        [1]
  *   tail_max      FP32 iterations: once at most tail_max of a system's points are
  *                 still running, a per-point solver (one workgroup per point,
  *                 matrix-vector iterations, certificate and search step in one
